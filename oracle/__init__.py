@@ -1,0 +1,185 @@
+"""Python access to the FP64 CPU oracle (oracle.cpp).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.  It never imports the GPU library and the GPU
+library never imports it; the two share only the seeded inputs from `synth`.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
+
+
+def build(force=False):
+    """Compile oracle.cpp into liboracle.so with g++ (OpenMP over trajectories)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Sys(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("R", C.c_void_p), ("E", C.c_void_p),
+                ("M", C.c_void_p), ("M2", C.c_void_p), ("dM", C.c_void_p), ("dM2", C.c_void_p),
+                ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p), ("jx_col", C.c_void_p),
+                ("jx_val", C.c_void_p), ("mu", C.c_double), ("literal_phase", C.c_int32),
+                ("plant_coriolis_flip", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        _lib.oracle_spline_prepare.argtypes = [i32, vp, i64, vp, vp]
+        _lib.oracle_spline_eval.argtypes = [i32, vp, i64, vp, vp, d, vp, vp]
+        _lib.oracle_spline_eval.restype = i32
+        _lib.oracle_rhs.argtypes = [vp, d, vp, vp]
+        _lib.oracle_rhs.restype = d
+        _lib.oracle_total_energy.argtypes = [vp, d, vp]
+        _lib.oracle_total_energy.restype = d
+        _lib.oracle_propagate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp,
+                                          d, d, i64, d] + [vp] * 10
+        _lib.oracle_tangent_rk4.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib.oracle_cross_sections.argtypes = [i64, i32, vp, vp, vp, vp, i32, d, vp]
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def spline_prepare(x, y):
+    """Natural-spline second derivatives of the columns of y[K, ...] on knots x[K]."""
+    x = _f64(x)
+    y = _f64(y)
+    y2 = np.empty_like(y)
+    ncol = int(np.prod(y.shape[1:])) if y.ndim > 1 else 1
+    lib().oracle_spline_prepare(len(x), _p(x), ncol, _p(y), _p(y2))
+    return y2
+
+
+def spline_eval(x, y, y2, r):
+    x = _f64(x); y = _f64(y); y2 = _f64(y2)
+    shape = y.shape[1:]
+    ncol = int(np.prod(shape)) if shape else 1
+    v = np.empty(ncol); d = np.empty(ncol)
+    below = lib().oracle_spline_eval(len(x), _p(x), ncol, _p(y), _p(y2), float(r), _p(v), _p(d))
+    return v.reshape(shape), d.reshape(shape), bool(below)
+
+
+class OracleSystem:
+    """A system prepared for the oracle: complex tables and their spline curvature."""
+
+    def __init__(self, system, literal_phase=False, tables=None, tangent_tables=None,
+                 plant_coriolis_flip=False):
+        M = system.M if tables is None else tables
+        self.N, self.K = int(system.E.shape[0]), int(system.R_grid.shape[0])
+        self.R = _f64(system.R_grid)
+        self.E = _f64(system.E)
+        self.M = np.ascontiguousarray(M, dtype=np.complex128)
+        self.M2 = spline_prepare(self.R, self.M.view(np.float64).reshape(self.K, -1)) \
+            .reshape(self.K, self.N, self.N, 2)
+        self.dM = self.dM2 = None
+        if tangent_tables is not None:
+            self.dM = np.ascontiguousarray(tangent_tables, dtype=np.complex128)
+            self.dM2 = spline_prepare(self.R, self.dM.view(np.float64).reshape(self.K, -1)) \
+                .reshape(self.K, self.N, self.N, 2)
+        self.jx_row = np.ascontiguousarray(system.jx_row, np.int32)
+        self.jx_col = np.ascontiguousarray(system.jx_col, np.int32)
+        self.jx_val = _f64(system.jx_val)
+        self.mu = float(system.mu)
+        self.system = system
+        self.s = _Sys(self.N, self.K, _p(self.R), _p(self.E), _p(self.M), _p(self.M2),
+                      _p(self.dM), _p(self.dM2), len(self.jx_val), _p(self.jx_row),
+                      _p(self.jx_col), _p(self.jx_val), self.mu, 1 if literal_phase else 0,
+                      1 if plant_coriolis_flip else 0)
+
+    def rhs(self, t, y):
+        y = _f64(y)
+        f = np.empty_like(y)
+        eq = lib().oracle_rhs(C.byref(self.s), float(t), _p(y), _p(f))
+        return f, eq
+
+    def total_energy(self, t, y):
+        y = _f64(y)
+        return lib().oracle_total_energy(C.byref(self.s), float(t), _p(y))
+
+    def propagate(self, batch=None, *, init_channel=None, a0=None, classical0=None,
+                  E_coll=None, b=None, R0=None, t0=None, method="rk4", dt=None, n_steps=None,
+                  rtol=1e-8, atol=1e-8, max_steps=100000, h_min=1e-6):
+        if batch is not None:
+            init_channel = batch.init_channel if init_channel is None else init_channel
+            E_coll = batch.E_coll if E_coll is None else E_coll
+            b = batch.b if b is None else b
+            R0 = batch.R0 if R0 is None else R0
+            dt = batch.dt if dt is None else dt
+            n_steps = batch.n_steps if n_steps is None else n_steps
+        if classical0 is not None:
+            B = int(np.asarray(classical0).reshape(-1, 6).shape[0])
+        else:
+            B = int(np.asarray(E_coll).shape[0])
+        N = self.N
+        ic = None if init_channel is None else np.ascontiguousarray(init_channel, np.int32)
+        a0c = None if a0 is None else np.ascontiguousarray(
+            np.asarray(a0, np.complex128).reshape(B, N)).view(np.float64)
+        c0 = _f64(None if classical0 is None else np.reshape(classical0, (B, 6)))
+        Ec, bb, r0 = _f64(E_coll), _f64(b), _f64(R0)
+        t0c = _f64(t0)
+        dtc = _f64(np.broadcast_to(np.asarray(dt if dt is not None else 0.0, np.float64), (B,)))
+        ns = np.ascontiguousarray(np.broadcast_to(
+            np.asarray(n_steps if n_steps is not None else 0, np.int64), (B,)))
+        out = {
+            "P": np.empty((B, N)), "a_final": np.empty((B, N), np.complex128),
+            "classical": np.empty((B, 6)), "t_final": np.empty(B),
+            "steps": np.empty(B, np.int64), "rejects": np.empty(B, np.int64),
+            "status": np.empty(B, np.int32), "norm_err": np.empty(B),
+            "energy_err": np.empty(B), "angmom_err": np.empty(B)}
+        lib().oracle_propagate(
+            C.byref(self.s), B, _p(ic), _p(a0c), _p(c0), _p(Ec), _p(bb), _p(r0), _p(t0c),
+            0 if method == "rk4" else 1, _p(dtc), _p(ns), float(rtol), float(atol),
+            int(max_steps), float(h_min),
+            _p(out["P"]), _p(out["a_final"]), _p(out["classical"]), _p(out["t_final"]),
+            _p(out["steps"]), _p(out["rejects"]), _p(out["status"]), _p(out["norm_err"]),
+            _p(out["energy_err"]), _p(out["angmom_err"]))
+        return out
+
+    def tangent_rk4(self, batch):
+        assert self.dM is not None, "tangent tables required"
+        B, N = batch.B, self.N
+        P = np.empty((B, N)); dP = np.empty((B, N))
+        ic = np.ascontiguousarray(batch.init_channel, np.int32)
+        Ec, bb, r0 = _f64(batch.E_coll), _f64(batch.b), _f64(batch.R0)
+        dtc = _f64(batch.dt)
+        ns = np.ascontiguousarray(batch.n_steps, np.int64)
+        lib().oracle_tangent_rk4(C.byref(self.s), B, _p(ic), _p(Ec), _p(bb), _p(r0), _p(dtc),
+                                 _p(ns), _p(P), _p(dP))
+        return P, dP
+
+
+def cross_sections(init_level, b, P, level_of_channel, n_levels, b_max):
+    P = _f64(P)
+    B, N = P.shape
+    sig = np.empty((n_levels, n_levels))
+    il = np.ascontiguousarray(init_level, np.int32)
+    lc = np.ascontiguousarray(level_of_channel, np.int32)
+    bb = _f64(b)
+    lib().oracle_cross_sections(B, N, _p(il), _p(bb), _p(P), _p(lc), int(n_levels),
+                                float(b_max), _p(sig))
+    return sig
