@@ -1,0 +1,217 @@
+/*
+ * mqct.h -- C ABI of the MI355X (gfx950) batched Ehrenfest mean-field trajectory
+ * propagator for mixed quantum/classical collision dynamics (MQCT).
+ *
+ * Physics (paper Section II): for every trajectory the interaction-picture
+ * amplitudes a_n (Eq. 4) obey
+ *     da_n/dt = -i sum_m M_nm(R) e^{i(E_n - E_m)t} a_m - i Phidot (J_x a)_n     (Eq. 5)
+ * and the classical separation R, angle Phi and momenta P_R, P_Phi obey
+ * Eqs. 7-10 in the collision plane Theta = pi/2 (end of Section II).  M(R) is
+ * the coupling matrix (Eq. 6) tabulated on an R grid and interpolated with a
+ * natural cubic spline (Section III).  J_x is the Coriolis operator: its
+ * elements are the square-root factors of Eq. 5; the generator is taken as
+ * -i Phidot J_x (the reading that conserves norm and total energy).  The
+ * torque dP_Phi/dt = -i<[J_x, V]> is Eq. 10.  Final |a_n|^2 give state-to-state
+ * probabilities and cross sections (end of Section II).
+ *
+ * Units: atomic units everywhere at this interface (hartree, bohr, electron
+ * masses, hbar/E_h).
+ *
+ * Conventions:
+ *   - Every function returns mqct_status (0 = success, negative = error) and
+ *     never throws or aborts across the interface.  mqct_last_error() gives a
+ *     message for the most recent failure on a context.
+ *   - Argument and validation errors are reported before any device work.
+ *   - Input pointers are borrowed for the duration of the call (tables are
+ *     copied); result pointers are caller-owned.
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef MQCT_H
+#define MQCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mqct_context mqct_context;
+typedef int32_t mqct_status;
+
+enum {
+  MQCT_OK = 0,
+  MQCT_ERR_ARG = -1,           /* invalid argument (sizes, pointers, ranges)           */
+  MQCT_ERR_NONFINITE = -2,     /* NaN or Inf in an input table                         */
+  MQCT_ERR_NOT_HERMITIAN = -3, /* |M - M^H| > 1e-12 max|M| at some knot                */
+  MQCT_ERR_OOM = -4,           /* device allocation failed                             */
+  MQCT_ERR_DEVICE = -5,        /* a HIP runtime call failed                            */
+  MQCT_ERR_UNSUPPORTED = -6,   /* a valid request this build does not implement        */
+  MQCT_ERR_STATE = -7          /* call out of order (e.g. unknown system id)           */
+};
+
+/* element types of coupling tables */
+enum { MQCT_R64 = 0, MQCT_C128 = 1, MQCT_R32 = 2, MQCT_C64 = 3 };
+/* time steppers */
+enum { MQCT_RK4 = 0, MQCT_DP5 = 1 };
+/* where a caller buffer lives */
+enum { MQCT_MEM_HOST = 0, MQCT_MEM_DEVICE = 1 };
+/* per-trajectory status bits */
+enum {
+  MQCT_T_EXITED = 1,          /* DP5: left the interaction region (R >= R0, P_R > 0)   */
+  MQCT_T_MAX_STEPS = 2,       /* DP5: accepted-step limit reached                      */
+  MQCT_T_STEP_UNDERFLOW = 4,  /* DP5: step size fell below h_min                       */
+  MQCT_T_BELOW_GRID = 8,      /* R went below the first knot (linear continuation used) */
+  MQCT_T_NONFINITE = 16       /* NaN/Inf appeared; the trajectory was stopped          */
+};
+/* batch schedules */
+enum {
+  MQCT_SCHED_AUTO = 0,        /* library chooses                                        */
+  MQCT_SCHED_GEMV = 1,        /* one workgroup per trajectory, step loop inside a kernel */
+  MQCT_SCHED_BINNED = 2,      /* lockstep stages, trajectories binned by spline knot,
+                                 table x amplitude-columns products on matrix cores    */
+  MQCT_SCHED_PERSISTENT = 3   /* persistent workgroups draining a trajectory queue     */
+};
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue all work on (NULL: the context creates and owns its own stream). */
+mqct_status mqct_create(int32_t device, void* hip_stream, mqct_context** out);
+/* Free every device buffer of the context (waits for its stream first). */
+void mqct_destroy(mqct_context* ctx);
+/* Message of the most recent failure on ctx (static text when ctx is NULL);
+ * valid until the next call on ctx. */
+const char* mqct_last_error(const mqct_context* ctx);
+/* Block until all work enqueued on the context stream has finished. */
+mqct_status mqct_synchronize(mqct_context* ctx);
+
+/*
+ * A collision system: channel energies, coupling tables on an R grid and the
+ * Coriolis operator (Section II, Eqs. 5-6; Section III for the grid + spline).
+ *   N, K      channels; grid points (K >= 4).
+ *   R_grid    host [K] bohr, strictly increasing.
+ *   E         host [N] hartree.
+ *   in_dtype  MQCT_R64 or MQCT_C128: element type of M as passed.
+ *   M_mem     MQCT_MEM_HOST or MQCT_MEM_DEVICE: where M lives.
+ *   M         [K][N][N] row-major, M[k][n][m] = <n|V(R_k)|m> (hartree), Hermitian
+ *             per knot.  Copied; the caller may free it after the call.
+ *   storage   MQCT_R64/MQCT_C128 (FP64 path) or MQCT_R32/MQCT_C64 (FP32-table
+ *             path).  A real storage type requires real input.
+ *   jx_*      J_x as a coordinate list (host), real symmetric, at most 8
+ *             nonzeros per row; jx_nnz may be 0.
+ *   mu        reduced mass, electron masses.
+ * The natural-spline second derivatives of every element are computed on the
+ * device in FP64 and stored with the tables in the storage type.
+ */
+typedef struct {
+  int32_t N, K;
+  const double* R_grid;
+  const double* E;
+  int32_t in_dtype;
+  int32_t M_mem;
+  const void* M;
+  int32_t storage;
+  int32_t jx_nnz;
+  const int32_t* jx_row;
+  const int32_t* jx_col;
+  const double* jx_val;
+  double mu;
+} mqct_system_desc;
+
+/* Validate (finite, Hermitian, increasing grid), upload, spline-prepare.
+ * Errors: MQCT_ERR_ARG, MQCT_ERR_NONFINITE, MQCT_ERR_NOT_HERMITIAN,
+ * MQCT_ERR_OOM, MQCT_ERR_DEVICE.  Synchronous. */
+mqct_status mqct_system_load(mqct_context* ctx, const mqct_system_desc* desc,
+                             int32_t* system_id);
+/* Device bytes held by a loaded system's tables (values + second derivatives). */
+mqct_status mqct_system_bytes(mqct_context* ctx, int32_t system_id, int64_t* bytes);
+/* Release a system's device memory; its id becomes invalid. */
+mqct_status mqct_system_free(mqct_context* ctx, int32_t system_id);
+
+/*
+ * A batch of trajectories (Section III: Monte-Carlo initial conditions).  All
+ * pointers are host arrays.  Per trajectory b:
+ *   system_id[b]     a loaded system; trajectories may mix systems.
+ *   init_channel[b]  a(0) = e_n; ignored when a0 is given.
+ *   a0               optional [sum_b N_b][2] initial amplitudes (complex
+ *                    interleaved, concatenated in batch order).
+ *   classical0       optional [B][6] initial (R, Theta, Phi, P_R, P_Theta,
+ *                    P_Phi).  Without it: R = R0, Theta = pi/2, Phi = 0,
+ *                    P_Phi = b sqrt(2 mu E_coll), P_R = -sqrt(2 mu E_coll - P_Phi^2/R0^2).
+ *   E_coll, b        [B] hartree, bohr (0 <= b < R0); unused with classical0.
+ *   R0               optional [B] start (and DP5 exit) radius; NULL = last knot.
+ *   t0               optional [B] start time; NULL = 0.
+ *   dt               [B] RK4 step (required for RK4).
+ *   n_steps          [B] RK4 step count (exact; no early exit).
+ *   rtol, atol, max_steps, h_min   DP5 controls (scaled RMS error norm).
+ *   schedule         MQCT_SCHED_*.
+ */
+typedef struct {
+  int64_t B;
+  const int32_t* system_id;
+  const int32_t* init_channel;
+  const double* a0;
+  const double* classical0;
+  const double* E_coll;
+  const double* b;
+  const double* R0;
+  const double* t0;
+  int32_t integrator;
+  const double* dt;
+  const int64_t* n_steps;
+  double rtol, atol;
+  int64_t max_steps;
+  double h_min;
+  int32_t schedule;
+} mqct_batch_desc;
+
+/*
+ * Results.  `mem` says where ALL arrays below live.  With MQCT_MEM_DEVICE the
+ * run is asynchronous on the context stream; with MQCT_MEM_HOST mqct_run
+ * returns after the host arrays are filled.  Arrays other than P may be NULL.
+ *   P          [sum_b N_b] final |a_n|^2 (batch order, offsets = prefix sums of N_b)
+ *   a_final    [sum_b N_b][2]
+ *   classical  [B][6] final R, Theta, Phi, P_R, P_Theta, P_Phi
+ *   t_final, steps, rejects, status  [B]
+ *   norm_err   [B] sum|a|^2 - 1;  energy_err [B] relative change of the total
+ *   (classical + rotational + mean-field) energy;  angmom_err [B] change of
+ *   P_Phi - <J_x>.
+ */
+typedef struct {
+  int32_t mem;
+  double* P;
+  double* a_final;
+  double* classical;
+  double* t_final;
+  int64_t* steps;
+  int64_t* rejects;
+  int32_t* status;
+  double* norm_err;
+  double* energy_err;
+  double* angmom_err;
+} mqct_batch_result;
+
+/* Propagate a batch.  Errors: MQCT_ERR_ARG, MQCT_ERR_STATE (unknown system),
+ * MQCT_ERR_UNSUPPORTED (schedule/integrator combination), MQCT_ERR_OOM,
+ * MQCT_ERR_DEVICE.  Per-trajectory problems go to the status bits. */
+mqct_status mqct_run(mqct_context* ctx, const mqct_batch_desc* batch,
+                     mqct_batch_result* result);
+
+/*
+ * Monte-Carlo cross sections (end of Section II; b sampled uniformly on
+ * [0, b_max]):
+ *   sigma[L'][L''] = (2 pi b_max / N_L') sum_{b : level(b) = L'} b_b sum_{n in L''} P_b(n)
+ * in bohr^2, with N_L' the number of trajectories started in level L'.  All
+ * trajectories share one channel-to-level map.  Computed on the device.
+ *   mem               where P, b, init_level and sigma live.
+ *   P                 [B][N]; b [B]; init_level [B]; level_of_channel host [N].
+ *   sigma             [n_levels][n_levels].
+ */
+mqct_status mqct_cross_sections(mqct_context* ctx, int32_t mem, int64_t B, int32_t N,
+                                const double* P, const double* b, const int32_t* init_level,
+                                const int32_t* level_of_channel, int32_t n_levels,
+                                double b_max, double* sigma);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MQCT_H */

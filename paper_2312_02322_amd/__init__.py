@@ -1,0 +1,303 @@
+"""MI355X (gfx950) batched Ehrenfest mean-field trajectory propagation (MQCT).
+
+A thin ctypes binding of libmqct (include/mqct.h): argument marshalling only,
+every step of the propagation runs in the library's HIP kernels.  PyTorch
+provides device memory and the stream.  The binding fails loudly when the
+library has not been built or no GPU is visible.
+
+    ctx = Context()                       # on torch's current stream of cuda:0
+    sid = ctx.load_system(system, storage="C128")
+    out = ctx.run([sid] * B, init_channel=..., E_coll=..., b=..., dt=..., n_steps=...)
+    torch.cuda.synchronize(); out["P"]     # final |a_n|^2, concatenated per trajectory
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmqct.so")
+
+OK, ERR_ARG, ERR_NONFINITE, ERR_NOT_HERMITIAN, ERR_OOM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
+INTEGRATORS = {"rk4": 0, "dp5": 1}
+SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "persistent": 3}
+MEM_HOST, MEM_DEVICE = 0, 1
+STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
+
+# exported C functions, as declared in include/mqct.h
+EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
+           "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
+           "mqct_cross_sections"]
+
+
+class MQCTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mqct error %d: %s" % (code, msg))
+        self.code = code
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("R_grid", C.c_void_p), ("E", C.c_void_p),
+                ("in_dtype", C.c_int32), ("M_mem", C.c_int32), ("M", C.c_void_p),
+                ("storage", C.c_int32), ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p),
+                ("jx_col", C.c_void_p), ("jx_val", C.c_void_p), ("mu", C.c_double)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("B", C.c_int64), ("system_id", C.c_void_p), ("init_channel", C.c_void_p),
+                ("a0", C.c_void_p), ("classical0", C.c_void_p), ("E_coll", C.c_void_p),
+                ("b", C.c_void_p), ("R0", C.c_void_p), ("t0", C.c_void_p),
+                ("integrator", C.c_int32), ("dt", C.c_void_p), ("n_steps", C.c_void_p),
+                ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int64),
+                ("h_min", C.c_double), ("schedule", C.c_int32)]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [("mem", C.c_int32), ("P", C.c_void_p), ("a_final", C.c_void_p),
+                ("classical", C.c_void_p), ("t_final", C.c_void_p), ("steps", C.c_void_p),
+                ("rejects", C.c_void_p), ("status", C.c_void_p), ("norm_err", C.c_void_p),
+                ("energy_err", C.c_void_p), ("angmom_err", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmqct; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmqct.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.mqct_create.argtypes = [i32, vp, C.POINTER(vp)]
+        L.mqct_create.restype = i32
+        L.mqct_destroy.argtypes = [vp]
+        L.mqct_destroy.restype = None
+        L.mqct_last_error.argtypes = [vp]
+        L.mqct_last_error.restype = C.c_char_p
+        L.mqct_synchronize.argtypes = [vp]
+        L.mqct_synchronize.restype = i32
+        L.mqct_system_load.argtypes = [vp, C.POINTER(SystemDesc), C.POINTER(i32)]
+        L.mqct_system_load.restype = i32
+        L.mqct_system_bytes.argtypes = [vp, i32, C.POINTER(i64)]
+        L.mqct_system_bytes.restype = i32
+        L.mqct_system_free.argtypes = [vp, i32]
+        L.mqct_system_free.restype = i32
+        L.mqct_run.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(BatchResult)]
+        L.mqct_run.restype = i32
+        L.mqct_cross_sections.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp, i32, d, vp]
+        L.mqct_cross_sections.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+class Context:
+    """A library context on one GPU, bound to torch's current stream there."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the MQCT propagator runs only on the GPU")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        code = lib().mqct_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if code != OK:
+            raise MQCTError(code, "mqct_create failed")
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mqct_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        if code != OK:
+            raise MQCTError(code, lib().mqct_last_error(self.h).decode())
+
+    def synchronize(self):
+        self._check(lib().mqct_synchronize(self.h))
+
+    # ------------------------------------------------------------------ systems
+    def load_system(self, system=None, *, R_grid=None, E=None, M=None, jx=None, mu=None,
+                    storage=None):
+        """Upload a system (tables copied; spline prepared on the device).
+
+        `system` may be any object with R_grid, E, M, jx_row, jx_col, jx_val and mu
+        (atomic units).  M may be a numpy array (host) or a CUDA tensor (device),
+        real or complex, shaped [K, N, N].  storage: "R64", "C128", "R32", "C64"
+        (default: the input's own precision).
+        """
+        if system is not None:
+            R_grid, E, M, mu = system.R_grid, system.E, system.M, system.mu
+            jx = (system.jx_row, system.jx_col, system.jx_val)
+        Rg = _host(R_grid, np.float64)
+        Eh = _host(E, np.float64)
+        is_dev = hasattr(M, "data_ptr")
+        if is_dev:
+            torch = self.torch
+            cplx = M.is_complex()
+            Mt = M.contiguous()
+            Mt = Mt.to(torch.complex128 if cplx else torch.float64)
+            M_ptr, mem = Mt.data_ptr(), MEM_DEVICE
+            keep = Mt
+        else:
+            cplx = np.iscomplexobj(M)
+            Mt = np.ascontiguousarray(M, dtype=np.complex128 if cplx else np.float64)
+            M_ptr, mem = Mt.ctypes.data, MEM_HOST
+            keep = Mt
+        K, N = Rg.shape[0], Eh.shape[0]
+        if tuple(Mt.shape) != (K, N, N):
+            raise ValueError("M must be shaped [K, N, N] = [%d, %d, %d]" % (K, N, N))
+        if storage is None:
+            storage = "C128" if cplx else "R64"
+        jr = jc = jv = None
+        nnz = 0
+        if jx is not None and len(jx[0]) > 0:
+            jr, jc, jv = _host(jx[0], np.int32), _host(jx[1], np.int32), _host(jx[2], np.float64)
+            nnz = jr.shape[0]
+        d = SystemDesc(N, K, Rg.ctypes.data, Eh.ctypes.data, DTYPES["C128" if cplx else "R64"],
+                       mem, M_ptr, DTYPES[storage], nnz, _ptr(jr), _ptr(jc), _ptr(jv), float(mu))
+        sid = C.c_int32()
+        self._check(lib().mqct_system_load(self.h, C.byref(d), C.byref(sid)))
+        del keep
+        return sid.value
+
+    def system_bytes(self, sid):
+        out = C.c_int64()
+        self._check(lib().mqct_system_bytes(self.h, sid, C.byref(out)))
+        return out.value
+
+    def free_system(self, sid):
+        self._check(lib().mqct_system_free(self.h, sid))
+
+    # ------------------------------------------------------------------ batches
+    def run(self, system_id, N_of, *, init_channel=None, a0=None, classical0=None, E_coll=None,
+            b=None, R0=None, t0=None, dt=None, n_steps=None, integrator="rk4", rtol=1e-8,
+            atol=1e-8, max_steps=100000, h_min=1e-6, schedule="auto", out=None,
+            with_amplitudes=True):
+        """Propagate a batch; results are CUDA tensors filled asynchronously on the stream.
+
+        system_id: [B] system ids; N_of: [B] channel count of each trajectory's system.
+        """
+        torch = self.torch
+        sid = _host(system_id, np.int32)
+        B = int(sid.shape[0])
+        Nof = np.asarray(N_of, np.int64).reshape(-1)
+        total = int(Nof.sum())
+        dev = self.device
+        if out is None:
+            out = {"P": torch.empty(total, dtype=torch.float64, device=dev),
+                   "classical": torch.empty((B, 6), dtype=torch.float64, device=dev),
+                   "t_final": torch.empty(B, dtype=torch.float64, device=dev),
+                   "steps": torch.empty(B, dtype=torch.int64, device=dev),
+                   "rejects": torch.empty(B, dtype=torch.int64, device=dev),
+                   "status": torch.empty(B, dtype=torch.int32, device=dev),
+                   "norm_err": torch.empty(B, dtype=torch.float64, device=dev),
+                   "energy_err": torch.empty(B, dtype=torch.float64, device=dev),
+                   "angmom_err": torch.empty(B, dtype=torch.float64, device=dev)}
+            if with_amplitudes:
+                out["a_final"] = torch.empty(total, dtype=torch.complex128, device=dev)
+        a0h = None
+        if a0 is not None:
+            a0h = np.ascontiguousarray(np.asarray(a0, np.complex128).reshape(-1)).view(np.float64)
+        c0h = None if classical0 is None else _host(np.reshape(classical0, (B, 6)), np.float64)
+        bd = BatchDesc(
+            B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None, INTEGRATORS[integrator], None, None,
+            float(rtol), float(atol), int(max_steps), float(h_min), SCHEDULES[schedule])
+        hold = []
+        for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
+                               ("b", b, np.float64), ("R0", R0, np.float64), ("t0", t0, np.float64),
+                               ("dt", dt, np.float64), ("n_steps", n_steps, np.int64)):
+            if arr is None:
+                continue
+            h = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtp), (B,)))
+            hold.append(h)
+            setattr(bd, name, h.ctypes.data)
+        res = BatchResult(MEM_DEVICE, _ptr(out.get("P")), _ptr(out.get("a_final")),
+                          _ptr(out.get("classical")), _ptr(out.get("t_final")),
+                          _ptr(out.get("steps")), _ptr(out.get("rejects")),
+                          _ptr(out.get("status")), _ptr(out.get("norm_err")),
+                          _ptr(out.get("energy_err")), _ptr(out.get("angmom_err")))
+        self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
+        return out
+
+    def run_host(self, system_id, N_of, **kw):
+        """As run(), with host (numpy) results; returns after they are filled."""
+        sid = _host(system_id, np.int32)
+        B = int(sid.shape[0])
+        total = int(np.asarray(N_of, np.int64).sum())
+        out = {"P": np.empty(total), "a_final": np.empty(total, np.complex128),
+               "classical": np.empty((B, 6)), "t_final": np.empty(B),
+               "steps": np.empty(B, np.int64), "rejects": np.empty(B, np.int64),
+               "status": np.empty(B, np.int32), "norm_err": np.empty(B),
+               "energy_err": np.empty(B), "angmom_err": np.empty(B)}
+        kw = dict(kw)
+        schedule = kw.pop("schedule", "auto")
+        integrator = kw.pop("integrator", "rk4")
+        a0 = kw.pop("a0", None)
+        classical0 = kw.pop("classical0", None)
+        a0h = None
+        if a0 is not None:
+            a0h = np.ascontiguousarray(np.asarray(a0, np.complex128).reshape(-1)).view(np.float64)
+        c0h = None if classical0 is None else _host(np.reshape(classical0, (B, 6)), np.float64)
+        bd = BatchDesc(B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None,
+                       INTEGRATORS[integrator], None, None, float(kw.pop("rtol", 1e-8)),
+                       float(kw.pop("atol", 1e-8)), int(kw.pop("max_steps", 100000)),
+                       float(kw.pop("h_min", 1e-6)), SCHEDULES[schedule])
+        hold = []
+        for name, dtp in (("init_channel", np.int32), ("E_coll", np.float64), ("b", np.float64),
+                          ("R0", np.float64), ("t0", np.float64), ("dt", np.float64),
+                          ("n_steps", np.int64)):
+            arr = kw.pop(name, None)
+            if arr is None:
+                continue
+            h = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtp), (B,)))
+            hold.append(h)
+            setattr(bd, name, h.ctypes.data)
+        if kw:
+            raise TypeError("unknown arguments: %s" % sorted(kw))
+        res = BatchResult(MEM_HOST, *[out[k].ctypes.data for k in
+                                      ("P", "a_final", "classical", "t_final", "steps", "rejects",
+                                       "status", "norm_err", "energy_err", "angmom_err")])
+        self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
+        return out
+
+    def cross_sections(self, P, b, init_level, level_of_channel, n_levels, b_max):
+        """Monte-Carlo cross sections (bohr^2) from P [B, N] on the device."""
+        torch = self.torch
+        P = P.contiguous()
+        B, N = P.shape
+        bt = torch.as_tensor(np.asarray(b, np.float64), device=self.device)
+        il = torch.as_tensor(np.asarray(init_level, np.int32), device=self.device)
+        lev = _host(level_of_channel, np.int32)
+        sig = torch.empty((n_levels, n_levels), dtype=torch.float64, device=self.device)
+        self._check(lib().mqct_cross_sections(self.h, MEM_DEVICE, B, N, P.data_ptr(),
+                                              bt.data_ptr(), il.data_ptr(), lev.ctypes.data,
+                                              int(n_levels), float(b_max), sig.data_ptr()))
+        return sig

@@ -1,0 +1,574 @@
+// C ABI of libmqct: contexts, system loading and batch launch (include/mqct.h).
+#include "internal.h"
+
+#include "../../include/mqct.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace mqct;
+
+namespace {
+
+struct SysHost {
+  bool live = false;
+  DevSystem dev{};
+  void* bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t table_bytes = 0;
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct mqct_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<SysHost> systems;
+  DevSystem* d_systems = nullptr;
+  size_t d_systems_cap = 0;
+  DevBuf traj, a0, outs[10], xs[4];
+  TrajIn* h_traj = nullptr;        // pinned staging for trajectory records
+  size_t h_traj_cap = 0;
+  hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
+};
+
+namespace {
+
+mqct_status fail(mqct_context* c, mqct_status code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+mqct_status hip_fail(mqct_context* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(c, MQCT_ERR_OOM, "%s: out of device memory", what);
+  return fail(c, MQCT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)              \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+mqct_status ensure(mqct_context* c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes <= b.cap) return MQCT_OK;
+  if (b.p) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = std::max(bytes, (size_t)4096);
+  HIP_TRY(c, hipMalloc(&b.p, want), what);
+  b.cap = want;
+  return MQCT_OK;
+}
+
+mqct_status upload_systems(mqct_context* c) {
+  std::vector<DevSystem> h(c->systems.size());
+  for (size_t i = 0; i < h.size(); ++i) h[i] = c->systems[i].dev;
+  size_t bytes = std::max<size_t>(1, h.size()) * sizeof(DevSystem);
+  if (bytes > c->d_systems_cap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "system table");
+    if (c->d_systems) hipFree(c->d_systems);
+    c->d_systems = nullptr;
+    size_t want = bytes * 2;
+    HIP_TRY(c, hipMalloc((void**)&c->d_systems, want), "system table");
+    c->d_systems_cap = want;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_systems, h.data(), h.size() * sizeof(DevSystem),
+                            hipMemcpyHostToDevice, c->stream), "system table");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "system table");
+  return MQCT_OK;
+}
+
+bool finite_arr(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!isfinite(p[i])) return false;
+  return true;
+}
+
+void free_system(SysHost& s) {
+  for (auto& p : s.bufs) {
+    if (p) hipFree(p);
+    p = nullptr;
+  }
+  s.live = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+mqct_status mqct_create(int32_t device, void* hip_stream, mqct_context** out) {
+  if (!out) return MQCT_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MQCT_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return MQCT_ERR_DEVICE;
+  mqct_context* c = new mqct_context();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return MQCT_ERR_DEVICE; }
+    c->own_stream = true;
+  }
+  if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return MQCT_ERR_DEVICE;
+  }
+  *out = c;
+  return MQCT_OK;
+}
+
+void mqct_destroy(mqct_context* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& s : c->systems) free_system(s);
+  if (c->d_systems) hipFree(c->d_systems);
+  DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3]};
+  for (DevBuf* b : all) if (b->p) hipFree(b->p);
+  for (auto& b : c->outs) if (b.p) hipFree(b.p);
+  if (c->h_traj) hipHostFree(c->h_traj);
+  if (c->staged) hipEventDestroy(c->staged);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* mqct_last_error(const mqct_context* c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+mqct_status mqct_synchronize(mqct_context* c) {
+  if (!c) return MQCT_ERR_ARG;
+  HIP_TRY(c, hipSetDevice(c->device), "synchronize");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t* system_id) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!d || !system_id) return fail(c, MQCT_ERR_ARG, "system_load: null argument");
+  const int N = d->N, K = d->K;
+  if (N < 1 || K < 4 || K > 2048)
+    return fail(c, MQCT_ERR_ARG, "system_load: need N >= 1 and 4 <= K <= 2048 (N=%d K=%d)", N, K);
+  if (!d->R_grid || !d->E || !d->M) return fail(c, MQCT_ERR_ARG, "system_load: null R_grid/E/M");
+  if (d->in_dtype != MQCT_R64 && d->in_dtype != MQCT_C128)
+    return fail(c, MQCT_ERR_ARG, "system_load: in_dtype must be MQCT_R64 or MQCT_C128");
+  if (d->storage < MQCT_R64 || d->storage > MQCT_C64)
+    return fail(c, MQCT_ERR_ARG, "system_load: unknown storage type %d", d->storage);
+  const bool cplx = d->in_dtype == MQCT_C128;
+  if (dtype_complex(d->storage) != cplx)
+    return fail(c, MQCT_ERR_ARG, "system_load: storage and input must both be real or both complex");
+  if (d->M_mem != MQCT_MEM_HOST && d->M_mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "system_load: M_mem must be host or device");
+  if (!(d->mu > 0.0) || !isfinite(d->mu)) return fail(c, MQCT_ERR_ARG, "system_load: mu must be > 0");
+  if (!finite_arr(d->R_grid, K)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite R grid");
+  for (int k = 1; k < K; ++k)
+    if (!(d->R_grid[k] > d->R_grid[k - 1]))
+      return fail(c, MQCT_ERR_ARG, "system_load: R grid not strictly increasing at %d", k);
+  if (!finite_arr(d->E, N)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite E");
+  // Coriolis operator: coordinate list -> ELL, checked for range and symmetry
+  if (d->jx_nnz < 0 || (d->jx_nnz > 0 && (!d->jx_row || !d->jx_col || !d->jx_val)))
+    return fail(c, MQCT_ERR_ARG, "system_load: bad J_x arrays");
+  std::vector<std::vector<std::pair<int, double>>> rows(N);
+  std::map<std::pair<int, int>, double> jmap;
+  for (int q = 0; q < d->jx_nnz; ++q) {
+    int r = d->jx_row[q], cc = d->jx_col[q];
+    double v = d->jx_val[q];
+    if (r < 0 || r >= N || cc < 0 || cc >= N)
+      return fail(c, MQCT_ERR_ARG, "system_load: J_x index out of range at %d", q);
+    if (!isfinite(v)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite J_x");
+    if (jmap.count({r, cc})) return fail(c, MQCT_ERR_ARG, "system_load: duplicate J_x entry");
+    jmap[{r, cc}] = v;
+    rows[r].push_back({cc, v});
+  }
+  for (auto& kv : jmap) {
+    auto it = jmap.find({kv.first.second, kv.first.first});
+    if (it == jmap.end() || fabs(it->second - kv.second) > 1e-12 * (1.0 + fabs(kv.second)))
+      return fail(c, MQCT_ERR_ARG, "system_load: J_x is not symmetric");
+  }
+  // Eq. 5: the Coriolis term couples m +- 1 within one channel n, i.e. states of
+  // equal energy; the kernels rely on that (J_x a = e^{iEt} J_x c row by row).
+  double emax = 0.0;
+  for (int n = 0; n < N; ++n) emax = std::max(emax, fabs(d->E[n]));
+  for (auto& kv : jmap)
+    if (fabs(d->E[kv.first.first] - d->E[kv.first.second]) > 1e-12 * emax)
+      return fail(c, MQCT_ERR_ARG, "system_load: J_x couples channels of different energy");
+  int W = 0;
+  for (auto& r : rows) W = std::max<int>(W, (int)r.size());
+  if (W > 8) return fail(c, MQCT_ERR_UNSUPPORTED, "system_load: J_x has more than 8 nonzeros per row");
+
+  HIP_TRY(c, hipSetDevice(c->device), "system_load");
+  const int ncomp = cplx ? 2 : 1;
+  const int Npad = (N + 15) / 16 * 16;
+  const int64_t in_elems = (int64_t)K * N * N * ncomp;
+  const int64_t store_elems = (int64_t)K * N * Npad * ncomp;
+  const int es = dtype_fp32(d->storage) ? 4 : 8;
+
+  SysHost sh;
+  sh.dev.N = N; sh.dev.K = K; sh.dev.Npad = Npad; sh.dev.dtype = d->storage;
+  sh.dev.jx_w = W; sh.dev.mu = d->mu; sh.dev.knot_stride = (int64_t)N * Npad;
+  sh.table_bytes = 2 * store_elems * es;
+
+  double* din = nullptr;
+  bool own_in = false;
+  unsigned long long* stats = nullptr;
+  double* tmp = nullptr;
+  mqct_status st = MQCT_OK;
+  auto cleanup = [&]() {
+    if (own_in && din) hipFree(din);
+    if (stats) hipFree(stats);
+    if (tmp) hipFree(tmp);
+  };
+  auto dfail = [&](hipError_t e, const char* what) {
+    cleanup();
+    free_system(sh);
+    return hip_fail(c, e, what);
+  };
+  hipError_t e;
+  if (d->M_mem == MQCT_MEM_HOST) {
+    if ((e = hipMalloc((void**)&din, in_elems * 8)) != hipSuccess) return dfail(e, "system_load: input");
+    own_in = true;
+    if ((e = hipMemcpy(din, d->M, in_elems * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return dfail(e, "system_load: upload");
+  } else {
+    din = (double*)d->M;
+  }
+  if ((e = hipMalloc((void**)&stats, 3 * sizeof(unsigned long long))) != hipSuccess)
+    return dfail(e, "system_load: stats");
+  if ((e = hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), c->stream)) != hipSuccess)
+    return dfail(e, "system_load: stats");
+  if ((e = launch_validate(din, N, K, ncomp, stats, c->stream)) != hipSuccess)
+    return dfail(e, "system_load: validate");
+  unsigned long long hs[3];
+  if ((e = hipMemcpyAsync(hs, stats, sizeof hs, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return dfail(e, "system_load: validate");
+  double herm, amax;
+  memcpy(&herm, &hs[0], 8);
+  memcpy(&amax, &hs[1], 8);
+  if (hs[2] > 0) {
+    cleanup();
+    return fail(c, MQCT_ERR_NONFINITE, "system_load: %llu non-finite table entries", hs[2]);
+  }
+  if (herm > 1e-12 * amax) {
+    cleanup();
+    return fail(c, MQCT_ERR_NOT_HERMITIAN, "system_load: |M - M^H| = %.3e > 1e-12 max|M| = %.3e",
+                herm, 1e-12 * amax);
+  }
+  // storage, spline curvature, small arrays
+  if ((e = hipMalloc(&sh.bufs[0], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
+  if ((e = hipMalloc(&sh.bufs[1], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
+  if ((e = hipMalloc(&sh.bufs[2], K * 8)) != hipSuccess) return dfail(e, "system_load: grid");
+  if ((e = hipMalloc(&sh.bufs[3], N * 8)) != hipSuccess) return dfail(e, "system_load: energies");
+  int64_t per_col = (int64_t)N * Npad * ncomp;
+  int64_t tmp_doubles = std::min<int64_t>((int64_t)K * per_col, (int64_t)64 << 20);
+  tmp_doubles = std::max<int64_t>(tmp_doubles, K);
+  if ((e = hipMalloc((void**)&tmp, tmp_doubles * 8)) != hipSuccess) return dfail(e, "system_load: scratch");
+  if ((e = hipMemcpy(sh.bufs[2], d->R_grid, K * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return dfail(e, "system_load: grid");
+  if ((e = hipMemcpy(sh.bufs[3], d->E, N * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return dfail(e, "system_load: energies");
+  if ((e = launch_spline_prepare(din, (const double*)sh.bufs[2], N, K, Npad, ncomp, d->storage,
+                                 sh.bufs[0], sh.bufs[1], tmp, tmp_doubles, c->stream)) != hipSuccess)
+    return dfail(e, "system_load: spline");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return dfail(e, "system_load: spline");
+  if (W > 0) {
+    std::vector<int32_t> col((size_t)N * W);
+    std::vector<double> val((size_t)N * W, 0.0);
+    for (int r = 0; r < N; ++r)
+      for (int w = 0; w < W; ++w) {
+        if (w < (int)rows[r].size()) {
+          col[(size_t)r * W + w] = rows[r][w].first;
+          val[(size_t)r * W + w] = rows[r][w].second;
+        } else {
+          col[(size_t)r * W + w] = r;
+        }
+      }
+    if ((e = hipMalloc(&sh.bufs[4], col.size() * 4)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = hipMalloc(&sh.bufs[5], val.size() * 8)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = hipMemcpy(sh.bufs[4], col.data(), col.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(sh.bufs[5], val.data(), val.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return dfail(e, "system_load: J_x");
+  }
+  cleanup();
+  sh.dev.M = sh.bufs[0];
+  sh.dev.M2 = sh.bufs[1];
+  sh.dev.R = (const double*)sh.bufs[2];
+  sh.dev.E = (const double*)sh.bufs[3];
+  sh.dev.jx_col = (const int32_t*)sh.bufs[4];
+  sh.dev.jx_val = (const double*)sh.bufs[5];
+  sh.live = true;
+  int id = -1;
+  for (size_t i = 0; i < c->systems.size(); ++i)
+    if (!c->systems[i].live) { id = (int)i; break; }
+  if (id < 0) { id = (int)c->systems.size(); c->systems.push_back(sh); }
+  else c->systems[id] = sh;
+  st = upload_systems(c);
+  if (st != MQCT_OK) return st;
+  *system_id = id;
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_bytes(mqct_context* c, int32_t id, int64_t* bytes) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!bytes) return fail(c, MQCT_ERR_ARG, "system_bytes: null output");
+  if (id < 0 || id >= (int)c->systems.size() || !c->systems[id].live)
+    return fail(c, MQCT_ERR_STATE, "system_bytes: unknown system %d", id);
+  *bytes = c->systems[id].table_bytes;
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_free(mqct_context* c, int32_t id) {
+  if (!c) return MQCT_ERR_ARG;
+  if (id < 0 || id >= (int)c->systems.size() || !c->systems[id].live)
+    return fail(c, MQCT_ERR_STATE, "system_free: unknown system %d", id);
+  HIP_TRY(c, hipSetDevice(c->device), "system_free");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "system_free");
+  free_system(c->systems[id]);
+  c->systems[id].dev = DevSystem{};
+  return upload_systems(c);
+}
+
+mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_result* res) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!bd || !res) return fail(c, MQCT_ERR_ARG, "run: null argument");
+  const int64_t B = bd->B;
+  if (B < 0) return fail(c, MQCT_ERR_ARG, "run: B < 0");
+  if (B == 0) return MQCT_OK;
+  if (!bd->system_id) return fail(c, MQCT_ERR_ARG, "run: system_id is required");
+  if (!res->P) return fail(c, MQCT_ERR_ARG, "run: result P is required");
+  if (res->mem != MQCT_MEM_HOST && res->mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "run: result mem must be host or device");
+  if (bd->integrator != MQCT_RK4 && bd->integrator != MQCT_DP5)
+    return fail(c, MQCT_ERR_ARG, "run: unknown integrator %d", bd->integrator);
+  if (bd->integrator == MQCT_DP5)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run: DP5 is not available in this build");
+  if (bd->schedule != MQCT_SCHED_AUTO && bd->schedule != MQCT_SCHED_GEMV)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run: schedule %d is not available in this build",
+                bd->schedule);
+  if (!bd->dt || !bd->n_steps) return fail(c, MQCT_ERR_ARG, "run: RK4 needs dt and n_steps");
+  if (!bd->classical0 && (!bd->E_coll || !bd->b))
+    return fail(c, MQCT_ERR_ARG, "run: E_coll and b are required without classical0");
+  if (!bd->a0 && !bd->init_channel)
+    return fail(c, MQCT_ERR_ARG, "run: init_channel is required without a0");
+
+  // trajectory records
+  HIP_TRY(c, hipSetDevice(c->device), "run");
+  if ((size_t)B > c->h_traj_cap) {
+    if (c->h_traj) {
+      HIP_TRY(c, hipEventSynchronize(c->staged), "run");
+      hipHostFree(c->h_traj);
+      c->h_traj = nullptr;
+    }
+    HIP_TRY(c, hipHostMalloc((void**)&c->h_traj, B * sizeof(TrajIn), 0), "run: staging");
+    c->h_traj_cap = B;
+  } else {
+    HIP_TRY(c, hipEventSynchronize(c->staged), "run");
+  }
+  int64_t amp_total = 0;
+  std::vector<int64_t> order[4];
+  std::vector<int> max_npad(4, 0);
+  for (int64_t b = 0; b < B; ++b) {
+    int sid = bd->system_id[b];
+    if (sid < 0 || sid >= (int)c->systems.size() || !c->systems[sid].live)
+      return fail(c, MQCT_ERR_STATE, "run: trajectory %lld uses unknown system %d", (long long)b, sid);
+    const DevSystem& sy = c->systems[sid].dev;
+    TrajIn t{};
+    t.id = b;
+    t.amp_off = amp_total;
+    t.sys = sid;
+    t.n_steps = bd->n_steps[b];
+    t.dt = bd->dt[b];
+    t.t0 = bd->t0 ? bd->t0[b] : 0.0;
+    if (t.n_steps < 0) return fail(c, MQCT_ERR_ARG, "run: n_steps[%lld] < 0", (long long)b);
+    if (!isfinite(t.dt) || !isfinite(t.t0)) return fail(c, MQCT_ERR_ARG, "run: non-finite dt/t0");
+    if (bd->a0) {
+      t.flags |= TRAJ_HAS_A0;
+    } else {
+      t.init_channel = bd->init_channel[b];
+      if (t.init_channel < 0 || t.init_channel >= sy.N)
+        return fail(c, MQCT_ERR_ARG, "run: init_channel[%lld] out of range", (long long)b);
+    }
+    if (bd->classical0) {
+      t.flags |= TRAJ_HAS_C0;
+      for (int i = 0; i < 6; ++i) t.c0[i] = bd->classical0[b * 6 + i];
+      if (!finite_arr(t.c0, 6) || !(t.c0[0] > 0.0))
+        return fail(c, MQCT_ERR_ARG, "run: classical0[%lld] invalid", (long long)b);
+    } else {
+      t.E_coll = bd->E_coll[b];
+      t.b = bd->b[b];
+      t.R0 = bd->R0 ? bd->R0[b] : -1.0;
+      if (!(t.E_coll > 0.0) || !isfinite(t.E_coll))
+        return fail(c, MQCT_ERR_ARG, "run: E_coll[%lld] must be > 0", (long long)b);
+      if (t.R0 < 0.0) t.R0 = -1.0;   // resolved below from the grid
+    }
+    amp_total += sy.N;
+    order[sy.dtype].push_back(b);
+    max_npad[sy.dtype] = std::max(max_npad[sy.dtype], sy.Npad);
+    c->h_traj[b] = t;
+  }
+  // default R0 = last knot (needs the grid on the host: read it back once per system)
+  if (!bd->classical0) {
+    std::map<int, double> last;
+    for (int64_t b = 0; b < B; ++b) {
+      TrajIn& t = c->h_traj[b];
+      if (t.R0 < 0.0) {
+        auto it = last.find(t.sys);
+        if (it == last.end()) {
+          const DevSystem& sy = c->systems[t.sys].dev;
+          double r;
+          HIP_TRY(c, hipMemcpy(&r, sy.R + (sy.K - 1), 8, hipMemcpyDeviceToHost), "run: grid");
+          it = last.emplace(t.sys, r).first;
+        }
+        t.R0 = it->second;
+      }
+      if (!(t.R0 > 0.0) || !isfinite(t.R0) || !(t.b >= 0.0) || !(t.b < t.R0))
+        return fail(c, MQCT_ERR_ARG, "run: need 0 <= b < R0 (trajectory %lld)", (long long)b);
+    }
+  }
+  // group by storage type so each launch uses one kernel family
+  std::vector<TrajIn> sorted;
+  sorted.reserve(B);
+  std::vector<std::pair<int64_t, int64_t>> ranges(4);
+  for (int d = 0; d < 4; ++d) {
+    ranges[d].first = (int64_t)sorted.size();
+    for (int64_t b : order[d]) sorted.push_back(c->h_traj[b]);
+    ranges[d].second = (int64_t)sorted.size();
+  }
+  memcpy(c->h_traj, sorted.data(), B * sizeof(TrajIn));
+
+  mqct_status st;
+  if ((st = ensure(c, c->traj, B * sizeof(TrajIn), "run: trajectories")) != MQCT_OK) return st;
+  HIP_TRY(c, hipMemcpyAsync(c->traj.p, c->h_traj, B * sizeof(TrajIn), hipMemcpyHostToDevice,
+                            c->stream), "run: upload");
+  HIP_TRY(c, hipEventRecord(c->staged, c->stream), "run: upload");
+  const double* d_a0 = nullptr;
+  if (bd->a0) {
+    if ((st = ensure(c, c->a0, amp_total * 16, "run: a0")) != MQCT_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->a0.p, bd->a0, amp_total * 16, hipMemcpyHostToDevice, c->stream),
+            "run: a0");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "run: a0");
+    d_a0 = (const double*)c->a0.p;
+  }
+
+  // result arrays: caller's device pointers, or device staging for host results
+  TrajOut out{};
+  struct Piece { void* host; size_t bytes; int slot; };
+  std::vector<Piece> back;
+  void* hp[10] = {res->P, res->a_final, res->classical, res->t_final, res->steps,
+                  res->rejects, res->status, res->norm_err, res->energy_err, res->angmom_err};
+  size_t sz[10] = {(size_t)amp_total * 8, (size_t)amp_total * 16, (size_t)B * 48, (size_t)B * 8,
+                   (size_t)B * 8, (size_t)B * 8, (size_t)B * 4, (size_t)B * 8, (size_t)B * 8,
+                   (size_t)B * 8};
+  void* dp[10];
+  for (int i = 0; i < 10; ++i) {
+    dp[i] = hp[i];
+    if (hp[i] && res->mem == MQCT_MEM_HOST) {
+      if ((st = ensure(c, c->outs[i], sz[i], "run: results")) != MQCT_OK) return st;
+      dp[i] = c->outs[i].p;
+      back.push_back({hp[i], sz[i], i});
+    }
+  }
+  out.P = (double*)dp[0]; out.a_final = (double*)dp[1]; out.classical = (double*)dp[2];
+  out.t_final = (double*)dp[3]; out.steps = (int64_t*)dp[4]; out.rejects = (int64_t*)dp[5];
+  out.status = (int32_t*)dp[6]; out.norm_err = (double*)dp[7]; out.energy_err = (double*)dp[8];
+  out.angmom_err = (double*)dp[9];
+
+  for (int d = 0; d < 4; ++d) {
+    int64_t n = ranges[d].second - ranges[d].first;
+    if (n == 0) continue;
+    hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->traj.p + ranges[d].first, n,
+                                   d_a0, out, d, max_npad[d], c->stream);
+    if (e == hipErrorInvalidValue)
+      return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the per-trajectory schedule");
+    if (e != hipSuccess) return hip_fail(c, e, "run: launch");
+  }
+  for (auto& p : back)
+    HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
+            "run: results");
+  if (res->mem == MQCT_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream), "run: results");
+  return MQCT_OK;
+}
+
+mqct_status mqct_cross_sections(mqct_context* c, int32_t mem, int64_t B, int32_t N,
+                                const double* P, const double* b, const int32_t* init_level,
+                                const int32_t* level_of_channel, int32_t n_levels,
+                                double b_max, double* sigma) {
+  if (!c) return MQCT_ERR_ARG;
+  if (B < 1 || N < 1 || n_levels < 1 || !P || !b || !init_level || !level_of_channel || !sigma)
+    return fail(c, MQCT_ERR_ARG, "cross_sections: bad arguments");
+  if (mem != MQCT_MEM_HOST && mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "cross_sections: mem must be host or device");
+  if (!(b_max > 0.0)) return fail(c, MQCT_ERR_ARG, "cross_sections: b_max must be > 0");
+  for (int n = 0; n < N; ++n)
+    if (level_of_channel[n] < 0 || level_of_channel[n] >= n_levels)
+      return fail(c, MQCT_ERR_ARG, "cross_sections: level_of_channel out of range");
+  if (mem == MQCT_MEM_HOST)
+    for (int64_t i = 0; i < B; ++i)
+      if (init_level[i] < 0 || init_level[i] >= n_levels)
+        return fail(c, MQCT_ERR_ARG, "cross_sections: init_level out of range");
+  HIP_TRY(c, hipSetDevice(c->device), "cross_sections");
+  mqct_status st;
+  const size_t lsz = (size_t)B * n_levels * 8, ssz = (size_t)n_levels * n_levels * 8;
+  if ((st = ensure(c, c->xs[0], lsz + N * 4, "cross_sections")) != MQCT_OK) return st;
+  double* lsum = (double*)c->xs[0].p;
+  int32_t* dlev = (int32_t*)((char*)c->xs[0].p + lsz);
+  HIP_TRY(c, hipMemcpyAsync(dlev, level_of_channel, N * 4, hipMemcpyHostToDevice, c->stream),
+          "cross_sections");
+  const double *dP = P, *db = b;
+  const int32_t* dil = init_level;
+  double* dsig = sigma;
+  if (mem == MQCT_MEM_HOST) {
+    if ((st = ensure(c, c->xs[1], (size_t)B * N * 8 + B * 8 + B * 4 + 64, "cross_sections")) != MQCT_OK)
+      return st;
+    if ((st = ensure(c, c->xs[2], ssz, "cross_sections")) != MQCT_OK) return st;
+    char* base = (char*)c->xs[1].p;
+    HIP_TRY(c, hipMemcpyAsync(base, P, (size_t)B * N * 8, hipMemcpyHostToDevice, c->stream), "cross_sections");
+    HIP_TRY(c, hipMemcpyAsync(base + (size_t)B * N * 8, b, B * 8, hipMemcpyHostToDevice, c->stream), "cross_sections");
+    HIP_TRY(c, hipMemcpyAsync(base + (size_t)B * N * 8 + B * 8, init_level, B * 4,
+                              hipMemcpyHostToDevice, c->stream), "cross_sections");
+    dP = (const double*)base;
+    db = (const double*)(base + (size_t)B * N * 8);
+    dil = (const int32_t*)(base + (size_t)B * N * 8 + B * 8);
+    dsig = (double*)c->xs[2].p;
+  }
+  HIP_TRY(c, launch_xsec(B, N, dP, db, dil, dlev, n_levels, b_max, lsum, dsig, c->stream),
+          "cross_sections");
+  if (mem == MQCT_MEM_HOST) {
+    HIP_TRY(c, hipMemcpyAsync(sigma, dsig, ssz, hipMemcpyDeviceToHost, c->stream), "cross_sections");
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "cross_sections");
+  return MQCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal device/host structures of libmqct (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mqct {
+
+// Storage element kinds (same numbering as the public MQCT_R64 ... MQCT_C64).
+enum Dtype { R64 = 0, C128 = 1, R32 = 2, C64 = 3 };
+
+inline bool dtype_complex(int d) { return d == C128 || d == C64; }
+inline bool dtype_fp32(int d) { return d == R32 || d == C64; }
+inline int dtype_bytes(int d) { return d == C128 ? 16 : (d == R32 ? 4 : 8); }
+
+// A loaded system as the kernels see it.  Tables are stored [K][N][Npad]:
+// knot k, stored row m, column n (Npad = N rounded up to a multiple of 16,
+// padding columns are zero).  Because every knot's matrix is Hermitian, column n
+// of the stored matrix is the complex conjugate of row n, which lets a lane
+// that owns output row n stream memory contiguously with its neighbours.
+struct DevSystem {
+  int32_t N, K, Npad, dtype;
+  int32_t jx_w;              // ELL width of J_x (0 when there is no Coriolis term)
+  int32_t pad0;
+  double mu;
+  const double* R;           // [K]
+  const double* E;           // [N]
+  const void* M;             // [K][N][Npad] values
+  const void* M2;            // [K][N][Npad] natural-spline second derivatives
+  const int32_t* jx_col;     // [N][jx_w], padding entries point at the row itself
+  const double* jx_val;      // [N][jx_w], padding entries are 0
+  int64_t knot_stride;       // N * Npad elements
+};
+
+// Per-trajectory launch record.
+struct TrajIn {
+  int64_t id;                // index in the caller's batch
+  int64_t amp_off;           // offset of this trajectory's amplitudes (sum of N before it)
+  int64_t n_steps;           // RK4 steps
+  int32_t sys;               // index into the device system table
+  int32_t init_channel;
+  int32_t flags;             // bit 0: a0 given; bit 1: classical0 given
+  int32_t pad0;
+  double E_coll, b, R0, t0, dt;
+  double c0[6];              // classical0 when flags & 2
+};
+
+enum { TRAJ_HAS_A0 = 1, TRAJ_HAS_C0 = 2 };
+
+// Where a kernel writes its per-trajectory results (device pointers; any may be
+// null except P).
+struct TrajOut {
+  double* P;
+  double* a_final;
+  double* classical;
+  double* t_final;
+  int64_t* steps;
+  int64_t* rejects;
+  int32_t* status;
+  double* norm_err;
+  double* energy_err;
+  double* angmom_err;
+};
+
+enum { ST_EXITED = 1, ST_MAX_STEPS = 2, ST_STEP_UNDERFLOW = 4, ST_BELOW_GRID = 8,
+       ST_NONFINITE = 16 };
+
+// ---- launchers (defined in the .hip files) ----------------------------------
+
+// Table preparation: from FP64 input (device, [K][N][N], real or complex
+// interleaved) write storage tables and their natural-spline second
+// derivatives.  tmp holds tmp_doubles doubles (>= K); columns are processed in
+// chunks of tmp_doubles / K.
+hipError_t launch_validate(const double* M_in, int N, int K, int ncomp,
+                           unsigned long long* stats /*[3], zeroed*/, hipStream_t s);
+hipError_t launch_spline_prepare(const double* M_in, const double* R, int N, int K, int Npad,
+                                 int ncomp, int dtype, void* M_out, void* M2_out, double* tmp,
+                                 int64_t tmp_doubles, hipStream_t s);
+
+// Fixed-step RK4, one workgroup per trajectory.  All trajectories of one launch
+// must use systems of the same dtype whose padded column count is <= max_npad.
+hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                           const double* d_a0, TrajOut out, int dtype, int max_npad,
+                           hipStream_t s);
+
+// Cross sections on the device.
+hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
+                       const int32_t* level_of_channel, int n_levels, double b_max,
+                       double* level_sums /*[B][n_levels]*/, double* sigma, hipStream_t s);
+
+}  // namespace mqct

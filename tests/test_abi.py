@@ -1,0 +1,48 @@
+"""Host-side checks of the C ABI: the library loads and exports every declared symbol."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mqct.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mqct_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    import paper_2312_02322_amd as mq
+    assert declared_functions() == sorted(mq.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2312_02322_amd as mq
+    if not os.path.exists(mq.LIB_PATH):
+        pytest.fail("libmqct.so is not built; run __graft_entry__.build()")
+    lib = C.CDLL(mq.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_null_context_calls_fail_cleanly():
+    """Argument errors are reported without touching a device."""
+    import paper_2312_02322_amd as mq
+    L = mq.lib()
+    assert L.mqct_last_error(None) == b"no context"
+    assert L.mqct_synchronize(None) == mq.ERR_ARG
+    assert L.mqct_run(None, None, None) == mq.ERR_ARG
+    assert L.mqct_system_load(None, None, None) == mq.ERR_ARG
+    L.mqct_destroy(None)
+
+
+def test_struct_layouts_match_header():
+    """The ctypes mirrors have the sizes the C compiler gives the header's structs."""
+    import paper_2312_02322_amd as mq
+    assert C.sizeof(mq.SystemDesc) == 80
+    assert C.sizeof(mq.BatchDesc) == 136
+    assert C.sizeof(mq.BatchResult) == 88
