@@ -1,0 +1,172 @@
+"""Throughput of batched Ehrenfest mean-field trajectory propagation on one MI355X.
+
+Workload: the asymmetric-top + atom system with j <= 8 (all k, m; N = 969
+channels), random smooth Hermitian complex coupling tables on 200 R points,
+4096 trajectories in a mid-collision population (R0 uniform in 4-19.5 A,
+b uniform in 0-min(12 A, 0.9 R0), E_coll uniform in 100-2000 cm^-1, initial
+channel uniform over the 35 channels with j <= 2).  One bench step advances
+every trajectory by a window of RK4 steps (dt = 12 a.u.) through the whole hot
+path (interval lookup, phases, fused spline + complex matvec, mean-field
+force and torque, classical update, final probabilities and diagnostics).
+Inputs are synthetic and resident in HBM before timing starts.
+
+Reported: trajectory-steps/s for the FP32-table form (value) and the FP64
+form, the roofline position of the step kernel (HBM-bound: algorithmic table
+bytes / measured kernel time), the FP32 - FP64 probability difference, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("trajectory-steps/s × N² (coupling GB/s), FP32 vs FP64 at "
+          "ΔP≤1e-4; adjoint s/grad")
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--window", type=int, default=10, help="RK4 steps per bench step")
+    ap.add_argument("--traj", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["C64", "C128"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(trajectories shard trivially; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+
+    t0 = time.time()
+    (s,), b = S.config2(n_traj=args.traj, full_collision=False, window_steps=args.window)
+    log("generated N=%d K=%d B=%d in %.1fs" % (s.N, s.K, b.B, time.time() - t0))
+    N, B, W = s.N, b.B, args.window
+    ctx = mq.Context(0)
+    dev = ctx.device
+    results = {}
+    P_of = {}
+    for storage in ([args.only] if args.only else ["C64", "C128"]):
+        t0 = time.time()
+        sid = ctx.load_system(s, storage=storage)
+        torch.cuda.synchronize()
+        log("loaded %s tables (%.1f GB) in %.1fs" % (storage, ctx.system_bytes(sid) / 1e9,
+                                                     time.time() - t0))
+        out = {"P": torch.empty(B * N, dtype=torch.float64, device=dev),
+               "classical": torch.empty((B, 6), dtype=torch.float64, device=dev),
+               "t_final": torch.empty(B, dtype=torch.float64, device=dev),
+               "steps": torch.empty(B, dtype=torch.int64, device=dev),
+               "rejects": torch.empty(B, dtype=torch.int64, device=dev),
+               "status": torch.empty(B, dtype=torch.int32, device=dev),
+               "norm_err": torch.empty(B, dtype=torch.float64, device=dev),
+               "energy_err": torch.empty(B, dtype=torch.float64, device=dev),
+               "angmom_err": torch.empty(B, dtype=torch.float64, device=dev)}
+        sids = np.full(B, sid, np.int32)
+        Ns = np.full(B, N, np.int64)
+
+        def step():
+            ctx.run(sids, Ns, init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0,
+                    dt=b.dt, n_steps=b.n_steps, out=out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.time()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.time() - wall0) / args.steps
+        ms = e0.elapsed_time(e1) / args.steps
+        es = 8 if storage == "C64" else 16
+        evals = B * (4 * W + 1)                   # RK4 stages + the final diagnostic evaluation
+        alg_bytes = evals * 4.0 * N * N * es      # four spline slices of N x N per evaluation
+        gbps = alg_bytes / (ms * 1e-3) / 1e9
+        st = out["status"].cpu().numpy()
+        results[storage] = {
+            "value": B * W / (ms * 1e-3), "ms_per_step": ms, "wall_ms_per_step": wall * 1e3,
+            "coupling_GBps": gbps, "N2_traj_steps_per_s": B * W * N * N / (ms * 1e-3),
+            "status_nonzero": int(np.count_nonzero(st)),
+            "max_norm_err": float(out["norm_err"].abs().max().item()),
+            "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                         "alg_bytes_per_launch": alg_bytes},
+        }
+        P_of[storage] = out["P"].reshape(B, N).cpu().numpy()
+        log("%s: %.2f ms/step, %.3g traj-steps/s, %.0f GB/s (%.1f%% of HBM)" %
+            (storage, ms, results[storage]["value"], gbps, 100 * gbps / HBM_PEAK_GBPS))
+        ctx.free_system(sid)
+
+    head = results.get("C64") or results["C128"]
+    line = {
+        "metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if "C64" in results else "f64", "data": "synthetic",
+        "config": {"workload": "asymmetric top + atom, j<=8 all k,m (N=969), 200-point "
+                               "Hermitian complex tables, %d trajectories mid-collision, "
+                               "%d RK4 steps of 12 a.u. per bench step" % (B, W),
+                   "N": N, "K": s.K, "trajectories": B, "rk4_steps_per_bench_step": W,
+                   "schedule": "gemv (one workgroup per trajectory)"},
+        "roofline": head["roofline"],
+        "coupling_GBps": head["coupling_GBps"],
+        "N2_traj_steps_per_s": head["N2_traj_steps_per_s"],
+    }
+    if "C128" in results and "C64" in results:
+        line["fp64"] = results["C128"]
+        line["fp32_speedup_over_fp64"] = results["C64"]["value"] / results["C128"]["value"]
+        line["fp32_vs_fp64_max_abs_dP"] = float(np.max(np.abs(P_of["C64"] - P_of["C128"])))
+    line["status_nonzero"] = head["status_nonzero"]
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(s, b, W)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(s, b, W):
+    """The FP64 oracle on a bounded sample of the same workload (rank 0 only)."""
+    import numpy as np
+    import oracle
+    t0 = time.time()
+    o = oracle.OracleSystem(s)
+    log("oracle spline prep %.1fs" % (time.time() - t0))
+    th = oracle.threads()
+    n = max(1, min(b.B, th))
+    sub = b.subset(range(n))
+    t0 = time.time()
+    o.propagate(sub, n_steps=np.full(n, 1))
+    t1 = time.time() - t0
+    steps = int(max(1, min(W, round(12.0 / max(t1, 1e-3)))))
+    sub = b.subset(range(n))
+    t0 = time.time()
+    o.propagate(sub, n_steps=np.full(n, steps))
+    dt = time.time() - t0
+    log("oracle: %d trajectories x %d steps in %.1fs on %d threads" % (n, steps, dt, th))
+    return {"value": n * steps / dt, "unit": "traj-steps/s", "cores": th, "kind": "oracle",
+            "sample": "first %d trajectories of the batch x %d RK4 steps (FP64, complex tables, "
+                      "N=969), wall time of the propagation only" % (n, steps)}
+
+
+if __name__ == "__main__":
+    main()

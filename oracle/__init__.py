@@ -54,7 +54,13 @@ def lib():
                                           d, d, i64, d] + [vp] * 10
         _lib.oracle_tangent_rk4.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.oracle_cross_sections.argtypes = [i64, i32, vp, vp, vp, vp, i32, d, vp]
+        _lib.oracle_threads.restype = i32
     return _lib
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 def _p(a):

@@ -481,7 +481,20 @@ void initial_classical(double mu, double E_coll, double b, double R0, double* c6
 
 }  // namespace
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 extern "C" {
+
+// Number of OpenMP threads a parallel region of the oracle uses.
+int32_t oracle_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Evaluate the spline of ncol columns at r: value and derivative.  Returns 1 when
 // r lies below the first knot (linear continuation), else 0.
