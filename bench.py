@@ -28,6 +28,14 @@ METRIC = ("trajectory-steps/s × N² (coupling GB/s), FP32 vs FP64 at "
           "ΔP≤1e-4; adjoint s/grad")
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per launch of the step kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs scaled by the same counters on a plain 1 GiB copy (profiles/
+# rk4_gemv_N969_window.md).  Valid only for the kernel source they were taken on.
+MEASURED_TRAFFIC = {
+    "C64": {"source_sha256_16": "b5621ce316b9d137", "bytes": 4.764148906e12,
+            "window": 10, "trajectories": 4096},
+}
+
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -42,7 +50,12 @@ def main():
     ap.add_argument("--traj", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["C64", "C128"], default=None)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(trajectories shard trivially; see the design notes). Run with --gpus 1.",
@@ -112,6 +125,10 @@ def main():
                          "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
                          "alg_bytes_per_launch": alg_bytes},
         }
+        tr = MEASURED_TRAFFIC.get(storage)
+        if tr and tr["source_sha256_16"] == _kernel_hash() and tr["window"] == W and \
+                tr["trajectories"] == B:
+            results[storage]["roofline"]["traffic"] = tr["bytes"]
         P_of[storage] = out["P"].reshape(B, N).cpu().numpy()
         log("%s: %.2f ms/step, %.3g traj-steps/s, %.0f GB/s (%.1f%% of HBM)" %
             (storage, ms, results[storage]["value"], gbps, 100 * gbps / HBM_PEAK_GBPS))
@@ -144,8 +161,18 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def _kernel_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2312_02322_amd", "csrc", "gemv.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
 def cpu_baseline(s, b, W):
-    """The FP64 oracle on a bounded sample of the same workload (rank 0 only)."""
+    """The FP64 oracle on a bounded sample of the same workload (rank 0 only).
+
+    The sample is the first n trajectories of the batch over the same window of
+    W RK4 steps, with n sized from a short calibration run to take ~12 s.
+    """
     import numpy as np
     import oracle
     t0 = time.time()
@@ -153,19 +180,28 @@ def cpu_baseline(s, b, W):
     log("oracle spline prep %.1fs" % (time.time() - t0))
     th = oracle.threads()
     n = max(1, min(b.B, th))
-    sub = b.subset(range(n))
     t0 = time.time()
-    o.propagate(sub, n_steps=np.full(n, 1))
+    o.propagate(b.subset(range(n)), n_steps=np.full(n, W))
     t1 = time.time() - t0
-    steps = int(max(1, min(W, round(12.0 / max(t1, 1e-3)))))
-    sub = b.subset(range(n))
+    n = int(min(b.B, max(n, th * round(12.0 / max(t1, 1e-3)))))
     t0 = time.time()
-    o.propagate(sub, n_steps=np.full(n, steps))
+    o.propagate(b.subset(range(n)), n_steps=np.full(n, W))
     dt = time.time() - t0
-    log("oracle: %d trajectories x %d steps in %.1fs on %d threads" % (n, steps, dt, th))
-    return {"value": n * steps / dt, "unit": "traj-steps/s", "cores": th, "kind": "oracle",
-            "sample": "first %d trajectories of the batch x %d RK4 steps (FP64, complex tables, "
-                      "N=969), wall time of the propagation only" % (n, steps)}
+    log("oracle: %d trajectories x %d steps in %.1fs on %d threads" % (n, W, dt, th))
+    return {"value": n * W / dt, "unit": "traj-steps/s", "cores": th, "kind": "oracle",
+            "sample": "first %d of the %d trajectories x the same %d RK4 steps (FP64 oracle, "
+                      "complex N=969 tables); wall time of the propagation only" % (n, b.B, W)}
+
+
+def copy_probe(nbytes):
+    """A plain device-to-device copy of known size, for calibrating byte counters."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reads": nbytes, "writes": nbytes}))
 
 
 if __name__ == "__main__":
