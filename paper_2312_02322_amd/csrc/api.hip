@@ -41,7 +41,7 @@ struct mqct_context {
   std::vector<SysHost> systems;
   DevSystem* d_systems = nullptr;
   size_t d_systems_cap = 0;
-  DevBuf traj, a0, outs[10], xs[4];
+  DevBuf traj, a0, outs[10], xs[4], kscratch, counter;
   TrajIn* h_traj = nullptr;        // pinned staging for trajectory records
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
@@ -153,7 +153,8 @@ void mqct_destroy(mqct_context* c) {
   hipStreamSynchronize(c->stream);
   for (auto& s : c->systems) free_system(s);
   if (c->d_systems) hipFree(c->d_systems);
-  DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3]};
+  DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3],
+                   &c->kscratch, &c->counter};
   for (DevBuf* b : all) if (b->p) hipFree(b->p);
   for (auto& b : c->outs) if (b.p) hipFree(b.p);
   if (c->h_traj) hipHostFree(c->h_traj);
@@ -371,12 +372,19 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     return fail(c, MQCT_ERR_ARG, "run: result mem must be host or device");
   if (bd->integrator != MQCT_RK4 && bd->integrator != MQCT_DP5)
     return fail(c, MQCT_ERR_ARG, "run: unknown integrator %d", bd->integrator);
-  if (bd->integrator == MQCT_DP5)
-    return fail(c, MQCT_ERR_UNSUPPORTED, "run: DP5 is not available in this build");
-  if (bd->schedule != MQCT_SCHED_AUTO && bd->schedule != MQCT_SCHED_GEMV)
-    return fail(c, MQCT_ERR_UNSUPPORTED, "run: schedule %d is not available in this build",
-                bd->schedule);
-  if (!bd->dt || !bd->n_steps) return fail(c, MQCT_ERR_ARG, "run: RK4 needs dt and n_steps");
+  if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_PERSISTENT)
+    return fail(c, MQCT_ERR_ARG, "run: unknown schedule %d", bd->schedule);
+  if (bd->schedule == MQCT_SCHED_BINNED)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run: the binned schedule is not available in this build");
+  const bool dp5 = bd->integrator == MQCT_DP5;
+  // DP5 always runs on the persistent queue (trajectory lengths differ)
+  const bool persistent = dp5 || bd->schedule == MQCT_SCHED_PERSISTENT;
+  if (dp5) {
+    if (!(bd->rtol > 0.0) || !(bd->atol > 0.0) || bd->max_steps < 1 || !(bd->h_min >= 0.0))
+      return fail(c, MQCT_ERR_ARG, "run: DP5 needs rtol > 0, atol > 0, max_steps >= 1, h_min >= 0");
+  } else if (!bd->dt || !bd->n_steps) {
+    return fail(c, MQCT_ERR_ARG, "run: RK4 needs dt and n_steps");
+  }
   if (!bd->classical0 && (!bd->E_coll || !bd->b))
     return fail(c, MQCT_ERR_ARG, "run: E_coll and b are required without classical0");
   if (!bd->a0 && !bd->init_channel)
@@ -407,8 +415,8 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     t.id = b;
     t.amp_off = amp_total;
     t.sys = sid;
-    t.n_steps = bd->n_steps[b];
-    t.dt = bd->dt[b];
+    t.n_steps = bd->n_steps ? bd->n_steps[b] : 0;
+    t.dt = bd->dt ? bd->dt[b] : 0.0;
     t.t0 = bd->t0 ? bd->t0[b] : 0.0;
     if (t.n_steps < 0) return fail(c, MQCT_ERR_ARG, "run: n_steps[%lld] < 0", (long long)b);
     if (!isfinite(t.dt) || !isfinite(t.t0)) return fail(c, MQCT_ERR_ARG, "run: non-finite dt/t0");
@@ -456,14 +464,39 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
         return fail(c, MQCT_ERR_ARG, "run: need 0 <= b < R0 (trajectory %lld)", (long long)b);
     }
   }
-  // group by storage type so each launch uses one kernel family
+  // Order of the records on the device.  Per-trajectory launches need each
+  // storage type contiguous.  Persistent launches need each precision family
+  // (C64 + R32, C128 + R64) contiguous, and take the most expensive
+  // trajectories first (cost ~ N^2 x free-flight time 2 R0 / v0), so the
+  // longest ones never start last.
   std::vector<TrajIn> sorted;
   sorted.reserve(B);
-  std::vector<std::pair<int64_t, int64_t>> ranges(4);
-  for (int d = 0; d < 4; ++d) {
-    ranges[d].first = (int64_t)sorted.size();
-    for (int64_t b : order[d]) sorted.push_back(c->h_traj[b]);
-    ranges[d].second = (int64_t)sorted.size();
+  std::vector<std::pair<int64_t, int64_t>> ranges(4, {0, 0});
+  auto cost_of = [&](int64_t b) {
+    const TrajIn& t = c->h_traj[b];
+    const double n = c->systems[t.sys].dev.N;
+    double T = 1.0;
+    if (!(t.flags & TRAJ_HAS_C0) && t.E_coll > 0.0)
+      T = 2.0 * t.R0 / sqrt(2.0 * t.E_coll / c->systems[t.sys].dev.mu);
+    return n * n * T;
+  };
+  if (!persistent) {
+    for (int d = 0; d < 4; ++d) {
+      ranges[d].first = (int64_t)sorted.size();
+      for (int64_t b : order[d]) sorted.push_back(c->h_traj[b]);
+      ranges[d].second = (int64_t)sorted.size();
+    }
+  } else {
+    const int fams[2][2] = {{C64, R32}, {C128, R64}};
+    for (auto& fam : fams) {
+      std::vector<std::pair<double, int64_t>> cost;
+      for (int d : fam)
+        for (int64_t b : order[d]) cost.push_back({-cost_of(b), b});
+      std::stable_sort(cost.begin(), cost.end());
+      const int64_t lo = (int64_t)sorted.size();
+      for (auto& pr : cost) sorted.push_back(c->h_traj[pr.second]);
+      for (int d : fam) ranges[d] = {lo, (int64_t)sorted.size()};
+    }
   }
   memcpy(c->h_traj, sorted.data(), B * sizeof(TrajIn));
 
@@ -504,14 +537,42 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   out.status = (int32_t*)dp[6]; out.norm_err = (double*)dp[7]; out.energy_err = (double*)dp[8];
   out.angmom_err = (double*)dp[9];
 
-  for (int d = 0; d < 4; ++d) {
-    int64_t n = ranges[d].second - ranges[d].first;
-    if (n == 0) continue;
-    hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->traj.p + ranges[d].first, n,
-                                   d_a0, out, d, max_npad[d], c->stream);
-    if (e == hipErrorInvalidValue)
-      return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the per-trajectory schedule");
-    if (e != hipSuccess) return hip_fail(c, e, "run: launch");
+  if (!persistent) {
+    for (int d = 0; d < 4; ++d) {
+      int64_t n = ranges[d].second - ranges[d].first;
+      if (n == 0) continue;
+      hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->traj.p + ranges[d].first, n,
+                                     d_a0, out, d, max_npad[d], c->stream);
+      if (e == hipErrorInvalidValue)
+        return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the per-trajectory schedule");
+      if (e != hipSuccess) return hip_fail(c, e, "run: launch");
+    }
+  } else {
+    // one persistent launch per precision family (FP32 tables: C64 + R32,
+    // FP64 tables: C128 + R64); records are ordered by the host (largest first)
+    DpCtl ctl{bd->rtol, bd->atol, bd->h_min, bd->max_steps};
+    const int fams[2][2] = {{C64, R32}, {C128, R64}};
+    for (int f = 0; f < 2; ++f) {
+      const int d0 = fams[f][0], d1 = fams[f][1];
+      const int64_t lo = ranges[d0].first;
+      const int64_t n = ranges[d0].second - ranges[d0].first;
+      if (n == 0) continue;
+      const int npad = std::max(max_npad[d0], max_npad[d1]);
+      const int groups = std::max(max_npad[d0] / (d0 == C128 ? 1 : 2), max_npad[d1] / 2);
+      if (groups > 1024)
+        return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the persistent schedule");
+      int64_t slots = persistent_slots(f == 0, groups, npad);
+      if (slots <= 0) return fail(c, MQCT_ERR_DEVICE, "run: occupancy query failed");
+      slots = std::min(slots, n);
+      if ((st = ensure(c, c->kscratch, (size_t)slots * 8 * npad * 16, "run: stage scratch")) != MQCT_OK)
+        return st;
+      if ((st = ensure(c, c->counter, 64, "run: queue counter")) != MQCT_OK) return st;
+      hipError_t e = launch_persistent(c->d_systems, (const TrajIn*)c->traj.p + lo, n, d_a0, out,
+                                       f == 0, npad, groups, dp5 ? 1 : 0, ctl,
+                                       (unsigned long long*)c->counter.p, (double2*)c->kscratch.p,
+                                       slots, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "run: persistent launch");
+    }
   }
   for (auto& p : back)
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),

@@ -1,5 +1,7 @@
-// Fixed-step RK4 propagation of Ehrenfest mean-field trajectories, one
-// workgroup per trajectory with the whole step loop inside the kernel.
+// Propagation of Ehrenfest mean-field trajectories with the whole step loop
+// inside the kernel: fixed-step RK4 with one workgroup per trajectory, and a
+// persistent form (RK4 or adaptive Dormand-Prince 5(4)) in which workgroups
+// drain a queue of trajectories of uneven size and length.
 //
 // Right-hand side (paper Section II, Eqs. 5 and 7-10, collision plane
 // Theta = pi/2):
@@ -47,11 +49,25 @@ template <> struct Tr<R64> {
   static constexpr int VEC = 2; static constexpr bool CPLX = false;
 };
 template <> struct Tr<R32> {
-  using S = float; using L = float4; using CS = float2;
-  static constexpr int VEC = 4; static constexpr bool CPLX = false;
+  using S = float; using L = float2; using CS = float2;
+  static constexpr int VEC = 2; static constexpr bool CPLX = false;
 };
 
 constexpr int CHUNK = 64;   // stored rows per FP32 partial sum
+
+// Dormand-Prince 5(4) tableau (Dormand & Prince 1980): nodes, stage
+// coefficients, and fifth-order minus embedded fourth-order weights.
+__constant__ double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+__constant__ double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+__constant__ double DP_E[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
+                               -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
 
 // Spline interval and weights at R (natural cubic spline on knots x[0..K-1]):
 // value = w0 y_k + w1 y_{k+1} + w2 y2_k + w3 y2_{k+1}; derivative with d0..d3.
@@ -100,7 +116,8 @@ __device__ __forceinline__ Spl spline_at(const double* __restrict__ x, int K, do
 
 // Buffer resource over one knot slice of a table: the base and size live in
 // scalar registers and every lane supplies only a 32-bit byte offset (a knot
-// slice is far below 4 GiB).  Reads past `bytes` return zero.
+// slice is far below 4 GiB).  Reads past `bytes` return zero.  Lanes load 16
+// bytes (8 for real FP32 tables, which serve small systems).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void* p, uint32_t bytes) {
   uint64_t v = (uint64_t)p;
   uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -111,7 +128,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void* p, uint
 
 template <typename L>
 __device__ __forceinline__ L load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(L, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  if constexpr (sizeof(L) == 16)
+    return __builtin_bit_cast(L, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(L, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
 __device__ __forceinline__ double uni(double x) {
@@ -121,20 +141,23 @@ __device__ __forceinline__ double uni(double x) {
   return __hiloint2double(hi, lo);
 }
 
-template <int NW>
-__device__ __forceinline__ void block_sum6(double (&v)[6], double* red) {
+// Sum NV values over the workgroup: wave shuffles, then one LDS slot per wave
+// read back in a fixed order (deterministic, identical in every lane).  `red`
+// must not be reused by another reduction before a barrier separates them.
+template <int NV, int NW>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < NV; ++i)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) red[w * 8 + i] = v[i];
+    for (int i = 0; i < NV; ++i) red[w * 8 + i] = v[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < NV; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) s += red[q * 8 + i];
@@ -176,6 +199,34 @@ __device__ __forceinline__ void elem(F2& u, F2& v, F s0r, F s0i, F s1r, F s1i, F
   }
 }
 
+
+// LDS layout shared by the kernels (bytes):
+//   c     [Npad] in the matvec precision (float2 or double2)
+//   c64   [Npad] double2 (aliases c on the FP64 path)
+//   red0  [16][8] doubles, red1 [16][8] doubles  (two reduction areas)
+//   kcl   [8][4] doubles                        (DP5 classical stages and y5)
+__host__ __device__ inline size_t lds_bytes(int npad, bool fp32) {
+  size_t c = fp32 ? (((size_t)npad * 8 + 15) & ~(size_t)15) : 0;
+  return c + (size_t)npad * 16 + 2 * 16 * 8 * 8 + 8 * 4 * 8;
+}
+
+template <int DT>
+struct Lds {
+  typename Tr<DT>::CS* c;
+  double2* c64;
+  double* red0;
+  double* red1;
+  double* kcl;
+  __device__ Lds(unsigned char* smem, int npad) {
+    constexpr bool fp32 = (DT == C64 || DT == R32);
+    c = (typename Tr<DT>::CS*)smem;
+    c64 = fp32 ? (double2*)(smem + (((size_t)npad * 8 + 15) & ~(size_t)15)) : (double2*)smem;
+    red0 = (double*)(c64 + npad);
+    red1 = red0 + 16 * 8;
+    kcl = red1 + 16 * 8;
+  }
+};
+
 template <int DT, int BLOCK, int RPT>
 struct Kern {
   using T = Tr<DT>;
@@ -199,16 +250,14 @@ struct Kern {
     if constexpr (DT == C128) { re[0] = v.x; im[0] = v.y; }
     else if constexpr (DT == C64) { re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w; }
     else if constexpr (DT == R64) { re[0] = v.x; re[1] = v.y; im[0] = im[1] = 0.0; }
-    else { re[0] = v.x; re[1] = v.y; re[2] = v.z; re[3] = v.w;
-           im[0] = im[1] = im[2] = im[3] = 0.f; }
+    else { re[0] = v.x; re[1] = v.y; im[0] = im[1] = 0.f; }
   }
 
   // One evaluation of the right-hand side at time ts for the stage amplitudes
-  // a = a0 + cf * kk and classical stage state (R, P_R, P_Phi).  Overwrites kk
-  // with da/dt; returns the reduced sums.
-  __device__ static void eval(const DevSystem& sy, double ts, double R, double pphi, double cf,
-                              const double2 (&a0)[NR], double2 (&kk)[NR], Sums& tot,
-                              bool& below, CS* lds_c, double2* lds_c64, double* red) {
+  // cur (this lane's rows) and classical stage values R, P_Phi.  Overwrites
+  // cur with da/dt of this lane's rows and returns the workgroup sums in tot.
+  __device__ static void eval(const DevSystem& sy, double ts, double R, double pphi,
+                              double2 (&cur)[NR], Sums& tot, bool& below, const Lds<DT>& lds) {
     const int N = sy.N, Npad = sy.Npad;
     const Spl sp = spline_at(sy.R, sy.K, R);
     below |= sp.below;
@@ -218,12 +267,12 @@ struct Kern {
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
       if (n < N) {
-        const double2 cur = make_double2(fma(cf, kk[r].x, a0[r].x), fma(cf, kk[r].y, a0[r].y));
         double sn, cs;
         sincos(sy.E[n] * ts, &sn, &cs);
-        const double2 c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
-        if constexpr (FP32) lds_c[n] = make_float2((float)c.x, (float)c.y);
-        lds_c64[n] = c;
+        const double2 c = make_double2(cs * cur[r].x + sn * cur[r].y,
+                                       cs * cur[r].y - sn * cur[r].x);
+        if constexpr (FP32) lds.c[n] = make_float2((float)c.x, (float)c.y);
+        lds.c64[n] = c;
       }
     }
     __syncthreads();
@@ -252,15 +301,15 @@ struct Kern {
       }
 #pragma unroll UNR
       for (int m = m0; m < m1; ++m) {
-        const CS cm = lds_c[m];
-        const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * 16u;
+        const CS cm = lds.c[m];
+        const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
         // No lane guard: a lane whose column group lies past the last one reads
         // into the next stored row (or past the slice, which returns zero) and
         // its sums are never used, so the loads of consecutive m stay in flight
         // together.
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-          const uint32_t off = rowoff + (uint32_t)(threadIdx.x + j * BLOCK) * 16u;
+          const uint32_t off = rowoff + (uint32_t)(threadIdx.x + j * BLOCK) * (uint32_t)sizeof(L);
           const L v0 = load16<L>(rs0, off);
           const L v1 = load16<L>(rs1, off);
           const L v2 = load16<L>(rs2, off);
@@ -287,16 +336,16 @@ struct Kern {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
-      if (n >= N) { kk[r] = make_double2(0.0, 0.0); continue; }
-      const double2 cur = make_double2(fma(cf, kk[r].x, a0[r].x), fma(cf, kk[r].y, a0[r].y));
+      if (n >= N) { cur[r] = make_double2(0.0, 0.0); continue; }
       double sn, cs;
       sincos(sy.E[n] * ts, &sn, &cs);
-      const double2 c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+      const double2 c = make_double2(cs * cur[r].x + sn * cur[r].y,
+                                     cs * cur[r].y - sn * cur[r].x);
       double2 xc = make_double2(0.0, 0.0);
       for (int q = 0; q < sy.jx_w; ++q) {
         const int col = sy.jx_col[(int64_t)n * sy.jx_w + q];
         const double jv = sy.jx_val[(int64_t)n * sy.jx_w + q];
-        const double2 cm = lds_c64[col];
+        const double2 cm = lds.c64[col];
         xc.x = fma(jv, cm.x, xc.x);
         xc.y = fma(jv, cm.y, xc.y);
       }
@@ -304,172 +353,409 @@ struct Kern {
       sums[0] += c.x * v.x + c.y * v.y;
       sums[1] += xc.x * u.y - xc.y * u.x;
       sums[2] += c.x * u.x + c.y * u.y;
-      const double pn = cur.x * cur.x + cur.y * cur.y;
+      const double pn = cur[r].x * cur[r].x + cur[r].y * cur[r].y;
       sums[3] += sy.E[n] * pn;
       sums[4] += pn;
       sums[5] += c.x * xc.x + c.y * xc.y;
       // da/dt = -i e^{iE_n t} (u + Phidot J_x c)
       const double gx = u.x + phidot * xc.x, gy = u.y + phidot * xc.y;
       const double yx = cs * gx - sn * gy, yy = cs * gy + sn * gx;
-      kk[r] = make_double2(yy, -yx);
+      cur[r] = make_double2(yy, -yx);
     }
-    block_sum6<NW>(sums, red);
+    block_sum<6, NW>(sums, lds.red0);
     tot.force = sums[0]; tot.torque = sums[1]; tot.vexp = sums[2];
     tot.erot = sums[3]; tot.norm = sums[4]; tot.jx = sums[5];
   }
+
+  // classical derivatives of (R, Phi, P_R, P_Phi), Eqs. 7-10
+  __device__ static void classical_rhs(double mu, const double (&ys)[4], const Sums& tot,
+                                       double (&ky)[4]) {
+    const double R = ys[0];
+    ky[0] = ys[2] / mu;
+    ky[1] = ys[3] / (mu * R * R);
+    ky[2] = -tot.force + ys[3] * ys[3] / (mu * R * R * R);
+    ky[3] = 2.0 * tot.torque;
+  }
+
+  __device__ static double energy(double mu, const double (&ys)[4], const Sums& s) {
+    return ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * ys[0] * ys[0]) + s.erot +
+           s.vexp;
+  }
+
+  // initial amplitudes and classical state of a trajectory
+  __device__ static void init_state(const DevSystem& sy, const TrajIn& tj,
+                                    const double* __restrict__ a0_all, double2 (&a)[NR],
+                                    double (&y)[4], double& theta, double& ptheta) {
+    const int N = sy.N;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int n = row(r);
+      double2 v = make_double2(0.0, 0.0);
+      if (n < N) {
+        if (tj.flags & TRAJ_HAS_A0) v = ((const double2*)a0_all)[tj.amp_off + n];
+        else if (n == tj.init_channel) v = make_double2(1.0, 0.0);
+      }
+      a[r] = v;
+    }
+    theta = 0.5 * M_PI;
+    ptheta = 0.0;
+    if (tj.flags & TRAJ_HAS_C0) {
+      y[0] = tj.c0[0]; theta = tj.c0[1]; y[1] = tj.c0[2]; y[2] = tj.c0[3]; ptheta = tj.c0[4];
+      y[3] = tj.c0[5];
+    } else {
+      // end of Section II / Section III: P_Phi = b k, P_R = -sqrt(k^2 - P_Phi^2/R0^2)
+      const double k = sqrt(2.0 * sy.mu * tj.E_coll);
+      const double pphi = tj.b * k;
+      y[0] = tj.R0; y[1] = 0.0;
+      y[2] = -sqrt(2.0 * sy.mu * tj.E_coll - pphi * pphi / (tj.R0 * tj.R0));
+      y[3] = pphi;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = uni(y[i]);
+  }
+
+  __device__ static void write_out(const DevSystem& sy, const TrajIn& tj, TrajOut& out,
+                                   const double2 (&a)[NR], const double (&y)[4], double theta,
+                                   double ptheta, double tend, int64_t steps, int64_t rejects,
+                                   int32_t status, const Sums& tot, double E0, double J0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int n = row(r);
+      if (n < sy.N) {
+        out.P[tj.amp_off + n] = a[r].x * a[r].x + a[r].y * a[r].y;
+        if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a[r];
+      }
+    }
+    if (threadIdx.x == 0) {
+      const int64_t id = tj.id;
+      if (out.classical) {
+        double* o = out.classical + id * 6;
+        o[0] = y[0]; o[1] = theta; o[2] = y[1]; o[3] = y[2]; o[4] = ptheta; o[5] = y[3];
+      }
+      if (out.t_final) out.t_final[id] = tend;
+      if (out.steps) out.steps[id] = steps;
+      if (out.rejects) out.rejects[id] = rejects;
+      if (out.status) out.status[id] = status;
+      if (out.norm_err) out.norm_err[id] = tot.norm - 1.0;
+      if (out.energy_err) out.energy_err[id] = (energy(sy.mu, y, tot) - E0) / fabs(E0);
+      if (out.angmom_err) out.angmom_err[id] = (y[3] - tot.jx) - J0;
+    }
+  }
+
+  // Fixed-step classical RK4: exactly n_steps steps, t_j = t0 + j h.
+  __device__ static void run_rk4(const DevSystem& sy, const TrajIn& tj,
+                                 const double* __restrict__ a0_all, TrajOut& out,
+                                 const Lds<DT>& lds) {
+    const double mu = sy.mu;
+    double2 a0[NR], kk[NR], acc[NR];   // kk: stage input, then its derivative
+    double y[4], ky[4] = {0.0, 0.0, 0.0, 0.0}, ay[4], theta, ptheta;
+    init_state(sy, tj, a0_all, a0, y, theta, ptheta);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) kk[r] = make_double2(0.0, 0.0);
+    const double h = tj.dt, t0 = tj.t0;
+    bool below = false;
+    int32_t status = 0;
+    double E0 = 0.0, J0 = 0.0;
+    bool first = true;
+    Sums tot;
+    int64_t j = 0;
+    for (; j < tj.n_steps; ++j) {
+      const double t = t0 + (double)j * h;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ay[i] = 0.0;
+      for (int st = 0; st < 4; ++st) {
+        const double cf = st == 0 ? 0.0 : (st == 3 ? h : 0.5 * h);
+        const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+        double ys[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ys[i] = fma(cf, ky[i], y[i]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          kk[r] = make_double2(fma(cf, kk[r].x, a0[r].x), fma(cf, kk[r].y, a0[r].y));
+        eval(sy, t + cf, ys[0], ys[3], kk, tot, below, lds);
+        if (first) {
+          E0 = energy(mu, ys, tot);
+          J0 = ys[3] - tot.jx;
+          first = false;
+        }
+        classical_rhs(mu, ys, tot, ky);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          acc[r].x = fma(wgt, kk[r].x, acc[r].x);
+          acc[r].y = fma(wgt, kk[r].y, acc[r].y);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ay[i] = fma(wgt, ky[i], ay[i]);
+      }
+      const double h6 = h / 6.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        a0[r].x += h6 * acc[r].x;
+        a0[r].y += h6 * acc[r].y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[i] = uni(y[i] + h6 * ay[i]);
+      if (!isfinite(tot.force) || !isfinite(tot.torque) || !isfinite(tot.norm) ||
+          !isfinite(y[0]) || !isfinite(y[2]) || !isfinite(y[3])) {
+        status |= ST_NONFINITE;
+        ++j;
+        break;
+      }
+    }
+    // diagnostics at the final state (one more evaluation; its derivative is unused)
+    const double tend = t0 + (double)j * h;
+    bool b2 = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = a0[r];
+    eval(sy, tend, y[0], y[3], acc, tot, b2, lds);
+    if (first) {
+      E0 = energy(mu, y, tot);
+      J0 = y[3] - tot.jx;
+    }
+    if (below) status |= ST_BELOW_GRID;
+    write_out(sy, tj, out, a0, y, theta, ptheta, tend, j, 0, status, tot, E0, J0);
+  }
+
+  // Adaptive Dormand-Prince 5(4) (Dormand & Prince 1980 tableau) with
+  // first-same-as-last, the scaled RMS error over the 2N+6 real state
+  // components (sc_i = atol + rtol max(|y_i|, |y_new,i|); Theta and P_Theta
+  // are constant and contribute zero error), the step factor
+  // min(5, max(0.2, 0.9 err^-1/5)) with no growth right after a rejection, and
+  // the Hairer-Norsett-Wanner starting step.  Stops after the first accepted
+  // step with R >= R0 and P_R > 0, or on max_steps / h < h_min / non-finite.
+  // Amplitude stage derivatives live in this workgroup's slice ks[7][Npad] of
+  // global scratch (each lane touches only its own rows); the classical ones
+  // live in LDS (every lane writes the same values, then reads its own).
+  __device__ static void run_dp5(const DevSystem& sy, const TrajIn& tj,
+                                 const double* __restrict__ a0_all, TrajOut& out,
+                                 const Lds<DT>& lds, double2* __restrict__ ks, int npad_max,
+                                 const DpCtl& ctl) {
+    const int N = sy.N;
+    const double mu = sy.mu;
+    const double rtol = ctl.rtol, atol = ctl.atol;
+    const double ncomp = 2.0 * N + 6.0;
+    double2 y[NR], st[NR];     // solution; stage input, then its derivative
+    double yc[4], theta, ptheta;
+    init_state(sy, tj, a0_all, y, yc, theta, ptheta);
+    const double R_exit = yc[0];
+    double* kcl = lds.kcl;     // [8][4]: classical stage derivatives, then slot 7 = y5
+    // ks[q][n], q = 0..6 stage derivatives, q = 7 the fifth-order solution
+    auto kidx = [&](int q, int r) { return (int64_t)q * npad_max + row(r); };
+    bool below = false;
+    int32_t status = 0;
+    Sums tot;
+    double t = tj.t0;
+    // first evaluation k1 = f(t0, y0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) st[r] = y[r];
+    eval(sy, t, yc[0], yc[3], st, tot, below, lds);
+    const double E0 = energy(mu, yc, tot), J0 = yc[3] - tot.jx;
+    {
+      double kc[4];
+      classical_rhs(mu, yc, tot, kc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) kcl[i] = kc[i];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) if (row(r) < N) ks[kidx(0, r)] = st[r];
+    }
+    const double yfull[6] = {yc[0], theta, yc[1], yc[2], ptheta, yc[3]};
+    // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4)
+    double h;
+    {
+      double s2[2] = {0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (row(r) >= N) continue;
+        const double sx = atol + rtol * fabs(y[r].x), sy_ = atol + rtol * fabs(y[r].y);
+        s2[0] += (y[r].x / sx) * (y[r].x / sx) + (y[r].y / sy_) * (y[r].y / sy_);
+        s2[1] += (st[r].x / sx) * (st[r].x / sx) + (st[r].y / sy_) * (st[r].y / sy_);
+      }
+      block_sum<2, NW>(s2, lds.red1);
+      const double kf[6] = {kcl[0], 0.0, kcl[1], kcl[2], 0.0, kcl[3]};
+      for (int i = 0; i < 6; ++i) {
+        const double sc = atol + rtol * fabs(yfull[i]);
+        s2[0] += (yfull[i] / sc) * (yfull[i] / sc);
+        s2[1] += (kf[i] / sc) * (kf[i] / sc);
+      }
+      const double d0 = sqrt(s2[0] / ncomp), d1 = sqrt(s2[1] / ncomp);
+      const double h0 = uni((d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        st[r] = make_double2(fma(h0, st[r].x, y[r].x), fma(h0, st[r].y, y[r].y));
+      double ys[4];
+      for (int i = 0; i < 4; ++i) ys[i] = uni(fma(h0, kcl[i], yc[i]));
+      eval(sy, t + h0, ys[0], ys[3], st, tot, below, lds);
+      double kc1[4];
+      classical_rhs(mu, ys, tot, kc1);
+      double s1[1] = {0.0};
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (row(r) >= N) continue;
+        const double2 f0 = ks[kidx(0, r)];
+        const double sx = atol + rtol * fabs(y[r].x), sy_ = atol + rtol * fabs(y[r].y);
+        const double ex = (st[r].x - f0.x) / sx, ey = (st[r].y - f0.y) / sy_;
+        s1[0] += ex * ex + ey * ey;
+      }
+      block_sum<1, NW>(s1, lds.red1);
+      const double dk[6] = {kc1[0] - kcl[0], 0.0, kc1[1] - kcl[1], kc1[2] - kcl[2], 0.0,
+                            kc1[3] - kcl[3]};
+      for (int i = 0; i < 6; ++i) {
+        const double sc = atol + rtol * fabs(yfull[i]);
+        s1[0] += (dk[i] / sc) * (dk[i] / sc);
+      }
+      const double d2 = sqrt(s1[0] / ncomp) / h0;
+      const double dm = fmax(d1, d2);
+      const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / 5.0);
+      h = uni(fmin(100.0 * h0, h1));
+    }
+    int64_t steps = 0, rejects = 0;
+    bool last_rejected = false;
+    for (;;) {
+      if (steps >= ctl.max_steps) { status |= ST_MAX_STEPS; break; }
+      for (int s = 1; s < 7; ++s) {
+        // stage input y + h sum_q a_sq k_q
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          double2 acc = y[r];
+          if (row(r) < N) {
+            for (int q = 0; q < s; ++q) {
+              const double2 kq = ks[kidx(q, r)];
+              const double c = h * DP_A[s][q];
+              acc.x = fma(c, kq.x, acc.x);
+              acc.y = fma(c, kq.y, acc.y);
+            }
+            if (s == 6) ks[kidx(7, r)] = acc;
+          }
+          st[r] = acc;
+        }
+        double ys[4];
+        for (int i = 0; i < 4; ++i) {
+          double acc = yc[i];
+          for (int q = 0; q < s; ++q) acc = fma(h * DP_A[s][q], kcl[q * 4 + i], acc);
+          ys[i] = uni(acc);
+          if (s == 6) kcl[28 + i] = ys[i];
+        }
+        eval(sy, t + DP_C[s] * h, ys[0], ys[3], st, tot, below, lds);
+        double kc[4];
+        classical_rhs(mu, ys, tot, kc);
+        for (int i = 0; i < 4; ++i) kcl[s * 4 + i] = kc[i];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) if (row(r) < N) ks[kidx(s, r)] = st[r];
+      }
+      // scaled RMS error of h sum_q e_q k_q
+      double e2[1] = {0.0};
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (row(r) >= N) continue;
+        double ex = 0.0, ey = 0.0;
+        for (int q = 0; q < 7; ++q) {
+          const double2 kq = ks[kidx(q, r)];
+          ex = fma(DP_E[q], kq.x, ex);
+          ey = fma(DP_E[q], kq.y, ey);
+        }
+        ex *= h; ey *= h;
+        const double2 y5 = ks[kidx(7, r)];
+        const double sx = atol + rtol * fmax(fabs(y[r].x), fabs(y5.x));
+        const double sy_ = atol + rtol * fmax(fabs(y[r].y), fabs(y5.y));
+        e2[0] += (ex / sx) * (ex / sx) + (ey / sy_) * (ey / sy_);
+      }
+      block_sum<1, NW>(e2, lds.red1);
+      for (int i = 0; i < 4; ++i) {
+        double e = 0.0;
+        for (int q = 0; q < 7; ++q) e = fma(DP_E[q], kcl[q * 4 + i], e);
+        e *= h;
+        const double sc = atol + rtol * fmax(fabs(yc[i]), fabs(kcl[28 + i]));
+        e2[0] += (e / sc) * (e / sc);
+      }
+      const double en = uni(sqrt(e2[0] / ncomp));
+      if (!isfinite(en)) { status |= ST_NONFINITE; break; }
+      if (en <= 1.0) {
+        t += h;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (row(r) < N) {
+            y[r] = ks[kidx(7, r)];
+            ks[kidx(0, r)] = ks[kidx(6, r)];
+          }
+        }
+        for (int i = 0; i < 4; ++i) { yc[i] = uni(kcl[28 + i]); kcl[i] = kcl[24 + i]; }
+        ++steps;
+        double fac = en == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(en, -0.2)));
+        if (last_rejected) fac = fmin(1.0, fac);
+        last_rejected = false;
+        if (yc[0] >= R_exit && yc[2] > 0.0) { status |= ST_EXITED; break; }
+        h = uni(h * fac);
+      } else {
+        ++rejects;
+        h = uni(h * fmax(0.2, 0.9 * pow(en, -0.2)));
+        last_rejected = true;
+      }
+      if (h < ctl.h_min) { status |= ST_STEP_UNDERFLOW; break; }
+    }
+    bool b2 = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) st[r] = y[r];
+    eval(sy, t, yc[0], yc[3], st, tot, b2, lds);
+    if (below) status |= ST_BELOW_GRID;
+    write_out(sy, tj, out, y, yc, theta, ptheta, t, steps, rejects, status, tot, E0, J0);
+  }
 };
 
-// classical state carried by the kernel: R, Phi, P_R, P_Phi (Theta = pi/2 and
-// P_Theta = 0 are constants of the planar motion)
+// One workgroup per trajectory (grid = number of trajectories), RK4.
 template <int DT, int BLOCK, int RPT>
 __global__ void __launch_bounds__(BLOCK)
 rk4_gemv_kernel(const DevSystem* __restrict__ systems, const TrajIn* __restrict__ trajs,
-                const double* __restrict__ a0_all, double2* __restrict__ cfull, TrajOut out) {
-  using KK = Kern<DT, BLOCK, RPT>;
-  using CS = typename KK::CS;
-  constexpr int NR = KK::NR;
+                const double* __restrict__ a0_all, TrajOut out) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TrajIn tj = trajs[blockIdx.x];
   const DevSystem sy = systems[tj.sys];
-  const int N = sy.N;
-  const double mu = sy.mu;
-  // LDS: c in the matvec precision, c in FP64 (the same array on the FP64
-  // path), then the reduction scratch
-  CS* lds_c = (CS*)smem;
-  double2* lds_c64 = KK::FP32 ? (double2*)(smem + ((sy.Npad * sizeof(CS) + 15) & ~(size_t)15))
-                              : (double2*)smem;
-  double* red = (double*)(lds_c64 + sy.Npad);
-  (void)cfull;
+  Lds<DT> lds(smem, sy.Npad);
+  Kern<DT, BLOCK, RPT>::run_rk4(sy, tj, a0_all, out, lds);
+}
 
-  double2 a0[NR], kk[NR], acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int n = KK::row(r);
-    double2 v = make_double2(0.0, 0.0);
-    if (n < N) {
-      if (tj.flags & TRAJ_HAS_A0) v = ((const double2*)a0_all)[tj.amp_off + n];
-      else if (n == tj.init_channel) v = make_double2(1.0, 0.0);
+// Persistent workgroups draining a trajectory queue.  Each workgroup takes the
+// next index from a global counter (so long trajectories never hold up the
+// rest of the batch) and runs it to completion with the storage type of its
+// system (any of the types in TYPES, chosen at run time); it exits once the
+// queue is empty, so every wave reaches the end.
+template <int T0, int T1, int BLOCK, int RPT>
+__global__ void __launch_bounds__(BLOCK)
+persistent_kernel(const DevSystem* __restrict__ systems, const TrajIn* __restrict__ trajs,
+                  int64_t n_traj, const double* __restrict__ a0_all, TrajOut out,
+                  unsigned long long* __restrict__ counter, double2* __restrict__ kscratch,
+                  int npad_max, int method, DpCtl ctl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long next;
+  double2* ks = kscratch + (int64_t)blockIdx.x * 8 * npad_max;
+  for (;;) {
+    if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long idx = next;
+    __syncthreads();
+    if (idx >= n_traj) break;
+    const TrajIn tj = trajs[idx];
+    const DevSystem sy = systems[tj.sys];
+    if (sy.dtype == T0) {
+      Lds<T0> lds(smem, npad_max);
+      if (method == 0) Kern<T0, BLOCK, RPT>::run_rk4(sy, tj, a0_all, out, lds);
+      else Kern<T0, BLOCK, RPT>::run_dp5(sy, tj, a0_all, out, lds, ks, npad_max, ctl);
+    } else if (T1 != T0 && sy.dtype == T1) {
+      Lds<T1> lds(smem, npad_max);
+      if (method == 0) Kern<T1, BLOCK, RPT>::run_rk4(sy, tj, a0_all, out, lds);
+      else Kern<T1, BLOCK, RPT>::run_dp5(sy, tj, a0_all, out, lds, ks, npad_max, ctl);
     }
-    a0[r] = v;
-    kk[r] = make_double2(0.0, 0.0);
-  }
-  // y = (R, Phi, P_R, P_Phi)
-  double y[4], ky[4] = {0.0, 0.0, 0.0, 0.0}, ay[4];
-  double theta = 0.5 * M_PI, ptheta = 0.0;
-  if (tj.flags & TRAJ_HAS_C0) {
-    y[0] = tj.c0[0]; theta = tj.c0[1]; y[1] = tj.c0[2]; y[2] = tj.c0[3]; ptheta = tj.c0[4];
-    y[3] = tj.c0[5];
-  } else {
-    const double k = sqrt(2.0 * mu * tj.E_coll);
-    const double pphi = tj.b * k;
-    y[0] = tj.R0; y[1] = 0.0;
-    y[2] = -sqrt(2.0 * mu * tj.E_coll - pphi * pphi / (tj.R0 * tj.R0));
-    y[3] = pphi;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) y[i] = uni(y[i]);
-
-  const double h = tj.dt, t0 = tj.t0;
-  bool below = false;
-  int32_t status = 0;
-  double E0 = 0.0, J0 = 0.0;
-  bool first = true;
-  Sums tot;
-  int64_t j = 0;
-  auto energy = [&](const double* ys, const Sums& s) {
-    return ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * ys[0] * ys[0]) + s.erot +
-           s.vexp;
-  };
-  for (; j < tj.n_steps; ++j) {
-    const double t = t0 + (double)j * h;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ay[i] = 0.0;
-    for (int st = 0; st < 4; ++st) {
-      const double cf = st == 0 ? 0.0 : (st == 3 ? h : 0.5 * h);
-      const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
-      double ys[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ys[i] = fma(cf, ky[i], y[i]);
-      KK::eval(sy, t + cf, ys[0], ys[3], cf, a0, kk, tot, below, lds_c, lds_c64, red);
-      if (first) {
-        E0 = energy(ys, tot);
-        J0 = ys[3] - tot.jx;
-        first = false;
-      }
-      const double R = ys[0];
-      ky[0] = ys[2] / mu;
-      ky[1] = ys[3] / (mu * R * R);
-      ky[2] = -tot.force + ys[3] * ys[3] / (mu * R * R * R);
-      ky[3] = 2.0 * tot.torque;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        acc[r].x = fma(wgt, kk[r].x, acc[r].x);
-        acc[r].y = fma(wgt, kk[r].y, acc[r].y);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ay[i] = fma(wgt, ky[i], ay[i]);
-    }
-    const double h6 = h / 6.0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      a0[r].x += h6 * acc[r].x;
-      a0[r].y += h6 * acc[r].y;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) y[i] = uni(y[i] + h6 * ay[i]);
-    if (!isfinite(tot.force) || !isfinite(tot.torque) || !isfinite(tot.norm) ||
-        !isfinite(y[0]) || !isfinite(y[2]) || !isfinite(y[3])) {
-      status |= ST_NONFINITE;
-      ++j;
-      break;
-    }
-  }
-  // diagnostics at the final state (one more evaluation; its derivative is unused)
-  const double tend = t0 + (double)j * h;
-  {
-    bool b2 = false;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = kk[r];
-    KK::eval(sy, tend, y[0], y[3], 0.0, a0, acc, tot, b2, lds_c, lds_c64, red);
-    if (first) {
-      E0 = energy(y, tot);
-      J0 = y[3] - tot.jx;
-    }
-  }
-  if (below) status |= ST_BELOW_GRID;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int n = KK::row(r);
-    if (n < N) {
-      out.P[tj.amp_off + n] = a0[r].x * a0[r].x + a0[r].y * a0[r].y;
-      if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a0[r];
-    }
-  }
-  if (threadIdx.x == 0) {
-    const int64_t id = tj.id;
-    if (out.classical) {
-      double* o = out.classical + id * 6;
-      o[0] = y[0]; o[1] = theta; o[2] = y[1]; o[3] = y[2]; o[4] = ptheta; o[5] = y[3];
-    }
-    if (out.t_final) out.t_final[id] = tend;
-    if (out.steps) out.steps[id] = j;
-    if (out.rejects) out.rejects[id] = 0;
-    if (out.status) out.status[id] = status;
-    if (out.norm_err) out.norm_err[id] = tot.norm - 1.0;
-    if (out.energy_err) out.energy_err[id] = (energy(y, tot) - E0) / fabs(E0);
-    if (out.angmom_err) out.angmom_err[id] = (y[3] - tot.jx) - J0;
   }
 }
+
+__global__ void zero_counter(unsigned long long* c) { *c = 0ull; }
 
 template <int DT, int BLOCK, int RPT>
 hipError_t launch_one(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
                       const double* d_a0, TrajOut out, int max_npad, hipStream_t s) {
-  using CS = typename Tr<DT>::CS;
   const bool fp32 = DT == C64 || DT == R32;
-  size_t lds = (fp32 ? ((max_npad * sizeof(CS) + 15) & ~(size_t)15) : 0) + (size_t)max_npad * 16 +
-               (BLOCK / 64) * 8 * sizeof(double);
+  size_t lds = lds_bytes(max_npad, fp32);
   auto kern = rk4_gemv_kernel<DT, BLOCK, RPT>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -478,7 +764,7 @@ hipError_t launch_one(const DevSystem* d_systems, const TrajIn* d_traj, int64_t 
   }
   for (int64_t first = 0; first < n_traj; first += 1 << 30) {
     int64_t cnt = n_traj - first < (1 << 30) ? n_traj - first : (1 << 30);
-    kern<<<(unsigned)cnt, BLOCK, lds, s>>>(d_systems, d_traj + first, d_a0, nullptr, out);
+    kern<<<(unsigned)cnt, BLOCK, lds, s>>>(d_systems, d_traj + first, d_a0, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -499,6 +785,29 @@ hipError_t launch_dt(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n
   return hipErrorInvalidValue;
 }
 
+template <int T0, int T1, int RPT>
+hipError_t launch_persistent_t(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                               const double* d_a0, TrajOut out, int max_npad, int method,
+                               DpCtl ctl, unsigned long long* counter, double2* kscratch,
+                               int64_t slots, hipStream_t s) {
+  constexpr int BLOCK = 512;
+  const bool fp32 = T0 == C64 || T0 == R32 || T1 == C64 || T1 == R32;
+  size_t lds = lds_bytes(max_npad, fp32) + 16;
+  auto kern = persistent_kernel<T0, T1, BLOCK, RPT>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  zero_counter<<<1, 1, 0, s>>>(counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t grid = slots < n_traj ? slots : n_traj;
+  kern<<<(unsigned)grid, BLOCK, lds, s>>>(d_systems, d_traj, n_traj, d_a0, out, counter,
+                                          kscratch, max_npad, method, ctl);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
@@ -511,6 +820,39 @@ hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int
     case R32: return launch_dt<R32>(d_systems, d_traj, n_traj, d_a0, out, max_npad, s);
   }
   return hipErrorInvalidValue;
+}
+
+int64_t persistent_slots(bool fp32_family, int max_groups, int max_npad) {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const bool two = max_groups > 512;
+  const size_t lds = lds_bytes(max_npad, fp32_family) + 16;
+  const void* k;
+  if (fp32_family) k = two ? (const void*)persistent_kernel<C64, R32, 512, 2>
+                           : (const void*)persistent_kernel<C64, R32, 512, 1>;
+  else k = two ? (const void*)persistent_kernel<C128, R64, 512, 2>
+               : (const void*)persistent_kernel<C128, R64, 512, 1>;
+  if (lds > 65536 &&
+      hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 512, lds) != hipSuccess) return 0;
+  return (int64_t)cus * (nb > 0 ? nb : 1);
+}
+
+hipError_t launch_persistent(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                             const double* d_a0, TrajOut out, bool fp32_family, int max_npad,
+                             int max_groups, int method, DpCtl ctl, unsigned long long* counter,
+                             double2* kscratch, int64_t slots, hipStream_t s) {
+  if (max_groups > 1024) return hipErrorInvalidValue;
+  const bool two = max_groups > 512;
+  if (fp32_family) {
+    if (two) return launch_persistent_t<C64, R32, 2>(d_systems, d_traj, n_traj, d_a0, out, max_npad, method, ctl, counter, kscratch, slots, s);
+    return launch_persistent_t<C64, R32, 1>(d_systems, d_traj, n_traj, d_a0, out, max_npad, method, ctl, counter, kscratch, slots, s);
+  }
+  if (two) return launch_persistent_t<C128, R64, 2>(d_systems, d_traj, n_traj, d_a0, out, max_npad, method, ctl, counter, kscratch, slots, s);
+  return launch_persistent_t<C128, R64, 1>(d_systems, d_traj, n_traj, d_a0, out, max_npad, method, ctl, counter, kscratch, slots, s);
 }
 
 }  // namespace mqct

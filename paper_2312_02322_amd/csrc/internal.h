@@ -83,6 +83,24 @@ hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int
                            const double* d_a0, TrajOut out, int dtype, int max_npad,
                            hipStream_t s);
 
+// Adaptive-step controls.
+struct DpCtl {
+  double rtol, atol, h_min;
+  int64_t max_steps;
+};
+
+// Persistent workgroups over a trajectory queue, RK4 (method 0) or DP5
+// (method 1).  All systems of the launch belong to one precision family
+// (fp32_family: C64/R32, else C128/R64); max_groups = max over systems of the
+// 16-byte column groups per stored row (<= 1024).  kscratch holds
+// slots * 8 * max_npad double2; counter is one zeroed-by-the-launch word.
+hipError_t launch_persistent(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                             const double* d_a0, TrajOut out, bool fp32_family, int max_npad,
+                             int max_groups, int method, DpCtl ctl, unsigned long long* counter,
+                             double2* kscratch, int64_t slots, hipStream_t s);
+// Resident workgroups of the persistent kernel on the current device.
+int64_t persistent_slots(bool fp32_family, int max_groups, int max_npad);
+
 // Cross sections on the device.
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
                        const int32_t* level_of_channel, int n_levels, double b_max,

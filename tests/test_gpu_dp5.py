@@ -1,0 +1,113 @@
+"""GPU parity of the adaptive Dormand-Prince path and the persistent trajectory queue.
+
+Adaptive steps: the oracle and the GPU take the same accept/reject decisions
+except when an error estimate lands within rounding of 1, so final
+probabilities are compared at 10 x rtol (FP64 tables) and 1e-4 (FP32 tables);
+step counts must agree to within a few steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import systems as S, units as U
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-8
+
+
+def say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context()
+    yield c
+    c.synchronize()
+    c.close()
+
+
+def gpu_dp5(ctx, sids, Ns, batch, **kw):
+    args = dict(init_channel=batch.init_channel, E_coll=batch.E_coll, b=batch.b, R0=batch.R0,
+                integrator="dp5", rtol=RTOL, atol=RTOL, max_steps=200000, h_min=1e-6)
+    args.update(kw)
+    return ctx.run_host(sids, Ns, **args)
+
+
+def test_dp5_fp64_matches_oracle(ctx):
+    (s,), b = S.config1(n_traj=8)
+    say("dp5 config1 N=49 R64, 8 trajectories")
+    sid = ctx.load_system(s)
+    g = gpu_dp5(ctx, [sid] * b.B, [s.N] * b.B, b)
+    o = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=RTOL, atol=RTOL,
+                                         max_steps=200000, h_min=1e-6)
+    P = g["P"].reshape(b.B, s.N)
+    say("dp5 steps gpu %s oracle %s" % (g["steps"].tolist(), o["steps"].tolist()))
+    assert np.all(g["status"] & 1) and np.all(o["status"] & 1)          # exited
+    assert np.max(np.abs(g["steps"] - o["steps"])) <= 2
+    assert np.max(np.abs(P - o["P"])) < 10 * RTOL
+    assert np.max(np.abs(g["t_final"] - o["t_final"]) / o["t_final"]) < 1e-3
+    assert np.max(np.abs(g["energy_err"])) < 1e-6
+    ctx.free_system(sid)
+
+
+def test_persistent_rk4_matches_per_trajectory_schedule(ctx):
+    (s,), b = S.config1(n_traj=16, n_steps=300)
+    say("persistent rk4 vs gemv N=49")
+    sid = ctx.load_system(s)
+    common = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt,
+                  n_steps=b.n_steps)
+    g1 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="gemv", **common)
+    g2 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="persistent", **common)
+    assert np.max(np.abs(g1["a_final"] - g2["a_final"])) < 1e-12
+    assert np.array_equal(g1["steps"], g2["steps"])
+    ctx.free_system(sid)
+
+
+def _mixed(storage_real, storage_cplx, n_each=(6, 4, 3)):
+    """Three systems of different N and kind, uneven trajectory counts, shuffled."""
+    systems, batch = S.config3(n_traj=sum(n_each), split=tuple(np.array(n_each) / sum(n_each)),
+                               jmax=(4, 1, 2))
+    kinds = [storage_real, storage_real, storage_cplx]
+    return systems, batch, kinds
+
+
+@pytest.mark.parametrize("fam", ["fp64", "fp32"])
+def test_uneven_mixed_batch_one_launch(ctx, fam):
+    real, cplx = ("R64", "C128") if fam == "fp64" else ("R32", "C64")
+    systems, b, kinds = _mixed(real, cplx)
+    say("uneven mix %s N=%s B=%d" % (fam, [s.N for s in systems], b.B))
+    ids = [ctx.load_system(s, storage=k) for s, k in zip(systems, kinds)]
+    sids = np.array([ids[i] for i in b.system_index])
+    Ns = np.array([systems[i].N for i in b.system_index])
+    g = gpu_dp5(ctx, sids, Ns, b)
+    offs = np.concatenate([[0], np.cumsum(Ns)])
+    tol = 10 * RTOL if fam == "fp64" else 1e-4
+    worst = 0.0
+    for si, s in enumerate(systems):
+        idx = np.where(b.system_index == si)[0]
+        o = oracle.OracleSystem(s).propagate(b.subset(idx), method="dp5", rtol=RTOL, atol=RTOL,
+                                             max_steps=200000, h_min=1e-6)
+        for k, i in enumerate(idx):
+            worst = max(worst, np.max(np.abs(g["P"][offs[i]:offs[i + 1]] - o["P"][k])))
+            assert g["status"][i] & 1
+            assert abs(int(g["steps"][i]) - int(o["steps"][k])) <= 3 + 0.01 * o["steps"][k]
+    say("uneven mix %s max|dP| = %.3e" % (fam, worst))
+    assert worst < tol
+    for i in ids:
+        ctx.free_system(i)
+
+
+def test_dp5_failure_statuses(ctx):
+    (s,), b = S.config1(n_traj=2, jmax=2)
+    say("dp5 failure statuses N=9")
+    sid = ctx.load_system(s)
+    g = gpu_dp5(ctx, [sid] * 2, [s.N] * 2, b, max_steps=10)
+    assert np.all(g["status"] & 2) and np.all(g["steps"] == 10)
+    g = gpu_dp5(ctx, [sid] * 2, [s.N] * 2, b, rtol=1e-30, atol=1e-30, h_min=1e-3)
+    assert np.all(g["status"] & 4)
+    ctx.free_system(sid)
