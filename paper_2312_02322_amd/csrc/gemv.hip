@@ -661,15 +661,20 @@ struct Kern {
         const double sy_ = atol + rtol * fmax(fabs(y[r].y), fabs(y5.y));
         e2[0] += (ex / sx) * (ex / sx) + (ey / sy_) * (ey / sy_);
       }
-      block_sum<1, NW>(e2, lds.red1);
+      // The classical part reads kcl[0..3] (k1), which the accept branch below
+      // overwrites with k7: it must be read before the reduction's barrier, or
+      // a wave that is already past the barrier can replace k1 under a slower
+      // wave and the waves would disagree on accept/reject.
+      double ecl = 0.0;
       for (int i = 0; i < 4; ++i) {
         double e = 0.0;
         for (int q = 0; q < 7; ++q) e = fma(DP_E[q], kcl[q * 4 + i], e);
         e *= h;
         const double sc = atol + rtol * fmax(fabs(yc[i]), fabs(kcl[28 + i]));
-        e2[0] += (e / sc) * (e / sc);
+        ecl += (e / sc) * (e / sc);
       }
-      const double en = uni(sqrt(e2[0] / ncomp));
+      block_sum<1, NW>(e2, lds.red1);
+      const double en = uni(sqrt((e2[0] + ecl) / ncomp));
       if (!isfinite(en)) { status |= ST_NONFINITE; break; }
       if (en <= 1.0) {
         t += h;

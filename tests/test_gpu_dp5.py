@@ -33,7 +33,7 @@ def ctx(gpu_lib):
 
 def gpu_dp5(ctx, sids, Ns, batch, **kw):
     args = dict(init_channel=batch.init_channel, E_coll=batch.E_coll, b=batch.b, R0=batch.R0,
-                integrator="dp5", rtol=RTOL, atol=RTOL, max_steps=200000, h_min=1e-6)
+                integrator="dp5", rtol=RTOL, atol=RTOL, max_steps=50000, h_min=1e-6)
     args.update(kw)
     return ctx.run_host(sids, Ns, **args)
 
@@ -44,7 +44,7 @@ def test_dp5_fp64_matches_oracle(ctx):
     sid = ctx.load_system(s)
     g = gpu_dp5(ctx, [sid] * b.B, [s.N] * b.B, b)
     o = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=RTOL, atol=RTOL,
-                                         max_steps=200000, h_min=1e-6)
+                                         max_steps=50000, h_min=1e-6)
     P = g["P"].reshape(b.B, s.N)
     say("dp5 steps gpu %s oracle %s" % (g["steps"].tolist(), o["steps"].tolist()))
     assert np.all(g["status"] & 1) and np.all(o["status"] & 1)          # exited
@@ -91,7 +91,7 @@ def test_uneven_mixed_batch_one_launch(ctx, fam):
     for si, s in enumerate(systems):
         idx = np.where(b.system_index == si)[0]
         o = oracle.OracleSystem(s).propagate(b.subset(idx), method="dp5", rtol=RTOL, atol=RTOL,
-                                             max_steps=200000, h_min=1e-6)
+                                             max_steps=50000, h_min=1e-6)
         for k, i in enumerate(idx):
             worst = max(worst, np.max(np.abs(g["P"][offs[i]:offs[i + 1]] - o["P"][k])))
             assert g["status"][i] & 1
