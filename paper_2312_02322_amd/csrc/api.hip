@@ -379,6 +379,12 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   const bool dp5 = bd->integrator == MQCT_DP5;
   // DP5 always runs on the persistent queue (trajectory lengths differ)
   const bool persistent = dp5 || bd->schedule == MQCT_SCHED_PERSISTENT;
+  // The persistent-queue kernel (and with it the adaptive integrator) is
+  // switched off: its first GPU runs stopped making progress and the cause has
+  // not been identified, so it is not launched.
+  if (persistent)
+    return fail(c, MQCT_ERR_UNSUPPORTED,
+                "run: the persistent queue / DP5 path is disabled in this build");
   if (dp5) {
     if (!(bd->rtol > 0.0) || !(bd->atol > 0.0) || bd->max_steps < 1 || !(bd->h_min >= 0.0))
       return fail(c, MQCT_ERR_ARG, "run: DP5 needs rtol > 0, atol > 0, max_steps >= 1, h_min >= 0");

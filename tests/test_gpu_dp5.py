@@ -13,7 +13,12 @@ import pytest
 import oracle
 from synth import systems as S, units as U
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="persistent-queue / DP5 kernel disabled: its first GPU runs stopped "
+                            "making progress on the 8-trajectory N=49 case and the cause is not "
+                            "identified; the library returns MQCT_ERR_UNSUPPORTED for it"),
+]
 
 RTOL = 1e-8
 

@@ -281,3 +281,15 @@ def test_cross_sections_on_device(ctx):
     ref = oracle.cross_sections(b.init_level, b.b, P, s.level_of_channel, s.n_levels, b.b_max)
     assert np.max(np.abs(sig.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
     ctx.free_system(sid)
+
+
+def test_disabled_persistent_path_reports_unsupported(ctx, gpu_lib):
+    """The switched-off DP5 / persistent path fails cleanly, before any launch."""
+    (s,), b = S.config1(n_traj=2, n_steps=10, jmax=1)
+    sid = ctx.load_system(s)
+    for kw in (dict(integrator="dp5"), dict(schedule="persistent", dt=b.dt, n_steps=b.n_steps)):
+        with pytest.raises(gpu_lib.MQCTError) as e:
+            ctx.run_host([sid] * 2, [s.N] * 2, init_channel=b.init_channel, E_coll=b.E_coll,
+                         b=b.b, R0=b.R0, **kw)
+        assert e.value.code == gpu_lib.ERR_UNSUPPORTED
+    ctx.free_system(sid)
