@@ -41,7 +41,7 @@ struct mqct_context {
   std::vector<SysHost> systems;
   DevSystem* d_systems = nullptr;
   size_t d_systems_cap = 0;
-  DevBuf traj, a0, outs[10], xs[4], kscratch, counter;
+  DevBuf traj, a0, outs[10], xs[4], kscratch, counter, binws;
   TrajIn* h_traj = nullptr;        // pinned staging for trajectory records
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
@@ -154,7 +154,7 @@ void mqct_destroy(mqct_context* c) {
   for (auto& s : c->systems) free_system(s);
   if (c->d_systems) hipFree(c->d_systems);
   DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3],
-                   &c->kscratch, &c->counter};
+                   &c->kscratch, &c->counter, &c->binws};
   for (DevBuf* b : all) if (b->p) hipFree(b->p);
   for (auto& b : c->outs) if (b.p) hipFree(b.p);
   if (c->h_traj) hipHostFree(c->h_traj);
@@ -374,8 +374,14 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     return fail(c, MQCT_ERR_ARG, "run: unknown integrator %d", bd->integrator);
   if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_PERSISTENT)
     return fail(c, MQCT_ERR_ARG, "run: unknown schedule %d", bd->schedule);
-  if (bd->schedule == MQCT_SCHED_BINNED)
-    return fail(c, MQCT_ERR_UNSUPPORTED, "run: the binned schedule is not available in this build");
+  const bool binned = bd->schedule == MQCT_SCHED_BINNED;
+  if (binned && bd->integrator != MQCT_RK4)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run: the binned schedule steps in lockstep (RK4 only)");
+  if (binned) {
+    for (int64_t b = 1; b < B; ++b)
+      if (bd->system_id[b] != bd->system_id[0])
+        return fail(c, MQCT_ERR_UNSUPPORTED, "run: a binned batch must use a single system");
+  }
   const bool dp5 = bd->integrator == MQCT_DP5;
   // DP5 always runs on the persistent queue (trajectory lengths differ)
   const bool persistent = dp5 || bd->schedule == MQCT_SCHED_PERSISTENT;
@@ -543,7 +549,16 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   out.status = (int32_t*)dp[6]; out.norm_err = (double*)dp[7]; out.energy_err = (double*)dp[8];
   out.angmom_err = (double*)dp[9];
 
-  if (!persistent) {
+  if (binned) {
+    const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
+    int64_t max_steps = 0;
+    for (int64_t b = 0; b < B; ++b) max_steps = std::max(max_steps, c->h_traj[b].n_steps);
+    const size_t wsb = binned_workspace_bytes((int)B, hs.Npad, hs.K, dtype_fp32(hs.dtype));
+    if ((st = ensure(c, c->binws, wsb, "run: binned workspace")) != MQCT_OK) return st;
+    hipError_t e = run_binned(c->d_systems, hs, (const TrajIn*)c->traj.p, (int)B, max_steps,
+                              d_a0, out, c->binws.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "run: binned launch");
+  } else if (!persistent) {
     for (int d = 0; d < 4; ++d) {
       int64_t n = ranges[d].second - ranges[d].first;
       if (n == 0) continue;

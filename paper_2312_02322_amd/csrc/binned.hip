@@ -1,0 +1,547 @@
+// R-binned lockstep schedule for fixed-step RK4 on matrix cores.
+//
+// Every trajectory of the batch advances stage by stage in lockstep.  At each
+// stage a trajectory at separation R in spline interval k needs four table
+// slices, M_k, M_{k+1}, M2_k, M2_{k+1} (the natural cubic spline of the
+// coupling matrix, paper Section III).  Grouping trajectories by knot rather
+// than by interval ("grid-point-centric" bins) lets knot g serve both the
+// trajectories of interval g (as left knot) and of interval g-1 (as right
+// knot): each knot's slices M_g, M2_g are then read once per stage and multiply
+// all amplitude columns of its bin, a dense table x columns product that runs on
+// the MFMA units.  The spline weights differ per column (every trajectory has
+// its own R), so they are applied in the product's epilogue.
+//
+// Complex products as one real product: with a row of the stored table read as
+// 2N interleaved reals (re, im, re, im, ...), Re(M c)_n is that row dotted with
+// (Re c_0, -Im c_0, Re c_1, -Im c_1, ...) and Im(M c)_n with (Im c_0, Re c_0,
+// ...); each trajectory therefore contributes two real columns and the table
+// is read exactly as stored.
+//
+// Per stage: prep (stage state, interval, weights, phases, c columns, bin
+// counts) -> scan (bin offsets and GEMM work list) -> scatter (bin lists) ->
+// gemm (per knot and 32-trajectory tile) -> combine (J_x, force, torque,
+// derivatives, RK4 accumulation).  The right-hand side is the same as the
+// per-trajectory kernels' (Eqs. 5 and 7-10).
+#include "device.h"
+
+#include <math.h>
+
+namespace mqct {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int TB = 32;     // trajectories per GEMM work item (64 real columns)
+constexpr int NT = 256;    // threads of the per-trajectory kernels
+constexpr int NWT = NT / 64;
+
+struct BinWS {
+  int B, N, Npad, K;
+  const TrajIn* traj;     // [B], batch order
+  double2* a0;            // [B][Npad] amplitudes at the start of the step
+  double2* kv;            // [B][Npad] derivative of the last stage
+  double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
+  double2* c64;           // [B][Npad] c = e^{-iEt} a at the current stage, FP64
+  void* cst;              // [B][Npad] c in the table precision (aliases c64 for FP64)
+  double4* uv;            // [2][B][Npad] (Re u, Im u, Re v, Im v) from the left / right knot
+  double* ycl;            // [B][4] R, Phi, P_R, P_Phi at the start of the step
+  double* kcl;            // [B][4] classical derivative of the last stage
+  double* acl;            // [B][4] classical accumulator
+  double* ysb;            // [B][4] classical stage state
+  double* wts;            // [B][8] spline weights w0..w3, d0..d3 at the stage
+  double* tst;            // [B] stage time
+  double* diag;           // [B][4] E0, J0, Theta, P_Theta
+  int* kb;                // [B] interval of the stage, -1 when inactive
+  int* status;            // [B]
+  int* done;              // [B] steps completed when stopped early, else -1
+  int* cnt;               // [K] bin sizes
+  int* cursor;            // [K]
+  int* offset;            // [K]
+  int* list;              // [2B] bin entries 2 b + side (0: left knot, 1: right knot)
+  int4* items;            // [max_items] (knot, first entry, count, 0)
+  int* n_items;           // [1]
+};
+
+__device__ __forceinline__ double stage_frac(int st) {
+  return st == 0 ? 0.0 : (st == 3 ? 1.0 : 0.5);
+}
+
+__global__ void __launch_bounds__(NT)
+bin_init(BinWS ws, const DevSystem* __restrict__ systems, const double* __restrict__ a0_all) {
+  const int b = blockIdx.x;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  for (int n = threadIdx.x; n < Npad; n += NT) {
+    double2 v = make_double2(0.0, 0.0);
+    if (n < N) {
+      if (tj.flags & TRAJ_HAS_A0) v = ((const double2*)a0_all)[tj.amp_off + n];
+      else if (n == tj.init_channel) v = make_double2(1.0, 0.0);
+    }
+    const int64_t o = (int64_t)b * Npad + n;
+    ws.a0[o] = v;
+    ws.kv[o] = make_double2(0.0, 0.0);
+    ws.acc[o] = make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x == 0) {
+    double y[4], theta = 0.5 * M_PI, ptheta = 0.0;
+    if (tj.flags & TRAJ_HAS_C0) {
+      y[0] = tj.c0[0]; theta = tj.c0[1]; y[1] = tj.c0[2]; y[2] = tj.c0[3]; ptheta = tj.c0[4];
+      y[3] = tj.c0[5];
+    } else {
+      const double k = sqrt(2.0 * sy.mu * tj.E_coll);
+      const double pphi = tj.b * k;
+      y[0] = tj.R0; y[1] = 0.0;
+      y[2] = -sqrt(2.0 * sy.mu * tj.E_coll - pphi * pphi / (tj.R0 * tj.R0));
+      y[3] = pphi;
+    }
+    for (int i = 0; i < 4; ++i) {
+      ws.ycl[b * 4 + i] = y[i];
+      ws.kcl[b * 4 + i] = 0.0;
+      ws.acl[b * 4 + i] = 0.0;
+    }
+    ws.diag[b * 4 + 2] = theta;
+    ws.diag[b * 4 + 3] = ptheta;
+    ws.status[b] = 0;
+    ws.done[b] = -1;
+  }
+}
+
+__global__ void bin_zero(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Stage state of every trajectory: classical stage values, interval and
+// weights, phases and the c columns; adds the trajectory to the counts of its
+// two knots.  diag = 1: the final diagnostic evaluation at the end state.
+template <typename CS>
+__global__ void __launch_bounds__(NT)
+bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag) {
+  const int b = blockIdx.x;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const int dn = ws.done[b];
+  const bool active = diag || (j < tj.n_steps && dn < 0);
+  if (!active) {
+    if (threadIdx.x == 0) ws.kb[b] = -1;
+    return;
+  }
+  const double h = tj.dt;
+  const double cf = diag ? 0.0 : stage_frac(st) * h;
+  const int64_t jsteps = diag ? (dn >= 0 ? (int64_t)dn : tj.n_steps) : j;
+  const double t = tj.t0 + (double)jsteps * h + cf;
+  double ys[4];
+  for (int i = 0; i < 4; ++i) ys[i] = fma(cf, ws.kcl[b * 4 + i], ws.ycl[b * 4 + i]);
+  const Spl sp = spline_at(sy.R, sy.K, ys[0]);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) ws.ysb[b * 4 + i] = ys[i];
+    double* w = ws.wts + (int64_t)b * 8;
+    w[0] = sp.w0; w[1] = sp.w1; w[2] = sp.w2; w[3] = sp.w3;
+    w[4] = sp.d0; w[5] = sp.d1; w[6] = sp.d2; w[7] = sp.d3;
+    ws.tst[b] = t;
+    ws.kb[b] = sp.k;
+    atomicAdd(&ws.cnt[sp.k], 1);
+    atomicAdd(&ws.cnt[sp.k + 1], 1);
+    if (sp.below && !diag) ws.status[b] |= ST_BELOW_GRID;
+  }
+  CS* cst = (CS*)ws.cst;
+  for (int n = threadIdx.x; n < Npad; n += NT) {
+    const int64_t o = (int64_t)b * Npad + n;
+    double2 c = make_double2(0.0, 0.0);
+    if (n < N) {
+      const double2 a = ws.a0[o], k = ws.kv[o];
+      const double2 cur = make_double2(fma(cf, k.x, a.x), fma(cf, k.y, a.y));
+      double sn, cs;
+      sincos(sy.E[n] * t, &sn, &cs);
+      c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+    }
+    ws.c64[o] = c;
+    if constexpr (sizeof(CS) == 8) cst[o] = make_float2((float)c.x, (float)c.y);
+  }
+}
+
+// Bin offsets and the GEMM work list; resets the counters for the next stage.
+__global__ void __launch_bounds__(1024) bin_scan(BinWS ws) {
+  const int K = ws.K;
+  __shared__ int ioff_s[2049];
+  if (threadIdx.x == 0) {
+    int off = 0, io = 0;
+    for (int g = 0; g < K; ++g) {
+      const int c = ws.cnt[g];
+      ws.offset[g] = off;
+      ioff_s[g] = io;
+      off += c;
+      io += (c + TB - 1) / TB;
+    }
+    ioff_s[K] = io;
+    *ws.n_items = io;
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < K; g += blockDim.x) {
+    const int c = ws.cnt[g];
+    const int base = ioff_s[g];
+    for (int q = 0; q * TB < c; ++q)
+      ws.items[base + q] = make_int4(g, ws.offset[g] + q * TB, min(TB, c - q * TB), 0);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < K; g += blockDim.x) {
+    ws.cnt[g] = 0;
+    ws.cursor[g] = 0;
+  }
+}
+
+__global__ void bin_scatter(BinWS ws) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ws.B) return;
+  const int k = ws.kb[b];
+  if (k < 0) return;
+  const int p0 = atomicAdd(&ws.cursor[k], 1);
+  ws.list[ws.offset[k] + p0] = 2 * b;
+  const int p1 = atomicAdd(&ws.cursor[k + 1], 1);
+  ws.list[ws.offset[k + 1] + p1] = 2 * b + 1;
+}
+
+template <typename S> struct MF;
+template <> struct MF<float> {
+  using V = v4f;
+  __device__ static V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MF<double> {
+  using V = v4d;
+  __device__ static V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// Four consecutive reals of a stored table row (row >= N lies past the slice
+// and reads as zero).
+template <typename S>
+__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t off, S (&o)[4]) {
+  if constexpr (sizeof(S) == 4) {
+    const float4 v = load16<float4>(r, off);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else {
+    const double2 v0 = load16<double2>(r, off), v1 = load16<double2>(r, off + 16);
+    o[0] = v0.x; o[1] = v0.y; o[2] = v1.x; o[3] = v1.y;
+  }
+}
+
+// One work item (knot g, up to 32 trajectories of its bin) x a tile of rows.
+// Wave w owns RB 16-row blocks; every lane holds, for each of 4 column blocks
+// of 16 real columns (8 trajectories), the 16x16 accumulators of both slices
+// (v_mfma_*_16x16x4: lane l supplies A[l%16][k] and B[k][l%16] with
+// k = l/16; its D values are column l%16, rows 4(l/16)+r for the f32 form
+// and l/16+4r for the f64 form).  Along K each lane loads four
+// consecutive reals, and the four MFMAs of one step take k = k0 + 4(l/16) + i,
+// i = 0..3, on both operands (a permutation of K).
+template <int DT>
+__global__ void __launch_bounds__(256)
+bin_gemm(BinWS ws, const DevSystem* __restrict__ systems) {
+  constexpr bool FP32 = (DT == C64 || DT == R32);
+  constexpr bool CPLX = (DT == C64 || DT == C128);
+  using S = typename std::conditional<FP32, float, double>::type;
+  using CS = typename std::conditional<FP32, float2, double2>::type;
+  using V = typename MF<S>::V;
+  constexpr int RB = FP32 ? 2 : 1;
+  constexpr int NCOMP = CPLX ? 2 : 1;
+  const int item = blockIdx.y;
+  if (item >= *ws.n_items) return;
+  const int4 it = ws.items[item];
+  const int g = it.x, start = it.y, count = it.z;
+  const DevSystem sy = systems[ws.traj[0].sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int row0 = blockIdx.x * (4 * RB * 16) + wave * RB * 16;
+  const int64_t ks = sy.knot_stride;
+  const uint32_t sbytes = (uint32_t)(ks * NCOMP * (int64_t)sizeof(S));
+  const auto rA = slice_rsrc((const S*)sy.M + (int64_t)g * ks * NCOMP, sbytes);
+  const auto rB = slice_rsrc((const S*)sy.M2 + (int64_t)g * ks * NCOMP, sbytes);
+  const uint32_t rowbytes = (uint32_t)(Npad * NCOMP * sizeof(S));
+
+  // this lane's trajectory in each column block and which real column it is
+  const CS* cols[4];
+  int part[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int jt = (cb * 16 + c16) >> 1;
+    const int e = ws.list[start + (jt < count ? jt : 0)];
+    cols[cb] = (const CS*)ws.cst + (int64_t)(e >> 1) * Npad;
+    part[cb] = c16 & 1;
+  }
+  V acc[RB][2][4];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[r][s][cb] = V{0, 0, 0, 0};
+
+  const int KR = Npad * NCOMP;   // real K extent (zero-padded past N)
+  for (int k0 = 0; k0 < KR; k0 += 16) {
+    const int kq = k0 + 4 * q;
+    S a[RB][2][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const uint32_t off = (uint32_t)(row0 + r * 16 + c16) * rowbytes + (uint32_t)kq * sizeof(S);
+      load4<S>(rA, off, a[r][0]);
+      load4<S>(rB, off, a[r][1]);
+    }
+    S bv[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if constexpr (CPLX) {
+        const CS c0 = cols[cb][kq >> 1], c1 = cols[cb][(kq >> 1) + 1];
+        if (part[cb] == 0) { bv[cb][0] = c0.x; bv[cb][1] = -c0.y; bv[cb][2] = c1.x; bv[cb][3] = -c1.y; }
+        else { bv[cb][0] = c0.y; bv[cb][1] = c0.x; bv[cb][2] = c1.y; bv[cb][3] = c1.x; }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const CS c = cols[cb][kq + i];
+          bv[cb][i] = part[cb] == 0 ? c.x : c.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[r][s][cb] = MF<S>::mfma(a[r][s][i], bv[cb][i], acc[r][s][cb]);
+  }
+
+  // epilogue: apply this column's spline weights (left or right knot)
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int jt = (cb * 16 + c16) >> 1;
+    if (jt >= count) continue;
+    const int e = ws.list[start + jt];
+    const int b = e >> 1, side = e & 1, p = part[cb];
+    const double* w = ws.wts + (int64_t)b * 8;
+    const double wA = side ? w[1] : w[0], wB = side ? w[3] : w[2];
+    const double dA = side ? w[5] : w[4], dB = side ? w[7] : w[6];
+    double* o = (double*)(ws.uv + ((int64_t)side * ws.B + b) * Npad);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // D rows of lane group q: 4q + i (f32 form), q + 4i (f64 form)
+        const int n = row0 + r * 16 + (FP32 ? 4 * q + i : q + 4 * i);
+        if (n < N) {
+          const double z = (double)acc[r][0][cb][i], z2 = (double)acc[r][1][cb][i];
+          o[(int64_t)n * 4 + p] = wA * z + wB * z2;
+          o[(int64_t)n * 4 + 2 + p] = dA * z + dB * z2;
+        }
+      }
+  }
+}
+
+// Combine the two knots' contributions, add the Coriolis term, reduce the
+// mean-field force and torque, and advance the RK4 accumulators.
+__global__ void __launch_bounds__(NT)
+bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag,
+            TrajOut out) {
+  __shared__ double red[NWT * 8];
+  const int b = blockIdx.x;
+  if (ws.kb[b] < 0) return;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const double mu = sy.mu, h = tj.dt;
+  const double cf = diag ? 0.0 : stage_frac(st) * h;
+  double ys[4];
+  for (int i = 0; i < 4; ++i) ys[i] = ws.ysb[b * 4 + i];
+  const double t = ws.tst[b];
+  const double R = ys[0];
+  const double phidot = ys[3] / (mu * R * R);
+  const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+  double sums[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int n = threadIdx.x; n < N; n += NT) {
+    const int64_t o = (int64_t)b * Npad + n;
+    const double4 L = ws.uv[o], Rr = ws.uv[(int64_t)ws.B * Npad + o];
+    const double2 u = make_double2(L.x + Rr.x, L.y + Rr.y);
+    const double2 v = make_double2(L.z + Rr.z, L.w + Rr.w);
+    const double2 c = ws.c64[o];
+    double2 xc = make_double2(0.0, 0.0);
+    for (int qq = 0; qq < sy.jx_w; ++qq) {
+      const int col = sy.jx_col[(int64_t)n * sy.jx_w + qq];
+      const double jv = sy.jx_val[(int64_t)n * sy.jx_w + qq];
+      const double2 cm = ws.c64[(int64_t)b * Npad + col];
+      xc.x = fma(jv, cm.x, xc.x);
+      xc.y = fma(jv, cm.y, xc.y);
+    }
+    const double2 a = ws.a0[o], kold = ws.kv[o];
+    const double2 cur = make_double2(fma(cf, kold.x, a.x), fma(cf, kold.y, a.y));
+    sums[0] += c.x * v.x + c.y * v.y;
+    sums[1] += xc.x * u.y - xc.y * u.x;
+    sums[2] += c.x * u.x + c.y * u.y;
+    const double pn = cur.x * cur.x + cur.y * cur.y;
+    sums[3] += sy.E[n] * pn;
+    sums[4] += pn;
+    sums[5] += c.x * xc.x + c.y * xc.y;
+    if (!diag) {
+      double sn, cs;
+      sincos(sy.E[n] * t, &sn, &cs);
+      const double gx = u.x + phidot * xc.x, gy = u.y + phidot * xc.y;
+      const double yx = cs * gx - sn * gy, yy = cs * gy + sn * gx;
+      const double2 k = make_double2(yy, -yx);
+      double2 ac = st == 0 ? make_double2(0.0, 0.0) : ws.acc[o];
+      ac.x = fma(wgt, k.x, ac.x);
+      ac.y = fma(wgt, k.y, ac.y);
+      ws.kv[o] = k;
+      if (st == 3) {
+        const double h6 = h / 6.0;
+        ws.a0[o] = make_double2(a.x + h6 * ac.x, a.y + h6 * ac.y);
+      } else {
+        ws.acc[o] = ac;
+      }
+    }
+  }
+  block_sum<6, NWT>(sums, red);
+  const double force = sums[0], torque = sums[1], vexp = sums[2], erot = sums[3];
+  const double norm = sums[4], jx = sums[5];
+  const double E = ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * R * R) + erot + vexp;
+  if (diag) {
+    const int64_t steps = ws.done[b] >= 0 ? (int64_t)ws.done[b] : tj.n_steps;
+    for (int n = threadIdx.x; n < N; n += NT) {
+      const double2 a = ws.a0[(int64_t)b * Npad + n];
+      out.P[tj.amp_off + n] = a.x * a.x + a.y * a.y;
+      if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a;
+    }
+    if (threadIdx.x == 0) {
+      const int64_t id = tj.id;
+      if (out.classical) {
+        double* o = out.classical + id * 6;
+        o[0] = ys[0]; o[1] = ws.diag[b * 4 + 2]; o[2] = ys[1]; o[3] = ys[2];
+        o[4] = ws.diag[b * 4 + 3]; o[5] = ys[3];
+      }
+      if (out.t_final) out.t_final[id] = t;
+      if (out.steps) out.steps[id] = steps;
+      if (out.rejects) out.rejects[id] = 0;
+      if (out.status) out.status[id] = ws.status[b];
+      if (out.norm_err) out.norm_err[id] = norm - 1.0;
+      if (out.energy_err) {
+        const double E0 = steps > 0 ? ws.diag[b * 4] : E;
+        out.energy_err[id] = (E - E0) / fabs(E0);
+      }
+      if (out.angmom_err) {
+        const double J0 = steps > 0 ? ws.diag[b * 4 + 1] : ys[3] - jx;
+        out.angmom_err[id] = (ys[3] - jx) - J0;
+      }
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    if (j == 0 && st == 0) {
+      ws.diag[b * 4] = E;
+      ws.diag[b * 4 + 1] = ys[3] - jx;
+    }
+    const double kc[4] = {ys[2] / mu, phidot, -force + ys[3] * ys[3] / (mu * R * R * R),
+                          2.0 * torque};
+    for (int i = 0; i < 4; ++i) {
+      const double ac = (st == 0 ? 0.0 : ws.acl[b * 4 + i]) + wgt * kc[i];
+      ws.kcl[b * 4 + i] = kc[i];
+      if (st == 3) ws.ycl[b * 4 + i] += h / 6.0 * ac;
+      else ws.acl[b * 4 + i] = ac;
+    }
+    if (st == 3) {
+      bool ok = isfinite(force) && isfinite(torque) && isfinite(norm);
+      for (int i = 0; i < 4; ++i) ok = ok && isfinite(ws.ycl[b * 4 + i]);
+      if (!ok) {
+        ws.status[b] |= ST_NONFINITE;
+        ws.done[b] = (int)(j + 1);
+      }
+    }
+  }
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
+  const size_t v = (size_t)B * Npad;
+  size_t s = 0;
+  s += 4 * al(v * 16);                    // a0, kv, acc, c64
+  s += fp32 ? al(v * 8) : 0;              // cst
+  s += al(2 * v * 32);                    // uv
+  s += 4 * al((size_t)B * 32);            // ycl kcl acl ysb
+  s += al((size_t)B * 64) + al((size_t)B * 8) + al((size_t)B * 32);   // wts tst diag
+  s += 3 * al((size_t)B * 4);             // kb status done
+  s += 3 * al((size_t)K * 4);             // cnt cursor offset
+  s += al((size_t)2 * B * 4);             // list
+  s += al(((size_t)2 * B / TB + K + 1) * 16) + al(16);   // items, n_items
+  return s;
+}
+
+hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                      int B, int64_t max_steps, const double* d_a0, TrajOut out, void* wsp,
+                      hipStream_t s) {
+  const bool fp32 = dtype_fp32(hs.dtype);
+  BinWS ws;
+  ws.B = B; ws.N = hs.N; ws.Npad = hs.Npad; ws.K = hs.K;
+  ws.traj = d_traj;
+  char* p = (char*)wsp;
+  auto take = [&](size_t bytes) { void* q = p; p += al(bytes); return q; };
+  const size_t v = (size_t)B * hs.Npad;
+  ws.a0 = (double2*)take(v * 16);
+  ws.kv = (double2*)take(v * 16);
+  ws.acc = (double2*)take(v * 16);
+  ws.c64 = (double2*)take(v * 16);
+  ws.cst = fp32 ? take(v * 8) : (void*)ws.c64;
+  ws.uv = (double4*)take(2 * v * 32);
+  ws.ycl = (double*)take((size_t)B * 32);
+  ws.kcl = (double*)take((size_t)B * 32);
+  ws.acl = (double*)take((size_t)B * 32);
+  ws.ysb = (double*)take((size_t)B * 32);
+  ws.wts = (double*)take((size_t)B * 64);
+  ws.tst = (double*)take((size_t)B * 8);
+  ws.diag = (double*)take((size_t)B * 32);
+  ws.kb = (int*)take((size_t)B * 4);
+  ws.status = (int*)take((size_t)B * 4);
+  ws.done = (int*)take((size_t)B * 4);
+  ws.cnt = (int*)take((size_t)hs.K * 4);
+  ws.cursor = (int*)take((size_t)hs.K * 4);
+  ws.offset = (int*)take((size_t)hs.K * 4);
+  ws.list = (int*)take((size_t)2 * B * 4);
+  const int max_items = 2 * B / TB + hs.K + 1;
+  ws.items = (int4*)take((size_t)max_items * 16);
+  ws.n_items = (int*)take(16);
+
+  const bool cplx = dtype_complex(hs.dtype);
+  const int rows_per_block = (fp32 ? 2 : 1) * 4 * 16;
+  const dim3 ggrid((hs.N + rows_per_block - 1) / rows_per_block, max_items);
+  hipError_t e;
+  bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
+  bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cnt, hs.K);
+  bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cursor, hs.K);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  auto stage = [&](int64_t j, int st, int diag) -> hipError_t {
+    if (fp32) bin_prep<float2><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    else bin_prep<double2><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    bin_scan<<<1, 1024, 0, s>>>(ws);
+    bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
+    if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    else bin_gemm<R64><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    bin_combine<<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
+    return hipGetLastError();
+  };
+  (void)cplx;
+  for (int64_t j = 0; j < max_steps; ++j)
+    for (int st = 0; st < 4; ++st)
+      if ((e = stage(j, st, 0)) != hipSuccess) return e;
+  return stage(max_steps, 0, 1);
+}
+
+}  // namespace mqct

@@ -27,7 +27,7 @@
 // multiply in FP32 and accumulate in FP32 over chunks of 64 stored rows, then
 // add the chunk sums into FP64; phases (E t), spline weights, the classical
 // state and every RK accumulator stay FP64.
-#include "internal.h"
+#include "device.h"
 
 #include <math.h>
 
@@ -69,101 +69,6 @@ __constant__ double DP_A[7][6] = {
 __constant__ double DP_E[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
                                -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
 
-// Spline interval and weights at R (natural cubic spline on knots x[0..K-1]):
-// value = w0 y_k + w1 y_{k+1} + w2 y2_k + w3 y2_{k+1}; derivative with d0..d3.
-// Above the last knot the value is held and the slope is zero; below the first
-// knot the spline is continued linearly (and the trajectory flagged).
-struct Spl {
-  int k;
-  bool below;
-  double w0, w1, w2, w3, d0, d1, d2, d3;
-};
-
-__device__ __forceinline__ Spl spline_at(const double* __restrict__ x, int K, double R) {
-  Spl s;
-  s.below = R < x[0];
-  if (R > x[K - 1]) {
-    s.k = K - 2;
-    s.w0 = 0.0; s.w1 = 1.0; s.w2 = 0.0; s.w3 = 0.0;
-    s.d0 = 0.0; s.d1 = 0.0; s.d2 = 0.0; s.d3 = 0.0;
-    return s;
-  }
-  int lo = 0;
-  if (!s.below) {
-    int hi = K - 2;           // largest k in [0, K-2] with x[k] <= R
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (x[mid] <= R) lo = mid; else hi = mid - 1;
-    }
-  }
-  s.k = lo;
-  const double h = x[lo + 1] - x[lo];
-  if (s.below) {
-    const double dR = R - x[0];
-    s.d0 = -1.0 / h; s.d1 = 1.0 / h; s.d2 = -2.0 * h / 6.0; s.d3 = -h / 6.0;
-    s.w0 = 1.0 + dR * s.d0; s.w1 = dR * s.d1; s.w2 = dR * s.d2; s.w3 = dR * s.d3;
-    return s;
-  }
-  const double A = (x[lo + 1] - R) / h, B = 1.0 - A;
-  s.w0 = A; s.w1 = B;
-  s.w2 = (A * A * A - A) * (h * h / 6.0);
-  s.w3 = (B * B * B - B) * (h * h / 6.0);
-  s.d0 = -1.0 / h; s.d1 = 1.0 / h;
-  s.d2 = -(3.0 * A * A - 1.0) * (h / 6.0);
-  s.d3 = (3.0 * B * B - 1.0) * (h / 6.0);
-  return s;
-}
-
-// Buffer resource over one knot slice of a table: the base and size live in
-// scalar registers and every lane supplies only a 32-bit byte offset (a knot
-// slice is far below 4 GiB).  Reads past `bytes` return zero.  Lanes load 16
-// bytes (8 for real FP32 tables, which serve small systems).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void* p, uint32_t bytes) {
-  uint64_t v = (uint64_t)p;
-  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  void* q = (void*)(((uint64_t)hi << 32) | lo);
-  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, (int)bytes, 0x00020000);
-}
-
-template <typename L>
-__device__ __forceinline__ L load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  if constexpr (sizeof(L) == 16)
-    return __builtin_bit_cast(L, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-  else
-    return __builtin_bit_cast(L, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-
-__device__ __forceinline__ double uni(double x) {
-  // the value is identical in every lane: keep it in scalar registers
-  int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-  int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
-// Sum NV values over the workgroup: wave shuffles, then one LDS slot per wave
-// read back in a fixed order (deterministic, identical in every lane).  `red`
-// must not be reused by another reduction before a barrier separates them.
-template <int NV, int NW>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[w * 8 + i] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) s += red[q * 8 + i];
-    v[i] = uni(s);
-  }
-}
 
 // Sums produced by one right-hand-side evaluation.
 struct Sums {

@@ -101,6 +101,12 @@ hipError_t launch_persistent(const DevSystem* d_systems, const TrajIn* d_traj, i
 // Resident workgroups of the persistent kernel on the current device.
 int64_t persistent_slots(bool fp32_family, int max_groups, int max_npad);
 
+// R-binned lockstep RK4 (all trajectories on one system, d_traj in any order).
+size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32);
+hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                      int B, int64_t max_steps, const double* d_a0, TrajOut out, void* ws,
+                      hipStream_t s);
+
 // Cross sections on the device.
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
                        const int32_t* level_of_channel, int n_levels, double b_max,

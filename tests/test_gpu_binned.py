@@ -1,0 +1,107 @@
+"""GPU parity of the R-binned lockstep schedule (matrix-core products per knot).
+
+Same bars as the per-trajectory kernels: FP64 tables within 1e-9 of the oracle,
+FP32 tables within 1e-4.  At the full N = 969 size of the benchmark the binned
+and per-trajectory schedules are compared on the whole 4096-trajectory batch
+and the oracle checks a sample of trajectories.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import systems as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context()
+    yield c
+    c.synchronize()
+    c.close()
+
+
+def run(ctx, sid, s, b, schedule, **kw):
+    args = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt,
+                n_steps=b.n_steps, schedule=schedule)
+    args.update(kw)
+    g = ctx.run_host([sid] * b.B, [s.N] * b.B, **args)
+    g["P"] = g["P"].reshape(b.B, s.N)
+    g["a_final"] = g["a_final"].reshape(b.B, s.N)
+    return g
+
+
+def test_binned_config1_fp64(ctx):
+    (s,), b = S.config1()
+    say("binned config1 N=49 B=64 2000 steps R64")
+    sid = ctx.load_system(s)
+    g = run(ctx, sid, s, b, "binned")
+    o = oracle.OracleSystem(s).propagate(b)
+    assert np.max(np.abs(g["P"] - o["P"])) < 1e-9
+    assert np.max(np.abs(g["classical"] - o["classical"]) / (1 + np.abs(o["classical"]))) < 1e-9
+    assert np.max(np.abs(g["energy_err"] - o["energy_err"])) < 1e-9
+    assert np.max(np.abs(g["angmom_err"] - o["angmom_err"])) < 1e-9
+    assert np.array_equal(g["steps"], b.n_steps) and np.all(g["status"] == 0)
+    ctx.free_system(sid)
+
+
+def test_binned_config2_reduced(ctx):
+    (s,), b = S.config2(n_traj=6, jmax=3)
+    b.n_steps[:] = np.minimum(b.n_steps, 2500)
+    say("binned config2 reduced N=84 C128 and C64")
+    o = oracle.OracleSystem(s).propagate(b)
+    sid = ctx.load_system(s, storage="C128")
+    g = run(ctx, sid, s, b, "binned")
+    assert np.max(np.abs(g["P"] - o["P"])) < 1e-9
+    ctx.free_system(sid)
+    sid = ctx.load_system(s, storage="C64")
+    g = run(ctx, sid, s, b, "binned")
+    err = np.max(np.abs(g["P"] - o["P"]))
+    say("binned config2 reduced fp32 max|dP| = %.3e" % err)
+    assert err < 1e-4
+    ctx.free_system(sid)
+
+
+def test_binned_config4_and_ragged_steps(ctx):
+    (s,), b = S.config4(n_traj=5, n_steps=500)
+    b.n_steps[:] = [500, 120, 0, 333, 499]
+    say("binned config4 N=256 R64 ragged steps")
+    o = oracle.OracleSystem(s).propagate(b)
+    sid = ctx.load_system(s)
+    g = run(ctx, sid, s, b, "binned")
+    assert np.array_equal(g["steps"], b.n_steps)
+    assert np.max(np.abs(g["P"] - o["P"])) < 1e-9
+    assert np.max(np.abs(g["t_final"] - o["t_final"])) < 1e-9 * np.max(o["t_final"])
+    ctx.free_system(sid)
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    return S.config2(n_traj=4096, full_collision=False, window_steps=2)
+
+
+@pytest.mark.parametrize("storage", ["C128", "C64"])
+def test_binned_full_size_bench_population(ctx, full_size, storage):
+    """N = 969, 4096 mid-collision trajectories (the benchmark's launch), 2 RK4 steps."""
+    (s,), b = full_size
+    say("full-size N=969 B=4096 %s: binned vs per-trajectory" % storage)
+    sid = ctx.load_system(s, storage=storage)
+    gb = run(ctx, sid, s, b, "binned")
+    gg = run(ctx, sid, s, b, "gemv")
+    d = np.max(np.abs(gb["P"] - gg["P"]))
+    say("full-size %s max|P_binned - P_gemv| = %.3e" % (storage, d))
+    assert d < (1e-12 if storage == "C128" else 1e-5)
+    ctx.free_system(sid)
+    sample = [0, 1, 2047, 4095]
+    o = oracle.OracleSystem(s).propagate(b.subset(sample))
+    tol = 1e-9 if storage == "C128" else 1e-4
+    assert np.max(np.abs(gb["P"][sample] - o["P"])) < tol
+    assert np.max(np.abs(gg["P"][sample] - o["P"])) < tol
