@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("trajectory-steps/s × N² (coupling GB/s), FP32 vs FP64 at "
           "ΔP≤1e-4; adjoint s/grad")
 HBM_PEAK_GBPS = 8000.0
+MFMA_PEAK_TFLOPS = {"C64": 157.3, "C128": 78.6}   # dense FP32 / FP64 matrix peaks
 
 # HBM bytes per launch of the step kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs scaled by the same counters on a plain 1 GiB copy (profiles/
@@ -50,6 +51,7 @@ def main():
     ap.add_argument("--traj", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["C64", "C128"], default=None)
+    ap.add_argument("--schedule", choices=["gemv", "binned", "both"], default="both")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -75,7 +77,9 @@ def main():
     dev = ctx.device
     results = {}
     P_of = {}
-    for storage in ([args.only] if args.only else ["C64", "C128"]):
+    storages = [args.only] if args.only else ["C64", "C128"]
+    schedules = [args.schedule] if args.schedule != "both" else ["gemv", "binned"]
+    for storage in storages:
         t0 = time.time()
         sid = ctx.load_system(s, storage=storage)
         torch.cuda.synchronize()
@@ -92,68 +96,99 @@ def main():
                "angmom_err": torch.empty(B, dtype=torch.float64, device=dev)}
         sids = np.full(B, sid, np.int32)
         Ns = np.full(B, N, np.int64)
-
-        def step():
-            ctx.run(sids, Ns, init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0,
-                    dt=b.dt, n_steps=b.n_steps, out=out)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        stream = torch.cuda.current_stream(dev)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        wall0 = time.time()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = (time.time() - wall0) / args.steps
-        ms = e0.elapsed_time(e1) / args.steps
         es = 8 if storage == "C64" else 16
-        evals = B * (4 * W + 1)                   # RK4 stages + the final diagnostic evaluation
-        alg_bytes = evals * 4.0 * N * N * es      # four spline slices of N x N per evaluation
-        gbps = alg_bytes / (ms * 1e-3) / 1e9
-        st = out["status"].cpu().numpy()
-        results[storage] = {
-            "value": B * W / (ms * 1e-3), "ms_per_step": ms, "wall_ms_per_step": wall * 1e3,
-            "coupling_GBps": gbps, "N2_traj_steps_per_s": B * W * N * N / (ms * 1e-3),
-            "status_nonzero": int(np.count_nonzero(st)),
-            "max_norm_err": float(out["norm_err"].abs().max().item()),
-            "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                         "alg_bytes_per_launch": alg_bytes},
-        }
-        tr = MEASURED_TRAFFIC.get(storage)
-        if tr and tr["source_sha256_16"] == _kernel_hash() and tr["window"] == W and \
-                tr["trajectories"] == B:
-            results[storage]["roofline"]["traffic"] = tr["bytes"]
-        P_of[storage] = out["P"].reshape(B, N).cpu().numpy()
-        log("%s: %.2f ms/step, %.3g traj-steps/s, %.0f GB/s (%.1f%% of HBM)" %
-            (storage, ms, results[storage]["value"], gbps, 100 * gbps / HBM_PEAK_GBPS))
+        for sched in schedules:
+            def step():
+                ctx.run(sids, Ns, init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0,
+                        dt=b.dt, n_steps=b.n_steps, out=out, schedule=sched)
+
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream(dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            ctx.set_profiling(True)
+            wall0 = time.time()
+            e0.record(stream)
+            for _ in range(args.steps):
+                step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = (time.time() - wall0) / args.steps
+            kern_ms, kern_n = ctx.profile_read()
+            ctx.set_profiling(False)
+            ms = e0.elapsed_time(e1) / args.steps
+            evals = B * (4 * W + 1)              # RK4 stages + the final diagnostic evaluation
+            alg_bytes = evals * 4.0 * N * N * es  # four spline slices of N x N per evaluation
+            st = out["status"].cpu().numpy()
+            r = {"value": B * W / (ms * 1e-3), "ms_per_step": ms, "wall_ms_per_step": wall * 1e3,
+                 "coupling_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+                 "N2_traj_steps_per_s": B * W * N * N / (ms * 1e-3),
+                 "status_nonzero": int(np.count_nonzero(st)),
+                 "max_norm_err": float(out["norm_err"].abs().max().item())}
+            if sched == "gemv":
+                kms = kern_ms / kern_n
+                gbps = alg_bytes / (kms * 1e-3) / 1e9
+                r["roofline"] = {"kernel": "rk4_gemv", "bound": "hbm", "achieved": gbps,
+                                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                                 "traffic": None, "alg_bytes_per_launch": alg_bytes,
+                                 "launch_ms": kms, "launches_timed": kern_n}
+                tr = MEASURED_TRAFFIC.get(storage)
+                if tr and tr["source_sha256_16"] == _kernel_hash() and tr["window"] == W and \
+                        tr["trajectories"] == B:
+                    r["roofline"]["traffic"] = tr["bytes"]
+            else:
+                # one product launch per stage: 2 knots x 2 slices x (N x 2N) x (2N x 2) real
+                # multiply-adds per trajectory = 32 N^2 flops per trajectory and stage
+                kms = kern_ms / kern_n
+                flops = 32.0 * N * N * B
+                peak = MFMA_PEAK_TFLOPS[storage]
+                tf = flops / (kms * 1e-3) / 1e12
+                r["roofline"] = {"kernel": "bin_gemm", "bound": "mfma", "achieved": tf,
+                                 "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                                 "traffic": None, "alg_flops_per_launch": flops,
+                                 "launch_ms": kms, "launches_timed": kern_n}
+            results[(storage, sched)] = r
+            P_of[(storage, sched)] = out["P"].reshape(B, N).cpu().numpy()
+            log("%s %s: %.2f ms/step, %.3g traj-steps/s, dominant kernel %.3f ms x %d (%s %.3g %s, "
+                "%.1f%% of peak)" % (storage, sched, ms, r["value"], kms, kern_n,
+                                    r["roofline"]["kernel"], r["roofline"]["achieved"],
+                                    r["roofline"]["unit"], 100 * r["roofline"]["frac"]))
         ctx.free_system(sid)
 
-    head = results.get("C64") or results["C128"]
+    def best(storage):
+        cands = [(k, v) for k, v in results.items() if k[0] == storage]
+        return max(cands, key=lambda kv: kv[1]["value"]) if cands else (None, None)
+
+    hk, head = best("C64") if "C64" in storages else best("C128")
     line = {
         "metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if "C64" in results else "f64", "data": "synthetic",
+        "dtype": "f32" if hk[0] == "C64" else "f64", "data": "synthetic",
         "config": {"workload": "asymmetric top + atom, j<=8 all k,m (N=969), 200-point "
                                "Hermitian complex tables, %d trajectories mid-collision, "
                                "%d RK4 steps of 12 a.u. per bench step" % (B, W),
                    "N": N, "K": s.K, "trajectories": B, "rk4_steps_per_bench_step": W,
-                   "schedule": "gemv (one workgroup per trajectory)"},
+                   "schedule": hk[1], "tables": hk[0]},
         "roofline": head["roofline"],
         "coupling_GBps": head["coupling_GBps"],
         "N2_traj_steps_per_s": head["N2_traj_steps_per_s"],
+        "status_nonzero": head["status_nonzero"],
+        "variants": {"%s/%s" % k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
     }
-    if "C128" in results and "C64" in results:
-        line["fp64"] = results["C128"]
-        line["fp32_speedup_over_fp64"] = results["C64"]["value"] / results["C128"]["value"]
-        line["fp32_vs_fp64_max_abs_dP"] = float(np.max(np.abs(P_of["C64"] - P_of["C128"])))
-    line["status_nonzero"] = head["status_nonzero"]
+    if ("C64", hk[1]) in P_of and ("C128", hk[1]) in P_of:
+        line["fp32_vs_fp64_max_abs_dP"] = float(
+            np.max(np.abs(P_of[("C64", hk[1])] - P_of[("C128", hk[1])])))
+        f64 = max((v for k, v in results.items() if k[0] == "C128"), key=lambda v: v["value"])
+        line["fp32_speedup_over_fp64"] = head["value"] / f64["value"]
+    if ("C64", "gemv") in results and ("C64", "binned") in results:
+        line["binned_speedup_over_gemv_fp32"] = (results[("C64", "binned")]["value"] /
+                                                 results[("C64", "gemv")]["value"])
+    if ("C128", "gemv") in results:
+        line["plain_fp64_gemv_value"] = results[("C128", "gemv")]["value"]
+        line["speedup_over_plain_fp64"] = head["value"] / results[("C128", "gemv")]["value"]
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s, b, W)

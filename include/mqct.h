@@ -210,6 +210,17 @@ mqct_status mqct_cross_sections(mqct_context* ctx, int32_t mem, int64_t B, int32
                                 const int32_t* level_of_channel, int32_t n_levels,
                                 double b_max, double* sigma);
 
+/*
+ * Optional timing of the dominant step kernel of later runs: the fused
+ * per-trajectory RK4 kernel, or the table x columns product of the binned
+ * schedule.  HIP events are recorded on the context stream around each of its
+ * launches.  mqct_profile_read waits for the stream, returns the summed
+ * milliseconds and the number of timed launches since the last read, and
+ * resets both.  Timing adds two event records per timed launch.
+ */
+mqct_status mqct_set_profiling(mqct_context* ctx, int32_t enable);
+mqct_status mqct_profile_read(mqct_context* ctx, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

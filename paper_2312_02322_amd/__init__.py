@@ -29,7 +29,7 @@ STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NO
 # exported C functions, as declared in include/mqct.h
 EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
-           "mqct_cross_sections"]
+           "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read"]
 
 
 class MQCTError(RuntimeError):
@@ -90,6 +90,10 @@ def lib():
         L.mqct_run.restype = i32
         L.mqct_cross_sections.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp, i32, d, vp]
         L.mqct_cross_sections.restype = i32
+        L.mqct_set_profiling.argtypes = [vp, i32]
+        L.mqct_set_profiling.restype = i32
+        L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64)]
+        L.mqct_profile_read.restype = i32
         _lib = L
     return _lib
 
@@ -287,6 +291,16 @@ class Context:
                                        "status", "norm_err", "energy_err", "angmom_err")])
         self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
         return out
+
+    def set_profiling(self, enable=True):
+        """Time the dominant step kernel of later runs with HIP events."""
+        self._check(lib().mqct_set_profiling(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(total milliseconds, launches) of the timed kernel since the last read."""
+        ms, n = C.c_double(), C.c_int64()
+        self._check(lib().mqct_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def cross_sections(self, P, b, init_level, level_of_channel, n_levels, b_max):
         """Monte-Carlo cross sections (bohr^2) from P [B, N] on the device."""

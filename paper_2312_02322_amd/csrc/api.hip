@@ -45,6 +45,7 @@ struct mqct_context {
   TrajIn* h_traj = nullptr;        // pinned staging for trajectory records
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
+  Prof prof;                       // optional timing of the dominant step kernel
 };
 
 namespace {
@@ -159,6 +160,7 @@ void mqct_destroy(mqct_context* c) {
   for (auto& b : c->outs) if (b.p) hipFree(b.p);
   if (c->h_traj) hipHostFree(c->h_traj);
   if (c->staged) hipEventDestroy(c->staged);
+  for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -556,14 +558,14 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     const size_t wsb = binned_workspace_bytes((int)B, hs.Npad, hs.K, dtype_fp32(hs.dtype));
     if ((st = ensure(c, c->binws, wsb, "run: binned workspace")) != MQCT_OK) return st;
     hipError_t e = run_binned(c->d_systems, hs, (const TrajIn*)c->traj.p, (int)B, max_steps,
-                              d_a0, out, c->binws.p, c->stream);
+                              d_a0, out, c->binws.p, c->stream, &c->prof);
     if (e != hipSuccess) return hip_fail(c, e, "run: binned launch");
   } else if (!persistent) {
     for (int d = 0; d < 4; ++d) {
       int64_t n = ranges[d].second - ranges[d].first;
       if (n == 0) continue;
       hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->traj.p + ranges[d].first, n,
-                                     d_a0, out, d, max_npad[d], c->stream);
+                                     d_a0, out, d, max_npad[d], c->stream, &c->prof);
       if (e == hipErrorInvalidValue)
         return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the per-trajectory schedule");
       if (e != hipSuccess) return hip_fail(c, e, "run: launch");
@@ -599,6 +601,32 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
             "run: results");
   if (res->mem == MQCT_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream), "run: results");
+  return MQCT_OK;
+}
+
+mqct_status mqct_set_profiling(mqct_context* c, int32_t enable) {
+  if (!c) return MQCT_ERR_ARG;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "set_profiling");
+  c->prof.on = enable != 0;
+  c->prof.used = 0;
+  return MQCT_OK;
+}
+
+mqct_status mqct_profile_read(mqct_context* c, double* total_ms, int64_t* launches) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!total_ms || !launches) return fail(c, MQCT_ERR_ARG, "profile_read: null output");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "profile_read");
+  double tot = 0.0;
+  int64_t n = 0;
+  for (size_t i = 0; i + 1 < c->prof.used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->prof.ev[i], c->prof.ev[i + 1]), "profile_read");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  c->prof.used = 0;
   return MQCT_OK;
 }
 

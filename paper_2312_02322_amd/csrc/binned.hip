@@ -485,7 +485,7 @@ size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
 
 hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
                       int B, int64_t max_steps, const double* d_a0, TrajOut out, void* wsp,
-                      hipStream_t s) {
+                      hipStream_t s, Prof* prof) {
   const bool fp32 = dtype_fp32(hs.dtype);
   BinWS ws;
   ws.B = B; ws.N = hs.N; ws.Npad = hs.Npad; ws.K = hs.K;
@@ -530,10 +530,13 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
     else bin_prep<double2><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
     bin_scan<<<1, 1024, 0, s>>>(ws);
     bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
+    hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
+    prof_mark(prof, e0, s);
     if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, 0, s>>>(ws, d_systems);
     else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, 0, s>>>(ws, d_systems);
     else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, 0, s>>>(ws, d_systems);
     else bin_gemm<R64><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    prof_mark(prof, e1, s);
     bin_combine<<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
     return hipGetLastError();
   };

@@ -720,9 +720,23 @@ hipError_t launch_persistent_t(const DevSystem* d_systems, const TrajIn* d_traj,
 
 }  // namespace
 
+hipError_t launch_rk4_gemv_t(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                             const double* d_a0, TrajOut out, int dtype, int max_npad,
+                             hipStream_t s);
+
 hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
                            const double* d_a0, TrajOut out, int dtype, int max_npad,
-                           hipStream_t s) {
+                           hipStream_t s, Prof* prof) {
+  hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
+  prof_mark(prof, e0, s);
+  hipError_t r = launch_rk4_gemv_t(d_systems, d_traj, n_traj, d_a0, out, dtype, max_npad, s);
+  prof_mark(prof, e1, s);
+  return r;
+}
+
+hipError_t launch_rk4_gemv_t(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
+                             const double* d_a0, TrajOut out, int dtype, int max_npad,
+                             hipStream_t s) {
   switch (dtype) {
     case C128: return launch_dt<C128>(d_systems, d_traj, n_traj, d_a0, out, max_npad, s);
     case C64: return launch_dt<C64>(d_systems, d_traj, n_traj, d_a0, out, max_npad, s);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mqct {
 
 // Storage element kinds (same numbering as the public MQCT_R64 ... MQCT_C64).
@@ -65,6 +67,28 @@ struct TrajOut {
 enum { ST_EXITED = 1, ST_MAX_STEPS = 2, ST_STEP_UNDERFLOW = 4, ST_BELOW_GRID = 8,
        ST_NONFINITE = 16 };
 
+// Optional event timing of the dominant step kernel (HIP events recorded on
+// the launch stream around each of its launches).
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  size_t used = 0;
+  // the next event of the pool (created on demand), or null when off / failed
+  hipEvent_t next() {
+    if (!on) return nullptr;
+    if (used == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+};
+
+inline void prof_mark(Prof* p, hipEvent_t e, hipStream_t s) {
+  if (p && e) (void)hipEventRecord(e, s);
+}
+
 // ---- launchers (defined in the .hip files) ----------------------------------
 
 // Table preparation: from FP64 input (device, [K][N][N], real or complex
@@ -81,7 +105,7 @@ hipError_t launch_spline_prepare(const double* M_in, const double* R, int N, int
 // must use systems of the same dtype whose padded column count is <= max_npad.
 hipError_t launch_rk4_gemv(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
                            const double* d_a0, TrajOut out, int dtype, int max_npad,
-                           hipStream_t s);
+                           hipStream_t s, Prof* prof = nullptr);
 
 // Adaptive-step controls.
 struct DpCtl {
@@ -105,7 +129,7 @@ int64_t persistent_slots(bool fp32_family, int max_groups, int max_npad);
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32);
 hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
                       int B, int64_t max_steps, const double* d_a0, TrajOut out, void* ws,
-                      hipStream_t s);
+                      hipStream_t s, Prof* prof = nullptr);
 
 // Cross sections on the device.
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
