@@ -211,6 +211,34 @@ mqct_status mqct_cross_sections(mqct_context* ctx, int32_t mem, int64_t B, int32
                                 double b_max, double* sigma);
 
 /*
+ * Linear parametric form of a system's coupling tables, for gradients with
+ * respect to potential expansion coefficients (the potential expanded over
+ * angular functions with R-dependent coefficients, Section II, Eqs. 12-18):
+ *     M(R_k) = sum_p theta_p radial[p][k] G[gidx[p]],
+ * G real symmetric [nG][N][N] (host), radial [P][K] (host), P <= 256,
+ * nG <= 12, R64 storage only.  The natural spline of every radial[p] is
+ * prepared on the device.  The loaded tables are not changed.
+ */
+mqct_status mqct_system_set_params(mqct_context* ctx, int32_t system_id, int32_t P,
+                                   const double* radial, const int32_t* gidx, int32_t nG,
+                                   const double* G);
+/* Rebuild the system's tables on the device from the parametric form at theta
+ * [P] (host) and re-prepare their spline.  Synchronous. */
+mqct_status mqct_system_set_theta(mqct_context* ctx, int32_t system_id, const double* theta);
+/*
+ * Gradient of L = sum_b sum_n dL_dP[b][n] P_b(n) over the final probabilities
+ * of an RK4 batch with respect to theta (summed over the batch), by the
+ * discrete adjoint of RK4: a forward pass stores the state every
+ * `checkpoint_every` steps, then segments are recomputed from their checkpoints
+ * and swept backward.  One system per batch (with a parametric form),
+ * trajectories started from init_channel / E_coll / b / R0 (a0, classical0, t0
+ * must be NULL).  dL_dP [sum N_b] and dL_dtheta [P] are host arrays; P_out
+ * (host [sum N_b], may be NULL) receives the final probabilities.  Synchronous.
+ */
+mqct_status mqct_adjoint(mqct_context* ctx, const mqct_batch_desc* batch, int32_t checkpoint_every,
+                         const double* dL_dP, double* dL_dtheta, double* P_out);
+
+/*
  * Optional timing of the dominant step kernel of later runs: the fused
  * per-trajectory RK4 kernel, or the table x columns product of the binned
  * schedule.  HIP events are recorded on the context stream around each of its

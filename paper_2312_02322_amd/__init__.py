@@ -29,7 +29,8 @@ STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NO
 # exported C functions, as declared in include/mqct.h
 EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
-           "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read"]
+           "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
+           "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint"]
 
 
 class MQCTError(RuntimeError):
@@ -94,6 +95,12 @@ def lib():
         L.mqct_set_profiling.restype = i32
         L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64)]
         L.mqct_profile_read.restype = i32
+        L.mqct_system_set_params.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+        L.mqct_system_set_params.restype = i32
+        L.mqct_system_set_theta.argtypes = [vp, i32, vp]
+        L.mqct_system_set_theta.restype = i32
+        L.mqct_adjoint.argtypes = [vp, C.POINTER(BatchDesc), i32, vp, vp, vp]
+        L.mqct_adjoint.restype = i32
         _lib = L
     return _lib
 
@@ -292,6 +299,44 @@ class Context:
         self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
         return out
 
+    # ------------------------------------------------------------------ gradients
+    def set_params(self, sid, radial, gidx, G):
+        """Attach the linear parametric form M(R_k) = sum_p theta_p radial[p][k] G[gidx[p]]."""
+        rad = _host(radial, np.float64)
+        gi = _host(gidx, np.int32)
+        Gh = _host(G, np.float64)
+        self._check(lib().mqct_system_set_params(self.h, sid, rad.shape[0], rad.ctypes.data,
+                                                 gi.ctypes.data, Gh.shape[0], Gh.ctypes.data))
+        self._nparam = rad.shape[0]
+
+    def set_theta(self, sid, theta):
+        """Rebuild the system's tables on the device at the coefficients theta."""
+        th = _host(theta, np.float64)
+        self._check(lib().mqct_system_set_theta(self.h, sid, th.ctypes.data))
+
+    def adjoint(self, sid, N, dL_dP, *, init_channel, E_coll, b, dt, n_steps, R0=None,
+                checkpoint_every=256, n_param=None):
+        """dL/dtheta of L = sum dL_dP * P (host arrays); returns (grad, P)."""
+        B = len(np.atleast_1d(E_coll))
+        sids = np.full(B, sid, np.int32)
+        hold = []
+        bd = BatchDesc(B, sids.ctypes.data, None, None, None, None, None, None, None, 0, None,
+                       None, 0.0, 0.0, 0, 0.0, 0)
+        for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
+                               ("b", b, np.float64), ("R0", R0, np.float64), ("dt", dt, np.float64),
+                               ("n_steps", n_steps, np.int64)):
+            if arr is None:
+                continue
+            h = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtp), (B,)))
+            hold.append(h)
+            setattr(bd, name, h.ctypes.data)
+        w = _host(np.reshape(dL_dP, -1), np.float64)
+        P = np.empty(B * N)
+        g = np.empty(n_param if n_param is not None else self._nparam)
+        self._check(lib().mqct_adjoint(self.h, C.byref(bd), int(checkpoint_every), w.ctypes.data,
+                                       g.ctypes.data, P.ctypes.data))
+        return g, P.reshape(B, N)
+
     def set_profiling(self, enable=True):
         """Time the dominant step kernel of later runs with HIP events."""
         self._check(lib().mqct_set_profiling(self.h, 1 if enable else 0))
@@ -315,3 +360,41 @@ class Context:
                                               bt.data_ptr(), il.data_ptr(), lev.ctypes.data,
                                               int(n_levels), float(b_max), sig.data_ptr()))
         return sig
+
+
+def _autograd_function():
+    import torch
+
+    class MQCTPropagate(torch.autograd.Function):
+        """P = propagate(theta): final probabilities [B, N] of an RK4 batch as a function of
+        the potential coefficients theta; backward runs the library's adjoint kernel."""
+
+        @staticmethod
+        def forward(fctx, theta, mq, sid, N, batch, checkpoint_every):
+            th = theta.detach().cpu().double().numpy()
+            mq.set_theta(sid, th)
+            B = len(batch["E_coll"])
+            out = mq.run_host([sid] * B, [N] * B, **batch)
+            fctx.mq, fctx.sid, fctx.N, fctx.batch, fctx.S = mq, sid, N, batch, checkpoint_every
+            fctx.save_for_backward(theta)
+            return torch.as_tensor(out["P"].reshape(B, N), dtype=theta.dtype, device=theta.device)
+
+        @staticmethod
+        def backward(fctx, grad_P):
+            (theta,) = fctx.saved_tensors
+            mq = fctx.mq
+            mq.set_theta(fctx.sid, theta.detach().cpu().double().numpy())
+            b = fctx.batch
+            g, _ = mq.adjoint(fctx.sid, fctx.N, grad_P.detach().cpu().double().numpy(),
+                              init_channel=b["init_channel"], E_coll=b["E_coll"], b=b["b"],
+                              dt=b["dt"], n_steps=b["n_steps"], R0=b.get("R0"),
+                              checkpoint_every=fctx.S, n_param=theta.numel())
+            return (torch.as_tensor(g, dtype=theta.dtype, device=theta.device),
+                    None, None, None, None, None)
+
+    return MQCTPropagate
+
+
+def propagate(theta, mq, sid, N, batch, checkpoint_every=256):
+    """Differentiable final probabilities (see MQCTPropagate)."""
+    return _autograd_function().apply(theta, mq, sid, N, batch, checkpoint_every)

@@ -23,6 +23,9 @@ struct SysHost {
   DevSystem dev{};
   void* bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t table_bytes = 0;
+  // optional linear parametric form of the tables (adjoint)
+  int P = 0, nG = 0;
+  void* pbufs[4] = {nullptr, nullptr, nullptr, nullptr};   // G, rad, rad2, gidx
 };
 
 // Grow-only device buffer.
@@ -113,11 +116,20 @@ bool finite_arr(const double* p, int64_t n) {
   return true;
 }
 
+void free_params(SysHost& s) {
+  for (auto& p : s.pbufs) {
+    if (p) hipFree(p);
+    p = nullptr;
+  }
+  s.P = s.nG = 0;
+}
+
 void free_system(SysHost& s) {
   for (auto& p : s.bufs) {
     if (p) hipFree(p);
     p = nullptr;
   }
+  free_params(s);
   s.live = false;
 }
 
@@ -601,6 +613,168 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
             "run: results");
   if (res->mem == MQCT_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream), "run: results");
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const double* radial,
+                                   const int32_t* gidx, int32_t nG, const double* G) {
+  if (!c) return MQCT_ERR_ARG;
+  if (id < 0 || id >= (int)c->systems.size() || !c->systems[id].live)
+    return fail(c, MQCT_ERR_STATE, "set_params: unknown system %d", id);
+  SysHost& sh = c->systems[id];
+  const int N = sh.dev.N, K = sh.dev.K, Npad = sh.dev.Npad;
+  if (sh.dev.dtype != R64)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "set_params: the parametric form needs R64 storage");
+  if (P < 1 || P > 256 || nG < 1 || nG > 12 || !radial || !gidx || !G)
+    return fail(c, MQCT_ERR_ARG, "set_params: need 1 <= P <= 256, 1 <= nG <= 12 and all arrays");
+  for (int p = 0; p < P; ++p)
+    if (gidx[p] < 0 || gidx[p] >= nG) return fail(c, MQCT_ERR_ARG, "set_params: gidx out of range");
+  if (!finite_arr(radial, (int64_t)P * K) || !finite_arr(G, (int64_t)nG * N * N))
+    return fail(c, MQCT_ERR_NONFINITE, "set_params: non-finite input");
+  for (int t = 0; t < nG; ++t)
+    for (int n = 0; n < N; ++n)
+      for (int m = n + 1; m < N; ++m)
+        if (G[((int64_t)t * N + n) * N + m] != G[((int64_t)t * N + m) * N + n])
+          return fail(c, MQCT_ERR_NOT_HERMITIAN, "set_params: G is not symmetric");
+  HIP_TRY(c, hipSetDevice(c->device), "set_params");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "set_params");
+  free_params(sh);
+  std::vector<double> Gp((size_t)nG * N * Npad, 0.0);
+  for (int t = 0; t < nG; ++t)
+    for (int n = 0; n < N; ++n)
+      for (int m = 0; m < N; ++m) Gp[((size_t)t * N + n) * Npad + m] = G[((int64_t)t * N + n) * N + m];
+  double* tmp = nullptr;
+  hipError_t e;
+  auto bail = [&](hipError_t err) {
+    if (tmp) hipFree(tmp);
+    free_params(sh);
+    return hip_fail(c, err, "set_params");
+  };
+  if ((e = hipMalloc(&sh.pbufs[0], Gp.size() * 8)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[1], (size_t)P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[2], (size_t)P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[3], (size_t)P * 4)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc((void**)&tmp, (size_t)2 * P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = hipMemcpy(sh.pbufs[0], Gp.data(), Gp.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.pbufs[1], radial, (size_t)P * K * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.pbufs[3], gidx, (size_t)P * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e);
+  if ((e = launch_spline_rows((const double*)sh.pbufs[1], sh.dev.R, K, P, (double*)sh.pbufs[2],
+                              tmp, c->stream)) != hipSuccess)
+    return bail(e);
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e);
+  hipFree(tmp);
+  sh.P = P;
+  sh.nG = nG;
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_set_theta(mqct_context* c, int32_t id, const double* theta) {
+  if (!c) return MQCT_ERR_ARG;
+  if (id < 0 || id >= (int)c->systems.size() || !c->systems[id].live)
+    return fail(c, MQCT_ERR_STATE, "set_theta: unknown system %d", id);
+  SysHost& sh = c->systems[id];
+  if (sh.P == 0) return fail(c, MQCT_ERR_STATE, "set_theta: no parametric form attached");
+  if (!theta || !finite_arr(theta, sh.P)) return fail(c, MQCT_ERR_ARG, "set_theta: bad theta");
+  const int N = sh.dev.N, K = sh.dev.K, Npad = sh.dev.Npad;
+  HIP_TRY(c, hipSetDevice(c->device), "set_theta");
+  double *Min = nullptr, *th = nullptr, *tmp = nullptr;
+  const int64_t tmp_doubles = std::max<int64_t>(K, std::min<int64_t>((int64_t)K * N * Npad,
+                                                                    (int64_t)64 << 20));
+  hipError_t e;
+  auto done = [&](hipError_t err) -> mqct_status {
+    if (Min) hipFree(Min);
+    if (th) hipFree(th);
+    if (tmp) hipFree(tmp);
+    return err == hipSuccess ? MQCT_OK : hip_fail(c, err, "set_theta");
+  };
+  if ((e = hipMalloc((void**)&Min, (size_t)K * N * N * 8)) != hipSuccess) return done(e);
+  if ((e = hipMalloc((void**)&th, (size_t)sh.P * 8)) != hipSuccess) return done(e);
+  if ((e = hipMalloc((void**)&tmp, (size_t)tmp_doubles * 8)) != hipSuccess) return done(e);
+  if ((e = hipMemcpyAsync(th, theta, (size_t)sh.P * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return done(e);
+  if ((e = launch_build_param_tables((const double*)sh.pbufs[0], (const double*)sh.pbufs[1],
+                                     (const int*)sh.pbufs[3], th, sh.P, sh.nG, N, Npad, K, Min,
+                                     c->stream)) != hipSuccess)
+    return done(e);
+  if ((e = launch_spline_prepare(Min, sh.dev.R, N, K, Npad, 1, sh.dev.dtype, sh.bufs[0],
+                                 sh.bufs[1], tmp, tmp_doubles, c->stream)) != hipSuccess)
+    return done(e);
+  return done(hipStreamSynchronize(c->stream));
+}
+
+mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t checkpoint_every,
+                         const double* dL_dP, double* dL_dtheta, double* P_out) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!bd || !dL_dP || !dL_dtheta) return fail(c, MQCT_ERR_ARG, "adjoint: null argument");
+  const int64_t B = bd->B;
+  if (B < 1 || !bd->system_id || !bd->init_channel || !bd->E_coll || !bd->b || !bd->dt ||
+      !bd->n_steps)
+    return fail(c, MQCT_ERR_ARG, "adjoint: needs B >= 1, system_id, init_channel, E_coll, b, dt, n_steps");
+  if (bd->integrator != MQCT_RK4) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: RK4 only");
+  if (bd->a0 || bd->classical0 || bd->t0)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: start states come from init_channel/E_coll/b/R0");
+  if (checkpoint_every < 1) return fail(c, MQCT_ERR_ARG, "adjoint: checkpoint_every must be >= 1");
+  const int sid = bd->system_id[0];
+  for (int64_t b = 0; b < B; ++b)
+    if (bd->system_id[b] != sid) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: one system per batch");
+  if (sid < 0 || sid >= (int)c->systems.size() || !c->systems[sid].live)
+    return fail(c, MQCT_ERR_STATE, "adjoint: unknown system %d", sid);
+  SysHost& sh = c->systems[sid];
+  if (sh.P == 0) return fail(c, MQCT_ERR_STATE, "adjoint: no parametric form attached");
+  const DevSystem& sy = sh.dev;
+  if (sy.Npad > 1024) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: N > 1024");
+  HIP_TRY(c, hipSetDevice(c->device), "adjoint");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "adjoint");
+  std::vector<TrajIn> tr(B);
+  int64_t maxn = 0, amp = 0;
+  double Rlast;
+  HIP_TRY(c, hipMemcpy(&Rlast, sy.R + (sy.K - 1), 8, hipMemcpyDeviceToHost), "adjoint");
+  for (int64_t b = 0; b < B; ++b) {
+    TrajIn t{};
+    t.id = b; t.amp_off = amp; t.sys = sid; t.n_steps = bd->n_steps[b]; t.dt = bd->dt[b];
+    t.init_channel = bd->init_channel[b]; t.E_coll = bd->E_coll[b]; t.b = bd->b[b];
+    t.R0 = bd->R0 ? bd->R0[b] : Rlast;
+    if (t.n_steps < 0 || !isfinite(t.dt) || t.init_channel < 0 || t.init_channel >= sy.N ||
+        !(t.E_coll > 0.0) || !(t.b >= 0.0) || !(t.b < t.R0))
+      return fail(c, MQCT_ERR_ARG, "adjoint: bad trajectory %lld", (long long)b);
+    maxn = std::max(maxn, t.n_steps);
+    amp += sy.N;
+    tr[b] = t;
+  }
+  const int S = checkpoint_every;
+  const int64_t stride = adjoint_scratch_doubles(sy.Npad, maxn, S);
+  size_t off = 0;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_traj = off; off += al(B * sizeof(TrajIn));
+  const size_t o_w = off; off += al((size_t)amp * 8);
+  const size_t o_part = off; off += al((size_t)B * sh.P * 8);
+  const size_t o_g = off; off += al((size_t)sh.P * 8);
+  const size_t o_P = off; off += al((size_t)amp * 8);
+  const size_t o_s = off; off += al((size_t)B * stride * 8);
+  mqct_status st;
+  if ((st = ensure(c, c->binws, off, "adjoint: workspace")) != MQCT_OK) return st;
+  char* base = (char*)c->binws.p;
+  HIP_TRY(c, hipMemcpyAsync(base + o_traj, tr.data(), B * sizeof(TrajIn), hipMemcpyHostToDevice,
+                            c->stream), "adjoint");
+  HIP_TRY(c, hipMemcpyAsync(base + o_w, dL_dP, (size_t)amp * 8, hipMemcpyHostToDevice, c->stream),
+          "adjoint");
+  hipEvent_t e0 = c->prof.next(), e1 = c->prof.next();
+  prof_mark(&c->prof, e0, c->stream);
+  HIP_TRY(c, launch_adjoint(c->d_systems, dtype_complex(sy.dtype), sy.Npad,
+                            (const TrajIn*)(base + o_traj), B, (const double*)(base + o_w),
+                            (double*)(base + o_part), (double*)(base + o_g),
+                            (double*)(base + o_P), (double*)(base + o_s), stride, S,
+                            (const double*)sh.pbufs[0], (const double*)sh.pbufs[1],
+                            (const double*)sh.pbufs[2], (const int*)sh.pbufs[3], sh.P, sh.nG,
+                            c->stream), "adjoint: launch");
+  prof_mark(&c->prof, e1, c->stream);
+  HIP_TRY(c, hipMemcpyAsync(dL_dtheta, base + o_g, (size_t)sh.P * 8, hipMemcpyDeviceToHost,
+                            c->stream), "adjoint");
+  if (P_out)
+    HIP_TRY(c, hipMemcpyAsync(P_out, base + o_P, (size_t)amp * 8, hipMemcpyDeviceToHost, c->stream),
+            "adjoint");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "adjoint");
   return MQCT_OK;
 }
 

@@ -80,8 +80,9 @@ __device__ __forceinline__ double uni(double x) {
 }
 
 // Sum NV values over the workgroup: wave shuffles, then one LDS slot per wave
-// read back in a fixed order (deterministic, identical in every lane).  `red`
-// must not be reused by another reduction before a barrier separates them.
+// (red[w * NV + i], NW * NV doubles) read back in a fixed order
+// (deterministic, identical in every lane).  `red` must not be reused by
+// another reduction before a barrier separates them.
 template <int NV, int NW>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 #pragma unroll
@@ -91,14 +92,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[w * 8 + i] = v[i];
+    for (int i = 0; i < NV; ++i) red[w * NV + i] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) s += red[q * 8 + i];
+    for (int q = 0; q < NW; ++q) s += red[q * NV + i];
     v[i] = uni(s);
   }
 }

@@ -131,6 +131,19 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
                       int B, int64_t max_steps, const double* d_a0, TrajOut out, void* ws,
                       hipStream_t s, Prof* prof = nullptr);
 
+// Adjoint (discrete RK4 adjoint with checkpointed recomputation).
+int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S);
+hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, int Npad, const TrajIn* d_traj,
+                          int64_t B, const double* dLdP, double* grad_part, double* grad_out,
+                          double* P_out, double* scratch, int64_t scratch_stride, int S,
+                          const double* G, const double* rad, const double* rad2, const int* gidx,
+                          int P, int nG, hipStream_t s);
+hipError_t launch_build_param_tables(const double* G, const double* rad, const int* gidx,
+                                     const double* theta, int P, int nG, int N, int Npad, int K,
+                                     double* Mout, hipStream_t s);
+hipError_t launch_spline_rows(const double* y, const double* x, int K, int ncol, double* y2,
+                              double* tmp, hipStream_t s);
+
 // Cross sections on the device.
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
                        const int32_t* level_of_channel, int n_levels, double b_max,
