@@ -52,6 +52,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["C64", "C128"], default=None)
     ap.add_argument("--schedule", choices=["gemv", "binned", "both"], default="both")
+    ap.add_argument("--adjoint", choices=["on", "off", "only"], default="on",
+                    help="time one full gradient on the N=256 two-rotor workload")
+    ap.add_argument("--adjoint-traj", type=int, default=1024)
+    ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -69,6 +73,9 @@ def main():
     import paper_2312_02322_amd as mq
     from synth import systems as S
 
+    if args.adjoint == "only":
+        print(json.dumps(adjoint_timing(args.adjoint_traj, args.adjoint_steps)), flush=True)
+        return
     t0 = time.time()
     (s,), b = S.config2(n_traj=args.traj, full_collision=False, window_steps=args.window)
     log("generated N=%d K=%d B=%d in %.1fs" % (s.N, s.K, b.B, time.time() - t0))
@@ -193,7 +200,43 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s, b, W)
     ctx.close()
+    if args.adjoint == "on":
+        line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps)
     print(json.dumps(line), flush=True)
+
+
+def adjoint_timing(n_traj, n_steps, checkpoint_every=256):
+    """Seconds per full 96-coefficient gradient of a b-weighted inelastic cross section.
+
+    Two linear rotors, j1, j2 <= 3 (N = 256), potential linear in 96 coefficients,
+    n_traj trajectories of n_steps RK4 steps; L = sum_i (2 pi b_max / B) b_i
+    sum_{n outside the initial level} P_i(n); discrete adjoint with checkpoints
+    every 256 steps.
+    """
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+    (s,), b = S.config4(n_traj=n_traj, n_steps=n_steps)
+    ctx = mq.Context(0)
+    sid = ctx.load_system(s)
+    ctx.set_params(sid, s.param_radial, s.param_G_index, s.G)
+    ctx.set_theta(sid, s.theta)
+    lev = s.level_of_channel
+    w = np.array([(2 * np.pi * b.b_max / b.B) * b.b[i] * (lev != b.init_level[i])
+                  for i in range(b.B)])
+    kw = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, dt=b.dt, n_steps=b.n_steps,
+              R0=b.R0, checkpoint_every=checkpoint_every)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    grad, P = ctx.adjoint(sid, s.N, w, **kw)
+    sec = time.time() - t0
+    ctx.close()
+    log("adjoint: %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad, |grad| = %.3e"
+        % (b.B, n_steps, s.N, grad.shape[0], sec, float(np.linalg.norm(grad))))
+    return {"s_per_grad": sec, "unit": "s", "trajectories": b.B, "rk4_steps": n_steps, "N": s.N,
+            "n_coefficients": int(grad.shape[0]), "checkpoint_every": checkpoint_every,
+            "L": float(np.sum(w * P)), "grad_norm": float(np.linalg.norm(grad))}
 
 
 def _kernel_hash():
