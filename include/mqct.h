@@ -216,8 +216,9 @@ mqct_status mqct_cross_sections(mqct_context* ctx, int32_t mem, int64_t B, int32
  * angular functions with R-dependent coefficients, Section II, Eqs. 12-18):
  *     M(R_k) = sum_p theta_p radial[p][k] G[gidx[p]],
  * G real symmetric [nG][N][N] (host), radial [P][K] (host), P <= 256,
- * nG <= 12, R64 storage only.  The natural spline of every radial[p] is
- * prepared on the device.  The loaded tables are not changed.
+ * nG <= 48, R64 storage only.  The natural spline of every radial[p] is
+ * prepared on the device; the adjoint reads the nonzeros of G as lists (the
+ * angular coupling matrices are sparse).  The loaded tables are not changed.
  */
 mqct_status mqct_system_set_params(mqct_context* ctx, int32_t system_id, int32_t P,
                                    const double* radial, const int32_t* gidx, int32_t nG,
@@ -230,7 +231,9 @@ mqct_status mqct_system_set_theta(mqct_context* ctx, int32_t system_id, const do
  * of an RK4 batch with respect to theta (summed over the batch), by the
  * discrete adjoint of RK4: a forward pass stores the state every
  * `checkpoint_every` steps, then segments are recomputed from their checkpoints
- * and swept backward.  One system per batch (with a parametric form),
+ * (storing the four stage states of each step) and swept backward.  Device
+ * workspace: (ceil(n_steps / checkpoint_every) + 4 checkpoint_every) x
+ * (2 Npad + 4) doubles per trajectory.  One system per batch (with a parametric form),
  * trajectories started from init_channel / E_coll / b / R0 (a0, classical0, t0
  * must be NULL).  dL_dP [sum N_b] and dL_dtheta [P] are host arrays; P_out
  * (host [sum N_b], may be NULL) receives the final probabilities.  Synchronous.

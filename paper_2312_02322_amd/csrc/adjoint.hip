@@ -40,17 +40,20 @@ namespace {
 
 constexpr int AB = 256;           // threads per trajectory
 constexpr int ANW = AB / 64;
-constexpr int NSC = 4;            // VJP scalars reduced besides the theta terms
+constexpr int NSC = 4;            // VJP scalars reduced over the workgroup
+constexpr int NGMAX = 48;         // angular terms (three bilinear forms each in LDS)
 
 struct AdjArgs {
   const TrajIn* traj;
   const double* dLdP;      // [sum N] weights of the final probabilities
   double* grad_part;       // [B][P] per-trajectory gradient
   double* P_out;           // [sum N] or null
-  double* scratch;         // per trajectory: checkpoints + segment states
+  double* scratch;         // per trajectory: checkpoints + stage states of one segment
   int64_t scratch_stride;  // doubles per trajectory
   int S;                   // checkpoint interval
-  const double* G;         // [nG][N][Npad]
+  const int* goff;         // [nG+1] nonzeros of G_t are goff[t] .. goff[t+1]-1
+  const uint32_t* gent;    // row | col << 16
+  const double* gval;
   const double* rad;       // [P][K] r_p at the knots
   const double* rad2;      // [P][K] their natural-spline second derivatives
   int P, nG;
@@ -68,24 +71,37 @@ struct Adj {
 
   __device__ static double2 mc(double2 x, double2 y) { return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x); }
 
-  // table element M_nm at the weights (column access: M_nm = conj(S[m][n]) for
-  // Hermitian tables, S[m][n] for real symmetric ones)
-  __device__ static double2 tab(const DevSystem& sy, int k, int m, int n, const double (&w)[4]) {
+  // the four spline coefficients of element (n, m) in interval k: value_k,
+  // value_{k+1}, second derivative_k, second derivative_{k+1}.  Column access:
+  // M_nm = conj(S[m][n]) for Hermitian tables, S[m][n] for real symmetric ones.
+  struct Raw {
+    double2 v[4];
+  };
+  __device__ static Raw raw(const DevSystem& sy, int k, int m, int n) {
     const int64_t ks = sy.knot_stride;
-    const int64_t o = (int64_t)m * sy.Npad + n;
+    const int64_t o = (int64_t)k * ks + (int64_t)m * sy.Npad + n;
+    Raw r;
     if constexpr (CPLX) {
       const double2* M = (const double2*)sy.M;
       const double2* M2 = (const double2*)sy.M2;
-      const double2 s0 = M[k * ks + o], s1 = M[(k + 1) * ks + o];
-      const double2 s2 = M2[k * ks + o], s3 = M2[(k + 1) * ks + o];
-      return make_double2(w[0] * s0.x + w[1] * s1.x + w[2] * s2.x + w[3] * s3.x,
-                          -(w[0] * s0.y + w[1] * s1.y + w[2] * s2.y + w[3] * s3.y));
+      r.v[0] = M[o]; r.v[1] = M[o + ks]; r.v[2] = M2[o]; r.v[3] = M2[o + ks];
     } else {
       const double* M = (const double*)sy.M;
       const double* M2 = (const double*)sy.M2;
-      return make_double2(w[0] * M[k * ks + o] + w[1] * M[(k + 1) * ks + o] +
-                              w[2] * M2[k * ks + o] + w[3] * M2[(k + 1) * ks + o], 0.0);
+      r.v[0].x = M[o]; r.v[1].x = M[o + ks]; r.v[2].x = M2[o]; r.v[3].x = M2[o + ks];
     }
+    return r;
+  }
+  __device__ static double2 comb(const Raw& r, const double (&w)[4]) {
+    double2 z;
+    z.x = w[0] * r.v[0].x + w[1] * r.v[1].x + w[2] * r.v[2].x + w[3] * r.v[3].x;
+    z.y = CPLX ? -(w[0] * r.v[0].y + w[1] * r.v[1].y + w[2] * r.v[2].y + w[3] * r.v[3].y) : 0.0;
+    return z;
+  }
+  // complex product with a table element that is real for real symmetric tables
+  __device__ static double2 mt(double2 M, double2 x) {
+    if constexpr (CPLX) return mc(M, x);
+    else return make_double2(M.x * x.x, M.x * x.y);
   }
 
   __device__ static void weights(const Spl& sp, double (&w)[4], double (&d)[4], double (&dd)[4],
@@ -136,10 +152,11 @@ struct Adj {
       const int n = row(r);
       if (n >= N) { F.a[r] = make_double2(0.0, 0.0); continue; }
       double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+#pragma unroll 4
       for (int m = 0; m < N; ++m) {
         const double2 cm = lc[m];
-        const double2 Mv = tab(sy, sp.k, m, n, w), Md = tab(sy, sp.k, m, n, d);
-        const double2 a1 = mc(Mv, cm), a2 = mc(Md, cm);
+        const Raw q = raw(sy, sp.k, m, n);
+        const double2 a1 = mt(comb(q, w), cm), a2 = mt(comb(q, d), cm);
         u.x += a1.x; u.y += a1.y; v.x += a2.x; v.y += a2.y;
       }
       const double2 c = lc[n];
@@ -163,15 +180,15 @@ struct Adj {
   // this thread's parameter's share to gth (thread p owns theta_p)
   __device__ static void vjp(const DevSystem& sy, const AdjArgs& A, double t, const St& Y,
                              const St& Gc, St& Yb, double& gth, double2* lc, double2* lg,
-                             double2* ljc, double2* lmc, double* red, double* redt) {
-    const int N = sy.N, Npad = sy.Npad;
+                             double2* ljc, double2* lmc, double* red, double* tq) {
+    const int N = sy.N;
     const double mu = sy.mu, R = Y.y[0], pphi = Y.y[3];
     const Spl sp = spline_at(sy.R, sy.K, R);
     double w[4], d[4], dd[4];
     weights(sp, w, d, dd, R, sy.R, sy.K);
     const double om = pphi / (mu * R * R);
     const double gR = Gc.y[0], gPhi = Gc.y[1], gPR = Gc.y[2], gPPhi = Gc.y[3];
-    // the previous product still reads lg and lmc after its last barrier
+    // the previous product still reads lg, lmc and tq after its last barrier
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -190,25 +207,49 @@ struct Adj {
       if (n < N) ljc[n] = jx(sy, n, lc);
     }
     __syncthreads();
-    // one pass over the four slices for five columns, and the G_t c products
+    // bilinear forms of the sparse G_t, one wave per angular term:
+    // tq[3t] = Im(g~^H G_t c), tq[3t+1] = Im((Jc)^H G_t c), tq[3t+2] = Re(c^H G_t c)
+    {
+      const int lane = threadIdx.x & 63;
+      for (int tt = threadIdx.x >> 6; tt < A.nG; tt += ANW) {
+        double f[3] = {0.0, 0.0, 0.0};
+        const int e1 = A.goff[tt + 1];
+        for (int e = A.goff[tt] + lane; e < e1; e += 64) {
+          const uint32_t nm = A.gent[e];
+          const int n = nm & 0xffff, m = nm >> 16;
+          const double v = A.gval[e];
+          const double2 cm = lc[m], cn = lc[n], gn = lg[n], jn = ljc[n];
+          f[0] = fma(v, gn.x * cm.y - gn.y * cm.x, f[0]);
+          f[1] = fma(v, jn.x * cm.y - jn.y * cm.x, f[1]);
+          f[2] = fma(v, cn.x * cm.x + cn.y * cm.y, f[2]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) f[i] += __shfl_xor(f[i], off, 64);
+        if (lane == 0) {
+          tq[3 * tt] = f[0]; tq[3 * tt + 1] = f[1]; tq[3 * tt + 2] = f[2];
+        }
+      }
+    }
+    // one pass over the four table slices for the five products
     double sc[NSC] = {0.0, 0.0, 0.0, 0.0};
-    double st3[36];
-    for (int q = 0; q < 36; ++q) st3[q] = 0.0;
-    double2 Mg[NR], Mc[NR], MJc[NR], Mpc[NR];
+    double2 Mg[NR], MJc[NR], Mpc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
-      Mg[r] = Mc[r] = MJc[r] = Mpc[r] = make_double2(0.0, 0.0);
+      Mg[r] = MJc[r] = Mpc[r] = make_double2(0.0, 0.0);
       if (n >= N) continue;
-      double2 Mppc = make_double2(0.0, 0.0);
+      double2 Mc = make_double2(0.0, 0.0), Mppc = make_double2(0.0, 0.0);
+#pragma unroll 2
       for (int m = 0; m < N; ++m) {
-        const double2 Mv = tab(sy, sp.k, m, n, w), Md = tab(sy, sp.k, m, n, d);
-        const double2 Mdd = tab(sy, sp.k, m, n, dd);
+        const Raw q = raw(sy, sp.k, m, n);
+        const double2 Mv = comb(q, w), Md = comb(q, d), Mdd = comb(q, dd);
         const double2 cm = lc[m], gm = lg[m], jm = ljc[m];
-        const double2 t1 = mc(Mv, gm), t2 = mc(Mv, cm), t3 = mc(Mv, jm), t4 = mc(Md, cm),
-                      t5 = mc(Mdd, cm);
+        const double2 t1 = mt(Mv, gm), t2 = mt(Mv, cm), t3 = mt(Mv, jm), t4 = mt(Md, cm),
+                      t5 = mt(Mdd, cm);
         Mg[r].x += t1.x; Mg[r].y += t1.y;
-        Mc[r].x += t2.x; Mc[r].y += t2.y;
+        Mc.x += t2.x; Mc.y += t2.y;
         MJc[r].x += t3.x; MJc[r].y += t3.y;
         Mpc[r].x += t4.x; Mpc[r].y += t4.y;
         Mppc.x += t5.x; Mppc.y += t5.y;
@@ -218,37 +259,19 @@ struct Adj {
       sc[1] += gt.x * jc.y - gt.y * jc.x;             // Im(g~^H J c)
       sc[2] += c.x * Mppc.x + c.y * Mppc.y;           // Re(c^H M'' c)
       sc[3] += jc.x * Mpc[r].y - jc.y * Mpc[r].x;     // Im((Jc)^H M' c)
-      for (int tt = 0; tt < A.nG; ++tt) {
-        const double* Gt = A.G + (int64_t)tt * N * Npad;
-        double2 z = make_double2(0.0, 0.0);
-        for (int m = 0; m < N; ++m) {
-          const double gv = Gt[(int64_t)m * Npad + n];
-          z.x = fma(gv, lc[m].x, z.x);
-          z.y = fma(gv, lc[m].y, z.y);
-        }
-        st3[3 * tt + 0] += gt.x * z.y - gt.y * z.x;   // Im(g~^H G_t c)
-        st3[3 * tt + 1] += jc.x * z.y - jc.y * z.x;   // Im((Jc)^H G_t c)
-        st3[3 * tt + 2] += c.x * z.x + c.y * z.y;     // Re(c^H G_t c)
-      }
-      lmc[n] = Mc[r];
+      lmc[n] = Mc;
     }
-    block_sum<NSC, ANW>(sc, red);
-    block_sum<36, ANW>(st3, redt);   // its barrier also publishes lmc
-    double2 JMc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int n = row(r);
-      JMc[r] = n < N ? jx(sy, n, lmc) : make_double2(0.0, 0.0);
-    }
+    block_sum<NSC, ANW>(sc, red);    // its barrier also publishes lmc and tq
     // grad_a = P* [ i M g~ + i omega J g~ - 2 g_PR M' c - 2 i g_PPhi (J M c - M J c) ]
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
       if (n >= N) { Yb.a[r] = make_double2(0.0, 0.0); continue; }
+      const double2 jmc = jx(sy, n, lmc);
       const double2 jg = jx(sy, n, lg);
       double2 s;
-      s.x = -(Mg[r].y + om * jg.y) - 2.0 * gPR * Mpc[r].x + 2.0 * gPPhi * (JMc[r].y - MJc[r].y);
-      s.y = (Mg[r].x + om * jg.x) - 2.0 * gPR * Mpc[r].y - 2.0 * gPPhi * (JMc[r].x - MJc[r].x);
+      s.x = -(Mg[r].y + om * jg.y) - 2.0 * gPR * Mpc[r].x + 2.0 * gPPhi * (jmc.y - MJc[r].y);
+      s.y = (Mg[r].x + om * jg.x) - 2.0 * gPR * Mpc[r].y - 2.0 * gPPhi * (jmc.x - MJc[r].x);
       double sn, cs;
       sincos(sy.E[n] * t, &sn, &cs);
       Yb.a[r] = mc(make_double2(cs, sn), s);
@@ -269,7 +292,7 @@ struct Adj {
       const int k = sp.k;
       const double sv = w[0] * rp[k] + w[1] * rp[k + 1] + w[2] * r2[k] + w[3] * r2[k + 1];
       const double sd = d[0] * rp[k] + d[1] * rp[k + 1] + d[2] * r2[k] + d[3] * r2[k + 1];
-      gth += sv * (st3[3 * tt] + 2.0 * gPPhi * st3[3 * tt + 1]) - gPR * sd * st3[3 * tt + 2];
+      gth += sv * (tq[3 * tt] + 2.0 * gPPhi * tq[3 * tt + 1]) - gPR * sd * tq[3 * tt + 2];
     }
   }
 
@@ -280,22 +303,11 @@ struct Adj {
 #pragma unroll
     for (int i = 0; i < 4; ++i) o.y[i] = fma(a, y.y[i], x.y[i]);
   }
-
-  __device__ static void rk4(const DevSystem& sy, double t, double h, St& y, double2* lc,
-                             double* red) {
-    St k, acc, Ys;
-    rhs(sy, t, y, k, lc, red);
-    acc = k;
-    axpy(Ys, y, 0.5 * h, k);
-    rhs(sy, t + 0.5 * h, Ys, k, lc, red);
-    axpy(acc, acc, 2.0, k);
-    axpy(Ys, y, 0.5 * h, k);
-    rhs(sy, t + 0.5 * h, Ys, k, lc, red);
-    axpy(acc, acc, 2.0, k);
-    axpy(Ys, y, h, k);
-    rhs(sy, t + h, Ys, k, lc, red);
-    axpy(acc, acc, 1.0, k);
-    axpy(y, y, h / 6.0, acc);
+  __device__ static void scale(St& o, double a, const St& y) {                // o = a y
+#pragma unroll
+    for (int r = 0; r < NR; ++r) o.a[r] = make_double2(a * y.a[r].x, a * y.a[r].y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o.y[i] = a * y.y[i];
   }
 
   __device__ static void save(double* dst, const St& y, int N, int Npad) {
@@ -316,6 +328,29 @@ struct Adj {
     }
     for (int i = 0; i < 4; ++i) y.y[i] = src[2 * Npad + i];
   }
+
+  // one RK4 step; with `stages` non-null the four stage states are stored there
+  // (stride SV doubles), in the order Y1 = y, Y2, Y3, Y4
+  __device__ static void rk4(const DevSystem& sy, double t, double h, St& y, double2* lc,
+                             double* red, double* stages, int64_t SV) {
+    St k, acc, Ys;
+    if (stages) save(stages, y, sy.N, sy.Npad);
+    rhs(sy, t, y, k, lc, red);
+    acc = k;
+    axpy(Ys, y, 0.5 * h, k);
+    if (stages) save(stages + SV, Ys, sy.N, sy.Npad);
+    rhs(sy, t + 0.5 * h, Ys, k, lc, red);
+    axpy(acc, acc, 2.0, k);
+    axpy(Ys, y, 0.5 * h, k);
+    if (stages) save(stages + 2 * SV, Ys, sy.N, sy.Npad);
+    rhs(sy, t + 0.5 * h, Ys, k, lc, red);
+    axpy(acc, acc, 2.0, k);
+    axpy(Ys, y, h, k);
+    if (stages) save(stages + 3 * SV, Ys, sy.N, sy.Npad);
+    rhs(sy, t + h, Ys, k, lc, red);
+    axpy(acc, acc, 1.0, k);
+    axpy(y, y, h / 6.0, acc);
+  }
 };
 
 template <bool CPLX, int NR>
@@ -332,15 +367,15 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   double2* lg = lc + Npad;
   double2* ljc = lg + Npad;
   double2* lmc = ljc + Npad;
-  double* red = (double*)(lmc + Npad);     // [ANW][<= 8]
-  double* redt = red + ANW * 8;            // [ANW][36]
+  double* red = (double*)(lmc + Npad);     // [ANW][<= NSC]
+  double* tq = red + ANW * NSC;            // [3 * NGMAX]
   double* scr = A.scratch + (int64_t)b * A.scratch_stride;
   const int64_t SV = 2 * (int64_t)Npad + 4;
   const int S = A.S;
   const int64_t n = tj.n_steps;
   const int64_t nseg = (n + S - 1) / S;
-  double* ck = scr;                          // [nseg][SV]
-  double* seg = scr + (nseg > 0 ? nseg : 1) * SV;   // [S][SV]
+  double* ck = scr;                                   // [nseg][SV]
+  double* seg = scr + (nseg > 0 ? nseg : 1) * SV;     // [S][4][SV] stage states
   const double h = tj.dt, t0 = tj.t0;
 
   St y;
@@ -359,7 +394,7 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   // forward pass with checkpoints
   for (int64_t j = 0; j < n; ++j) {
     if (j % S == 0) K::save(ck + (j / S) * SV, y, N, Npad);
-    K::rk4(sy, t0 + (double)j * h, h, y, lc, red);
+    K::rk4(sy, t0 + (double)j * h, h, y, lc, red, nullptr, SV);
   }
   // final probabilities and the starting adjoint lambda_a = 2 a dL/dP
   St lam;
@@ -378,43 +413,35 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   double gth = 0.0;
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t j0 = sg * S, j1 = (j0 + S < n) ? j0 + S : n;
+    __syncthreads();                     // stage states of the previous segment are consumed
     K::load(ck + sg * SV, y, N, Npad);
-    __syncthreads();
-    for (int64_t j = j0; j < j1; ++j) {
-      K::save(seg + (j - j0) * SV, y, N, Npad);
-      K::rk4(sy, t0 + (double)j * h, h, y, lc, red);
-    }
-    __syncthreads();
+    for (int64_t j = j0; j < j1; ++j)
+      K::rk4(sy, t0 + (double)j * h, h, y, lc, red, seg + 4 * (j - j0) * SV, SV);
+    __syncthreads();                     // publishes the stored classical coordinates
     for (int64_t j = j1 - 1; j >= j0; --j) {
       const double t = t0 + (double)j * h;
-      St Y1, Y2, Y3, Y4, k, kb, yb, dl;
-      K::load(seg + (j - j0) * SV, Y1, N, Npad);
-      K::rhs(sy, t, Y1, k, lc, red);
-      K::axpy(Y2, Y1, 0.5 * h, k);
-      K::rhs(sy, t + 0.5 * h, Y2, k, lc, red);
-      K::axpy(Y3, Y1, 0.5 * h, k);
-      K::rhs(sy, t + 0.5 * h, Y3, k, lc, red);
-      K::axpy(Y4, Y1, h, k);
-      // kbar4 = h/6 lambda
-      for (int r = 0; r < NR; ++r) dl.a[r] = make_double2(0.0, 0.0);
-      for (int i = 0; i < 4; ++i) dl.y[i] = 0.0;
-      St z;
-      for (int r = 0; r < NR; ++r) z.a[r] = make_double2(0.0, 0.0);
-      for (int i = 0; i < 4; ++i) z.y[i] = 0.0;
-      K::axpy(kb, z, h / 6.0, lam);
-      K::vjp(sy, A, t + h, Y4, kb, yb, gth, lc, lg, ljc, lmc, red, redt);
-      K::axpy(dl, dl, 1.0, yb);
-      K::axpy(kb, z, h / 3.0, lam);
+      const double* st = seg + 4 * (j - j0) * SV;
+      St Ys, kb, yb, dl;
+      // kbar4 = h/6 lambda; kbar3 = h/3 lambda + h ybar4; kbar2 = h/3 lambda + h/2 ybar3;
+      // kbar1 = h/6 lambda + h/2 ybar2; lambda += ybar4 + ybar3 + ybar2 + ybar1
+      K::scale(kb, h / 6.0, lam);
+      K::load(st + 3 * SV, Ys, N, Npad);
+      K::vjp(sy, A, t + h, Ys, kb, yb, gth, lc, lg, ljc, lmc, red, tq);
+      dl = yb;
+      K::scale(kb, h / 3.0, lam);
       K::axpy(kb, kb, h, yb);
-      K::vjp(sy, A, t + 0.5 * h, Y3, kb, yb, gth, lc, lg, ljc, lmc, red, redt);
+      K::load(st + 2 * SV, Ys, N, Npad);
+      K::vjp(sy, A, t + 0.5 * h, Ys, kb, yb, gth, lc, lg, ljc, lmc, red, tq);
       K::axpy(dl, dl, 1.0, yb);
-      K::axpy(kb, z, h / 3.0, lam);
+      K::scale(kb, h / 3.0, lam);
       K::axpy(kb, kb, 0.5 * h, yb);
-      K::vjp(sy, A, t + 0.5 * h, Y2, kb, yb, gth, lc, lg, ljc, lmc, red, redt);
+      K::load(st + SV, Ys, N, Npad);
+      K::vjp(sy, A, t + 0.5 * h, Ys, kb, yb, gth, lc, lg, ljc, lmc, red, tq);
       K::axpy(dl, dl, 1.0, yb);
-      K::axpy(kb, z, h / 6.0, lam);
+      K::scale(kb, h / 6.0, lam);
       K::axpy(kb, kb, 0.5 * h, yb);
-      K::vjp(sy, A, t, Y1, kb, yb, gth, lc, lg, ljc, lmc, red, redt);
+      K::load(st, Ys, N, Npad);
+      K::vjp(sy, A, t, Ys, kb, yb, gth, lc, lg, ljc, lmc, red, tq);
       K::axpy(dl, dl, 1.0, yb);
       K::axpy(lam, lam, 1.0, dl);
     }
@@ -486,17 +513,20 @@ __global__ void spline_rows(const double* __restrict__ y, const double* __restri
 int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S) {
   const int64_t SV = 2 * (int64_t)Npad + 4;
   const int64_t nseg = (n_steps + S - 1) / S;
-  return ((nseg > 0 ? nseg : 1) + S) * SV;
+  return ((nseg > 0 ? nseg : 1) + 4 * (int64_t)S) * SV;
 }
 
 hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, int Npad, const TrajIn* d_traj,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
-                          const double* G, const double* rad, const double* rad2, const int* gidx,
-                          int P, int nG, hipStream_t s) {
-  AdjArgs A{d_traj, dLdP, grad_part, P_out, scratch, scratch_stride, S, G, rad, rad2, P, nG, gidx};
-  // four double2 vectors, then red [ANW][8] and redt [ANW][36]
-  const size_t lds = (size_t)Npad * 64 + (size_t)ANW * 8 * 8 + (size_t)ANW * 36 * 8;
+                          const int* goff, const uint32_t* gent, const double* gval,
+                          const double* rad, const double* rad2, const int* gidx, int P, int nG,
+                          hipStream_t s) {
+  if (nG > NGMAX || P > AB) return hipErrorInvalidValue;
+  AdjArgs A{d_traj, dLdP, grad_part, P_out, scratch, scratch_stride, S, goff, gent, gval,
+            rad, rad2, P, nG, gidx};
+  // four double2 vectors, then red [ANW][NSC] and tq [3 NGMAX]
+  const size_t lds = (size_t)Npad * 64 + (size_t)ANW * NSC * 8 + (size_t)3 * NGMAX * 8;
   const int nr = (Npad + AB - 1) / AB;
   hipError_t e;
   if (cplx) {

@@ -25,7 +25,8 @@ struct SysHost {
   int64_t table_bytes = 0;
   // optional linear parametric form of the tables (adjoint)
   int P = 0, nG = 0;
-  void* pbufs[4] = {nullptr, nullptr, nullptr, nullptr};   // G, rad, rad2, gidx
+  // G (dense), rad, rad2, gidx, then the nonzeros of G: offsets, row | col << 16, values
+  void* pbufs[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 // Grow-only device buffer.
@@ -625,8 +626,8 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
   const int N = sh.dev.N, K = sh.dev.K, Npad = sh.dev.Npad;
   if (sh.dev.dtype != R64)
     return fail(c, MQCT_ERR_UNSUPPORTED, "set_params: the parametric form needs R64 storage");
-  if (P < 1 || P > 256 || nG < 1 || nG > 12 || !radial || !gidx || !G)
-    return fail(c, MQCT_ERR_ARG, "set_params: need 1 <= P <= 256, 1 <= nG <= 12 and all arrays");
+  if (P < 1 || P > 256 || nG < 1 || nG > 48 || !radial || !gidx || !G)
+    return fail(c, MQCT_ERR_ARG, "set_params: need 1 <= P <= 256, 1 <= nG <= 48 and all arrays");
   for (int p = 0; p < P; ++p)
     if (gidx[p] < 0 || gidx[p] >= nG) return fail(c, MQCT_ERR_ARG, "set_params: gidx out of range");
   if (!finite_arr(radial, (int64_t)P * K) || !finite_arr(G, (int64_t)nG * N * N))
@@ -640,9 +641,22 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
   HIP_TRY(c, hipStreamSynchronize(c->stream), "set_params");
   free_params(sh);
   std::vector<double> Gp((size_t)nG * N * Npad, 0.0);
-  for (int t = 0; t < nG; ++t)
+  std::vector<int> goff(nG + 1, 0);
+  std::vector<uint32_t> gent;
+  std::vector<double> gval;
+  for (int t = 0; t < nG; ++t) {
     for (int n = 0; n < N; ++n)
-      for (int m = 0; m < N; ++m) Gp[((size_t)t * N + n) * Npad + m] = G[((int64_t)t * N + n) * N + m];
+      for (int m = 0; m < N; ++m) {
+        const double v = G[((int64_t)t * N + n) * N + m];
+        Gp[((size_t)t * N + n) * Npad + m] = v;
+        if (v != 0.0) {
+          gent.push_back((uint32_t)n | ((uint32_t)m << 16));
+          gval.push_back(v);
+        }
+      }
+    goff[t + 1] = (int)gent.size();
+  }
+  const size_t nnz = std::max<size_t>(gent.size(), 1);
   double* tmp = nullptr;
   hipError_t e;
   auto bail = [&](hipError_t err) {
@@ -654,7 +668,15 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
   if ((e = hipMalloc(&sh.pbufs[1], (size_t)P * K * 8)) != hipSuccess) return bail(e);
   if ((e = hipMalloc(&sh.pbufs[2], (size_t)P * K * 8)) != hipSuccess) return bail(e);
   if ((e = hipMalloc(&sh.pbufs[3], (size_t)P * 4)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[4], (size_t)(nG + 1) * 4)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[5], nnz * 4)) != hipSuccess) return bail(e);
+  if ((e = hipMalloc(&sh.pbufs[6], nnz * 8)) != hipSuccess) return bail(e);
   if ((e = hipMalloc((void**)&tmp, (size_t)2 * P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = hipMemcpy(sh.pbufs[4], goff.data(), (size_t)(nG + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (!gent.empty() &&
+       ((e = hipMemcpy(sh.pbufs[5], gent.data(), gent.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(sh.pbufs[6], gval.data(), gval.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)))
+    return bail(e);
   if ((e = hipMemcpy(sh.pbufs[0], Gp.data(), Gp.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(sh.pbufs[1], radial, (size_t)P * K * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(sh.pbufs[3], gidx, (size_t)P * 4, hipMemcpyHostToDevice)) != hipSuccess)
@@ -765,7 +787,8 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
                             (const TrajIn*)(base + o_traj), B, (const double*)(base + o_w),
                             (double*)(base + o_part), (double*)(base + o_g),
                             (double*)(base + o_P), (double*)(base + o_s), stride, S,
-                            (const double*)sh.pbufs[0], (const double*)sh.pbufs[1],
+                            (const int*)sh.pbufs[4], (const uint32_t*)sh.pbufs[5],
+                            (const double*)sh.pbufs[6], (const double*)sh.pbufs[1],
                             (const double*)sh.pbufs[2], (const int*)sh.pbufs[3], sh.P, sh.nG,
                             c->stream), "adjoint: launch");
   prof_mark(&c->prof, e1, c->stream);
