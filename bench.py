@@ -29,12 +29,12 @@ METRIC = ("trajectory-steps/s × N² (coupling GB/s), FP32 vs FP64 at "
 HBM_PEAK_GBPS = 8000.0
 MFMA_PEAK_TFLOPS = {"C64": 157.3, "C128": 78.6}   # dense FP32 / FP64 matrix peaks
 
-# HBM bytes per launch of the step kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# runs scaled by the same counters on a plain 1 GiB copy (profiles/
-# rk4_gemv_N969_window.md).  Valid only for the kernel source they were taken on.
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (profiles/).
+# Valid only for the kernel source file and workload they were taken on.
 MEASURED_TRAFFIC = {
-    "C64": {"source_sha256_16": "b5621ce316b9d137", "bytes": 4.764148906e12,
-            "window": 10, "trajectories": 4096},
+    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "67387674b93d455e",
+                        "bytes": 4.6352e9, "window": 10, "trajectories": 4096},
 }
 
 
@@ -141,10 +141,6 @@ def main():
                                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
                                  "traffic": None, "alg_bytes_per_launch": alg_bytes,
                                  "launch_ms": kms, "launches_timed": kern_n}
-                tr = MEASURED_TRAFFIC.get(storage)
-                if tr and tr["source_sha256_16"] == _kernel_hash() and tr["window"] == W and \
-                        tr["trajectories"] == B:
-                    r["roofline"]["traffic"] = tr["bytes"]
             else:
                 # one product launch per stage: 2 knots x 2 slices x (N x 2N) x (2N x 2) real
                 # multiply-adds per trajectory = 32 N^2 flops per trajectory and stage
@@ -156,6 +152,10 @@ def main():
                                  "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                                  "traffic": None, "alg_flops_per_launch": flops,
                                  "launch_ms": kms, "launches_timed": kern_n}
+            tr = MEASURED_TRAFFIC.get((storage, sched))
+            if tr and tr["source_sha256_16"] == _source_hash(tr["source"]) and \
+                    tr["window"] == W and tr["trajectories"] == B:
+                r["roofline"]["traffic"] = tr["bytes"]
             results[(storage, sched)] = r
             P_of[(storage, sched)] = out["P"].reshape(B, N).cpu().numpy()
             log("%s %s: %.2f ms/step, %.3g traj-steps/s, dominant kernel %.3f ms x %d (%s %.3g %s, "
@@ -239,9 +239,9 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256):
             "L": float(np.sum(w * P)), "grad_norm": float(np.linalg.norm(grad))}
 
 
-def _kernel_hash():
+def _source_hash(name):
     import hashlib
-    src = os.path.join(ROOT, "paper_2312_02322_amd", "csrc", "gemv.hip")
+    src = os.path.join(ROOT, "paper_2312_02322_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 

@@ -33,7 +33,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TB = 32;     // trajectories per GEMM work item (64 real columns)
+constexpr int TB = 32;     // trajectories per GEMM work item (2 TB real columns), a multiple of 8
 constexpr int NT = 256;    // threads of the per-trajectory kernels
 constexpr int NWT = NT / 64;
 
@@ -44,7 +44,7 @@ struct BinWS {
   double2* kv;            // [B][Npad] derivative of the last stage
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
   double2* c64;           // [B][Npad] c = e^{-iEt} a at the current stage, FP64
-  void* cst;              // [B][Npad] c in the table precision (aliases c64 for FP64)
+  void* cst;              // [B][2][KR] the two real columns of c in the table precision
   double4* uv;            // [2][B][Npad] (Re u, Im u, Re v, Im v) from the left / right knot
   double* ycl;            // [B][4] R, Phi, P_R, P_Phi at the start of the step
   double* kcl;            // [B][4] classical derivative of the last stage
@@ -117,7 +117,10 @@ __global__ void bin_zero(int* p, int n) {
 // Stage state of every trajectory: classical stage values, interval and
 // weights, phases and the c columns; adds the trajectory to the counts of its
 // two knots.  diag = 1: the final diagnostic evaluation at the end state.
-template <typename CS>
+// The two real columns of a trajectory (KR = 2 Npad reals for complex tables,
+// Npad for real ones): complex tables take (Re c_n, -Im c_n) and (Im c_n, Re c_n)
+// at reals 2n, 2n+1; real tables take Re c_n and Im c_n.
+template <typename S, bool CPLX>
 __global__ void __launch_bounds__(NT)
 bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag) {
   const int b = blockIdx.x;
@@ -148,7 +151,9 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
     atomicAdd(&ws.cnt[sp.k + 1], 1);
     if (sp.below && !diag) ws.status[b] |= ST_BELOW_GRID;
   }
-  CS* cst = (CS*)ws.cst;
+  const int64_t KR = (CPLX ? 2 : 1) * (int64_t)Npad;
+  S* col0 = (S*)ws.cst + (int64_t)b * 2 * KR;
+  S* col1 = col0 + KR;
   for (int n = threadIdx.x; n < Npad; n += NT) {
     const int64_t o = (int64_t)b * Npad + n;
     double2 c = make_double2(0.0, 0.0);
@@ -160,7 +165,14 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
       c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
     }
     ws.c64[o] = c;
-    if constexpr (sizeof(CS) == 8) cst[o] = make_float2((float)c.x, (float)c.y);
+    const S re = (S)c.x, im = (S)c.y;
+    if constexpr (CPLX) {
+      col0[2 * n] = re; col0[2 * n + 1] = -im;
+      col1[2 * n] = im; col1[2 * n + 1] = re;
+    } else {
+      col0[n] = re;
+      col1[n] = im;
+    }
   }
 }
 
@@ -232,100 +244,113 @@ __device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t off, S 
   }
 }
 
-// One work item (knot g, up to 32 trajectories of its bin) x a tile of rows.
-// Wave w owns RB 16-row blocks; every lane holds, for each of 4 column blocks
+// One work item (knot g, up to TB trajectories of its bin) x a tile of rows.
+// Wave w owns RB 16-row blocks; every lane holds, for each of NX column blocks
 // of 16 real columns (8 trajectories), the 16x16 accumulators of both slices
 // (v_mfma_*_16x16x4: lane l supplies A[l%16][k] and B[k][l%16] with
 // k = l/16; its D values are column l%16, rows 4(l/16)+r for the f32 form
-// and l/16+4r for the f64 form).  Along K each lane loads four
-// consecutive reals, and the four MFMAs of one step take k = k0 + 4(l/16) + i,
-// i = 0..3, on both operands (a permutation of K).
-template <int DT>
-__global__ void __launch_bounds__(256)
-bin_gemm(BinWS ws, const DevSystem* __restrict__ systems) {
+// and l/16+4r for the f64 form).  Along K each lane loads four consecutive
+// reals of the table row and of its real column, and the four MFMAs of one
+// step take k = k0 + 4(l/16) + i, i = 0..3, on both operands (a permutation
+// of K).  NX is the number of column blocks that hold trajectories, so empty
+// blocks cost nothing; the operands of step k0 + 16 are loaded while the MFMAs
+// of step k0 run.
+template <int DT, int NX>
+__device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, int rb, int g,
+                                          int start, int count) {
   constexpr bool FP32 = (DT == C64 || DT == R32);
   constexpr bool CPLX = (DT == C64 || DT == C128);
   using S = typename std::conditional<FP32, float, double>::type;
-  using CS = typename std::conditional<FP32, float2, double2>::type;
   using V = typename MF<S>::V;
-  constexpr int RB = FP32 ? 2 : 1;
+  constexpr int RB = 2;
   constexpr int NCOMP = CPLX ? 2 : 1;
-  const int item = blockIdx.y;
-  if (item >= *ws.n_items) return;
-  const int4 it = ws.items[item];
-  const int g = it.x, start = it.y, count = it.z;
-  const DevSystem sy = systems[ws.traj[0].sys];
   const int N = sy.N, Npad = sy.Npad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int q = lane >> 4, c16 = lane & 15;
-  const int row0 = blockIdx.x * (4 * RB * 16) + wave * RB * 16;
+  const int q = lane >> 4, c16 = lane & 15, part = c16 & 1;
+  const int row0 = rb * (4 * RB * 16) + wave * RB * 16;
   const int64_t ks = sy.knot_stride;
   const uint32_t sbytes = (uint32_t)(ks * NCOMP * (int64_t)sizeof(S));
   const auto rA = slice_rsrc((const S*)sy.M + (int64_t)g * ks * NCOMP, sbytes);
   const auto rB = slice_rsrc((const S*)sy.M2 + (int64_t)g * ks * NCOMP, sbytes);
   const uint32_t rowbytes = (uint32_t)(Npad * NCOMP * sizeof(S));
+  const int KR = Npad * NCOMP;   // real K extent (zero-padded past N)
 
-  // this lane's trajectory in each column block and which real column it is
-  const CS* cols[4];
-  int part[4];
+  // this lane's real column in each column block
+  const S* col[NX];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NX; ++cb) {
     const int jt = (cb * 16 + c16) >> 1;
     const int e = ws.list[start + (jt < count ? jt : 0)];
-    cols[cb] = (const CS*)ws.cst + (int64_t)(e >> 1) * Npad;
-    part[cb] = c16 & 1;
+    col[cb] = (const S*)ws.cst + ((int64_t)(e >> 1) * 2 + part) * KR + 4 * q;
   }
-  V acc[RB][2][4];
+  V acc[RB][2][NX];
 #pragma unroll
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[r][s][cb] = V{0, 0, 0, 0};
+      for (int cb = 0; cb < NX; ++cb) acc[r][s][cb] = V{0, 0, 0, 0};
 
-  const int KR = Npad * NCOMP;   // real K extent (zero-padded past N)
-  for (int k0 = 0; k0 < KR; k0 += 16) {
-    const int kq = k0 + 4 * q;
-    S a[RB][2][4];
+  S a[RB][2][4], an[RB][2][4], bv[NX][4], bn[NX][4];
+  auto load = [&](int k0, S (&ao)[RB][2][4], S (&bo)[NX][4]) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const uint32_t off = (uint32_t)(row0 + r * 16 + c16) * rowbytes + (uint32_t)kq * sizeof(S);
-      load4<S>(rA, off, a[r][0]);
-      load4<S>(rB, off, a[r][1]);
+      const uint32_t off =
+          (uint32_t)(row0 + r * 16 + c16) * rowbytes + (uint32_t)(k0 + 4 * q) * sizeof(S);
+      load4<S>(rA, off, ao[r][0]);
+      load4<S>(rB, off, ao[r][1]);
     }
-    S bv[4][4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      if constexpr (CPLX) {
-        const CS c0 = cols[cb][kq >> 1], c1 = cols[cb][(kq >> 1) + 1];
-        if (part[cb] == 0) { bv[cb][0] = c0.x; bv[cb][1] = -c0.y; bv[cb][2] = c1.x; bv[cb][3] = -c1.y; }
-        else { bv[cb][0] = c0.y; bv[cb][1] = c0.x; bv[cb][2] = c1.y; bv[cb][3] = c1.x; }
+    for (int cb = 0; cb < NX; ++cb) {
+      if constexpr (FP32) {
+        const float4 v = *(const float4*)(col[cb] + k0);
+        bo[cb][0] = v.x; bo[cb][1] = v.y; bo[cb][2] = v.z; bo[cb][3] = v.w;
       } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const CS c = cols[cb][kq + i];
-          bv[cb][i] = part[cb] == 0 ? c.x : c.y;
-        }
+        const double2 v0 = *(const double2*)(col[cb] + k0);
+        const double2 v1 = *(const double2*)(col[cb] + k0 + 2);
+        bo[cb][0] = v0.x; bo[cb][1] = v0.y; bo[cb][2] = v1.x; bo[cb][3] = v1.y;
       }
     }
+  };
+  auto mma = [&](const S (&ai)[RB][2][4], const S (&bi)[NX][4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
+      for (int cb = 0; cb < NX; ++cb)
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-            acc[r][s][cb] = MF<S>::mfma(a[r][s][i], bv[cb][i], acc[r][s][cb]);
+          for (int s = 0; s < 2; ++s)
+            acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bi[cb][i], acc[r][s][cb]);
+  };
+  load(0, a, bv);
+  for (int k0 = 0; k0 < KR; k0 += 16) {
+    // the last step reloads its own operands (unused) rather than branch
+    load(k0 + 16 < KR ? k0 + 16 : k0, an, bn);
+    // keep the loads ahead of the products and the register moves (and hence
+    // the waits for the loads) behind them
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a, bv);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[r][s][i] = an[r][s][i];
+#pragma unroll
+    for (int cb = 0; cb < NX; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bv[cb][i] = bn[cb][i];
   }
 
   // epilogue: apply this column's spline weights (left or right knot)
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NX; ++cb) {
     const int jt = (cb * 16 + c16) >> 1;
     if (jt >= count) continue;
     const int e = ws.list[start + jt];
-    const int b = e >> 1, side = e & 1, p = part[cb];
+    const int b = e >> 1, side = e & 1;
     const double* w = ws.wts + (int64_t)b * 8;
     const double wA = side ? w[1] : w[0], wB = side ? w[3] : w[2];
     const double dA = side ? w[5] : w[4], dB = side ? w[7] : w[6];
@@ -338,11 +363,50 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems) {
         const int n = row0 + r * 16 + (FP32 ? 4 * q + i : q + 4 * i);
         if (n < N) {
           const double z = (double)acc[r][0][cb][i], z2 = (double)acc[r][1][cb][i];
-          o[(int64_t)n * 4 + p] = wA * z + wB * z2;
-          o[(int64_t)n * 4 + 2 + p] = dA * z + dB * z2;
+          o[(int64_t)n * 4 + part] = wA * z + wB * z2;
+          o[(int64_t)n * 4 + 2 + part] = dA * z + dB * z2;
         }
       }
   }
+}
+
+template <int DT, int NX>
+__device__ __forceinline__ void gemm_dispatch(const BinWS& ws, const DevSystem& sy, int rb, int g,
+                                              int start, int count, int ncb) {
+  if constexpr (NX > 1) {
+    if (ncb < NX) {
+      gemm_dispatch<DT, NX - 1>(ws, sy, rb, g, start, count, ncb);
+      return;
+    }
+  }
+  gemm_item<DT, NX>(ws, sy, rb, g, start, count);
+}
+
+constexpr int NXCD = 8;    // accelerator dies (each with its own L2) of the device
+// Dynamic LDS requested by every product workgroup (unused): more than half of
+// a CU's 160 KiB, so one workgroup is resident per CU.  Fewer concurrent items
+// keep the table rows and columns streaming through each die's L2 small; with
+// the operands of the next K step in flight this ran faster than two or three
+// resident workgroups per CU.
+constexpr size_t GEMM_LDS_CAP = 96 * 1024;
+
+// Work w = item * nrb + row block, items ordered by knot.  Workgroups are
+// handed to the dies round-robin by id, so die x receives ids x, x + 8, ...;
+// mapping those to one contiguous share of the work list keeps the row blocks
+// of an item (which read the same columns) and the items of one knot (which
+// read the same table rows) on one die's L2.
+template <int DT>
+__global__ void __launch_bounds__(256)
+bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
+  const int total = *ws.n_items * nrb;
+  const int per = (total + NXCD - 1) / NXCD;
+  const int x = blockIdx.x % NXCD, jj = blockIdx.x / NXCD;
+  const int w = x * per + jj;
+  if (jj >= per || w >= total) return;
+  const int item = w / nrb, rb = w - item * nrb;
+  const int4 it = ws.items[item];
+  const DevSystem sy = systems[ws.traj[0].sys];
+  gemm_dispatch<DT, TB / 8>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
 }
 
 // Combine the two knots' contributions, add the Coriolis term, reduce the
@@ -472,7 +536,7 @@ size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
   const size_t v = (size_t)B * Npad;
   size_t s = 0;
   s += 4 * al(v * 16);                    // a0, kv, acc, c64
-  s += fp32 ? al(v * 8) : 0;              // cst
+  s += al(v * 2 * 2 * (fp32 ? 4 : 8));    // cst (two real columns, complex worst case)
   s += al(2 * v * 32);                    // uv
   s += 4 * al((size_t)B * 32);            // ycl kcl acl ysb
   s += al((size_t)B * 64) + al((size_t)B * 8) + al((size_t)B * 32);   // wts tst diag
@@ -497,7 +561,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   ws.kv = (double2*)take(v * 16);
   ws.acc = (double2*)take(v * 16);
   ws.c64 = (double2*)take(v * 16);
-  ws.cst = fp32 ? take(v * 8) : (void*)ws.c64;
+  ws.cst = take(v * 2 * 2 * (fp32 ? 4 : 8));
   ws.uv = (double4*)take(2 * v * 32);
   ws.ycl = (double*)take((size_t)B * 32);
   ws.kcl = (double*)take((size_t)B * 32);
@@ -518,24 +582,28 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   ws.n_items = (int*)take(16);
 
   const bool cplx = dtype_complex(hs.dtype);
-  const int rows_per_block = (fp32 ? 2 : 1) * 4 * 16;
-  const dim3 ggrid((hs.N + rows_per_block - 1) / rows_per_block, max_items);
+  const int rows_per_block = 2 * 4 * 16;
+  const int nrb = (hs.N + rows_per_block - 1) / rows_per_block;
+  const int64_t gblocks = ((int64_t)nrb * max_items + NXCD - 1) / NXCD * NXCD;
+  const dim3 ggrid((unsigned)gblocks);
   hipError_t e;
   bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cnt, hs.K);
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cursor, hs.K);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   auto stage = [&](int64_t j, int st, int diag) -> hipError_t {
-    if (fp32) bin_prep<float2><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
-    else bin_prep<double2><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    if (hs.dtype == C64) bin_prep<float, true><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    else if (hs.dtype == C128) bin_prep<double, true><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    else if (hs.dtype == R32) bin_prep<float, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+    else bin_prep<double, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
     bin_scan<<<1, 1024, 0, s>>>(ws);
     bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
     hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
     prof_mark(prof, e0, s);
-    if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, 0, s>>>(ws, d_systems);
-    else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, 0, s>>>(ws, d_systems);
-    else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, 0, s>>>(ws, d_systems);
-    else bin_gemm<R64><<<ggrid, 256, 0, s>>>(ws, d_systems);
+    if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+    else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+    else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+    else bin_gemm<R64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
     prof_mark(prof, e1, s);
     bin_combine<<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
     return hipGetLastError();
