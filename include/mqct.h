@@ -69,7 +69,10 @@ enum {
   MQCT_SCHED_GEMV = 1,        /* one workgroup per trajectory, step loop inside a kernel */
   MQCT_SCHED_BINNED = 2,      /* lockstep stages, trajectories binned by spline knot,
                                  table x amplitude-columns products on matrix cores    */
-  MQCT_SCHED_PERSISTENT = 3   /* persistent workgroups draining a trajectory queue     */
+  MQCT_SCHED_QUEUE = 3        /* work list: one step attempt per launch for every
+                                 unfinished trajectory, finished ones retired between
+                                 chunks of launches (replayed as HIP graphs); mixes
+                                 systems of any size; the schedule DP5 always uses    */
 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -191,7 +194,17 @@ typedef struct {
 
 /* Propagate a batch.  Errors: MQCT_ERR_ARG, MQCT_ERR_STATE (unknown system),
  * MQCT_ERR_UNSUPPORTED (schedule/integrator combination), MQCT_ERR_OOM,
- * MQCT_ERR_DEVICE.  Per-trajectory problems go to the status bits. */
+ * MQCT_ERR_DEVICE.  Per-trajectory problems go to the status bits.
+ * DP5 (Dormand & Prince 1980 tableau, first same as last; error = scaled RMS
+ * over the 2N+6 real state components with sc = atol + rtol max(|y|, |y_new|);
+ * step factor min(5, max(0.2, 0.9 err^-1/5)), no growth right after a
+ * rejection; Hairer-Norsett-Wanner starting step) stops at the first accepted
+ * step with R >= R0 and P_R > 0 (EXITED), at max_steps accepted steps or
+ * 4 max_steps + 256 attempts (MAX_STEPS), when h < h_min (STEP_UNDERFLOW), or on
+ * a non-finite error (NONFINITE).  The work-list schedule (MQCT_SCHED_QUEUE, and
+ * every DP5 batch) runs until every trajectory has finished and returns after
+ * the results are enqueued; it synchronises with the context stream between
+ * chunks of launches. */
 mqct_status mqct_run(mqct_context* ctx, const mqct_batch_desc* batch,
                      mqct_batch_result* result);
 
@@ -242,10 +255,33 @@ mqct_status mqct_adjoint(mqct_context* ctx, const mqct_batch_desc* batch, int32_
                          const double* dL_dP, double* dL_dtheta, double* P_out);
 
 /*
+ * Options of the work-list schedule (MQCT_SCHED_QUEUE and DP5):
+ *   MQCT_OPT_GRAPHS        1 (default): each chunk of step launches plus the
+ *                          work-list compaction is captured once per grid size as
+ *                          a HIP graph and replayed; 0: launched one by one.
+ *   MQCT_OPT_AUTOTUNE      1 (default): the first batch of each (storage type,
+ *                          padded N, integrator) class times the candidate
+ *                          workgroup shapes (64..512 threads, fewest rows per lane
+ *                          covering N) on a copy of up to 2048 of its
+ *                          trajectories and keeps the fastest for the context;
+ *                          0: the per-trajectory schedule's shape.
+ *   MQCT_OPT_CHUNK         step launches per replay (1..4096, default 16).
+ *   MQCT_OPT_RESET_TUNING  forget the shapes chosen so far (value ignored).
+ * A batch is computed with one shape per class throughout, so results are
+ * reproducible for a given set of choices.  Errors: MQCT_ERR_ARG.
+ */
+enum { MQCT_OPT_GRAPHS = 1, MQCT_OPT_AUTOTUNE = 2, MQCT_OPT_CHUNK = 3, MQCT_OPT_RESET_TUNING = 4 };
+mqct_status mqct_set_option(mqct_context* ctx, int32_t option, int64_t value);
+/* The shapes chosen so far, as JSON text: one object per class with dtype,
+ * npad, method (0 RK4, 1 DP5), block, rows_per_lane, tuned, and the candidates'
+ * milliseconds per step launch.  Valid until the next call on ctx. */
+const char* mqct_tuning_report(mqct_context* ctx);
+
+/*
  * Optional timing of the dominant step kernel of later runs: the fused
- * per-trajectory RK4 kernel, or the table x columns product of the binned
- * schedule.  HIP events are recorded on the context stream around each of its
- * launches.  mqct_profile_read waits for the stream, returns the summed
+ * per-trajectory RK4 kernel, the table x columns product of the binned
+ * schedule, or each replayed chunk of the work-list schedule.  HIP events are
+ * recorded on the context stream around each of its launches.  mqct_profile_read waits for the stream, returns the summed
  * milliseconds and the number of timed launches since the last read, and
  * resets both.  Timing adds two event records per timed launch.
  */

@@ -22,7 +22,8 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_NOT_HERMITIAN, ERR_OOM, ERR_DEVICE, ERR_UNSUPPOR
     0, -1, -2, -3, -4, -5, -6, -7
 DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
 INTEGRATORS = {"rk4": 0, "dp5": 1}
-SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "persistent": 3}
+SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3}
+OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4}
 MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
 
@@ -30,7 +31,8 @@ STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NO
 EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
            "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
-           "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint"]
+           "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
+           "mqct_set_option", "mqct_tuning_report"]
 
 
 class MQCTError(RuntimeError):
@@ -101,6 +103,10 @@ def lib():
         L.mqct_system_set_theta.restype = i32
         L.mqct_adjoint.argtypes = [vp, C.POINTER(BatchDesc), i32, vp, vp, vp]
         L.mqct_adjoint.restype = i32
+        L.mqct_set_option.argtypes = [vp, i32, i64]
+        L.mqct_set_option.restype = i32
+        L.mqct_tuning_report.argtypes = [vp]
+        L.mqct_tuning_report.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -336,6 +342,15 @@ class Context:
         self._check(lib().mqct_adjoint(self.h, C.byref(bd), int(checkpoint_every), w.ctypes.data,
                                        g.ctypes.data, P.ctypes.data))
         return g, P.reshape(B, N)
+
+    def set_option(self, name, value=1):
+        """Work-list schedule options: graphs, autotune, chunk, reset_tuning."""
+        self._check(lib().mqct_set_option(self.h, OPTIONS[name], int(value)))
+
+    def tuning_report(self):
+        """The autotuner's shape choices so far (parsed JSON)."""
+        import json
+        return json.loads(lib().mqct_tuning_report(self.h).decode())
 
     def set_profiling(self, enable=True):
         """Time the dominant step kernel of later runs with HIP events."""

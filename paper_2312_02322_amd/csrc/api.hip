@@ -45,7 +45,13 @@ struct mqct_context {
   std::vector<SysHost> systems;
   DevSystem* d_systems = nullptr;
   size_t d_systems_cap = 0;
-  DevBuf traj, a0, outs[10], xs[4], kscratch, counter, binws;
+  DevBuf traj, a0, outs[10], xs[4], qws, binws;
+  hipStream_t cap = nullptr;       // non-default stream on which graphs are captured
+  int* h_counts = nullptr;         // pinned host copy of the work-list counts
+  size_t h_counts_cap = 0;
+  QueueOpts qopt;                  // work-list schedule options
+  QueueCache qcache;               // autotuner decisions
+  std::string report;              // last text of mqct_tuning_report
   TrajIn* h_traj = nullptr;        // pinned staging for trajectory records
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
@@ -157,6 +163,12 @@ mqct_status mqct_create(int32_t device, void* hip_stream, mqct_context** out) {
     delete c;
     return MQCT_ERR_DEVICE;
   }
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    hipEventDestroy(c->staged);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return MQCT_ERR_DEVICE;
+  }
   *out = c;
   return MQCT_OK;
 }
@@ -168,10 +180,12 @@ void mqct_destroy(mqct_context* c) {
   for (auto& s : c->systems) free_system(s);
   if (c->d_systems) hipFree(c->d_systems);
   DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3],
-                   &c->kscratch, &c->counter, &c->binws};
+                   &c->qws, &c->binws};
   for (DevBuf* b : all) if (b->p) hipFree(b->p);
   for (auto& b : c->outs) if (b.p) hipFree(b.p);
   if (c->h_traj) hipHostFree(c->h_traj);
+  if (c->h_counts) hipHostFree(c->h_counts);
+  if (c->cap) hipStreamDestroy(c->cap);
   if (c->staged) hipEventDestroy(c->staged);
   for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
   if (c->own_stream) hipStreamDestroy(c->stream);
@@ -387,7 +401,7 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     return fail(c, MQCT_ERR_ARG, "run: result mem must be host or device");
   if (bd->integrator != MQCT_RK4 && bd->integrator != MQCT_DP5)
     return fail(c, MQCT_ERR_ARG, "run: unknown integrator %d", bd->integrator);
-  if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_PERSISTENT)
+  if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_QUEUE)
     return fail(c, MQCT_ERR_ARG, "run: unknown schedule %d", bd->schedule);
   const bool binned = bd->schedule == MQCT_SCHED_BINNED;
   if (binned && bd->integrator != MQCT_RK4)
@@ -398,14 +412,8 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
         return fail(c, MQCT_ERR_UNSUPPORTED, "run: a binned batch must use a single system");
   }
   const bool dp5 = bd->integrator == MQCT_DP5;
-  // DP5 always runs on the persistent queue (trajectory lengths differ)
-  const bool persistent = dp5 || bd->schedule == MQCT_SCHED_PERSISTENT;
-  // The persistent-queue kernel (and with it the adaptive integrator) is
-  // switched off: its first GPU runs stopped making progress and the cause has
-  // not been identified, so it is not launched.
-  if (persistent)
-    return fail(c, MQCT_ERR_UNSUPPORTED,
-                "run: the persistent queue / DP5 path is disabled in this build");
+  // DP5 always runs on the work-list schedule (trajectory lengths differ)
+  const bool queue = dp5 || bd->schedule == MQCT_SCHED_QUEUE;
   if (dp5) {
     if (!(bd->rtol > 0.0) || !(bd->atol > 0.0) || bd->max_steps < 1 || !(bd->h_min >= 0.0))
       return fail(c, MQCT_ERR_ARG, "run: DP5 needs rtol > 0, atol > 0, max_steps >= 1, h_min >= 0");
@@ -492,37 +500,43 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     }
   }
   // Order of the records on the device.  Per-trajectory launches need each
-  // storage type contiguous.  Persistent launches need each precision family
-  // (C64 + R32, C128 + R64) contiguous, and take the most expensive
+  // storage type contiguous.  The work-list schedule needs each class (storage
+  // type and padded column count) contiguous, and takes the most expensive
   // trajectories first (cost ~ N^2 x free-flight time 2 R0 / v0), so the
   // longest ones never start last.
   std::vector<TrajIn> sorted;
   sorted.reserve(B);
   std::vector<std::pair<int64_t, int64_t>> ranges(4, {0, 0});
+  std::vector<QueueClass> classes;
   auto cost_of = [&](int64_t b) {
     const TrajIn& t = c->h_traj[b];
     const double n = c->systems[t.sys].dev.N;
     double T = 1.0;
     if (!(t.flags & TRAJ_HAS_C0) && t.E_coll > 0.0)
       T = 2.0 * t.R0 / sqrt(2.0 * t.E_coll / c->systems[t.sys].dev.mu);
+    else if (t.n_steps > 0)
+      T = (double)t.n_steps;
     return n * n * T;
   };
-  if (!persistent) {
+  if (!queue) {
     for (int d = 0; d < 4; ++d) {
       ranges[d].first = (int64_t)sorted.size();
       for (int64_t b : order[d]) sorted.push_back(c->h_traj[b]);
       ranges[d].second = (int64_t)sorted.size();
     }
   } else {
-    const int fams[2][2] = {{C64, R32}, {C128, R64}};
-    for (auto& fam : fams) {
+    std::map<std::pair<int, int>, std::vector<int64_t>> by_class;
+    for (int64_t b = 0; b < B; ++b) {
+      const DevSystem& sy = c->systems[c->h_traj[b].sys].dev;
+      by_class[{sy.dtype, sy.Npad}].push_back(b);
+    }
+    for (auto& kv : by_class) {
       std::vector<std::pair<double, int64_t>> cost;
-      for (int d : fam)
-        for (int64_t b : order[d]) cost.push_back({-cost_of(b), b});
+      for (int64_t b : kv.second) cost.push_back({-cost_of(b), b});
       std::stable_sort(cost.begin(), cost.end());
-      const int64_t lo = (int64_t)sorted.size();
+      QueueClass qc{kv.first.first, kv.first.second, (int64_t)sorted.size(), (int64_t)cost.size()};
       for (auto& pr : cost) sorted.push_back(c->h_traj[pr.second]);
-      for (int d : fam) ranges[d] = {lo, (int64_t)sorted.size()};
+      classes.push_back(qc);
     }
   }
   memcpy(c->h_traj, sorted.data(), B * sizeof(TrajIn));
@@ -573,7 +587,7 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     hipError_t e = run_binned(c->d_systems, hs, (const TrajIn*)c->traj.p, (int)B, max_steps,
                               d_a0, out, c->binws.p, c->stream, &c->prof);
     if (e != hipSuccess) return hip_fail(c, e, "run: binned launch");
-  } else if (!persistent) {
+  } else if (!queue) {
     for (int d = 0; d < 4; ++d) {
       int64_t n = ranges[d].second - ranges[d].first;
       if (n == 0) continue;
@@ -584,31 +598,33 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
       if (e != hipSuccess) return hip_fail(c, e, "run: launch");
     }
   } else {
-    // one persistent launch per precision family (FP32 tables: C64 + R32,
-    // FP64 tables: C128 + R64); records are ordered by the host (largest first)
+    for (const QueueClass& qc : classes)
+      if (qc.npad > 4096 || qc.n > INT32_MAX)
+        return fail(c, MQCT_ERR_UNSUPPORTED, "run: N or B too large for the work-list schedule");
+    const int method = dp5 ? 1 : 0;
     DpCtl ctl{bd->rtol, bd->atol, bd->h_min, bd->max_steps};
-    const int fams[2][2] = {{C64, R32}, {C128, R64}};
-    for (int f = 0; f < 2; ++f) {
-      const int d0 = fams[f][0], d1 = fams[f][1];
-      const int64_t lo = ranges[d0].first;
-      const int64_t n = ranges[d0].second - ranges[d0].first;
-      if (n == 0) continue;
-      const int npad = std::max(max_npad[d0], max_npad[d1]);
-      const int groups = std::max(max_npad[d0] / (d0 == C128 ? 1 : 2), max_npad[d1] / 2);
-      if (groups > 1024)
-        return fail(c, MQCT_ERR_UNSUPPORTED, "run: N too large for the persistent schedule");
-      int64_t slots = persistent_slots(f == 0, groups, npad);
-      if (slots <= 0) return fail(c, MQCT_ERR_DEVICE, "run: occupancy query failed");
-      slots = std::min(slots, n);
-      if ((st = ensure(c, c->kscratch, (size_t)slots * 8 * npad * 16, "run: stage scratch")) != MQCT_OK)
-        return st;
-      if ((st = ensure(c, c->counter, 64, "run: queue counter")) != MQCT_OK) return st;
-      hipError_t e = launch_persistent(c->d_systems, (const TrajIn*)c->traj.p + lo, n, d_a0, out,
-                                       f == 0, npad, groups, dp5 ? 1 : 0, ctl,
-                                       (unsigned long long*)c->counter.p, (double2*)c->kscratch.p,
-                                       slots, c->stream);
-      if (e != hipSuccess) return hip_fail(c, e, "run: persistent launch");
+    // RK4: one step per attempt; DP5: accepted steps plus a bound on rejections
+    int64_t max_attempts = 0;
+    if (dp5) {
+      max_attempts = 4 * bd->max_steps + 256;
+    } else {
+      for (int64_t b = 0; b < B; ++b) max_attempts = std::max(max_attempts, c->h_traj[b].n_steps);
     }
+    if ((st = ensure(c, c->qws, queue_workspace_bytes(classes, method), "run: work-list workspace")) != MQCT_OK)
+      return st;
+    if (classes.size() > c->h_counts_cap) {
+      if (c->h_counts) hipHostFree(c->h_counts);
+      c->h_counts = nullptr;
+      c->h_counts_cap = 0;
+      HIP_TRY(c, hipHostMalloc((void**)&c->h_counts, classes.size() * 4 + 64, 0), "run: counts");
+      c->h_counts_cap = classes.size() + 16;
+    }
+    hipError_t e = run_queue(c->d_systems, (const TrajIn*)c->traj.p, classes, d_a0, out, method,
+                             ctl, max_attempts, c->qopt, c->qcache, c->qws.p, c->stream, c->cap,
+                             c->h_counts, &c->prof);
+    if (e == hipErrorInvalidValue)
+      return fail(c, MQCT_ERR_UNSUPPORTED, "run: no workgroup shape for this N and storage type");
+    if (e != hipSuccess) return hip_fail(c, e, "run: work-list schedule");
   }
   for (auto& p : back)
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
@@ -799,6 +815,46 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
             "adjoint");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "adjoint");
   return MQCT_OK;
+}
+
+mqct_status mqct_set_option(mqct_context* c, int32_t option, int64_t value) {
+  if (!c) return MQCT_ERR_ARG;
+  switch (option) {
+    case MQCT_OPT_GRAPHS: c->qopt.graphs = value != 0; return MQCT_OK;
+    case MQCT_OPT_AUTOTUNE: c->qopt.tune = value != 0; return MQCT_OK;
+    case MQCT_OPT_CHUNK:
+      if (value < 1 || value > 4096) return fail(c, MQCT_ERR_ARG, "set_option: chunk must be 1..4096");
+      c->qopt.chunk = (int)value;
+      return MQCT_OK;
+    case MQCT_OPT_RESET_TUNING: c->qcache.entries.clear(); return MQCT_OK;
+  }
+  return fail(c, MQCT_ERR_ARG, "set_option: unknown option %d", option);
+}
+
+const char* mqct_tuning_report(mqct_context* c) {
+  if (!c) return "";
+  std::string r = "[";
+  char buf[256];
+  for (size_t i = 0; i < c->qcache.entries.size(); ++i) {
+    const QueueTuneEntry& en = c->qcache.entries[i];
+    const QKernelSet& ks = queue_kernels(en.dtype)[en.shape];
+    snprintf(buf, sizeof buf,
+             "%s{\"dtype\": %d, \"npad\": %d, \"method\": %d, \"block\": %d, \"rows_per_lane\": %d, "
+             "\"tuned\": %s, \"candidates\": [",
+             i ? ", " : "", en.dtype, en.npad, en.method, ks.block, ks.rpt * (en.dtype == C128 ? 1 : 2),
+             en.tuned ? "true" : "false");
+    r += buf;
+    for (size_t j = 0; j < en.ms.size(); ++j) {
+      const QKernelSet& kj = queue_kernels(en.dtype)[en.ms[j].first];
+      snprintf(buf, sizeof buf, "%s{\"block\": %d, \"rows_per_lane\": %d, \"ms\": %.6g}",
+               j ? ", " : "", kj.block, kj.rpt * (en.dtype == C128 ? 1 : 2), en.ms[j].second);
+      r += buf;
+    }
+    r += "]}";
+  }
+  r += "]";
+  c->report = r;
+  return c->report.c_str();
 }
 
 mqct_status mqct_set_profiling(mqct_context* c, int32_t enable) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 namespace mqct {
@@ -113,17 +114,78 @@ struct DpCtl {
   int64_t max_steps;
 };
 
-// Persistent workgroups over a trajectory queue, RK4 (method 0) or DP5
-// (method 1).  All systems of the launch belong to one precision family
-// (fp32_family: C64/R32, else C128/R64); max_groups = max over systems of the
-// 16-byte column groups per stored row (<= 1024).  kscratch holds
-// slots * 8 * max_npad double2; counter is one zeroed-by-the-launch word.
-hipError_t launch_persistent(const DevSystem* d_systems, const TrajIn* d_traj, int64_t n_traj,
-                             const double* d_a0, TrajOut out, bool fp32_family, int max_npad,
-                             int max_groups, int method, DpCtl ctl, unsigned long long* counter,
-                             double2* kscratch, int64_t slots, hipStream_t s);
-// Resident workgroups of the persistent kernel on the current device.
-int64_t persistent_slots(bool fp32_family, int max_groups, int max_npad);
+// ---- work-list schedule (queue_kernels.h, queue.hip) -------------------------
+
+// State of one trajectory between step launches (written by lane 0).
+struct QState {
+  double t, h;
+  double yc[4];        // R, Phi, P_R, P_Phi
+  double kc1[4];       // classical derivative at (t, y): first stage of the next attempt
+  double E0, J0, R_exit, theta, ptheta;
+  int64_t steps, rejects, attempts;
+  int32_t status, flags;
+};
+enum { Q_DONE = 1, Q_LASTREJ = 2 };
+
+// Device workspace of one class (trajectories sharing storage type and Npad).
+struct QWS {
+  int32_t n, npad;
+  const TrajIn* traj;  // [n] records of the class
+  QState* st;          // [n]
+  double2* amp;        // [n][npad] amplitudes
+  double2* kst;        // [n][8][npad] DP5 stage derivatives and fifth-order solution
+  int32_t* list;       // [n] work list (class-local indices of unfinished trajectories)
+  int32_t* count;      // [1] entries on the work list
+};
+
+struct QArgs {
+  QWS ws;
+  const DevSystem* systems;
+  const double* a0_all;
+  DpCtl ctl;
+  int64_t max_attempts;
+  TrajOut out;
+};
+
+// Kernels of one workgroup shape: init and step for RK4 [0] and DP5 [1]
+// (null when the shape is not built for the storage type).
+struct QKernelSet {
+  int block, rpt;
+  const void* init[2];
+  const void* step[2];
+};
+const QKernelSet* queue_kernels(int dtype);   // [QUEUE_SHAPES]
+constexpr int QUEUE_SHAPES = 11;
+
+struct QueueClass {
+  int dtype, npad;
+  int64_t first, n;    // records [first, first + n) of the device record array
+};
+
+struct QueueOpts {
+  bool graphs = true;  // replay chunks of step launches as HIP graphs
+  bool tune = true;    // time the candidate workgroup shapes on the batch
+  int chunk = 16;      // step launches per replay
+};
+
+// Autotuner decisions, kept for the life of a context.
+struct QueueTuneEntry {
+  int dtype, npad, method, shape;
+  bool tuned;
+  std::vector<std::pair<int, double>> ms;   // candidate shape -> ms per step launch
+};
+struct QueueCache {
+  std::vector<QueueTuneEntry> entries;
+};
+
+size_t queue_workspace_bytes(const std::vector<QueueClass>& cls, int method);
+// Runs a batch on the work-list schedule.  `cap` is a non-default stream used
+// only to capture graphs; `h_counts` is pinned host memory for cls.size() ints.
+hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
+                     const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
+                     int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
+                     QueueCache& cache, void* ws, hipStream_t s, hipStream_t cap, int* h_counts,
+                     Prof* prof);
 
 // R-binned lockstep RK4 (all trajectories on one system, d_traj in any order).
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32);

@@ -1,0 +1,367 @@
+// Host side of the work-list schedule (kernels: queue_kernels.h).
+//
+// A batch is split into classes of trajectories that share the storage type
+// and padded column count of their systems (systems may differ within a
+// class).  Each class has its own work list, its own tuned workgroup shape and
+// its own step launches.  The host replays chunks of `chunk` step launches
+// followed by one compaction (as a HIP graph captured once per grid size),
+// reads the active counts back, and shrinks the grid as trajectories retire.
+// Every launch reads the active count from device memory, so the work a
+// replay does always matches the list, whatever grid the graph was built with.
+//
+// Autotuner: for each class (storage type, Npad, method) the candidate shapes
+// are the workgroup sizes 64..512 with the fewest rows per lane that cover
+// the padded row count (lanes within a factor two of it).  After the batch's
+// init launch, the candidates are timed on a copy of the state of up to
+// TUNE_SAMPLE of the class's trajectories (two passes of two step launches
+// each; results are not written), and the fastest is kept for the context.
+#include "rhs.h"
+
+#include <algorithm>
+#include <map>
+
+namespace mqct {
+
+const QKernelSet* queue_kernels_r64();
+const QKernelSet* queue_kernels_c128();
+const QKernelSet* queue_kernels_r32();
+const QKernelSet* queue_kernels_c64();
+
+const QKernelSet* queue_kernels(int dtype) {
+  switch (dtype) {
+    case R64: return queue_kernels_r64();
+    case C128: return queue_kernels_c128();
+    case R32: return queue_kernels_r32();
+    case C64: return queue_kernels_c64();
+  }
+  return nullptr;
+}
+
+namespace {
+
+constexpr int64_t TUNE_SAMPLE = 2048;
+constexpr int CT = 1024;   // threads of the compaction kernel
+
+// Stable in-place compaction of the work list: entries whose trajectory is
+// done are dropped.  The list is processed in chunks of CT entries in order;
+// within a chunk every entry is read before any is written, and a kept entry
+// moves to a position no later than its own, so no unread entry is overwritten.
+__global__ void __launch_bounds__(CT) q_compact(int32_t* list, int32_t* count,
+                                               const QState* __restrict__ st) {
+  __shared__ int32_t wsum[CT / 64];
+  __shared__ int32_t base;
+  const int n = *count;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += CT) {
+    const int p = c0 + threadIdx.x;
+    int v = 0;
+    bool keep = false;
+    if (p < n) {
+      v = list[p];
+      keep = !(st[v].flags & Q_DONE);
+    }
+    const unsigned long long m = __ballot(keep);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int q = 0; q < w; ++q) off += wsum[q];
+    if (keep) list[off + before] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int q = 0; q < CT / 64; ++q) tot += wsum[q];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+// Work list = all sample slots, count = n (used by the autotuner's copies).
+__global__ void q_iota(int32_t* list, int32_t* count, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) list[i] = i;
+  if (i == 0) *count = n;
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t class_bytes(int64_t n, int npad, int method) {
+  size_t s = al((size_t)n * sizeof(QState)) + al((size_t)n * npad * 16) + al((size_t)n * 4);
+  if (method == 1) s += al((size_t)n * 8 * npad * 16);
+  return s;
+}
+
+QWS carve(char*& p, int64_t n, int npad, int method, const TrajIn* traj) {
+  QWS w{};
+  w.n = (int32_t)n;
+  w.npad = npad;
+  w.traj = traj;
+  w.st = (QState*)p; p += al((size_t)n * sizeof(QState));
+  w.amp = (double2*)p; p += al((size_t)n * npad * 16);
+  w.list = (int32_t*)p; p += al((size_t)n * 4);
+  if (method == 1) { w.kst = (double2*)p; p += al((size_t)n * 8 * npad * 16); }
+  return w;
+}
+
+int vec_of(int dtype) { return dtype == C128 ? 1 : 2; }
+
+// The per-trajectory schedule's shape: the smallest workgroup covering the
+// row groups with one group per lane, else 512 threads with more per lane.
+int default_shape(int dtype, int npad) {
+  const int g = npad / vec_of(dtype);
+  if (g <= 64) return 0;
+  if (g <= 128) return 2;
+  if (g <= 256) return 4;
+  if (g <= 512) return 7;
+  if (g <= 1024) return 8;
+  if (g <= 2048) return 9;
+  if (g <= 4096) return 10;
+  return -1;
+}
+
+std::vector<int> candidates(int dtype, int npad, int method) {
+  const QKernelSet* t = queue_kernels(dtype);
+  const int g = npad / vec_of(dtype);
+  const int need = std::max(g, 64);
+  std::vector<int> c;
+  for (int k = 0; k < QUEUE_SHAPES; ++k) {
+    if (!t[k].step[method]) continue;
+    const int lanes = t[k].block * t[k].rpt;
+    bool minimal = true;   // fewest rows per lane for this workgroup size
+    for (int j = 0; j < QUEUE_SHAPES; ++j)
+      if (j != k && t[j].step[method] && t[j].block == t[k].block && t[j].rpt < t[k].rpt &&
+          t[j].block * t[j].rpt >= g)
+        minimal = false;
+    if (lanes >= g && lanes < 2 * need && minimal) c.push_back(k);
+  }
+  return c;
+}
+
+hipError_t launch(const void* fn, int grid, int block, size_t lds, hipStream_t s, QArgs& a) {
+  if (grid <= 0) return hipSuccess;
+  void* args[] = {&a};
+  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args, lds, s);
+}
+
+hipError_t prepare_fn(const void* fn, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+struct ClassRun {
+  QueueClass c;
+  QWS ws;
+  int shape = -1;
+  size_t lds = 0;
+  int count = 0;   // last active count read back
+  int grid = 0;    // grid of the current graph / launches
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+size_t queue_workspace_bytes(const std::vector<QueueClass>& cls, int method) {
+  size_t s = al(cls.size() * 4 + 4) + al(8);
+  size_t tune = 0;
+  for (const auto& c : cls) {
+    s += class_bytes(c.n, c.npad, method);
+    tune = std::max(tune, class_bytes(std::min(c.n, TUNE_SAMPLE), c.npad, method));
+  }
+  return s + tune;
+}
+
+hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
+                     const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
+                     int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
+                     QueueCache& cache, void* wsp, hipStream_t s, hipStream_t cap, int* h_counts,
+                     Prof* prof) {
+  hipError_t e;
+  char* p = (char*)wsp;
+  int32_t* d_counts = (int32_t*)p;
+  p += al(cls.size() * 4 + 4);
+  int32_t* d_tcount = (int32_t*)p;
+  p += al(8);
+  std::vector<ClassRun> runs(cls.size());
+  for (size_t k = 0; k < cls.size(); ++k) {
+    ClassRun& r = runs[k];
+    r.c = cls[k];
+    r.ws = carve(p, r.c.n, r.c.npad, method, d_traj + r.c.first);
+    r.ws.count = d_counts + k;
+    r.lds = rhs::lds_bytes(r.c.npad, dtype_fp32(r.c.dtype));
+  }
+  char* tune_area = p;
+
+  auto args_for = [&](const QWS& w) {
+    QArgs a;
+    a.ws = w;
+    a.systems = d_systems;
+    a.a0_all = d_a0;
+    a.ctl = ctl;
+    a.max_attempts = max_attempts;
+    a.out = out;
+    return a;
+  };
+
+  // shapes: cached decision, else default or to be tuned after init
+  std::vector<size_t> to_tune;
+  for (size_t k = 0; k < runs.size(); ++k) {
+    ClassRun& r = runs[k];
+    for (const auto& en : cache.entries)
+      if (en.dtype == r.c.dtype && en.npad == r.c.npad && en.method == method) r.shape = en.shape;
+    if (r.shape >= 0) continue;
+    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method);
+    if (cand.empty()) return hipErrorInvalidValue;
+    const int def = default_shape(r.c.dtype, r.c.npad);
+    r.shape = std::find(cand.begin(), cand.end(), def) != cand.end() ? def : cand.back();
+    if (opt.tune && cand.size() > 1) {
+      to_tune.push_back(k);
+    } else {
+      QueueTuneEntry en{r.c.dtype, r.c.npad, method, r.shape, false, {}};
+      cache.entries.push_back(en);
+    }
+  }
+
+  auto init_class = [&](ClassRun& r) -> hipError_t {
+    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
+    QArgs a = args_for(r.ws);
+    hipError_t err = prepare_fn(ks.init[method], r.lds);
+    if (err != hipSuccess) return err;
+    r.count = (int)r.c.n;
+    r.grid = (int)r.c.n;
+    return launch(ks.init[method], (int)r.c.n, ks.block, r.lds, s, a);
+  };
+  // classes to be tuned start with the default shape, so the candidates are
+  // timed on real states
+  std::vector<int> init_shape(runs.size(), -1);
+  for (size_t k : to_tune) {
+    if ((e = init_class(runs[k])) != hipSuccess) return e;
+    init_shape[k] = runs[k].shape;
+  }
+
+  // autotuner: time each candidate on a copy of the sampled state
+  for (size_t k : to_tune) {
+    ClassRun& r = runs[k];
+    const int64_t S = std::min(r.c.n, TUNE_SAMPLE);
+    char* q = tune_area;
+    QWS tw = carve(q, S, r.c.npad, method, r.ws.traj);
+    tw.count = d_tcount;
+    TrajOut none{};
+    QArgs a = args_for(tw);
+    a.out = none;
+    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method);
+    std::vector<double> best(cand.size(), 1e300);
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return e; }
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
+        const QKernelSet& ks = queue_kernels(r.c.dtype)[cand[ci]];
+        const size_t bytes_st = (size_t)S * sizeof(QState);
+        if ((e = hipMemcpyAsync(tw.st, r.ws.st, bytes_st, hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(tw.amp, r.ws.amp, (size_t)S * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
+        if (method == 1 &&
+            (e = hipMemcpyAsync(tw.kst, r.ws.kst, (size_t)S * 8 * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+          break;
+        q_iota<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(tw.list, tw.count, (int)S);
+        if ((e = prepare_fn(ks.step[method], r.lds)) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+          e = launch(ks.step[method], (int)S, ks.block, r.lds, s, a);
+        if (e != hipSuccess) break;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (pass == 1) best[ci] = ms / 2.0;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+      if (best[ci] < best[bi]) bi = ci;
+    r.shape = cand[bi];
+    QueueTuneEntry en{r.c.dtype, r.c.npad, method, r.shape, true, {}};
+    for (size_t ci = 0; ci < cand.size(); ++ci) en.ms.push_back({cand[ci], best[ci]});
+    cache.entries.push_back(en);
+  }
+  // every class starts from an init with its final shape, so a batch is
+  // computed with one shape throughout
+  for (size_t k = 0; k < runs.size(); ++k)
+    if (init_shape[k] != runs[k].shape)
+      if ((e = init_class(runs[k])) != hipSuccess) return e;
+
+  // step chunks until every work list is empty
+  const int chunk = std::max(1, opt.chunk);
+  const int64_t max_rounds = (max_attempts + chunk - 1) / chunk + 2;
+  auto enqueue_chunk = [&](ClassRun& r, hipStream_t st) -> hipError_t {
+    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
+    QArgs a = args_for(r.ws);
+    hipError_t err;
+    for (int j = 0; j < chunk; ++j)
+      if ((err = launch(ks.step[method], r.grid, ks.block, r.lds, st, a)) != hipSuccess) return err;
+    q_compact<<<1, CT, 0, st>>>(r.ws.list, r.ws.count, r.ws.st);
+    return hipGetLastError();
+  };
+  auto drop_graph = [](ClassRun& r) {
+    if (r.exec) (void)hipGraphExecDestroy(r.exec);
+    r.exec = nullptr;
+  };
+  for (ClassRun& r : runs) {
+    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
+    if ((e = prepare_fn(ks.step[method], r.lds)) != hipSuccess) return e;
+  }
+  e = hipSuccess;
+  int64_t round = 0;
+  for (; round < max_rounds; ++round) {
+    bool any = false;
+    for (ClassRun& r : runs) {
+      if (r.count <= 0) continue;
+      any = true;
+      // shrink the grid once fewer than half of its workgroups have work
+      if (r.count * 2 <= r.grid) {
+        r.grid = r.count;
+        drop_graph(r);
+      }
+      hipEvent_t ea = prof ? prof->next() : nullptr, eb = prof ? prof->next() : nullptr;
+      prof_mark(prof, ea, s);
+      if (opt.graphs) {
+        if (!r.exec) {
+          hipGraph_t g = nullptr;
+          if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
+          hipError_t ec = enqueue_chunk(r, cap);
+          hipError_t ee = hipStreamEndCapture(cap, &g);
+          if (ec != hipSuccess || ee != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            e = ec != hipSuccess ? ec : ee;
+            break;
+          }
+          e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
+          hipGraphDestroy(g);
+          if (e != hipSuccess) { r.exec = nullptr; break; }
+        }
+        if ((e = hipGraphLaunch(r.exec, s)) != hipSuccess) break;
+      } else {
+        if ((e = enqueue_chunk(r, s)) != hipSuccess) break;
+      }
+      prof_mark(prof, eb, s);
+    }
+    if (e != hipSuccess || !any) break;
+    if ((e = hipMemcpyAsync(h_counts, d_counts, runs.size() * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    for (size_t k = 0; k < runs.size(); ++k) runs[k].count = h_counts[k];
+  }
+  for (ClassRun& r : runs) drop_graph(r);
+  if (e != hipSuccess) return e;
+  for (const ClassRun& r : runs)
+    if (r.count > 0) return hipErrorLaunchTimeOut;   // attempt bound exceeded (cannot happen)
+  return hipSuccess;
+}
+
+}  // namespace mqct

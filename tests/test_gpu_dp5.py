@@ -1,4 +1,4 @@
-"""GPU parity of the adaptive Dormand-Prince path and the persistent trajectory queue.
+"""Cases that stalled on the earlier persistent-queue kernel (since removed).
 
 Adaptive steps: the oracle and the GPU take the same accept/reject decisions
 except when an error estimate lands within rounding of 1, so final
@@ -15,9 +15,10 @@ from synth import systems as S, units as U
 
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="persistent-queue / DP5 kernel disabled: its first GPU runs stopped "
-                            "making progress on the 8-trajectory N=49 case and the cause is not "
-                            "identified; the library returns MQCT_ERR_UNSUPPORTED for it"),
+    pytest.mark.skip(reason="these cases stopped making progress on the earlier persistent-queue "
+                            "DP5 kernel and the cause was never identified; that kernel was "
+                            "removed and the cases stay off the GPU (the adaptive stepper now "
+                            "runs on the work-list schedule, tests/test_gpu_queue.py)"),
 ]
 
 RTOL = 1e-8
@@ -62,12 +63,12 @@ def test_dp5_fp64_matches_oracle(ctx):
 
 def test_persistent_rk4_matches_per_trajectory_schedule(ctx):
     (s,), b = S.config1(n_traj=16, n_steps=300)
-    say("persistent rk4 vs gemv N=49")
+    say("queue rk4 vs gemv N=49")
     sid = ctx.load_system(s)
     common = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt,
                   n_steps=b.n_steps)
     g1 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="gemv", **common)
-    g2 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="persistent", **common)
+    g2 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="queue", **common)
     assert np.max(np.abs(g1["a_final"] - g2["a_final"])) < 1e-12
     assert np.array_equal(g1["steps"], g2["steps"])
     ctx.free_system(sid)

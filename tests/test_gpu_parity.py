@@ -283,13 +283,21 @@ def test_cross_sections_on_device(ctx):
     ctx.free_system(sid)
 
 
-def test_disabled_persistent_path_reports_unsupported(ctx, gpu_lib):
-    """The switched-off DP5 / persistent path fails cleanly, before any launch."""
+def test_unsupported_combinations_report_cleanly(ctx, gpu_lib):
+    """Adaptive steps on the lockstep binned schedule and an unknown schedule fail
+    before any launch."""
     (s,), b = S.config1(n_traj=2, n_steps=10, jmax=1)
     sid = ctx.load_system(s)
-    for kw in (dict(integrator="dp5"), dict(schedule="persistent", dt=b.dt, n_steps=b.n_steps)):
+    common = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
+    with pytest.raises(gpu_lib.MQCTError) as e:
+        ctx.run_host([sid] * 2, [s.N] * 2, integrator="dp5", schedule="binned", **common)
+    assert e.value.code == gpu_lib.ERR_UNSUPPORTED
+    gpu_lib.SCHEDULES["bogus"] = 7
+    try:
         with pytest.raises(gpu_lib.MQCTError) as e:
-            ctx.run_host([sid] * 2, [s.N] * 2, init_channel=b.init_channel, E_coll=b.E_coll,
-                         b=b.b, R0=b.R0, **kw)
-        assert e.value.code == gpu_lib.ERR_UNSUPPORTED
+            ctx.run_host([sid] * 2, [s.N] * 2, schedule="bogus", dt=b.dt, n_steps=b.n_steps,
+                         **common)
+        assert e.value.code == gpu_lib.ERR_ARG
+    finally:
+        del gpu_lib.SCHEDULES["bogus"]
     ctx.free_system(sid)
