@@ -58,6 +58,15 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--workload", choices=["window", "large", "uneven"], default="window",
+                    help="window: N=969 mid-collision windows (default, the headline); "
+                         "large: N=4096, 512 full collisions of 10,000 RK4 steps on the binned "
+                         "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5")
+    ap.add_argument("--large-n", type=int, default=4096)
+    ap.add_argument("--large-traj", type=int, default=512)
+    ap.add_argument("--large-steps", type=int, default=10000)
+    ap.add_argument("--large-window", type=int, default=1000)
+    ap.add_argument("--uneven-traj", type=int, default=20000)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -75,6 +84,12 @@ def main():
 
     if args.adjoint == "only":
         print(json.dumps(adjoint_timing(args.adjoint_traj, args.adjoint_steps)), flush=True)
+        return
+    if args.workload == "large":
+        print(json.dumps(large_workload(args)), flush=True)
+        return
+    if args.workload == "uneven":
+        print(json.dumps(uneven_workload(args)), flush=True)
         return
     t0 = time.time()
     (s,), b = S.config2(n_traj=args.traj, full_collision=False, window_steps=args.window)
@@ -123,7 +138,7 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             wall = (time.time() - wall0) / args.steps
-            kern_ms, kern_n = ctx.profile_read()
+            kern_ms, kern_n, kern_bytes = ctx.profile_read(with_bytes=True)
             ctx.set_profiling(False)
             ms = e0.elapsed_time(e1) / args.steps
             evals = B * (4 * W + 1)              # RK4 stages + the final diagnostic evaluation
@@ -151,7 +166,10 @@ def main():
                 r["roofline"] = {"kernel": "bin_gemm", "bound": "mfma", "achieved": tf,
                                  "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                                  "traffic": None, "alg_flops_per_launch": flops,
-                                 "launch_ms": kms, "launches_timed": kern_n}
+                                 "launch_ms": kms, "launches_timed": kern_n,
+                                 # the occupied knots' slices, read once per stage
+                                 "table_bytes_per_launch": kern_bytes / kern_n,
+                                 "table_GBps": kern_bytes / (kern_ms * 1e-3) / 1e9}
             tr = MEASURED_TRAFFIC.get((storage, sched))
             if tr and tr["source_sha256_16"] == _source_hash(tr["source"]) and \
                     tr["window"] == W and tr["trajectories"] == B:
@@ -203,6 +221,210 @@ def main():
     if args.adjoint == "on":
         line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps)
     print(json.dumps(line), flush=True)
+
+
+def large_workload(args):
+    """N = 4096 random Hermitian tables (54 GB as complex128 values, built on the
+    GPU), 512 trajectories from 20 A in lockstep, full collisions of 10,000 RK4
+    steps (dt = T/10^4) on the binned schedule, FP32 and FP64 tables.  The
+    collision runs as consecutive windows of --large-window steps chained through
+    the final amplitudes, classical state and time (one progress line each).
+    Also: per-trajectory schedule vs binned on 8 trajectories x 200 steps (FP64)."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+    N, B, T, W = args.large_n, args.large_traj, args.large_steps, args.large_window
+    t0 = time.time()
+    (s,), b = S.config5(n_traj=B, n_steps=T, N=N, build_tables=False)
+    ctx = mq.Context(0)
+    dev = ctx.device
+    Md = S.gp_tables_device(s, dev)
+    torch.cuda.synchronize()
+    s.labels["gp"] = None
+    log("large: N=%d tables built on the device in %.1fs" % (N, time.time() - t0))
+    res, finals = {}, {}
+    for storage in ([args.only] if args.only else ["C64", "C128"]):
+        t1 = time.time()
+        sid = ctx.load_system(R_grid=s.R_grid, E=s.E, M=Md, jx=None, mu=s.mu, storage=storage)
+        torch.cuda.synchronize()
+        log("large: loaded %s (%.1f GB) in %.1fs" % (storage, ctx.system_bytes(sid) / 1e9,
+                                                     time.time() - t1))
+        sids, Ns = np.full(B, sid, np.int32), np.full(B, N, np.int64)
+        stream = torch.cuda.current_stream(dev)
+        state = None
+        ms_tot = 0.0
+        kern_ms = kern_n = kern_bytes = 0
+        for w in range(T // W):
+            kw = dict(dt=b.dt, n_steps=np.full(B, W), schedule="binned")
+            if state is None:
+                kw.update(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
+            else:
+                kw.update(a0=state[0], classical0=state[1], t0=state[2])
+            ctx.set_profiling(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = ctx.run(sids, Ns, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            km, kn, kb = ctx.profile_read(with_bytes=True)
+            ctx.set_profiling(False)
+            kern_ms += km
+            kern_n += kn
+            kern_bytes += kb
+            ms = e0.elapsed_time(e1)
+            ms_tot += ms
+            state = (out["a_final"].cpu().numpy().reshape(B, N), out["classical"].cpu().numpy(),
+                     out["t_final"].cpu().numpy())
+            R = state[1][:, 0]
+            log("large %s: window %d/%d %.0f ms, R %.1f..%.1f bohr, max|norm-1| %.2e" % (
+                storage, w + 1, T // W, ms, R.min(), R.max(),
+                float(out["norm_err"].abs().max().item())))
+        P = np.abs(state[0]) ** 2
+        finals[storage] = P
+        flops = 32.0 * N * N * B
+        kms = kern_ms / max(kern_n, 1)
+        tf = flops / (kms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[storage]
+        gbps = kern_bytes / (kern_ms * 1e-3) / 1e9
+        # mid-collision only a few trajectories share a knot, so the product reads
+        # each occupied knot's slices for few columns: report the roof it is nearer
+        mf = {"kernel": "bin_gemm", "bound": "mfma", "achieved": tf, "peak": peak,
+              "unit": "TFLOP/s", "frac": tf / peak, "traffic": None,
+              "alg_flops_per_launch": flops, "launch_ms": kms, "launches_timed": kern_n}
+        hb = {"kernel": "bin_gemm", "bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS,
+              "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+              "alg_bytes_per_launch": kern_bytes / max(kern_n, 1), "launch_ms": kms,
+              "launches_timed": kern_n}
+        roof = dict(hb if hb["frac"] > mf["frac"] else mf)
+        roof["other_roof"] = {k: (mf if roof["bound"] == "hbm" else hb)[k]
+                              for k in ("bound", "achieved", "peak", "unit", "frac")}
+        res[storage] = {
+            "value": B * T / (ms_tot * 1e-3), "ms_per_window": ms_tot / (T // W),
+            "total_s": ms_tot * 1e-3,
+            "N2_traj_steps_per_s": B * T * float(N) * N / (ms_tot * 1e-3),
+            "roofline": roof,
+            "max_norm_err": float(np.max(np.abs(P.sum(1) - 1.0)))}
+        log("large %s: %.3g traj-steps/s, bin_gemm %.3f ms (%.1f TFLOP/s = %.1f%%; %.0f GB/s "
+            "of tables = %.1f%%)" % (storage, res[storage]["value"], kms, tf, 100 * tf / peak,
+                                     gbps, 100 * gbps / HBM_PEAK_GBPS))
+        if storage == "C128":
+            # per-trajectory schedule vs binned at full size: 8 trajectories x 200 steps
+            sub = np.arange(8)
+            kw = dict(init_channel=b.init_channel[sub], E_coll=b.E_coll[sub], b=b.b[sub],
+                      R0=b.R0[sub], dt=b.dt[sub], n_steps=np.full(8, 200))
+            g1 = ctx.run_host(np.full(8, sid, np.int32), np.full(8, N), schedule="gemv", **kw)
+            g2 = ctx.run_host(np.full(8, sid, np.int32), np.full(8, N), schedule="binned", **kw)
+            res[storage]["gemv_vs_binned_max_abs_dP_8x200"] = float(np.max(np.abs(g1["P"] - g2["P"])))
+            log("large: gemv vs binned (8 x 200 steps) max|dP| = %.3e"
+                % res[storage]["gemv_vs_binned_max_abs_dP_8x200"])
+        ctx.free_system(sid)
+    del Md
+    ctx.close()
+    head = res.get("C64") or res["C128"]
+    line = {"metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
+            "steps": T // W, "warmup": 0, "ms_per_step": head["ms_per_window"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if "C64" in res else "f64", "data": "synthetic",
+            "config": {"workload": "N=%d random Hermitian tables on 200 R points, %d full "
+                                   "collisions of %d RK4 steps from 20 A, binned schedule, "
+                                   "one bench step = %d steps" % (N, B, T, W),
+                       "N": N, "trajectories": B, "rk4_steps": T, "tables": list(res)},
+            "roofline": head["roofline"], "variants": res}
+    if "C64" in finals and "C128" in finals:
+        d = np.abs(finals["C64"] - finals["C128"])
+        line["fp32_vs_fp64_dP"] = {"max": float(d.max()), "mean": float(d.mean()),
+                                   "p99": float(np.percentile(d, 99))}
+        line["fp32_speedup_over_fp64"] = res["C64"]["value"] / res["C128"]["value"]
+    return line
+
+
+def uneven_workload(args):
+    """Three systems in one batch -- rotor + atom (N = 49), rotor + rotor (N = 256),
+    asymmetric top + atom (N = 969) -- 60 / 30 / 10 % of --uneven-traj trajectories,
+    collision energies log-uniform in 10-5000 cm^-1, adaptive DP5 (rtol = atol =
+    1e-8, at most 10^5 steps), FP32 tables, on the work-list schedule.  A warm-up
+    batch (the first 4000 trajectories, 50 steps) lets the autotuner pick each
+    class's shape; the timed run is the whole batch from start to finish."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+    t0 = time.time()
+    systems, b = S.config3(n_traj=args.uneven_traj)
+    log("uneven: generated %s, B=%d in %.1fs" % ([x.N for x in systems], b.B, time.time() - t0))
+    ctx = mq.Context(0)
+    kinds = ["R32", "R32", "C64"]
+    ids = [ctx.load_system(x, storage=k) for x, k in zip(systems, kinds)]
+    sids = np.array([ids[i] for i in b.system_index], np.int32)
+    Ns = np.array([systems[i].N for i in b.system_index], np.int64)
+    DP = dict(integrator="dp5", rtol=1e-8, atol=1e-8, h_min=1e-6)
+    start = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
+    w = np.arange(min(4000, b.B))
+    ctx.run_host(sids[w], Ns[w], init_channel=b.init_channel[w], E_coll=b.E_coll[w], b=b.b[w],
+                 R0=b.R0[w], max_steps=50, **DP)
+    log("uneven: autotuner %s" % ctx.tuning_report())
+    torch.cuda.synchronize()
+    t1 = time.time()
+    g = ctx.run_host(sids, Ns, max_steps=100000, **start, **DP)
+    sec = time.time() - t1
+    steps, rej = g["steps"], g["rejects"]
+    npad = ((Ns + 15) // 16) * 16
+    es = np.array([{"R32": 4, "C64": 8}[kinds[i]] for i in b.system_index])
+    evals = 6 * (steps + rej) + 3          # attempts x 6, the two starting evaluations, the end
+    alg_bytes = float(np.sum(evals * 4.0 * Ns * npad * es))
+    per = {}
+    for si, x in enumerate(systems):
+        m = b.system_index == si
+        st = steps[m]
+        per["N=%d" % x.N] = {"trajectories": int(m.sum()), "storage": kinds[si],
+                             "steps_p0_p50_p90_p100": [int(v) for v in
+                                                       np.percentile(st, [0, 50, 90, 100])],
+                             "rejects": int(rej[m].sum()),
+                             "exited": int(np.count_nonzero(g["status"][m] & 1)),
+                             "max_steps_reached": int(np.count_nonzero(g["status"][m] & 2))}
+    gbps = alg_bytes / sec / 1e9
+    line = {"metric": METRIC, "value": float(steps.sum()) / sec, "unit": "traj-steps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sec * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "uneven batch of %d trajectories: N=49/256/969 systems "
+                                   "60/30/10 %%, E_coll log-uniform 10-5000 cm^-1, DP5 rtol 1e-8, "
+                                   "FP32 tables, work-list schedule" % b.B,
+                       "trajectories": b.B},
+            "N2_traj_steps_per_s": float(np.sum(steps * Ns.astype(float) ** 2)) / sec,
+            "coupling_GBps": gbps,
+            "roofline": {"kernel": "q_step (all classes, whole job incl. tail)", "bound": "hbm",
+                         "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBPS, "traffic": None},
+            "per_system": per, "autotuner": ctx.tuning_report()}
+    log("uneven: %.1f s, %d steps, %.3g traj-steps/s, %.0f GB/s coupling" % (
+        sec, int(steps.sum()), line["value"], gbps))
+    ctx.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = uneven_cpu_baseline(systems, b)
+    return line
+
+
+def uneven_cpu_baseline(systems, b, per_system=8, max_steps=2000):
+    """The FP64 oracle's DP5 on 8 trajectories of each system (the first of each in
+    batch order), at most 2000 steps each."""
+    import numpy as np
+    import oracle
+    tot_steps, tot_s = 0, 0.0
+    th = oracle.threads()
+    for si, x in enumerate(systems):
+        idx = np.where(b.system_index == si)[0][:per_system]
+        o = oracle.OracleSystem(x)
+        t0 = time.time()
+        r = o.propagate(b.subset(idx), method="dp5", rtol=1e-8, atol=1e-8, max_steps=max_steps,
+                        h_min=1e-6)
+        tot_s += time.time() - t0
+        tot_steps += int(r["steps"].sum())
+    log("uneven oracle: %d steps in %.1fs on %d threads" % (tot_steps, tot_s, th))
+    return {"value": tot_steps / tot_s, "unit": "traj-steps/s", "cores": th, "kind": "oracle",
+            "sample": "%d trajectories of each of the three systems (FP64 oracle DP5, at most "
+                      "%d steps each); wall time of the propagation only" % (per_system, max_steps)}
 
 
 def adjoint_timing(n_traj, n_steps, checkpoint_every=256):

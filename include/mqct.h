@@ -281,12 +281,21 @@ const char* mqct_tuning_report(mqct_context* ctx);
  * Optional timing of the dominant step kernel of later runs: the fused
  * per-trajectory RK4 kernel, the table x columns product of the binned
  * schedule, or each replayed chunk of the work-list schedule.  HIP events are
- * recorded on the context stream around each of its launches.  mqct_profile_read waits for the stream, returns the summed
- * milliseconds and the number of timed launches since the last read, and
- * resets both.  Timing adds two event records per timed launch.
+ * recorded on the context stream around each of its launches.
+ * mqct_profile_read waits for the stream and returns, since the last read:
+ *   total_ms      summed milliseconds of the timed launches;
+ *   launches      their number;
+ *   table_bytes   (may be NULL) the algorithmic coupling-table bytes those
+ *                 launches had to read: per-trajectory RK4, 4 spline slices of
+ *                 N x Npad stored elements per right-hand side (4 per step plus
+ *                 the final diagnostic one); binned product, the value and
+ *                 second-derivative slices of every occupied knot once per stage
+ *                 (counted on the device); 0 for the work-list schedule.
+ * and resets them.  Timing adds two event records per timed launch.
  */
 mqct_status mqct_set_profiling(mqct_context* ctx, int32_t enable);
-mqct_status mqct_profile_read(mqct_context* ctx, double* total_ms, int64_t* launches);
+mqct_status mqct_profile_read(mqct_context* ctx, double* total_ms, int64_t* launches,
+                              double* table_bytes);
 
 #ifdef __cplusplus
 }

@@ -95,7 +95,7 @@ def lib():
         L.mqct_cross_sections.restype = i32
         L.mqct_set_profiling.argtypes = [vp, i32]
         L.mqct_set_profiling.restype = i32
-        L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64)]
+        L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)]
         L.mqct_profile_read.restype = i32
         L.mqct_system_set_params.argtypes = [vp, i32, i32, vp, vp, i32, vp]
         L.mqct_system_set_params.restype = i32
@@ -356,10 +356,13 @@ class Context:
         """Time the dominant step kernel of later runs with HIP events."""
         self._check(lib().mqct_set_profiling(self.h, 1 if enable else 0))
 
-    def profile_read(self):
-        """(total milliseconds, launches) of the timed kernel since the last read."""
-        ms, n = C.c_double(), C.c_int64()
-        self._check(lib().mqct_profile_read(self.h, C.byref(ms), C.byref(n)))
+    def profile_read(self, with_bytes=False):
+        """(total milliseconds, launches) of the timed kernel since the last read, and
+        with_bytes=True also the algorithmic table bytes those launches read."""
+        ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+        self._check(lib().mqct_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(by)))
+        if with_bytes:
+            return ms.value, n.value, by.value
         return ms.value, n.value
 
     def cross_sections(self, P, b, init_level, level_of_channel, n_levels, b_max):

@@ -188,6 +188,7 @@ void mqct_destroy(mqct_context* c) {
   if (c->cap) hipStreamDestroy(c->cap);
   if (c->staged) hipEventDestroy(c->staged);
   for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
+  if (c->prof.slots) hipHostFree(c->prof.slots);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -591,6 +592,14 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     for (int d = 0; d < 4; ++d) {
       int64_t n = ranges[d].second - ranges[d].first;
       if (n == 0) continue;
+      if (c->prof.on) {
+        // RK4 stages plus the final diagnostic evaluation, four slices each
+        for (int64_t q = ranges[d].first; q < ranges[d].second; ++q) {
+          const DevSystem& sy = c->systems[c->h_traj[q].sys].dev;
+          c->prof.bytes += (4.0 * c->h_traj[q].n_steps + 1.0) * 4.0 * sy.N * (double)sy.Npad *
+                           dtype_bytes(sy.dtype);
+        }
+      }
       hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->traj.p + ranges[d].first, n,
                                      d_a0, out, d, max_npad[d], c->stream, &c->prof);
       if (e == hipErrorInvalidValue)
@@ -861,11 +870,12 @@ mqct_status mqct_set_profiling(mqct_context* c, int32_t enable) {
   if (!c) return MQCT_ERR_ARG;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "set_profiling");
   c->prof.on = enable != 0;
-  c->prof.used = 0;
+  c->prof.reset();
   return MQCT_OK;
 }
 
-mqct_status mqct_profile_read(mqct_context* c, double* total_ms, int64_t* launches) {
+mqct_status mqct_profile_read(mqct_context* c, double* total_ms, int64_t* launches,
+                              double* table_bytes) {
   if (!c) return MQCT_ERR_ARG;
   if (!total_ms || !launches) return fail(c, MQCT_ERR_ARG, "profile_read: null output");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "profile_read");
@@ -879,7 +889,13 @@ mqct_status mqct_profile_read(mqct_context* c, double* total_ms, int64_t* launch
   }
   *total_ms = tot;
   *launches = n;
-  c->prof.used = 0;
+  if (table_bytes) {
+    double by = c->prof.bytes;
+    for (size_t i = 0; i < c->prof.slot_bytes.size(); ++i)
+      by += (double)c->prof.slots[i] * c->prof.slot_bytes[i];
+    *table_bytes = by;
+  }
+  c->prof.reset();
   return MQCT_OK;
 }
 

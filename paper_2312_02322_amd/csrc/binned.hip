@@ -62,6 +62,7 @@ struct BinWS {
   int* list;              // [2B] bin entries 2 b + side (0: left knot, 1: right knot)
   int4* items;            // [max_items] (knot, first entry, count, 0)
   int* n_items;           // [1]
+  unsigned long long* occ;   // [1] occupied knots summed over the stages of the run
 };
 
 __device__ __forceinline__ double stage_frac(int st) {
@@ -181,16 +182,18 @@ __global__ void __launch_bounds__(1024) bin_scan(BinWS ws) {
   const int K = ws.K;
   __shared__ int ioff_s[2049];
   if (threadIdx.x == 0) {
-    int off = 0, io = 0;
+    int off = 0, io = 0, occupied = 0;
     for (int g = 0; g < K; ++g) {
       const int c = ws.cnt[g];
       ws.offset[g] = off;
       ioff_s[g] = io;
       off += c;
       io += (c + TB - 1) / TB;
+      occupied += c > 0;
     }
     ioff_s[K] = io;
     *ws.n_items = io;
+    *ws.occ += (unsigned long long)occupied;
   }
   __syncthreads();
   for (int g = threadIdx.x; g < K; g += blockDim.x) {
@@ -544,6 +547,7 @@ size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
   s += 3 * al((size_t)K * 4);             // cnt cursor offset
   s += al((size_t)2 * B * 4);             // list
   s += al(((size_t)2 * B / TB + K + 1) * 16) + al(16);   // items, n_items
+  s += al(16);                                            // occ
   return s;
 }
 
@@ -580,6 +584,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   const int max_items = 2 * B / TB + hs.K + 1;
   ws.items = (int4*)take((size_t)max_items * 16);
   ws.n_items = (int*)take(16);
+  ws.occ = (unsigned long long*)take(16);
 
   const bool cplx = dtype_complex(hs.dtype);
   const int rows_per_block = 2 * 4 * 16;
@@ -590,6 +595,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cnt, hs.K);
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cursor, hs.K);
+  bin_zero<<<1, 256, 0, s>>>((int*)ws.occ, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   auto stage = [&](int64_t j, int st, int diag) -> hipError_t {
     if (hs.dtype == C64) bin_prep<float, true><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
@@ -612,7 +618,13 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   for (int64_t j = 0; j < max_steps; ++j)
     for (int st = 0; st < 4; ++st)
       if ((e = stage(j, st, 0)) != hipSuccess) return e;
-  return stage(max_steps, 0, 1);
+  if ((e = stage(max_steps, 0, 1)) != hipSuccess) return e;
+  // algorithmic table bytes of the timed products: each occupied knot's value
+  // and second-derivative slices, read once per stage
+  unsigned long long* slot =
+      prof ? prof->knot_slot(2.0 * hs.N * (double)hs.Npad * dtype_bytes(hs.dtype)) : nullptr;
+  if (slot) e = hipMemcpyAsync(slot, ws.occ, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  return e;
 }
 
 }  // namespace mqct

@@ -69,11 +69,18 @@ enum { ST_EXITED = 1, ST_MAX_STEPS = 2, ST_STEP_UNDERFLOW = 4, ST_BELOW_GRID = 8
        ST_NONFINITE = 16 };
 
 // Optional event timing of the dominant step kernel (HIP events recorded on
-// the launch stream around each of its launches).
+// the launch stream around each of its launches), with the algorithmic table
+// bytes those launches had to read: known on the host for the per-trajectory
+// kernel, counted on the device (occupied knots per stage) for the binned
+// product and copied into pinned slots read after the stream has finished.
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t used = 0;
+  double bytes = 0.0;           // host-known algorithmic bytes
+  unsigned long long* slots = nullptr;   // pinned, device-filled knot counts
+  std::vector<double> slot_bytes;        // bytes per counted knot of each used slot
+  static constexpr size_t SLOTS = 4096;
   // the next event of the pool (created on demand), or null when off / failed
   hipEvent_t next() {
     if (!on) return nullptr;
@@ -83,6 +90,22 @@ struct Prof {
       ev.push_back(e);
     }
     return ev[used++];
+  }
+  // a pinned slot for a device-side count of occupied knots (null when off / full)
+  unsigned long long* knot_slot(double bytes_per_knot) {
+    if (!on) return nullptr;
+    if (!slots && hipHostMalloc((void**)&slots, SLOTS * sizeof(unsigned long long), 0) != hipSuccess) {
+      slots = nullptr;
+      return nullptr;
+    }
+    if (slot_bytes.size() == SLOTS) return nullptr;
+    slot_bytes.push_back(bytes_per_knot);
+    return slots + (slot_bytes.size() - 1);
+  }
+  void reset() {
+    used = 0;
+    bytes = 0.0;
+    slot_bytes.clear();
   }
 };
 

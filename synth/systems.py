@@ -358,6 +358,33 @@ def large_random_system(N=4096, K=200, s_cm=2.0, mu_amu=9.0, cfg_index=5, Q=32,
     return sysm
 
 
+def gp_tables_device(system, device):
+    """The tables of a large random system built on a GPU with torch (hartree,
+    complex128 [K, N, N]): the same construction as gp_tables_cm, for sizes whose
+    tables do not fit comfortably in host memory."""
+    import torch
+    omega, phase, H = system.labels["gp"]
+    R_ang = system.labels["R_ang"]
+    s_cm = system.labels["s_cm"]
+    v_iso = system.labels["V_iso_cm"]
+    K = R_ang.shape[0]
+    Q, N, _ = H.shape
+    phi = gp_basis(omega, phase, R_ang) * (s_cm * np.exp(-(R_ang - 3.0)))[:, None]
+    phi_t = torch.as_tensor(U.cm_to_hartree(phi), dtype=torch.float64, device=device)
+    Hd = torch.as_tensor(H, device=device).reshape(Q, N * N)
+    M = torch.empty((K, N, N), dtype=torch.complex128, device=device)
+    Mr = torch.view_as_real(M).view(K, N * N, 2)
+    Mr[:, :, 0] = phi_t @ Hd.real
+    Mr[:, :, 1] = phi_t @ Hd.imag
+    del Hd
+    diag = torch.as_tensor(U.cm_to_hartree(v_iso), dtype=torch.float64, device=device)
+    for k in range(K):
+        Mk = M[k]
+        Mk.copy_(0.5 * (Mk + Mk.conj().transpose(0, 1).contiguous()))
+        Mk.diagonal().real.add_(diag[k])
+    return M
+
+
 def gp_knot_tables(system, ks):
     """Tables of a large random system at selected knots only (hartree, complex128)."""
     omega, phase, H = system.labels["gp"]

@@ -105,3 +105,28 @@ def test_binned_full_size_bench_population(ctx, full_size, storage):
     tol = 1e-9 if storage == "C128" else 1e-4
     assert np.max(np.abs(gb["P"][sample] - o["P"])) < tol
     assert np.max(np.abs(gg["P"][sample] - o["P"])) < tol
+
+
+def test_profiled_table_bytes(ctx):
+    """The algorithmic table bytes reported with the kernel timings.
+
+    Per-trajectory RK4: (4 n_steps + 1) right-hand sides x 4 slices of N x Npad
+    elements.  Binned: trajectories that stay inside one spline interval occupy
+    exactly its two knots at every stage, each read as a value and a
+    second-derivative slice: (4 n_steps + 1) stages x 2 knots x 2 slices."""
+    (s,), b = S.config1(n_traj=6, n_steps=3, jmax=3)      # N = 16, real FP64 tables
+    b.R0[:] = 0.5 * (s.R_grid[100] + s.R_grid[101])      # mid-interval, far from both knots
+    b.dt[:] = 1.0                                         # moves ~1e-3 bohr in 3 steps
+    say("profiled table bytes N=%d" % s.N)
+    sid = ctx.load_system(s, storage="R64")
+    npad = 16
+    per_slice = s.N * npad * 8
+    for sched, expect in (("gemv", b.B * (4 * 3 + 1) * 4 * per_slice),
+                          ("binned", (4 * 3 + 1) * 2 * 2 * per_slice)):
+        ctx.set_profiling(True)
+        run(ctx, sid, s, b, sched)
+        ms, n, by = ctx.profile_read(with_bytes=True)
+        ctx.set_profiling(False)
+        say("  %s: %d launches, %.0f bytes (expected %d)" % (sched, n, by, expect))
+        assert n > 0 and by == expect
+    ctx.free_system(sid)
