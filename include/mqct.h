@@ -264,17 +264,28 @@ mqct_status mqct_adjoint(mqct_context* ctx, const mqct_batch_desc* batch, int32_
  *                          workgroup shapes (64..512 threads, fewest rows per lane
  *                          covering N) on a copy of up to 2048 of its
  *                          trajectories and keeps the fastest for the context;
- *                          0: the per-trajectory schedule's shape.
+ *                          0: the per-trajectory schedule's shape throughout.
+ *                          The autotuner also times split-row shapes (4 or 8
+ *                          waves that each hold all rows and stream a share of
+ *                          the stored rows) against that choice on 32
+ *                          trajectories; if one wins, the class switches to it
+ *                          once its active count falls to twice the number of
+ *                          compute units (the latency-bound tail of a batch).
  *   MQCT_OPT_CHUNK         step launches per replay (1..4096, default 16).
  *   MQCT_OPT_RESET_TUNING  forget the shapes chosen so far (value ignored).
- * A batch is computed with one shape per class throughout, so results are
- * reproducible for a given set of choices.  Errors: MQCT_ERR_ARG.
+ *   MQCT_OPT_TAIL          1 (default): use the tuned tail shape; 0: never switch;
+ *                          2: run every class on its widest split-row shape from
+ *                          the first step (for testing that form).
+ * Results are reproducible for a given set of choices, chunk size and batch:
+ * a shape switch happens at a chunk boundary.  Errors: MQCT_ERR_ARG.
  */
-enum { MQCT_OPT_GRAPHS = 1, MQCT_OPT_AUTOTUNE = 2, MQCT_OPT_CHUNK = 3, MQCT_OPT_RESET_TUNING = 4 };
+enum { MQCT_OPT_GRAPHS = 1, MQCT_OPT_AUTOTUNE = 2, MQCT_OPT_CHUNK = 3, MQCT_OPT_RESET_TUNING = 4,
+       MQCT_OPT_TAIL = 5 };
 mqct_status mqct_set_option(mqct_context* ctx, int32_t option, int64_t value);
 /* The shapes chosen so far, as JSON text: one object per class with dtype,
- * npad, method (0 RK4, 1 DP5), block, rows_per_lane, tuned, and the candidates'
- * milliseconds per step launch.  Valid until the next call on ctx. */
+ * npad, method (0 RK4, 1 DP5), block, rows_per_lane, tuned, the candidates'
+ * milliseconds per step launch, and the tail shape (or null) with its
+ * candidates' timings.  Valid until the next call on ctx. */
 const char* mqct_tuning_report(mqct_context* ctx);
 
 /*

@@ -23,7 +23,7 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_NOT_HERMITIAN, ERR_OOM, ERR_DEVICE, ERR_UNSUPPOR
 DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
 INTEGRATORS = {"rk4": 0, "dp5": 1}
 SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3}
-OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4}
+OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5}
 MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
 
@@ -344,7 +344,7 @@ class Context:
         return g, P.reshape(B, N)
 
     def set_option(self, name, value=1):
-        """Work-list schedule options: graphs, autotune, chunk, reset_tuning."""
+        """Work-list schedule options: graphs, autotune, chunk, reset_tuning, tail."""
         self._check(lib().mqct_set_option(self.h, OPTIONS[name], int(value)))
 
     def tuning_report(self):

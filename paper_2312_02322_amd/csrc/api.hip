@@ -836,6 +836,10 @@ mqct_status mqct_set_option(mqct_context* c, int32_t option, int64_t value) {
       c->qopt.chunk = (int)value;
       return MQCT_OK;
     case MQCT_OPT_RESET_TUNING: c->qcache.entries.clear(); return MQCT_OK;
+    case MQCT_OPT_TAIL:
+      if (value < 0 || value > 2) return fail(c, MQCT_ERR_ARG, "set_option: tail must be 0, 1 or 2");
+      c->qopt.tail = (int)value;
+      return MQCT_OK;
   }
   return fail(c, MQCT_ERR_ARG, "set_option: unknown option %d", option);
 }
@@ -857,6 +861,24 @@ const char* mqct_tuning_report(mqct_context* c) {
       const QKernelSet& kj = queue_kernels(en.dtype)[en.ms[j].first];
       snprintf(buf, sizeof buf, "%s{\"block\": %d, \"rows_per_lane\": %d, \"ms\": %.6g}",
                j ? ", " : "", kj.block, kj.rpt * (en.dtype == C128 ? 1 : 2), en.ms[j].second);
+      r += buf;
+    }
+    r += "], \"tail\": ";
+    if (en.tail_shape >= 0) {
+      const QKernelSet& kt = queue_kernels(en.dtype)[en.tail_shape];
+      snprintf(buf, sizeof buf, "{\"block\": %d, \"rows_per_lane\": %d, \"split_waves\": %d}",
+               kt.block, kt.rpt * (en.dtype == C128 ? 1 : 2), kt.split_waves);
+      r += buf;
+    } else {
+      r += "null";
+    }
+    r += ", \"tail_candidates\": [";
+    for (size_t j = 0; j < en.tail_ms.size(); ++j) {
+      const QKernelSet& kj = queue_kernels(en.dtype)[en.tail_ms[j].first];
+      snprintf(buf, sizeof buf,
+               "%s{\"block\": %d, \"rows_per_lane\": %d, \"split_waves\": %d, \"ms\": %.6g}",
+               j ? ", " : "", kj.block, kj.rpt * (en.dtype == C128 ? 1 : 2), kj.split_waves,
+               en.tail_ms[j].second);
       r += buf;
     }
     r += "]}";

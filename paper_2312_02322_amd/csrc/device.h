@@ -79,6 +79,17 @@ __device__ __forceinline__ double uni(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum NV values over one wave (shuffles), identical in every lane.
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    v[i] = uni(v[i]);
+  }
+}
+
 // Sum NV values over the workgroup: wave shuffles, then one LDS slot per wave
 // (red[w * NV + i], NW * NV doubles) read back in a fixed order
 // (deterministic, identical in every lane).  `red` must not be reused by

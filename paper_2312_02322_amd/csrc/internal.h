@@ -174,11 +174,12 @@ struct QArgs {
 // (null when the shape is not built for the storage type).
 struct QKernelSet {
   int block, rpt;
+  int split_waves;     // 0: rows shared out over the workgroup; W: split-row form with W waves
   const void* init[2];
   const void* step[2];
 };
 const QKernelSet* queue_kernels(int dtype);   // [QUEUE_SHAPES]
-constexpr int QUEUE_SHAPES = 11;
+constexpr int QUEUE_SHAPES = 17;
 
 struct QueueClass {
   int dtype, npad;
@@ -188,6 +189,8 @@ struct QueueClass {
 struct QueueOpts {
   bool graphs = true;  // replay chunks of step launches as HIP graphs
   bool tune = true;    // time the candidate workgroup shapes on the batch
+  int tail = 1;        // 1: switch to the tuned split-row shape once few trajectories remain;
+                       // 0: never; 2: run every class on a split-row shape (tests)
   int chunk = 16;      // step launches per replay
 };
 
@@ -196,6 +199,8 @@ struct QueueTuneEntry {
   int dtype, npad, method, shape;
   bool tuned;
   std::vector<std::pair<int, double>> ms;   // candidate shape -> ms per step launch
+  int tail_shape = -1;                      // shape once few trajectories remain (-1: same)
+  std::vector<std::pair<int, double>> tail_ms;   // the same, timed on a small sample
 };
 struct QueueCache {
   std::vector<QueueTuneEntry> entries;

@@ -4,17 +4,23 @@
 // and padded column count of their systems (systems may differ within a
 // class).  Each class has its own work list, its own tuned workgroup shape and
 // its own step launches.  The host replays chunks of `chunk` step launches
-// followed by one compaction (as a HIP graph captured once per grid size),
-// reads the active counts back, and shrinks the grid as trajectories retire.
-// Every launch reads the active count from device memory, so the work a
-// replay does always matches the list, whatever grid the graph was built with.
+// followed by one compaction (as a HIP graph captured once per grid size and
+// shape), reads the active counts back, and shrinks the grid as trajectories
+// retire.  Every launch reads the active count from device memory, so the work
+// a replay does always matches the list, whatever grid the graph was built with.
 //
-// Autotuner: for each class (storage type, Npad, method) the candidate shapes
-// are the workgroup sizes 64..512 with the fewest rows per lane that cover
-// the padded row count (lanes within a factor two of it).  After the batch's
-// init launch, the candidates are timed on a copy of the state of up to
-// TUNE_SAMPLE of the class's trajectories (two passes of two step launches
-// each; results are not written), and the fastest is kept for the context.
+// Autotuner, two regimes per class (storage type, Npad, method):
+//   bulk  the row-split shapes (64..512 threads, fewest rows per lane covering
+//         Npad, lanes within a factor two of the rows), timed after the batch's
+//         init on a copy of the state of up to TUNE_SAMPLE trajectories;
+//   tail  the split-row shapes (4 or 8 waves that each hold all rows and stream
+//         a share of the stored rows) and the bulk choice, timed on a copy of
+//         TAIL_SAMPLE trajectories -- few enough that each has the device to
+//         itself, as in the last trajectories of a batch.  If a split-row shape
+//         wins, the class switches to it once its active count drops to twice
+//         the number of compute units.
+// Each candidate is timed in two passes of two step launches (results are not
+// written); the choices are kept for the context.
 #include "rhs.h"
 
 #include <algorithm>
@@ -40,6 +46,8 @@ const QKernelSet* queue_kernels(int dtype) {
 namespace {
 
 constexpr int64_t TUNE_SAMPLE = 2048;
+constexpr int64_t TAIL_SAMPLE = 32;
+constexpr size_t LDS_MAX = 160 * 1024;
 constexpr int CT = 1024;   // threads of the compaction kernel
 
 // Stable in-place compaction of the work list: entries whose trajectory is
@@ -123,18 +131,26 @@ int default_shape(int dtype, int npad) {
   return -1;
 }
 
-std::vector<int> candidates(int dtype, int npad, int method) {
+size_t shape_lds(int dtype, int npad, int shape) {
+  return rhs::lds_bytes(npad, dtype_fp32(dtype), queue_kernels(dtype)[shape].split_waves);
+}
+
+// Row-split shapes (split = false) or split-row shapes (split = true) with the
+// fewest rows per lane covering Npad, lanes within a factor two of the rows.
+std::vector<int> candidates(int dtype, int npad, int method, bool split) {
   const QKernelSet* t = queue_kernels(dtype);
   const int g = npad / vec_of(dtype);
   const int need = std::max(g, 64);
   std::vector<int> c;
   for (int k = 0; k < QUEUE_SHAPES; ++k) {
-    if (!t[k].step[method]) continue;
-    const int lanes = t[k].block * t[k].rpt;
+    if (!t[k].step[method] || (t[k].split_waves > 0) != split) continue;
+    if (shape_lds(dtype, npad, k) > LDS_MAX) continue;
+    const int lanes = (split ? 64 : t[k].block) * t[k].rpt;
     bool minimal = true;   // fewest rows per lane for this workgroup size
     for (int j = 0; j < QUEUE_SHAPES; ++j)
-      if (j != k && t[j].step[method] && t[j].block == t[k].block && t[j].rpt < t[k].rpt &&
-          t[j].block * t[j].rpt >= g)
+      if (j != k && t[j].step[method] && (t[j].split_waves > 0) == split &&
+          t[j].block == t[k].block && t[j].rpt < t[k].rpt &&
+          (split ? 64 : t[j].block) * t[j].rpt >= g)
         minimal = false;
     if (lanes >= g && lanes < 2 * need && minimal) c.push_back(k);
   }
@@ -155,10 +171,11 @@ hipError_t prepare_fn(const void* fn, size_t lds) {
 struct ClassRun {
   QueueClass c;
   QWS ws;
-  int shape = -1;
-  size_t lds = 0;
-  int count = 0;   // last active count read back
-  int grid = 0;    // grid of the current graph / launches
+  int shape = -1;        // shape in use
+  int tail_shape = -1;   // split-row shape for the tail (-1: none)
+  size_t entry = 0;      // its entry in the context's cache
+  int count = 0;         // last active count read back
+  int grid = 0;          // grid of the current graph / launches
   hipGraphExec_t exec = nullptr;
 };
 
@@ -191,9 +208,11 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     r.c = cls[k];
     r.ws = carve(p, r.c.n, r.c.npad, method, d_traj + r.c.first);
     r.ws.count = d_counts + k;
-    r.lds = rhs::lds_bytes(r.c.npad, dtype_fp32(r.c.dtype));
   }
   char* tune_area = p;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
   auto args_for = [&](const QWS& w) {
     QArgs a;
@@ -205,34 +224,44 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     a.out = out;
     return a;
   };
+  auto kset = [&](const ClassRun& r, int shape) -> const QKernelSet& {
+    return queue_kernels(r.c.dtype)[shape];
+  };
+  auto lds_of = [&](const ClassRun& r, int shape) { return shape_lds(r.c.dtype, r.c.npad, shape); };
 
-  // shapes: cached decision, else default or to be tuned after init
+  // shapes: cached decision, else default (and tuned after init)
   std::vector<size_t> to_tune;
   for (size_t k = 0; k < runs.size(); ++k) {
     ClassRun& r = runs[k];
-    for (const auto& en : cache.entries)
-      if (en.dtype == r.c.dtype && en.npad == r.c.npad && en.method == method) r.shape = en.shape;
-    if (r.shape >= 0) continue;
-    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method);
+    bool found = false;
+    for (size_t q = 0; q < cache.entries.size(); ++q) {
+      const QueueTuneEntry& en = cache.entries[q];
+      if (en.dtype == r.c.dtype && en.npad == r.c.npad && en.method == method) {
+        r.shape = en.shape;
+        r.tail_shape = en.tail_shape;
+        r.entry = q;
+        found = true;
+      }
+    }
+    if (found) continue;
+    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method, false);
     if (cand.empty()) return hipErrorInvalidValue;
     const int def = default_shape(r.c.dtype, r.c.npad);
     r.shape = std::find(cand.begin(), cand.end(), def) != cand.end() ? def : cand.back();
-    if (opt.tune && cand.size() > 1) {
-      to_tune.push_back(k);
-    } else {
-      QueueTuneEntry en{r.c.dtype, r.c.npad, method, r.shape, false, {}};
-      cache.entries.push_back(en);
-    }
+    QueueTuneEntry en{r.c.dtype, r.c.npad, method, r.shape, false, {}};
+    r.entry = cache.entries.size();
+    cache.entries.push_back(en);
+    if (opt.tune) to_tune.push_back(k);
   }
 
   auto init_class = [&](ClassRun& r) -> hipError_t {
-    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
+    const QKernelSet& ks = kset(r, r.shape);
     QArgs a = args_for(r.ws);
-    hipError_t err = prepare_fn(ks.init[method], r.lds);
+    hipError_t err = prepare_fn(ks.init[method], lds_of(r, r.shape));
     if (err != hipSuccess) return err;
     r.count = (int)r.c.n;
     r.grid = (int)r.c.n;
-    return launch(ks.init[method], (int)r.c.n, ks.block, r.lds, s, a);
+    return launch(ks.init[method], (int)r.c.n, ks.block, lds_of(r, r.shape), s, a);
   };
   // classes to be tuned start with the default shape, so the candidates are
   // timed on real states
@@ -242,56 +271,79 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     init_shape[k] = runs[k].shape;
   }
 
-  // autotuner: time each candidate on a copy of the sampled state
-  for (size_t k : to_tune) {
-    ClassRun& r = runs[k];
-    const int64_t S = std::min(r.c.n, TUNE_SAMPLE);
+  // time candidate shapes on a copy of the first S trajectories' states
+  auto time_shapes = [&](const ClassRun& r, int64_t S, const std::vector<int>& cand,
+                         std::vector<double>& best) -> hipError_t {
     char* q = tune_area;
     QWS tw = carve(q, S, r.c.npad, method, r.ws.traj);
     tw.count = d_tcount;
-    TrajOut none{};
     QArgs a = args_for(tw);
-    a.out = none;
-    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method);
-    std::vector<double> best(cand.size(), 1e300);
+    a.out = TrajOut{};
+    best.assign(cand.size(), 1e300);
     hipEvent_t e0, e1;
-    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return e; }
-    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-      for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
-        const QKernelSet& ks = queue_kernels(r.c.dtype)[cand[ci]];
-        const size_t bytes_st = (size_t)S * sizeof(QState);
-        if ((e = hipMemcpyAsync(tw.st, r.ws.st, bytes_st, hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(tw.amp, r.ws.amp, (size_t)S * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
+    hipError_t err;
+    if ((err = hipEventCreate(&e0)) != hipSuccess) return err;
+    if ((err = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return err; }
+    for (int pass = 0; pass < 2 && err == hipSuccess; ++pass) {
+      for (size_t ci = 0; ci < cand.size() && err == hipSuccess; ++ci) {
+        const QKernelSet& ks = kset(r, cand[ci]);
+        const size_t lds = lds_of(r, cand[ci]);
+        if ((err = hipMemcpyAsync(tw.st, r.ws.st, (size_t)S * sizeof(QState), hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
+        if ((err = hipMemcpyAsync(tw.amp, r.ws.amp, (size_t)S * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess) break;
         if (method == 1 &&
-            (e = hipMemcpyAsync(tw.kst, r.ws.kst, (size_t)S * 8 * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            (err = hipMemcpyAsync(tw.kst, r.ws.kst, (size_t)S * 8 * r.c.npad * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess)
           break;
         q_iota<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(tw.list, tw.count, (int)S);
-        if ((e = prepare_fn(ks.step[method], r.lds)) != hipSuccess) break;
-        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
-          e = launch(ks.step[method], (int)S, ks.block, r.lds, s, a);
-        if (e != hipSuccess) break;
-        if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((err = prepare_fn(ks.step[method], lds)) != hipSuccess) break;
+        if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep)
+          err = launch(ks.step[method], (int)S, ks.block, lds, s, a);
+        if (err != hipSuccess) break;
+        if ((err = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
         if (pass == 1) best[ci] = ms / 2.0;
       }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (e != hipSuccess) return e;
-    size_t bi = 0;
-    for (size_t ci = 1; ci < cand.size(); ++ci)
-      if (best[ci] < best[bi]) bi = ci;
-    r.shape = cand[bi];
-    QueueTuneEntry en{r.c.dtype, r.c.npad, method, r.shape, true, {}};
-    for (size_t ci = 0; ci < cand.size(); ++ci) en.ms.push_back({cand[ci], best[ci]});
-    cache.entries.push_back(en);
+    return err;
+  };
+  for (size_t k : to_tune) {
+    ClassRun& r = runs[k];
+    QueueTuneEntry& en = cache.entries[r.entry];
+    const std::vector<int> cand = candidates(r.c.dtype, r.c.npad, method, false);
+    std::vector<double> best;
+    if (cand.size() > 1) {
+      if ((e = time_shapes(r, std::min(r.c.n, TUNE_SAMPLE), cand, best)) != hipSuccess) return e;
+      size_t bi = 0;
+      for (size_t ci = 1; ci < cand.size(); ++ci)
+        if (best[ci] < best[bi]) bi = ci;
+      r.shape = cand[bi];
+      en.shape = r.shape;
+      en.tuned = true;
+      for (size_t ci = 0; ci < cand.size(); ++ci) en.ms.push_back({cand[ci], best[ci]});
+    }
+    std::vector<int> tc = candidates(r.c.dtype, r.c.npad, method, true);
+    if (!tc.empty()) {
+      tc.push_back(r.shape);
+      if ((e = time_shapes(r, std::min(r.c.n, TAIL_SAMPLE), tc, best)) != hipSuccess) return e;
+      size_t bi = 0;
+      for (size_t ci = 1; ci < tc.size(); ++ci)
+        if (best[ci] < best[bi]) bi = ci;
+      r.tail_shape = tc[bi] == r.shape ? -1 : tc[bi];
+      en.tail_shape = r.tail_shape;
+      for (size_t ci = 0; ci < tc.size(); ++ci) en.tail_ms.push_back({tc[ci], best[ci]});
+    }
   }
-  // every class starts from an init with its final shape, so a batch is
-  // computed with one shape throughout
+  // forced split-row form (tests): the widest split-row candidate throughout
+  if (opt.tail == 2)
+    for (ClassRun& r : runs) {
+      const std::vector<int> tc = candidates(r.c.dtype, r.c.npad, method, true);
+      r.tail_shape = tc.empty() ? -1 : tc.back();
+    }
+  // every class starts from an init with its first shape
   for (size_t k = 0; k < runs.size(); ++k)
     if (init_shape[k] != runs[k].shape)
       if ((e = init_class(runs[k])) != hipSuccess) return e;
@@ -300,11 +352,12 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
   const int chunk = std::max(1, opt.chunk);
   const int64_t max_rounds = (max_attempts + chunk - 1) / chunk + 2;
   auto enqueue_chunk = [&](ClassRun& r, hipStream_t st) -> hipError_t {
-    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
+    const QKernelSet& ks = kset(r, r.shape);
+    const size_t lds = lds_of(r, r.shape);
     QArgs a = args_for(r.ws);
     hipError_t err;
     for (int j = 0; j < chunk; ++j)
-      if ((err = launch(ks.step[method], r.grid, ks.block, r.lds, st, a)) != hipSuccess) return err;
+      if ((err = launch(ks.step[method], r.grid, ks.block, lds, st, a)) != hipSuccess) return err;
     q_compact<<<1, CT, 0, st>>>(r.ws.list, r.ws.count, r.ws.st);
     return hipGetLastError();
   };
@@ -313,8 +366,10 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     r.exec = nullptr;
   };
   for (ClassRun& r : runs) {
-    const QKernelSet& ks = queue_kernels(r.c.dtype)[r.shape];
-    if ((e = prepare_fn(ks.step[method], r.lds)) != hipSuccess) return e;
+    if ((e = prepare_fn(kset(r, r.shape).step[method], lds_of(r, r.shape))) != hipSuccess) return e;
+    if (r.tail_shape >= 0 &&
+        (e = prepare_fn(kset(r, r.tail_shape).step[method], lds_of(r, r.tail_shape))) != hipSuccess)
+      return e;
   }
   e = hipSuccess;
   int64_t round = 0;
@@ -323,6 +378,12 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     for (ClassRun& r : runs) {
       if (r.count <= 0) continue;
       any = true;
+      // few trajectories left: the latency shape, if the tuner found one
+      if (opt.tail && r.tail_shape >= 0 && r.shape != r.tail_shape &&
+          (r.count <= 2 * cus || opt.tail == 2)) {
+        r.shape = r.tail_shape;
+        drop_graph(r);
+      }
       // shrink the grid once fewer than half of its workgroups have work
       if (r.count * 2 <= r.grid) {
         r.grid = r.count;

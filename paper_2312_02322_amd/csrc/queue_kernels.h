@@ -41,9 +41,9 @@ static __constant__ double QA[7][6] = {
 static __constant__ double QE[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
                                     -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
 
-template <int DT, int BLOCK, int RPT>
-struct QK : Rhs<DT, BLOCK, RPT> {
-  using Base = Rhs<DT, BLOCK, RPT>;
+template <int DT, int BLOCK, int RPT, bool SPLIT>
+struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
+  using Base = Rhs<DT, BLOCK, RPT, SPLIT>;
   using Base::NR;
   using Base::NW;
   using Base::row;
@@ -218,7 +218,7 @@ struct QK : Rhs<DT, BLOCK, RPT> {
       s2[0] += (a[r].x / sx) * (a[r].x / sx) + (a[r].y / sy_) * (a[r].y / sy_);
       s2[1] += (f0[r].x / sx) * (f0[r].x / sx) + (f0[r].y / sy_) * (f0[r].y / sy_);
     }
-    block_sum<2, NW>(s2, lds.red1);
+    Base::template reduce<2>(s2, lds.red1);
     const double kf[6] = {s.kc1[0], 0.0, s.kc1[1], s.kc1[2], 0.0, s.kc1[3]};
     for (int k = 0; k < 6; ++k) {
       const double sc = atol + rtol * fabs(yfull[k]);
@@ -243,7 +243,7 @@ struct QK : Rhs<DT, BLOCK, RPT> {
       const double ex = (st[r].x - f0[r].x) / sx, ey = (st[r].y - f0[r].y) / sy_;
       s1[0] += ex * ex + ey * ey;
     }
-    block_sum<1, NW>(s1, lds.red1);
+    Base::template reduce<1>(s1, lds.red1);
     const double dk[6] = {kc[0] - s.kc1[0], 0.0, kc[1] - s.kc1[1], kc[2] - s.kc1[2], 0.0,
                           kc[3] - s.kc1[3]};
     for (int k = 0; k < 6; ++k) {
@@ -335,7 +335,7 @@ struct QK : Rhs<DT, BLOCK, RPT> {
       const double sc = atol + rtol * fmax(fabs(s.yc[k]), fabs(y5c[k]));
       ecl += (e / sc) * (e / sc);
     }
-    block_sum<1, NW>(e2, lds.red1);
+    Base::template reduce<1>(e2, lds.red1);
     const double en = uni(sqrt((e2[0] + ecl) / ncomp));
     if (below) s.status |= ST_BELOW_GRID;
     s.attempts += 1;
@@ -384,18 +384,18 @@ struct QK : Rhs<DT, BLOCK, RPT> {
   }
 };
 
-template <int DT, int BLOCK, int RPT, int METHOD>
+template <int DT, int BLOCK, int RPT, bool SPLIT, int METHOD>
 __global__ void __launch_bounds__(BLOCK) q_init(QArgs q) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int i = blockIdx.x;
   Lds<DT> lds(smem, q.ws.npad);
-  if (METHOD == 0) QK<DT, BLOCK, RPT>::init_rk4(q, i, lds);
-  else QK<DT, BLOCK, RPT>::init_dp5(q, i, lds);
+  if (METHOD == 0) QK<DT, BLOCK, RPT, SPLIT>::init_rk4(q, i, lds);
+  else QK<DT, BLOCK, RPT, SPLIT>::init_dp5(q, i, lds);
   if (threadIdx.x == 0) q.ws.list[i] = i;
   if (i == 0 && threadIdx.x == 0) *q.ws.count = q.ws.n;
 }
 
-template <int DT, int BLOCK, int RPT, int METHOD>
+template <int DT, int BLOCK, int RPT, bool SPLIT, int METHOD>
 __global__ void __launch_bounds__(BLOCK) q_step(QArgs q) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cnt = *q.ws.count;
@@ -404,35 +404,42 @@ __global__ void __launch_bounds__(BLOCK) q_step(QArgs q) {
   QState s = q.ws.st[i];
   if (s.flags & Q_DONE) return;
   Lds<DT> lds(smem, q.ws.npad);
-  if (METHOD == 0) QK<DT, BLOCK, RPT>::step_rk4(q, i, s, lds);
-  else QK<DT, BLOCK, RPT>::step_dp5(q, i, s, lds);
+  if (METHOD == 0) QK<DT, BLOCK, RPT, SPLIT>::step_rk4(q, i, s, lds);
+  else QK<DT, BLOCK, RPT, SPLIT>::step_dp5(q, i, s, lds);
   if (threadIdx.x == 0) q.ws.st[i] = s;
 }
 
-// Workgroup shapes (threads, rows per lane) the schedule can use.
+// Workgroup shapes (threads, 16-byte row groups per lane, split-row form) the
+// schedule can use: row-split 0..10, split-row 11..16.
 constexpr int QSHAPES = QUEUE_SHAPES;
 __host__ __device__ constexpr int qshape_block(int k) {
-  return k < 2 ? 64 : (k < 4 ? 128 : (k < 7 ? 256 : 512));
+  return k < 2 ? 64 : k < 4 ? 128 : k < 7 ? 256 : k < 11 ? 512 : k < 14 ? 256 : 512;
 }
 __host__ __device__ constexpr int qshape_rpt(int k) {
   return k == 0 ? 1 : k == 1 ? 2 : k == 2 ? 1 : k == 3 ? 2 : k == 4 ? 1 : k == 5 ? 2
-       : k == 6 ? 4 : k == 7 ? 1 : k == 8 ? 2 : k == 9 ? 4 : 8;
+       : k == 6 ? 4 : k == 7 ? 1 : k == 8 ? 2 : k == 9 ? 4 : k == 10 ? 8
+       : k == 11 || k == 14 ? 1 : k == 12 || k == 15 ? 2 : 4;
 }
+__host__ __device__ constexpr bool qshape_split(int k) { return k >= 11; }
 
 template <int DT, int K>
 void fill_one(QKernelSet& ks) {
   constexpr int BL = qshape_block(K), RP = qshape_rpt(K);
+  constexpr bool SP = qshape_split(K);
   ks.block = BL;
   ks.rpt = RP;
-  // rows per workgroup beyond the largest supported column count are not built
-  if constexpr (BL * RP * Tr<DT>::VEC > 4096) {
+  ks.split_waves = SP ? BL / 64 : 0;
+  // rows per workgroup (per wave for the split-row form) beyond the largest
+  // supported column count are not built
+  if constexpr ((SP ? 64 : BL) * RP * Tr<DT>::VEC > 4096) {
     ks.init[0] = ks.init[1] = ks.step[0] = ks.step[1] = nullptr;
     return;
+  } else {
+    ks.init[0] = (const void*)q_init<DT, BL, RP, SP, 0>;
+    ks.init[1] = (const void*)q_init<DT, BL, RP, SP, 1>;
+    ks.step[0] = (const void*)q_step<DT, BL, RP, SP, 0>;
+    ks.step[1] = (const void*)q_step<DT, BL, RP, SP, 1>;
   }
-  ks.init[0] = (const void*)q_init<DT, BL, RP, 0>;
-  ks.init[1] = (const void*)q_init<DT, BL, RP, 1>;
-  ks.step[0] = (const void*)q_step<DT, BL, RP, 0>;
-  ks.step[1] = (const void*)q_step<DT, BL, RP, 1>;
 }
 
 template <int DT, int K>

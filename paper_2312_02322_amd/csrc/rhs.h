@@ -97,9 +97,11 @@ __device__ __forceinline__ void elem(F2& u, F2& v, F s0r, F s0i, F s1r, F s1i, F
 //   c64   [Npad] double2 (aliases c on the FP64 path)
 //   red0  [16][8] doubles, red1 [16][8] doubles  (two reduction areas)
 //   kcl   [8][4] doubles                        (classical stage derivatives of DP5)
-__host__ __device__ inline size_t lds_bytes(int npad, bool fp32) {
+//   part  [W][Npad] double4                     (split-row form only: each wave's
+//                                                partial (u, v) before they are summed)
+__host__ __device__ inline size_t lds_bytes(int npad, bool fp32, int split_waves = 0) {
   size_t c = fp32 ? (((size_t)npad * 8 + 15) & ~(size_t)15) : 0;
-  return c + (size_t)npad * 16 + 2 * 16 * 8 * 8 + 8 * 4 * 8;
+  return c + (size_t)npad * 16 + 2 * 16 * 8 * 8 + 8 * 4 * 8 + (size_t)split_waves * npad * 32;
 }
 
 template <int DT>
@@ -109,6 +111,7 @@ struct Lds {
   double* red0;
   double* red1;
   double* kcl;
+  double4* part;
   __device__ Lds(unsigned char* smem, int npad) {
     constexpr bool fp32 = (DT == C64 || DT == R32);
     c = (typename Tr<DT>::CS*)smem;
@@ -116,10 +119,19 @@ struct Lds {
     red0 = (double*)(c64 + npad);
     red1 = red0 + 16 * 8;
     kcl = red1 + 16 * 8;
+    part = (double4*)(kcl + 8 * 4);
   }
 };
 
-template <int DT, int BLOCK, int RPT>
+// Right-hand side evaluated by one workgroup.  Row-split form (SPLIT = false):
+// the BLOCK threads share out the output rows and every thread streams all N
+// stored rows.  Split-row form (SPLIT = true): every wave holds all output rows
+// (64 lanes x RPT groups) and streams only its 1/W share of the stored rows;
+// the W partial sums meet in LDS and are added in a fixed order, so every wave
+// ends with the same u and v and carries the trajectory's state redundantly.
+// The split form shortens the dependent chain of loads W times: it serves
+// trajectories that run alone on the device (latency-bound tails).
+template <int DT, int BLOCK, int RPT, bool SPLIT = false>
 struct Rhs {
   using T = Tr<DT>;
   using S = typename T::S;
@@ -131,11 +143,30 @@ struct Rhs {
   static constexpr bool FP32 = (DT == C64 || DT == R32);
   static constexpr bool CPLX = T::CPLX;
   static constexpr int NCOMP = CPLX ? 2 : 1;
-  static constexpr int UNR = RPT >= 4 ? 1 : 4 / RPT;   // stored rows in flight per lane
+  // stored rows in flight per lane (the split-row form streams fewer rows per
+  // wave and is latency-bound, so it keeps more in flight)
+  static constexpr int UNR = SPLIT ? (RPT >= 8 ? 1 : 8 / RPT) : (RPT >= 4 ? 1 : 4 / RPT);
+  // keep each row's phase factor from the c computation for the epilogue
+  static constexpr bool CPH = NR <= 4;
   using F = typename std::conditional<FP32, float, double>::type;
   using F2 = typename std::conditional<FP32, float2, double2>::type;
 
-  __device__ static int row(int r) { return (threadIdx.x + (r / VEC) * BLOCK) * VEC + (r % VEC); }
+  static constexpr int ROWW = SPLIT ? 64 : BLOCK;   // threads that share out the rows
+  __device__ static int rlane() { return SPLIT ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
+  __device__ static int row(int r) { return (rlane() + (r / VEC) * ROWW) * VEC + (r % VEC); }
+
+  // Sum NV values over the trajectory's rows, identical in every lane.  The
+  // row-split form reduces over the workgroup; in the split-row form each wave
+  // holds all rows, so a wave reduction suffices.  Both end with a barrier.
+  template <int NV>
+  __device__ static void reduce(double (&v)[NV], double* red) {
+    if constexpr (SPLIT) {
+      wave_sum<NV>(v);
+      __syncthreads();
+    } else {
+      block_sum<NV, NW>(v, red);
+    }
+  }
 
   // The VEC elements of one 16-byte load, as (re, im) pairs.
   __device__ static void split(const L& v, F (&re)[VEC], F (&im)[VEC]) {
@@ -155,12 +186,17 @@ struct Rhs {
     below |= sp.below;
     const double phidot = uni(pphi / (sy.mu * R * R));
 
+    double pcos[CPH ? NR : 1], psin[CPH ? NR : 1];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
       if (n < N) {
         double sn, cs;
         sincos(sy.E[n] * ts, &sn, &cs);
+        if constexpr (CPH) {
+          pcos[r] = cs;
+          psin[r] = sn;
+        }
         const double2 c = make_double2(cs * cur[r].x + sn * cur[r].y,
                                        cs * cur[r].y - sn * cur[r].x);
         if constexpr (FP32) lds.c[n] = make_float2((float)c.x, (float)c.y);
@@ -184,8 +220,14 @@ struct Rhs {
 #pragma unroll
     for (int r = 0; r < NR; ++r) { U[r] = make_double2(0.0, 0.0); V[r] = make_double2(0.0, 0.0); }
 
-    for (int m0 = 0; m0 < N; m0 += (FP32 ? CHUNK : N)) {
-      const int m1 = FP32 ? min(N, m0 + CHUNK) : N;
+    int mb = 0, me = N;   // stored rows this thread streams
+    if constexpr (SPLIT) {
+      const int w = threadIdx.x >> 6;
+      mb = (N * w) / NW;
+      me = (N * (w + 1)) / NW;
+    }
+    for (int m0 = mb; m0 < me; m0 += (FP32 ? CHUNK : N)) {
+      const int m1 = FP32 ? min(me, m0 + CHUNK) : me;
       F2 pu[NR], pv[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -201,7 +243,7 @@ struct Rhs {
         // together.
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-          const uint32_t off = rowoff + (uint32_t)(threadIdx.x + j * BLOCK) * (uint32_t)sizeof(L);
+          const uint32_t off = rowoff + (uint32_t)(rlane() + j * ROWW) * (uint32_t)sizeof(L);
           const L v0 = load16<L>(rs0, off);
           const L v1 = load16<L>(rs1, off);
           const L v2 = load16<L>(rs2, off);
@@ -221,6 +263,29 @@ struct Rhs {
       }
     }
 
+    if constexpr (SPLIT) {
+      // every wave's partial sums of all rows, added in wave order
+      const int w = threadIdx.x >> 6;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int n = row(r);
+        if (n < Npad) lds.part[w * Npad + n] = make_double4(U[r].x, U[r].y, V[r].x, V[r].y);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int n = row(r);
+        if (n >= Npad) continue;
+        double4 acc = lds.part[n];
+        for (int q = 1; q < NW; ++q) {
+          const double4 p = lds.part[q * Npad + n];
+          acc.x += p.x; acc.y += p.y; acc.z += p.z; acc.w += p.w;
+        }
+        U[r] = make_double2(acc.x, acc.y);
+        V[r] = make_double2(acc.z, acc.w);
+      }
+    }
+
     // epilogue.  J_x couples only channels of equal energy, so
     // J_x a = e^{iE_n t} (J_x c) row by row, and with y = e^{iE t} u:
     //   Re(c^H v), Im(x^H y) = Im((J_x c)^H u), Re(c^H u), Re(a^H J_x a) = Re(c^H J_x c).
@@ -230,7 +295,12 @@ struct Rhs {
       const int n = row(r);
       if (n >= N) { cur[r] = make_double2(0.0, 0.0); continue; }
       double sn, cs;
-      sincos(sy.E[n] * ts, &sn, &cs);
+      if constexpr (CPH) {
+        sn = psin[r];
+        cs = pcos[r];
+      } else {
+        sincos(sy.E[n] * ts, &sn, &cs);
+      }
       const double2 c = make_double2(cs * cur[r].x + sn * cur[r].y,
                                      cs * cur[r].y - sn * cur[r].x);
       double2 xc = make_double2(0.0, 0.0);
@@ -254,7 +324,7 @@ struct Rhs {
       const double yx = cs * gx - sn * gy, yy = cs * gy + sn * gx;
       cur[r] = make_double2(yy, -yx);
     }
-    block_sum<6, NW>(sums, lds.red0);
+    reduce<6>(sums, lds.red0);
     tot.force = sums[0]; tot.torque = sums[1]; tot.vexp = sums[2];
     tot.erot = sums[3]; tot.norm = sums[4]; tot.jx = sums[5];
   }

@@ -190,3 +190,34 @@ def test_autotuner_reports_and_meets_the_bar(ctx):
                       **start(b))
     same(g, g2)
     ctx.free_system(sid)
+
+
+@pytest.mark.parametrize("storage", ["R64", "R32"])
+def test_split_row_form_matches_oracle(ctx, storage):
+    """The split-row form (8 waves that each hold all rows and stream an eighth of
+    the stored rows, partial sums added in LDS) forced for a whole batch: RK4 and
+    DP5 against the oracle, and RK4 against the row-split form."""
+    (s,), b = S.config4(n_traj=6, n_steps=80)
+    say("split-row form N=%d %s" % (s.N, storage))
+    sid = ctx.load_system(s, storage=storage)
+    common = dict(start(b), dt=b.dt, n_steps=b.n_steps)
+    tol = 1e-9 if storage == "R64" else 1e-4
+    ctx.set_option("tail", 2)
+    try:
+        g = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="queue", **common)
+        d = ctx.run_host([sid] * b.B, [s.N] * b.B, **start(b), **DP5)
+    finally:
+        ctx.set_option("tail", 1)
+    ref = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="gemv", **common)
+    o = oracle.OracleSystem(s).propagate(b)
+    od = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=RTOL, atol=RTOL, max_steps=50000,
+                                          h_min=1e-6)
+    e_rk = np.max(np.abs(g["P"].reshape(b.B, s.N) - o["P"]))
+    e_dp = np.max(np.abs(d["P"].reshape(b.B, s.N) - od["P"]))
+    say("  rk4 |dP| %.3e  dp5 |dP| %.3e  vs row-split %.3e" % (
+        e_rk, e_dp, np.max(np.abs(g["P"] - ref["P"]))))
+    assert e_rk < tol
+    assert e_dp < (10 * RTOL if storage == "R64" else 1e-4)
+    assert np.max(np.abs(g["P"] - ref["P"])) < tol
+    assert np.all(d["status"] & 1) and np.max(np.abs(d["steps"] - od["steps"])) <= 3
+    ctx.free_system(sid)
