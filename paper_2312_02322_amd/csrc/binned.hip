@@ -220,6 +220,11 @@ __global__ void bin_scatter(BinWS ws) {
   ws.list[ws.offset[k + 1] + p1] = 2 * b + 1;
 }
 
+constexpr int GEMM_PF32 = 2;   // K steps of operands in flight, FP32 tables (deeper rings measured slower)
+// ring periods per loop iteration: the compiler's waits for the loads are exact
+// inside an iteration and conservative only across the loop's back edge
+constexpr int GEMM_UF = 1;
+
 template <typename S> struct MF;
 template <> struct MF<float> {
   using V = v4f;
@@ -256,8 +261,8 @@ __device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t off, S 
 // reals of the table row and of its real column, and the four MFMAs of one
 // step take k = k0 + 4(l/16) + i, i = 0..3, on both operands (a permutation
 // of K).  NX is the number of column blocks that hold trajectories, so empty
-// blocks cost nothing; the operands of step k0 + 16 are loaded while the MFMAs
-// of step k0 run.
+// blocks cost nothing; the operands of the next PF - 1 steps are in flight
+// while the MFMAs of step k0 run.
 template <int DT, int NX>
 __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, int rb, int g,
                                           int start, int count) {
@@ -266,6 +271,8 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   using S = typename std::conditional<FP32, float, double>::type;
   using V = typename MF<S>::V;
   constexpr int RB = 2;
+  // K steps of operands in flight: the FP32 form has the registers for a deeper ring
+  constexpr int PF = FP32 ? GEMM_PF32 : 2;
   constexpr int NCOMP = CPLX ? 2 : 1;
   const int N = sy.N, Npad = sy.Npad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -294,7 +301,9 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
 #pragma unroll
       for (int cb = 0; cb < NX; ++cb) acc[r][s][cb] = V{0, 0, 0, 0};
 
-  S a[RB][2][4], an[RB][2][4], bv[NX][4], bn[NX][4];
+  // operands of PF K steps in a ring: step k0 + 16 j sits in stage j % PF; the
+  // loads for step k0 + 16 (PF - 1) are issued before the products of step k0
+  S a[PF][RB][2][4], bv[PF][NX][4];
   auto load = [&](int k0, S (&ao)[RB][2][4], S (&bo)[NX][4]) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -326,25 +335,19 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
           for (int s = 0; s < 2; ++s)
             acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bi[cb][i], acc[r][s][cb]);
   };
-  load(0, a, bv);
-  for (int k0 = 0; k0 < KR; k0 += 16) {
-    // the last step reloads its own operands (unused) rather than branch
-    load(k0 + 16 < KR ? k0 + 16 : k0, an, bn);
-    // keep the loads ahead of the products and the register moves (and hence
-    // the waits for the loads) behind them
-    __builtin_amdgcn_sched_barrier(0);
-    mma(a, bv);
-    __builtin_amdgcn_sched_barrier(0);
+  // K steps past the last one reload that step's operands (unused) rather than branch
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KR - 16), a[j], bv[j]);
+  for (int k0 = 0; k0 < KR; k0 += 16 * PF * GEMM_UF) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[r][s][i] = an[r][s][i];
-#pragma unroll
-    for (int cb = 0; cb < NX; ++cb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) bv[cb][i] = bn[cb][i];
+    for (int j = 0; j < PF * GEMM_UF; ++j) {
+      const int kl = k0 + 16 * (j + PF - 1);
+      load(kl < KR ? kl : KR - 16, a[(j + PF - 1) % PF], bv[(j + PF - 1) % PF]);
+      // keep the loads ahead of the products (and the waits for them behind)
+      __builtin_amdgcn_sched_barrier(0);
+      if (k0 + 16 * j < KR) mma(a[j % PF], bv[j % PF]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 
   // epilogue: apply this column's spline weights (left or right knot)
