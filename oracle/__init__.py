@@ -32,7 +32,8 @@ class _Sys(C.Structure):
                 ("M", C.c_void_p), ("M2", C.c_void_p), ("dM", C.c_void_p), ("dM2", C.c_void_p),
                 ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p), ("jx_col", C.c_void_p),
                 ("jx_val", C.c_void_p), ("mu", C.c_double), ("literal_phase", C.c_int32),
-                ("plant_coriolis_flip", C.c_int32)]
+                ("plant_coriolis_flip", C.c_int32), ("decoupled", C.c_int32),
+                ("drv", C.c_void_p), ("drv2", C.c_void_p)]
 
 
 _lib = None
@@ -94,7 +95,10 @@ class OracleSystem:
     """A system prepared for the oracle: complex tables and their spline curvature."""
 
     def __init__(self, system, literal_phase=False, tables=None, tangent_tables=None,
-                 plant_coriolis_flip=False):
+                 plant_coriolis_flip=False, driver=None):
+        """driver: U(R_k) [K] hartree -- switches to decoupled (AT) dynamics, in
+        which the trajectory is driven by the natural spline of U and feels no
+        force or torque from the quantum state."""
         M = system.M if tables is None else tables
         self.N, self.K = int(system.E.shape[0]), int(system.R_grid.shape[0])
         self.R = _f64(system.R_grid)
@@ -112,10 +116,15 @@ class OracleSystem:
         self.jx_val = _f64(system.jx_val)
         self.mu = float(system.mu)
         self.system = system
+        self.drv = self.drv2 = None
+        if driver is not None:
+            self.drv = _f64(driver).reshape(self.K)
+            self.drv2 = spline_prepare(self.R, self.drv.reshape(self.K, 1)).reshape(self.K)
         self.s = _Sys(self.N, self.K, _p(self.R), _p(self.E), _p(self.M), _p(self.M2),
                       _p(self.dM), _p(self.dM2), len(self.jx_val), _p(self.jx_row),
                       _p(self.jx_col), _p(self.jx_val), self.mu, 1 if literal_phase else 0,
-                      1 if plant_coriolis_flip else 0)
+                      1 if plant_coriolis_flip else 0, 1 if driver is not None else 0,
+                      _p(self.drv), _p(self.drv2))
 
     def rhs(self, t, y):
         y = _f64(y)

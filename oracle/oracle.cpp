@@ -94,6 +94,13 @@ typedef struct {
   double mu;              // reduced mass, m_e
   int32_t literal_phase;  // 1: form exp(i(E_n - E_m)t) per element instead of factorising
   int32_t plant_coriolis_flip;  // tests only: 1 plants the wrong sign +i Phidot J_x in Eq. 5
+  // Decoupled (AT) dynamics (Section III: the quantum equations, Eq. 5, are
+  // propagated along a classical trajectory whose Eqs. 7-10 no longer feel the
+  // quantum state).  The trajectory is driven by the tabulated potential U(R):
+  //   dP_R/dt = -U'(R) + P_Phi^2/(mu R^3),   dP_Phi/dt = 0.
+  int32_t decoupled;      // 1: AT dynamics (needs drv, drv2)
+  const double* drv;      // [K] U(R_k), hartree
+  const double* drv2;     // [K] its natural-spline second derivatives
 } oracle_system;
 
 enum { OR_EXITED = 1, OR_MAX_STEPS = 2, OR_STEP_UNDERFLOW = 4, OR_BELOW_GRID = 8,
@@ -236,7 +243,8 @@ inline Elem<Dual> table_elem<Dual>(const oracle_system* s, const SplineW<Dual>& 
 }
 
 // State layout y[2N + 6]: a_n as (re, im) pairs, then R, Theta, Phi, P_R, P_Theta, P_Phi.
-template <class T> struct Diag { T Eq; bool below; };
+// Eq: the quantum energy <H_rot + V>; U: the driving potential (AT dynamics).
+template <class T> struct Diag { T Eq; T U; bool below; };
 
 // Right-hand side of Eqs. 5 and 7-10.
 template <class T>
@@ -318,6 +326,18 @@ Diag<T> rhs(const oracle_system* s, T t, const T* y, T* f) {
   f[2 * N + 4] = T(0.0);
   f[2 * N + 5] = T(2.0) * xy.im;
   Diag<T> d;
+  d.U = T(0.0);
+  if (s->decoupled) {
+    // AT: the trajectory feels only the driving potential; no torque
+    const int k = w.k;
+    T U = w.wa * T(s->drv[k]) + w.wb * T(s->drv[k + 1]) + w.wc * T(s->drv2[k]) +
+          w.wd * T(s->drv2[k + 1]);
+    T dU = w.da * T(s->drv[k]) + w.db * T(s->drv[k + 1]) + w.dc * T(s->drv2[k]) +
+           w.dd * T(s->drv2[k + 1]);
+    f[2 * N + 3] = -dU + PPh * PPh / (mu * R * R * R);
+    f[2 * N + 5] = T(0.0);
+    d.U = U;
+  }
   T Erot = T(0.0);
   for (int n = 0; n < N; ++n) Erot += T(s->E[n]) * (amp[n].re * amp[n].re + amp[n].im * amp[n].im);
   d.Eq = Erot + Vexp.re;
@@ -325,17 +345,21 @@ Diag<T> rhs(const oracle_system* s, T t, const T* y, T* f) {
   return d;
 }
 
+// Conserved energy: classical kinetic + quantum <H_rot + V> (Ehrenfest), or
+// classical kinetic + U(R) (AT: the trajectory's own energy).
 template <class T> T total_energy(const oracle_system* s, T t, const T* y) {
   int N = s->N;
   std::vector<T> f(2 * N + 6);
   Diag<T> d = rhs<T>(s, t, y, f.data());
   T R = y[2 * N], PR = y[2 * N + 3], PPh = y[2 * N + 5], mu = T(s->mu);
-  return PR * PR / (T(2.0) * mu) + PPh * PPh / (T(2.0) * mu * R * R) + d.Eq;
+  return PR * PR / (T(2.0) * mu) + PPh * PPh / (T(2.0) * mu * R * R) +
+         (s->decoupled ? d.U : d.Eq);
 }
 
+// Conserved angular momentum: P_Phi - Re(a^H J_x a) (Ehrenfest), or P_Phi (AT).
 template <class T> T angular_invariant(const oracle_system* s, const T* y) {
-  // P_Phi - Re(a^H J_x a)
   int N = s->N;
+  if (s->decoupled) return y[2 * N + 5];
   T jx = T(0.0);
   for (int q = 0; q < s->jx_nnz; ++q) {
     int r = s->jx_row[q], c = s->jx_col[q];
