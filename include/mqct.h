@@ -53,6 +53,10 @@ enum {
 enum { MQCT_R64 = 0, MQCT_C128 = 1, MQCT_R32 = 2, MQCT_C64 = 3 };
 /* time steppers */
 enum { MQCT_RK4 = 0, MQCT_DP5 = 1 };
+/* dynamics: Ehrenfest mean field (Eqs. 5, 7-10 coupled), or AT -- the quantum
+   equations (Eq. 5) propagated along a trajectory that does not feel the
+   quantum state (Section III), driven by the system's driving potential */
+enum { MQCT_EHRENFEST = 0, MQCT_AT = 1 };
 /* where a caller buffer lives */
 enum { MQCT_MEM_HOST = 0, MQCT_MEM_DEVICE = 1 };
 /* per-trajectory status bits */
@@ -124,6 +128,13 @@ typedef struct {
  * MQCT_ERR_OOM, MQCT_ERR_DEVICE.  Synchronous. */
 mqct_status mqct_system_load(mqct_context* ctx, const mqct_system_desc* desc,
                              int32_t* system_id);
+/* The driving potential of decoupled (AT) dynamics (Section III: the classical
+ * trajectory is propagated apart from the quantum equations): U [K] host,
+ * hartree, on the system's grid, interpolated by its natural cubic spline (the
+ * same interval, weights and off-grid rule as the coupling tables).  Copied;
+ * replaces an earlier driver.  Errors: MQCT_ERR_ARG, MQCT_ERR_STATE,
+ * MQCT_ERR_NONFINITE, MQCT_ERR_OOM, MQCT_ERR_DEVICE.  Synchronous. */
+mqct_status mqct_system_set_driver(mqct_context* ctx, int32_t system_id, const double* U);
 /* Device bytes held by a loaded system's tables (values + second derivatives). */
 mqct_status mqct_system_bytes(mqct_context* ctx, int32_t system_id, int64_t* bytes);
 /* Release a system's device memory; its id becomes invalid. */
@@ -146,6 +157,15 @@ mqct_status mqct_system_free(mqct_context* ctx, int32_t system_id);
  *   n_steps          [B] RK4 step count (exact; no early exit).
  *   rtol, atol, max_steps, h_min   DP5 controls (scaled RMS error norm).
  *   schedule         MQCT_SCHED_*.
+ *   dynamics         MQCT_EHRENFEST, or MQCT_AT (every system of the batch needs a
+ *                    driving potential, mqct_system_set_driver).  With AT, each
+ *                    trajectory's classical equations read
+ *                        dP_R/dt = -U'(R) + P_Phi^2/(mu R^3),  dP_Phi/dt = 0,
+ *                    (Eq. 5 unchanged, Coriolis term included), so trajectories
+ *                    that share (E_coll, b, R0) share the path and differ only in
+ *                    their initial amplitudes: many initial states per trajectory.
+ *                    energy_err then follows P^2/2mu + P_Phi^2/(2 mu R^2) + U(R)
+ *                    and angmom_err follows P_Phi.
  */
 typedef struct {
   int64_t B;
@@ -164,6 +184,7 @@ typedef struct {
   int64_t max_steps;
   double h_min;
   int32_t schedule;
+  int32_t dynamics;
 } mqct_batch_desc;
 
 /*

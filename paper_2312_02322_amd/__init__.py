@@ -22,6 +22,7 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_NOT_HERMITIAN, ERR_OOM, ERR_DEVICE, ERR_UNSUPPOR
     0, -1, -2, -3, -4, -5, -6, -7
 DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
 INTEGRATORS = {"rk4": 0, "dp5": 1}
+DYNAMICS = {"ehrenfest": 0, "at": 1}
 SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3}
 OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5}
 MEM_HOST, MEM_DEVICE = 0, 1
@@ -32,7 +33,7 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
            "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
            "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
-           "mqct_set_option", "mqct_tuning_report"]
+           "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver"]
 
 
 class MQCTError(RuntimeError):
@@ -54,7 +55,7 @@ class BatchDesc(C.Structure):
                 ("b", C.c_void_p), ("R0", C.c_void_p), ("t0", C.c_void_p),
                 ("integrator", C.c_int32), ("dt", C.c_void_p), ("n_steps", C.c_void_p),
                 ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int64),
-                ("h_min", C.c_double), ("schedule", C.c_int32)]
+                ("h_min", C.c_double), ("schedule", C.c_int32), ("dynamics", C.c_int32)]
 
 
 class BatchResult(C.Structure):
@@ -103,6 +104,8 @@ def lib():
         L.mqct_system_set_theta.restype = i32
         L.mqct_adjoint.argtypes = [vp, C.POINTER(BatchDesc), i32, vp, vp, vp]
         L.mqct_adjoint.restype = i32
+        L.mqct_system_set_driver.argtypes = [vp, i32, vp]
+        L.mqct_system_set_driver.restype = i32
         L.mqct_set_option.argtypes = [vp, i32, i64]
         L.mqct_set_option.restype = i32
         L.mqct_tuning_report.argtypes = [vp]
@@ -205,6 +208,11 @@ class Context:
         del keep
         return sid.value
 
+    def set_driver(self, sid, U):
+        """Driving potential U(R_k) [K] (hartree) for AT dynamics on this system."""
+        Uh = _host(U, np.float64)
+        self._check(lib().mqct_system_set_driver(self.h, sid, Uh.ctypes.data))
+
     def system_bytes(self, sid):
         out = C.c_int64()
         self._check(lib().mqct_system_bytes(self.h, sid, C.byref(out)))
@@ -217,7 +225,7 @@ class Context:
     def run(self, system_id, N_of, *, init_channel=None, a0=None, classical0=None, E_coll=None,
             b=None, R0=None, t0=None, dt=None, n_steps=None, integrator="rk4", rtol=1e-8,
             atol=1e-8, max_steps=100000, h_min=1e-6, schedule="auto", out=None,
-            with_amplitudes=True):
+            with_amplitudes=True, dynamics="ehrenfest"):
         """Propagate a batch; results are CUDA tensors filled asynchronously on the stream.
 
         system_id: [B] system ids; N_of: [B] channel count of each trajectory's system.
@@ -246,7 +254,8 @@ class Context:
         c0h = None if classical0 is None else _host(np.reshape(classical0, (B, 6)), np.float64)
         bd = BatchDesc(
             B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None, INTEGRATORS[integrator], None, None,
-            float(rtol), float(atol), int(max_steps), float(h_min), SCHEDULES[schedule])
+            float(rtol), float(atol), int(max_steps), float(h_min), SCHEDULES[schedule],
+            DYNAMICS[dynamics])
         hold = []
         for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
                                ("b", b, np.float64), ("R0", R0, np.float64), ("t0", t0, np.float64),
@@ -277,6 +286,7 @@ class Context:
         kw = dict(kw)
         schedule = kw.pop("schedule", "auto")
         integrator = kw.pop("integrator", "rk4")
+        dynamics = kw.pop("dynamics", "ehrenfest")
         a0 = kw.pop("a0", None)
         classical0 = kw.pop("classical0", None)
         a0h = None
@@ -286,7 +296,7 @@ class Context:
         bd = BatchDesc(B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None,
                        INTEGRATORS[integrator], None, None, float(kw.pop("rtol", 1e-8)),
                        float(kw.pop("atol", 1e-8)), int(kw.pop("max_steps", 100000)),
-                       float(kw.pop("h_min", 1e-6)), SCHEDULES[schedule])
+                       float(kw.pop("h_min", 1e-6)), SCHEDULES[schedule], DYNAMICS[dynamics])
         hold = []
         for name, dtp in (("init_channel", np.int32), ("E_coll", np.float64), ("b", np.float64),
                           ("R0", np.float64), ("t0", np.float64), ("dt", np.float64),
@@ -327,7 +337,7 @@ class Context:
         sids = np.full(B, sid, np.int32)
         hold = []
         bd = BatchDesc(B, sids.ctypes.data, None, None, None, None, None, None, None, 0, None,
-                       None, 0.0, 0.0, 0, 0.0, 0)
+                       None, 0.0, 0.0, 0, 0.0, 0, 0)
         for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
                                ("b", b, np.float64), ("R0", R0, np.float64), ("dt", dt, np.float64),
                                ("n_steps", n_steps, np.int64)):

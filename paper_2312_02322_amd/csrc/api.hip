@@ -27,6 +27,7 @@ struct SysHost {
   int P = 0, nG = 0;
   // G (dense), rad, rad2, gidx, then the nonzeros of G: offsets, row | col << 16, values
   void* pbufs[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* dbuf = nullptr;   // driving potential of AT dynamics and its curvature: [2][K]
 };
 
 // Grow-only device buffer.
@@ -137,6 +138,8 @@ void free_system(SysHost& s) {
     p = nullptr;
   }
   free_params(s);
+  if (s.dbuf) hipFree(s.dbuf);
+  s.dbuf = nullptr;
   s.live = false;
 }
 
@@ -370,6 +373,27 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   return MQCT_OK;
 }
 
+mqct_status mqct_system_set_driver(mqct_context* c, int32_t id, const double* U) {
+  if (!c) return MQCT_ERR_ARG;
+  if (id < 0 || id >= (int)c->systems.size() || !c->systems[id].live)
+    return fail(c, MQCT_ERR_STATE, "set_driver: unknown system %d", id);
+  if (!U) return fail(c, MQCT_ERR_ARG, "set_driver: null U");
+  SysHost& sh = c->systems[id];
+  const int K = sh.dev.K;
+  if (!finite_arr(U, K)) return fail(c, MQCT_ERR_NONFINITE, "set_driver: non-finite U");
+  HIP_TRY(c, hipSetDevice(c->device), "set_driver");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "set_driver");
+  if (!sh.dbuf) HIP_TRY(c, hipMalloc(&sh.dbuf, (size_t)4 * K * sizeof(double)), "set_driver");
+  double* d = (double*)sh.dbuf;   // U [K], U'' [K], then 2K of elimination scratch
+  HIP_TRY(c, hipMemcpyAsync(d, U, (size_t)K * sizeof(double), hipMemcpyHostToDevice, c->stream),
+          "set_driver");
+  HIP_TRY(c, launch_spline_rows(d, sh.dev.R, K, 1, d + K, d + 2 * K, c->stream), "set_driver");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "set_driver");
+  sh.dev.drv = d;
+  sh.dev.drv2 = d + K;
+  return upload_systems(c);
+}
+
 mqct_status mqct_system_bytes(mqct_context* c, int32_t id, int64_t* bytes) {
   if (!c) return MQCT_ERR_ARG;
   if (!bytes) return fail(c, MQCT_ERR_ARG, "system_bytes: null output");
@@ -423,6 +447,8 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   }
   if (!bd->classical0 && (!bd->E_coll || !bd->b))
     return fail(c, MQCT_ERR_ARG, "run: E_coll and b are required without classical0");
+  if (bd->dynamics != MQCT_EHRENFEST && bd->dynamics != MQCT_AT)
+    return fail(c, MQCT_ERR_ARG, "run: unknown dynamics %d", bd->dynamics);
   if (!bd->a0 && !bd->init_channel)
     return fail(c, MQCT_ERR_ARG, "run: init_channel is required without a0");
 
@@ -475,6 +501,12 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
       if (!(t.E_coll > 0.0) || !isfinite(t.E_coll))
         return fail(c, MQCT_ERR_ARG, "run: E_coll[%lld] must be > 0", (long long)b);
       if (t.R0 < 0.0) t.R0 = -1.0;   // resolved below from the grid
+    }
+    if (bd->dynamics == MQCT_AT) {
+      if (!sy.drv)
+        return fail(c, MQCT_ERR_STATE, "run: AT dynamics needs a driving potential for system %d "
+                    "(mqct_system_set_driver)", sid);
+      t.flags |= TRAJ_AT;
     }
     amp_total += sy.N;
     order[sy.dtype].push_back(b);
@@ -759,6 +791,8 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
       !bd->n_steps)
     return fail(c, MQCT_ERR_ARG, "adjoint: needs B >= 1, system_id, init_channel, E_coll, b, dt, n_steps");
   if (bd->integrator != MQCT_RK4) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: RK4 only");
+  if (bd->dynamics != MQCT_EHRENFEST)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: Ehrenfest dynamics only");
   if (bd->a0 || bd->classical0 || bd->t0)
     return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: start states come from init_channel/E_coll/b/R0");
   if (checkpoint_every < 1) return fail(c, MQCT_ERR_ARG, "adjoint: checkpoint_every must be >= 1");

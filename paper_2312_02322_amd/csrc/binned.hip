@@ -477,6 +477,15 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
     }
   }
   block_sum<6, NWT>(sums, red);
+  if (tj.flags & TRAJ_AT) {
+    // decoupled (AT) dynamics: the driving potential at the stage's R (same
+    // interval and weights as the tables) replaces the mean field
+    const int k = ws.kb[b];
+    const double* w = ws.wts + (int64_t)b * 8;
+    sums[2] = w[0] * sy.drv[k] + w[1] * sy.drv[k + 1] + w[2] * sy.drv2[k] + w[3] * sy.drv2[k + 1];
+    sums[0] = w[4] * sy.drv[k] + w[5] * sy.drv[k + 1] + w[6] * sy.drv2[k] + w[7] * sy.drv2[k + 1];
+    sums[1] = sums[3] = sums[5] = 0.0;
+  }
   const double force = sums[0], torque = sums[1], vexp = sums[2], erot = sums[3];
   const double norm = sums[4], jx = sums[5];
   const double E = ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * R * R) + erot + vexp;

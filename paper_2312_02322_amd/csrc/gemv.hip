@@ -35,6 +35,7 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
     int32_t status = 0;
     double E0 = 0.0, J0 = 0.0;
     bool first = true;
+    const bool at = (tj.flags & TRAJ_AT) != 0;
     Sums tot;
     int64_t j = 0;
     for (; j < tj.n_steps; ++j) {
@@ -52,7 +53,7 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
           kk[r] = make_double2(fma(cf, kk[r].x, a0[r].x), fma(cf, kk[r].y, a0[r].y));
-        eval(sy, t + cf, ys[0], ys[3], kk, tot, below, lds);
+        eval(sy, t + cf, ys[0], ys[3], kk, tot, below, lds, at);
         if (first) {
           E0 = energy(mu, ys, tot);
           J0 = ys[3] - tot.jx;
@@ -87,7 +88,7 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
     bool b2 = false;
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = a0[r];
-    eval(sy, tend, y[0], y[3], acc, tot, b2, lds);
+    eval(sy, tend, y[0], y[3], acc, tot, b2, lds, at);
     if (first) {
       E0 = energy(mu, y, tot);
       J0 = y[3] - tot.jx;

@@ -32,6 +32,8 @@ struct DevSystem {
   const void* M2;            // [K][N][Npad] natural-spline second derivatives
   const int32_t* jx_col;     // [N][jx_w], padding entries point at the row itself
   const double* jx_val;      // [N][jx_w], padding entries are 0
+  const double* drv;         // [K] driving potential U(R_k) of decoupled (AT) dynamics, or null
+  const double* drv2;        // [K] its natural-spline second derivatives
   int64_t knot_stride;       // N * Npad elements
 };
 
@@ -48,7 +50,7 @@ struct TrajIn {
   double c0[6];              // classical0 when flags & 2
 };
 
-enum { TRAJ_HAS_A0 = 1, TRAJ_HAS_C0 = 2 };
+enum { TRAJ_HAS_A0 = 1, TRAJ_HAS_C0 = 2, TRAJ_AT = 4 };
 
 // Where a kernel writes its per-trajectory results (device pointers; any may be
 // null except P).

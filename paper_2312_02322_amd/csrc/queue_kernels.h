@@ -66,7 +66,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     for (int r = 0; r < NR; ++r) cur[r] = a[r];
     Sums tot;
     bool b2 = false;
-    eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, b2, lds);
+    eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, b2, lds, (tj.flags & TRAJ_AT) != 0);
     write_out(sy, tj, out, a, s.yc, s.theta, s.ptheta, s.t, s.steps, s.rejects, s.status, tot,
               s.E0, s.J0);
   }
@@ -101,7 +101,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     for (int r = 0; r < NR; ++r) cur[r] = a[r];
     Sums tot;
     bool below = false;
-    eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, below, lds);
+    eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
     s.E0 = energy(sy.mu, s.yc, tot);
     s.J0 = s.yc[3] - tot.jx;
     store_rows(q.ws.amp + (int64_t)i * q.ws.npad, sy.N, a);
@@ -140,7 +140,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         kk[r] = make_double2(fma(cf, kk[r].x, a0[r].x), fma(cf, kk[r].y, a0[r].y));
-      eval(sy, t + cf, ys[0], ys[3], kk, tot, below, lds);
+      eval(sy, t + cf, ys[0], ys[3], kk, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
       classical_rhs(mu, ys, tot, ky);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -202,7 +202,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     for (int r = 0; r < NR; ++r) f0[r] = a[r];
     Sums tot;
     bool below = false;
-    eval(sy, s.t, s.yc[0], s.yc[3], f0, tot, below, lds);
+    eval(sy, s.t, s.yc[0], s.yc[3], f0, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
     s.E0 = energy(mu, s.yc, tot);
     s.J0 = s.yc[3] - tot.jx;
     classical_rhs(mu, s.yc, tot, s.kc1);
@@ -233,7 +233,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
       st[r] = make_double2(fma(h0, f0[r].x, a[r].x), fma(h0, f0[r].y, a[r].y));
     double ys[4], kc[4];
     for (int k = 0; k < 4; ++k) ys[k] = uni(fma(h0, s.kc1[k], s.yc[k]));
-    eval(sy, s.t + h0, ys[0], ys[3], st, tot, below, lds);
+    eval(sy, s.t + h0, ys[0], ys[3], st, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
     classical_rhs(mu, ys, tot, kc);
     double s1[1] = {0.0};
 #pragma unroll
@@ -297,7 +297,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
         ys[k] = uni(acc);
         if (sg == 6) y5c[k] = ys[k];
       }
-      eval(sy, s.t + QC[sg] * h, ys[0], ys[3], st, tot, below, lds);
+      eval(sy, s.t + QC[sg] * h, ys[0], ys[3], st, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
       double kc[4];
       classical_rhs(mu, ys, tot, kc);
       if (threadIdx.x == 0)

@@ -179,8 +179,13 @@ struct Rhs {
   // One evaluation of the right-hand side at time ts for the stage amplitudes
   // cur (this lane's rows) and classical stage values R, P_Phi.  Overwrites
   // cur with da/dt of this lane's rows and returns the workgroup sums in tot.
+  // at: decoupled (AT) dynamics -- the trajectory feels the driving potential
+  // U(R) instead of the mean field (paper Section III): the sums then carry
+  // force = U'(R), torque = 0, and the conserved quantities become
+  // P^2/2mu + P_Phi^2/(2 mu R^2) + U(R) (vexp = U, erot = 0) and P_Phi (jx = 0).
   __device__ static void eval(const DevSystem& sy, double ts, double R, double pphi,
-                              double2 (&cur)[NR], Sums& tot, bool& below, const Lds<DT>& lds) {
+                              double2 (&cur)[NR], Sums& tot, bool& below, const Lds<DT>& lds,
+                              bool at = false) {
     const int N = sy.N, Npad = sy.Npad;
     const Spl sp = spline_at(sy.R, sy.K, R);
     below |= sp.below;
@@ -327,6 +332,16 @@ struct Rhs {
     reduce<6>(sums, lds.red0);
     tot.force = sums[0]; tot.torque = sums[1]; tot.vexp = sums[2];
     tot.erot = sums[3]; tot.norm = sums[4]; tot.jx = sums[5];
+    if (at) {
+      const int k = sp.k;
+      tot.vexp = uni(sp.w0 * sy.drv[k] + sp.w1 * sy.drv[k + 1] + sp.w2 * sy.drv2[k] +
+                     sp.w3 * sy.drv2[k + 1]);
+      tot.force = uni(sp.d0 * sy.drv[k] + sp.d1 * sy.drv[k + 1] + sp.d2 * sy.drv2[k] +
+                      sp.d3 * sy.drv2[k + 1]);
+      tot.torque = 0.0;
+      tot.erot = 0.0;
+      tot.jx = 0.0;
+    }
   }
 
   // classical derivatives of (R, Phi, P_R, P_Phi), Eqs. 7-10
