@@ -58,18 +58,27 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--workload", choices=["window", "large", "uneven"], default="window",
+    ap.add_argument("--workload", choices=["window", "large", "uneven", "at"], default="window",
                     help="window: N=969 mid-collision windows (default, the headline); "
                          "large: N=4096, 512 full collisions of 10,000 RK4 steps on the binned "
-                         "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5")
+                         "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5; "
+                         "at: decoupled (AT) dynamics, 64 trajectories x 100 initial states")
     ap.add_argument("--large-n", type=int, default=4096)
     ap.add_argument("--large-traj", type=int, default=512)
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-window", type=int, default=1000)
+    ap.add_argument("--large-windows", type=int, default=0,
+                    help="run only the first windows of the collision (0: all)")
     ap.add_argument("--uneven-traj", type=int, default=20000)
+    ap.add_argument("--uneven-max-steps", type=int, default=100000)
+    ap.add_argument("--probe-bw", action="store_true",
+                    help="only measure streaming-read bandwidth at 2 GB, 200 MB and 8 MB footprints")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.probe_bw:
+        print(json.dumps(read_bandwidth_probe()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -90,6 +99,9 @@ def main():
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_workload(args)), flush=True)
+        return
+    if args.workload == "at":
+        print(json.dumps(at_workload(args)), flush=True)
         return
     t0 = time.time()
     (s,), b = S.config2(n_traj=args.traj, full_collision=False, window_steps=args.window)
@@ -255,7 +267,8 @@ def large_workload(args):
         state = None
         ms_tot = 0.0
         kern_ms = kern_n = kern_bytes = 0
-        for w in range(T // W):
+        n_win = T // W if args.large_windows <= 0 else min(T // W, args.large_windows)
+        for w in range(n_win):
             kw = dict(dt=b.dt, n_steps=np.full(B, W), schedule="binned")
             if state is None:
                 kw.update(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
@@ -278,7 +291,7 @@ def large_workload(args):
                      out["t_final"].cpu().numpy())
             R = state[1][:, 0]
             log("large %s: window %d/%d %.0f ms, R %.1f..%.1f bohr, max|norm-1| %.2e" % (
-                storage, w + 1, T // W, ms, R.min(), R.max(),
+                storage, w + 1, n_win, ms, R.min(), R.max(),
                 float(out["norm_err"].abs().max().item())))
         P = np.abs(state[0]) ** 2
         finals[storage] = P
@@ -300,9 +313,9 @@ def large_workload(args):
         roof["other_roof"] = {k: (mf if roof["bound"] == "hbm" else hb)[k]
                               for k in ("bound", "achieved", "peak", "unit", "frac")}
         res[storage] = {
-            "value": B * T / (ms_tot * 1e-3), "ms_per_window": ms_tot / (T // W),
-            "total_s": ms_tot * 1e-3,
-            "N2_traj_steps_per_s": B * T * float(N) * N / (ms_tot * 1e-3),
+            "value": B * W * n_win / (ms_tot * 1e-3), "ms_per_window": ms_tot / n_win,
+            "total_s": ms_tot * 1e-3, "windows": n_win,
+            "N2_traj_steps_per_s": B * W * n_win * float(N) * N / (ms_tot * 1e-3),
             "roofline": roof,
             "max_norm_err": float(np.max(np.abs(P.sum(1) - 1.0)))}
         log("large %s: %.3g traj-steps/s, bin_gemm %.3f ms (%.1f TFLOP/s = %.1f%%; %.0f GB/s "
@@ -323,7 +336,7 @@ def large_workload(args):
     ctx.close()
     head = res.get("C64") or res["C128"]
     line = {"metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
-            "steps": T // W, "warmup": 0, "ms_per_step": head["ms_per_window"],
+            "steps": head["windows"], "warmup": 0, "ms_per_step": head["ms_per_window"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32" if "C64" in res else "f64", "data": "synthetic",
             "config": {"workload": "N=%d random Hermitian tables on 200 R points, %d full "
@@ -336,6 +349,81 @@ def large_workload(args):
         line["fp32_vs_fp64_dP"] = {"max": float(d.max()), "mean": float(d.mean()),
                                    "p99": float(np.percentile(d, 99))}
         line["fp32_speedup_over_fp64"] = res["C64"]["value"] / res["C128"]["value"]
+    return line
+
+
+def at_workload(args, n_paths=64, n_init=100):
+    """Decoupled (AT) dynamics on the N = 969 asymmetric-top system: 64
+    trajectories in the mid-collision population of the default workload, each
+    carrying the 100 lowest channels as initial states (6400 amplitude columns),
+    driven by the isotropic part of the coupling; one bench step = a window of
+    RK4 steps of 12 a.u. on the binned schedule, FP32 and FP64 tables."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+    W = args.window
+    (s,), b0 = S.config2(n_traj=n_paths, full_collision=False, window_steps=W)
+    N = s.N
+    U = np.real(np.einsum("knn->k", s.M)) / N
+    idx = np.repeat(np.arange(n_paths), n_init)
+    b = b0.subset(idx)
+    b.init_channel = np.tile(np.arange(n_init, dtype=np.int32), n_paths)
+    B = b.B
+    ctx = mq.Context(0)
+    dev = ctx.device
+    res = {}
+    P_of = {}
+    for storage in ([args.only] if args.only else ["C64", "C128"]):
+        sid = ctx.load_system(s, storage=storage)
+        ctx.set_driver(sid, U)
+        sids, Ns = np.full(B, sid, np.int32), np.full(B, N, np.int64)
+        kw = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt,
+                  n_steps=b.n_steps, schedule="binned", dynamics="at")
+        for _ in range(args.warmup):
+            out = ctx.run(sids, Ns, **kw)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.set_profiling(True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            out = ctx.run(sids, Ns, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        km, kn, kb = ctx.profile_read(with_bytes=True)
+        ctx.set_profiling(False)
+        ms = e0.elapsed_time(e1) / args.steps
+        kms = km / kn
+        flops = 32.0 * N * N * B
+        peak = MFMA_PEAK_TFLOPS[storage]
+        tf = flops / (kms * 1e-3) / 1e12
+        P_of[storage] = out["P"].reshape(B, N).cpu().numpy()
+        cl = out["classical"].reshape(n_paths, n_init, 6)
+        res[storage] = {
+            "value": B * W / (ms * 1e-3), "ms_per_step": ms,
+            "paths_shared_bitwise": bool(torch.all(cl == cl[:, :1, :]).item()),
+            "roofline": {"kernel": "bin_gemm", "bound": "mfma", "achieved": tf, "peak": peak,
+                         "unit": "TFLOP/s", "frac": tf / peak, "traffic": None,
+                         "alg_flops_per_launch": flops, "launch_ms": kms, "launches_timed": kn,
+                         "table_bytes_per_launch": kb / kn}}
+        log("at %s: %.2f ms/step, %.3g column-steps/s, bin_gemm %.3f ms (%.1f TFLOP/s, %.1f%%)"
+            % (storage, ms, res[storage]["value"], kms, tf, 100 * tf / peak))
+        ctx.free_system(sid)
+    ctx.close()
+    head = res.get("C64") or res["C128"]
+    line = {"metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if "C64" in res else "f64", "data": "synthetic",
+            "config": {"workload": "AT dynamics, N=969 asymmetric top + atom, %d mid-collision "
+                                   "paths x %d initial states (%d amplitude columns), %d RK4 "
+                                   "steps of 12 a.u. per bench step, binned schedule"
+                                   % (n_paths, n_init, B, W),
+                       "N": N, "paths": n_paths, "initial_states": n_init},
+            "roofline": head["roofline"], "variants": res}
+    if "C64" in P_of and "C128" in P_of:
+        line["fp32_vs_fp64_max_abs_dP"] = float(np.max(np.abs(P_of["C64"] - P_of["C128"])))
     return line
 
 
@@ -366,7 +454,7 @@ def uneven_workload(args):
     log("uneven: autotuner %s" % ctx.tuning_report())
     torch.cuda.synchronize()
     t1 = time.time()
-    g = ctx.run_host(sids, Ns, max_steps=100000, **start, **DP)
+    g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, **start, **DP)
     sec = time.time() - t1
     steps, rej = g["steps"], g["rejects"]
     npad = ((Ns + 15) // 16) * 16
@@ -491,6 +579,30 @@ def cpu_baseline(s, b, W):
     return {"value": n * W / dt, "unit": "traj-steps/s", "cores": th, "kind": "oracle",
             "sample": "first %d of the %d trajectories x the same %d RK4 steps (FP64 oracle, "
                       "complex N=969 tables); wall time of the propagation only" % (n, b.B, W)}
+
+
+def read_bandwidth_probe(reps=20):
+    """Achievable streaming-read bandwidth: a float32 sum over buffers of 2 GB
+    (HBM), 200 MB (fits the 256 MB Infinity Cache) and 8 MB, timed with events
+    over `reps` back-to-back reductions (the result is 4 bytes)."""
+    import torch
+    out = {}
+    for name, nbytes in (("2GB", 2 << 30), ("200MB", 200 << 20), ("8MB", 8 << 20)):
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            x.sum()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            x.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"bytes": nbytes, "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}
+        log("read probe %s: %.3f ms, %.0f GB/s" % (name, ms, out[name]["GBps"]))
+        del x
+    return {"read_bandwidth_probe": out}
 
 
 def copy_probe(nbytes):
