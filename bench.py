@@ -56,6 +56,9 @@ def main():
                     help="time one full gradient on the N=256 two-rotor workload")
     ap.add_argument("--adjoint-traj", type=int, default=1024)
     ap.add_argument("--adjoint-steps", type=int, default=4096)
+    ap.add_argument("--adjoint-layout", choices=["dense", "sparse"], default="sparse",
+                    help="table layout of the adjoint workload (sparse keeps every structural "
+                         "nonzero: the same gradient)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--workload", choices=["window", "large", "uneven", "at"], default="window",
@@ -71,6 +74,9 @@ def main():
                     help="run only the first windows of the collision (0: all)")
     ap.add_argument("--uneven-traj", type=int, default=20000)
     ap.add_argument("--uneven-max-steps", type=int, default=100000)
+    ap.add_argument("--uneven-layout", choices=["dense", "sparse"], default="sparse",
+                    help="sparse: systems whose tables are mostly structural zeros keep only the "
+                         "nonzeros (drop_below = 0, the same results)")
     ap.add_argument("--probe-bw", action="store_true",
                     help="only measure streaming-read bandwidth at 2 GB, 200 MB and 8 MB footprints")
     args = ap.parse_args()
@@ -92,7 +98,8 @@ def main():
     from synth import systems as S
 
     if args.adjoint == "only":
-        print(json.dumps(adjoint_timing(args.adjoint_traj, args.adjoint_steps)), flush=True)
+        print(json.dumps(adjoint_timing(args.adjoint_traj, args.adjoint_steps,
+                                        layout=args.adjoint_layout)), flush=True)
         return
     if args.workload == "large":
         print(json.dumps(large_workload(args)), flush=True)
@@ -231,7 +238,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(s, b, W)
     ctx.close()
     if args.adjoint == "on":
-        line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps)
+        line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps,
+                                         layout=args.adjoint_layout)
     print(json.dumps(line), flush=True)
 
 
@@ -443,7 +451,14 @@ def uneven_workload(args):
     log("uneven: generated %s, B=%d in %.1fs" % ([x.N for x in systems], b.B, time.time() - t0))
     ctx = mq.Context(0)
     kinds = ["R32", "R32", "C64"]
-    ids = [ctx.load_system(x, storage=k) for x, k in zip(systems, kinds)]
+    layouts = []
+    for x in systems:
+        A = np.abs(x.M).max(axis=0)
+        kept = float(np.mean((A > 0) | (A.T > 0)))
+        layouts.append("sparse" if args.uneven_layout == "sparse" and kept < 0.5 else "dense")
+    ids = [ctx.load_system(x, storage=k, layout=l) for x, k, l in zip(systems, kinds, layouts)]
+    # table bytes one right-hand side streams: four slices of the stored matrices
+    rhs_bytes = [2.0 * ctx.system_bytes(i) / x.K for i, x in zip(ids, systems)]
     sids = np.array([ids[i] for i in b.system_index], np.int32)
     Ns = np.array([systems[i].N for i in b.system_index], np.int64)
     DP = dict(integrator="dp5", rtol=1e-8, atol=1e-8, h_min=1e-6)
@@ -457,15 +472,14 @@ def uneven_workload(args):
     g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, **start, **DP)
     sec = time.time() - t1
     steps, rej = g["steps"], g["rejects"]
-    npad = ((Ns + 15) // 16) * 16
-    es = np.array([{"R32": 4, "C64": 8}[kinds[i]] for i in b.system_index])
     evals = 6 * (steps + rej) + 3          # attempts x 6, the two starting evaluations, the end
-    alg_bytes = float(np.sum(evals * 4.0 * Ns * npad * es))
+    alg_bytes = float(np.sum(evals * np.array([rhs_bytes[i] for i in b.system_index])))
     per = {}
     for si, x in enumerate(systems):
         m = b.system_index == si
         st = steps[m]
         per["N=%d" % x.N] = {"trajectories": int(m.sum()), "storage": kinds[si],
+                             "layout": layouts[si],
                              "steps_p0_p50_p90_p100": [int(v) for v in
                                                        np.percentile(st, [0, 50, 90, 100])],
                              "rejects": int(rej[m].sum()),
@@ -478,7 +492,8 @@ def uneven_workload(args):
             "data": "synthetic",
             "config": {"workload": "uneven batch of %d trajectories: N=49/256/969 systems "
                                    "60/30/10 %%, E_coll log-uniform 10-5000 cm^-1, DP5 rtol 1e-8, "
-                                   "FP32 tables, work-list schedule" % b.B,
+                                   "FP32 tables (%s layout where mostly zero), "
+                                   "work-list schedule" % (b.B, args.uneven_layout),
                        "trajectories": b.B},
             "N2_traj_steps_per_s": float(np.sum(steps * Ns.astype(float) ** 2)) / sec,
             "coupling_GBps": gbps,
@@ -515,13 +530,14 @@ def uneven_cpu_baseline(systems, b, per_system=8, max_steps=2000):
                       "%d steps each); wall time of the propagation only" % (per_system, max_steps)}
 
 
-def adjoint_timing(n_traj, n_steps, checkpoint_every=256):
+def adjoint_timing(n_traj, n_steps, checkpoint_every=256, layout="sparse"):
     """Seconds per full 96-coefficient gradient of a b-weighted inelastic cross section.
 
     Two linear rotors, j1, j2 <= 3 (N = 256), potential linear in 96 coefficients,
     n_traj trajectories of n_steps RK4 steps; L = sum_i (2 pi b_max / B) b_i
     sum_{n outside the initial level} P_i(n); discrete adjoint with checkpoints
-    every 256 steps.
+    every 256 steps.  layout="sparse" stores only the structural nonzeros of the
+    tables (drop_below = 0: the gradient of the same model).
     """
     import numpy as np
     import torch
@@ -529,7 +545,7 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256):
     from synth import systems as S
     (s,), b = S.config4(n_traj=n_traj, n_steps=n_steps)
     ctx = mq.Context(0)
-    sid = ctx.load_system(s)
+    sid = ctx.load_system(s, layout=layout)
     ctx.set_params(sid, s.param_radial, s.param_G_index, s.G)
     ctx.set_theta(sid, s.theta)
     lev = s.level_of_channel
@@ -541,10 +557,14 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256):
     t0 = time.time()
     grad, P = ctx.adjoint(sid, s.N, w, **kw)
     sec = time.time() - t0
+    table_bytes = ctx.system_bytes(sid)
     ctx.close()
-    log("adjoint: %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad, |grad| = %.3e"
-        % (b.B, n_steps, s.N, grad.shape[0], sec, float(np.linalg.norm(grad))))
-    return {"s_per_grad": sec, "unit": "s", "trajectories": b.B, "rk4_steps": n_steps, "N": s.N,
+    log("adjoint (%s tables): %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad, "
+        "|grad| = %.3e" % (layout, b.B, n_steps, s.N, grad.shape[0], sec,
+                           float(np.linalg.norm(grad))))
+    return {"s_per_grad": sec, "unit": "s", "layout": layout, "table_bytes": table_bytes,
+            "trajectories": b.B,
+            "rk4_steps": n_steps, "N": s.N,
             "n_coefficients": int(grad.shape[0]), "checkpoint_every": checkpoint_every,
             "L": float(np.sum(w * P)), "grad_norm": float(np.linalg.norm(grad))}
 

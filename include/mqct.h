@@ -53,6 +53,8 @@ enum {
 enum { MQCT_R64 = 0, MQCT_C128 = 1, MQCT_R32 = 2, MQCT_C64 = 3 };
 /* time steppers */
 enum { MQCT_RK4 = 0, MQCT_DP5 = 1 };
+/* table layouts */
+enum { MQCT_DENSE = 0, MQCT_SPARSE = 1 };
 /* dynamics: Ehrenfest mean field (Eqs. 5, 7-10 coupled), or AT -- the quantum
    equations (Eq. 5) propagated along a trajectory that does not feel the
    quantum state (Section III), driven by the system's driving potential */
@@ -105,6 +107,14 @@ mqct_status mqct_synchronize(mqct_context* ctx);
  *   jx_*      J_x as a coordinate list (host), real symmetric, at most 8
  *             nonzeros per row; jx_nnz may be 0.
  *   mu        reduced mass, electron masses.
+ *   layout    MQCT_DENSE: every element stored.  MQCT_SPARSE: only the elements
+ *             whose magnitude exceeds drop_below (hartree, >= 0) at some knot,
+ *             in (m, n) or (n, m), are kept -- the paper's truncated coupling
+ *             matrices (elements above 1 cm^-1, Section III) and the block
+ *             structure of couplings that conserve m.  Each column's kept rows
+ *             are stored as a slot list (ELL, width = the largest count), and
+ *             the dropped elements are exactly zero in every computation.  The
+ *             binned schedule needs dense tables.
  * The natural-spline second derivatives of every element are computed on the
  * device in FP64 and stored with the tables in the storage type.
  */
@@ -121,6 +131,8 @@ typedef struct {
   const int32_t* jx_col;
   const double* jx_val;
   double mu;
+  int32_t layout;
+  double drop_below;
 } mqct_system_desc;
 
 /* Validate (finite, Hermitian, increasing grid), upload, spline-prepare.

@@ -23,6 +23,7 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_NOT_HERMITIAN, ERR_OOM, ERR_DEVICE, ERR_UNSUPPOR
 DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
 INTEGRATORS = {"rk4": 0, "dp5": 1}
 DYNAMICS = {"ehrenfest": 0, "at": 1}
+LAYOUTS = {"dense": 0, "sparse": 1}
 SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3}
 OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5}
 MEM_HOST, MEM_DEVICE = 0, 1
@@ -46,7 +47,8 @@ class SystemDesc(C.Structure):
     _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("R_grid", C.c_void_p), ("E", C.c_void_p),
                 ("in_dtype", C.c_int32), ("M_mem", C.c_int32), ("M", C.c_void_p),
                 ("storage", C.c_int32), ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p),
-                ("jx_col", C.c_void_p), ("jx_val", C.c_void_p), ("mu", C.c_double)]
+                ("jx_col", C.c_void_p), ("jx_val", C.c_void_p), ("mu", C.c_double),
+                ("layout", C.c_int32), ("drop_below", C.c_double)]
 
 
 class BatchDesc(C.Structure):
@@ -165,13 +167,14 @@ class Context:
 
     # ------------------------------------------------------------------ systems
     def load_system(self, system=None, *, R_grid=None, E=None, M=None, jx=None, mu=None,
-                    storage=None):
+                    storage=None, layout="dense", drop_below=0.0):
         """Upload a system (tables copied; spline prepared on the device).
 
         `system` may be any object with R_grid, E, M, jx_row, jx_col, jx_val and mu
         (atomic units).  M may be a numpy array (host) or a CUDA tensor (device),
         real or complex, shaped [K, N, N].  storage: "R64", "C128", "R32", "C64"
-        (default: the input's own precision).
+        (default: the input's own precision).  layout="sparse" keeps only the
+        elements whose magnitude exceeds drop_below (hartree) at some knot.
         """
         if system is not None:
             R_grid, E, M, mu = system.R_grid, system.E, system.M, system.mu
@@ -202,7 +205,8 @@ class Context:
             jr, jc, jv = _host(jx[0], np.int32), _host(jx[1], np.int32), _host(jx[2], np.float64)
             nnz = jr.shape[0]
         d = SystemDesc(N, K, Rg.ctypes.data, Eh.ctypes.data, DTYPES["C128" if cplx else "R64"],
-                       mem, M_ptr, DTYPES[storage], nnz, _ptr(jr), _ptr(jc), _ptr(jv), float(mu))
+                       mem, M_ptr, DTYPES[storage], nnz, _ptr(jr), _ptr(jc), _ptr(jv), float(mu),
+                       LAYOUTS[layout], float(drop_below))
         sid = C.c_int32()
         self._check(lib().mqct_system_load(self.h, C.byref(d), C.byref(sid)))
         del keep

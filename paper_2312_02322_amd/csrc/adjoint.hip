@@ -60,7 +60,7 @@ struct AdjArgs {
   const int* gidx;         // [P]
 };
 
-template <bool CPLX, int NR>
+template <bool CPLX, int NR, bool ELL>
 struct Adj {
   __device__ static int row(int r) { return threadIdx.x + r * AB; }
 
@@ -73,7 +73,8 @@ struct Adj {
 
   // the four spline coefficients of element (n, m) in interval k: value_k,
   // value_{k+1}, second derivative_k, second derivative_{k+1}.  Column access:
-  // M_nm = conj(S[m][n]) for Hermitian tables, S[m][n] for real symmetric ones.
+  // M_nm = conj(S[m][n]) for Hermitian tables, S[m][n] for real symmetric ones
+  // (m is the stored row, or the slot of sparse tables).
   struct Raw {
     double2 v[4];
   };
@@ -131,6 +132,10 @@ struct Adj {
   __device__ static void rhs(const DevSystem& sy, double t, const St& Y, St& F, double2* lc,
                              double* red) {
     const int N = sy.N;
+    // stored rows per column: all N, or the kept slots of sparse tables (slot j
+    // of column n holds stored row ell_col[j][n])
+    constexpr bool ell = ELL;
+    const int nst = ell ? sy.ell_w : N;
     const double mu = sy.mu, R = Y.y[0], pphi = Y.y[3];
     const Spl sp = spline_at(sy.R, sy.K, R);
     double w[4], d[4], dd[4];
@@ -153,9 +158,10 @@ struct Adj {
       if (n >= N) { F.a[r] = make_double2(0.0, 0.0); continue; }
       double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
 #pragma unroll 4
-      for (int m = 0; m < N; ++m) {
+      for (int j = 0; j < nst; ++j) {
+        const int m = ell ? sy.ell_col[(int64_t)j * sy.Npad + n] : j;
         const double2 cm = lc[m];
-        const Raw q = raw(sy, sp.k, m, n);
+        const Raw q = raw(sy, sp.k, j, n);
         const double2 a1 = mt(comb(q, w), cm), a2 = mt(comb(q, d), cm);
         u.x += a1.x; u.y += a1.y; v.x += a2.x; v.y += a2.y;
       }
@@ -182,6 +188,10 @@ struct Adj {
                              const St& Gc, St& Yb, double& gth, double2* lc, double2* lg,
                              double2* ljc, double2* lmc, double* red, double* tq) {
     const int N = sy.N;
+    // stored rows per column: all N, or the kept slots of sparse tables (slot j
+    // of column n holds stored row ell_col[j][n])
+    constexpr bool ell = ELL;
+    const int nst = ell ? sy.ell_w : N;
     const double mu = sy.mu, R = Y.y[0], pphi = Y.y[3];
     const Spl sp = spline_at(sy.R, sy.K, R);
     double w[4], d[4], dd[4];
@@ -242,8 +252,9 @@ struct Adj {
       if (n >= N) continue;
       double2 Mc = make_double2(0.0, 0.0), Mppc = make_double2(0.0, 0.0);
 #pragma unroll 2
-      for (int m = 0; m < N; ++m) {
-        const Raw q = raw(sy, sp.k, m, n);
+      for (int j = 0; j < nst; ++j) {
+        const int m = ell ? sy.ell_col[(int64_t)j * sy.Npad + n] : j;
+        const Raw q = raw(sy, sp.k, j, n);
         const double2 Mv = comb(q, w), Md = comb(q, d), Mdd = comb(q, dd);
         const double2 cm = lc[m], gm = lg[m], jm = ljc[m];
         const double2 t1 = mt(Mv, gm), t2 = mt(Mv, cm), t3 = mt(Mv, jm), t4 = mt(Md, cm),
@@ -353,10 +364,10 @@ struct Adj {
   }
 };
 
-template <bool CPLX, int NR>
+template <bool CPLX, int NR, bool ELL>
 __global__ void __launch_bounds__(AB)
 adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
-  using K = Adj<CPLX, NR>;
+  using K = Adj<CPLX, NR, ELL>;
   using St = typename K::St;
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x;
@@ -516,7 +527,8 @@ int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S) {
   return ((nseg > 0 ? nseg : 1) + 4 * (int64_t)S) * SV;
 }
 
-hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, int Npad, const TrajIn* d_traj,
+hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
+                          const TrajIn* d_traj,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const uint32_t* gent, const double* gval,
@@ -529,16 +541,19 @@ hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, int Npad, const
   const size_t lds = (size_t)Npad * 64 + (size_t)ANW * NSC * 8 + (size_t)3 * NGMAX * 8;
   const int nr = (Npad + AB - 1) / AB;
   hipError_t e;
+  auto go = [&](auto cp, auto el) {
+    constexpr bool C = decltype(cp)::value, E = decltype(el)::value;
+    if (nr <= 1) adjoint_kernel<C, 1, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
+    else if (nr <= 2) adjoint_kernel<C, 2, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
+    else adjoint_kernel<C, 4, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
+  };
+  if (nr > 4) return hipErrorInvalidValue;
   if (cplx) {
-    if (nr <= 1) adjoint_kernel<true, 1><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 2) adjoint_kernel<true, 2><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 4) adjoint_kernel<true, 4><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else return hipErrorInvalidValue;
+    if (ell) go(std::true_type{}, std::true_type{});
+    else go(std::true_type{}, std::false_type{});
   } else {
-    if (nr <= 1) adjoint_kernel<false, 1><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 2) adjoint_kernel<false, 2><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 4) adjoint_kernel<false, 4><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else return hipErrorInvalidValue;
+    if (ell) go(std::false_type{}, std::true_type{});
+    else go(std::false_type{}, std::false_type{});
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   grad_reduce<<<(P + 127) / 128, 128, 0, s>>>(grad_part, B, P, grad_out);

@@ -28,6 +28,7 @@ struct SysHost {
   // G (dense), rad, rad2, gidx, then the nonzeros of G: offsets, row | col << 16, values
   void* pbufs[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   void* dbuf = nullptr;   // driving potential of AT dynamics and its curvature: [2][K]
+  void* ebuf[2] = {nullptr, nullptr};   // sparse tables: slot lists [W][Npad], kept per column [N]
 };
 
 // Grow-only device buffer.
@@ -140,6 +141,10 @@ void free_system(SysHost& s) {
   free_params(s);
   if (s.dbuf) hipFree(s.dbuf);
   s.dbuf = nullptr;
+  for (auto& p : s.ebuf) {
+    if (p) hipFree(p);
+    p = nullptr;
+  }
   s.live = false;
 }
 
@@ -225,6 +230,10 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   if (d->M_mem != MQCT_MEM_HOST && d->M_mem != MQCT_MEM_DEVICE)
     return fail(c, MQCT_ERR_ARG, "system_load: M_mem must be host or device");
   if (!(d->mu > 0.0) || !isfinite(d->mu)) return fail(c, MQCT_ERR_ARG, "system_load: mu must be > 0");
+  if (d->layout != MQCT_DENSE && d->layout != MQCT_SPARSE)
+    return fail(c, MQCT_ERR_ARG, "system_load: unknown layout %d", d->layout);
+  if (!(d->drop_below >= 0.0) || !isfinite(d->drop_below))
+    return fail(c, MQCT_ERR_ARG, "system_load: drop_below must be finite and >= 0");
   if (!finite_arr(d->R_grid, K)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite R grid");
   for (int k = 1; k < K; ++k)
     if (!(d->R_grid[k] > d->R_grid[k - 1]))
@@ -336,6 +345,48 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
                                  sh.bufs[0], sh.bufs[1], tmp, tmp_doubles, c->stream)) != hipSuccess)
     return dfail(e, "system_load: spline");
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return dfail(e, "system_load: spline");
+  if (d->layout == MQCT_SPARSE) {
+    // keep the elements above drop_below somewhere on the grid; slot lists per column
+    double* amax = nullptr;
+    auto efail = [&](hipError_t err, const char* what) {
+      if (amax) hipFree(amax);
+      return dfail(err, what);
+    };
+    if ((e = hipMalloc((void**)&amax, (size_t)N * N * 8)) != hipSuccess) return efail(e, "system_load: pattern");
+    if ((e = hipMalloc(&sh.ebuf[1], (size_t)N * 4)) != hipSuccess) return efail(e, "system_load: pattern");
+    if ((e = launch_ell_pattern(din, N, K, ncomp, d->drop_below, amax, (int*)sh.ebuf[1], c->stream)) != hipSuccess)
+      return efail(e, "system_load: pattern");
+    std::vector<int> cnt(N);
+    if ((e = hipMemcpyAsync(cnt.data(), sh.ebuf[1], (size_t)N * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return efail(e, "system_load: pattern");
+    int Wm = 1;
+    for (int n = 0; n < N; ++n) Wm = std::max(Wm, cnt[n]);
+    void* E = nullptr;
+    void* E2 = nullptr;
+    const size_t ebytes = (size_t)K * Wm * Npad * ncomp * es;
+    if ((e = hipMalloc(&sh.ebuf[0], (size_t)Wm * Npad * 4)) != hipSuccess) return efail(e, "system_load: slots");
+    if ((e = launch_ell_fill(amax, N, Npad, Wm, d->drop_below, (int32_t*)sh.ebuf[0], c->stream)) != hipSuccess)
+      return efail(e, "system_load: slots");
+    if ((e = hipMalloc(&E, ebytes)) != hipSuccess) return efail(e, "system_load: sparse tables");
+    if ((e = hipMalloc(&E2, ebytes)) != hipSuccess) { hipFree(E); return efail(e, "system_load: sparse tables"); }
+    if ((e = launch_ell_gather(sh.bufs[0], sh.bufs[1], (const int32_t*)sh.ebuf[0], (const int*)sh.ebuf[1],
+                               N, Npad, K, Wm, ncomp, d->storage, E, E2, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+      hipFree(E);
+      hipFree(E2);
+      return efail(e, "system_load: sparse tables");
+    }
+    hipFree(amax);
+    hipFree(sh.bufs[0]);
+    hipFree(sh.bufs[1]);
+    sh.bufs[0] = E;
+    sh.bufs[1] = E2;
+    sh.dev.ell_w = Wm;
+    sh.dev.ell_col = (const int32_t*)sh.ebuf[0];
+    sh.dev.knot_stride = (int64_t)Wm * Npad;
+    sh.table_bytes = 2 * (int64_t)ebytes;
+  }
   if (W > 0) {
     std::vector<int32_t> col((size_t)N * W);
     std::vector<double> val((size_t)N * W, 0.0);
@@ -435,6 +486,11 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     for (int64_t b = 1; b < B; ++b)
       if (bd->system_id[b] != bd->system_id[0])
         return fail(c, MQCT_ERR_UNSUPPORTED, "run: a binned batch must use a single system");
+    const int sid0 = bd->system_id[0];
+    if (sid0 >= 0 && sid0 < (int)c->systems.size() && c->systems[sid0].live &&
+        c->systems[sid0].dev.ell_w > 0)
+      return fail(c, MQCT_ERR_UNSUPPORTED,
+                  "run: the binned schedule multiplies dense tables (system %d is sparse)", sid0);
   }
   const bool dp5 = bd->integrator == MQCT_DP5;
   // DP5 always runs on the work-list schedule (trajectory lengths differ)
@@ -628,7 +684,7 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
         // RK4 stages plus the final diagnostic evaluation, four slices each
         for (int64_t q = ranges[d].first; q < ranges[d].second; ++q) {
           const DevSystem& sy = c->systems[c->h_traj[q].sys].dev;
-          c->prof.bytes += (4.0 * c->h_traj[q].n_steps + 1.0) * 4.0 * sy.N * (double)sy.Npad *
+          c->prof.bytes += (4.0 * c->h_traj[q].n_steps + 1.0) * 4.0 * (double)sy.knot_stride *
                            dtype_bytes(sy.dtype);
         }
       }
@@ -697,6 +753,21 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
   HIP_TRY(c, hipSetDevice(c->device), "set_params");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "set_params");
   free_params(sh);
+  // sparse tables keep the load-time pattern: the model is the truncated one,
+  // so its derivative in theta lists only the kept elements of each G_t
+  std::vector<char> kept;
+  if (sh.dev.ell_w > 0) {
+    const int W = sh.dev.ell_w;
+    std::vector<int32_t> col((size_t)W * Npad);
+    std::vector<int> cnt(N);
+    HIP_TRY(c, hipMemcpy(col.data(), sh.dev.ell_col, col.size() * 4, hipMemcpyDeviceToHost),
+            "set_params: pattern");
+    HIP_TRY(c, hipMemcpy(cnt.data(), sh.ebuf[1], (size_t)N * 4, hipMemcpyDeviceToHost),
+            "set_params: pattern");
+    kept.assign((size_t)N * N, 0);
+    for (int n = 0; n < N; ++n)
+      for (int q = 0; q < cnt[n]; ++q) kept[(size_t)col[(size_t)q * Npad + n] * N + n] = 1;
+  }
   std::vector<double> Gp((size_t)nG * N * Npad, 0.0);
   std::vector<int> goff(nG + 1, 0);
   std::vector<uint32_t> gent;
@@ -706,7 +777,7 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
       for (int m = 0; m < N; ++m) {
         const double v = G[((int64_t)t * N + n) * N + m];
         Gp[((size_t)t * N + n) * Npad + m] = v;
-        if (v != 0.0) {
+        if (v != 0.0 && (kept.empty() || kept[(size_t)n * N + m])) {
           gent.push_back((uint32_t)n | ((uint32_t)m << 16));
           gval.push_back(v);
         }
@@ -776,10 +847,28 @@ mqct_status mqct_system_set_theta(mqct_context* c, int32_t id, const double* the
                                      (const int*)sh.pbufs[3], th, sh.P, sh.nG, N, Npad, K, Min,
                                      c->stream)) != hipSuccess)
     return done(e);
-  if ((e = launch_spline_prepare(Min, sh.dev.R, N, K, Npad, 1, sh.dev.dtype, sh.bufs[0],
-                                 sh.bufs[1], tmp, tmp_doubles, c->stream)) != hipSuccess)
-    return done(e);
-  return done(hipStreamSynchronize(c->stream));
+  if (sh.dev.ell_w == 0) {
+    if ((e = launch_spline_prepare(Min, sh.dev.R, N, K, Npad, 1, sh.dev.dtype, sh.bufs[0],
+                                   sh.bufs[1], tmp, tmp_doubles, c->stream)) != hipSuccess)
+      return done(e);
+    return done(hipStreamSynchronize(c->stream));
+  }
+  // sparse tables: dense storage first, then the load-time slots (the pattern is
+  // fixed when the system is loaded)
+  void* D = nullptr;
+  void* D2 = nullptr;
+  const size_t dbytes = (size_t)K * N * Npad * dtype_bytes(sh.dev.dtype);
+  if ((e = hipMalloc(&D, dbytes)) != hipSuccess) return done(e);
+  if ((e = hipMalloc(&D2, dbytes)) != hipSuccess) { hipFree(D); return done(e); }
+  e = launch_spline_prepare(Min, sh.dev.R, N, K, Npad, 1, sh.dev.dtype, D, D2, tmp, tmp_doubles,
+                            c->stream);
+  if (e == hipSuccess)
+    e = launch_ell_gather(D, D2, sh.dev.ell_col, (const int*)sh.ebuf[1], N, Npad, K, sh.dev.ell_w,
+                          1, sh.dev.dtype, sh.bufs[0], sh.bufs[1], c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(D);
+  hipFree(D2);
+  return done(e);
 }
 
 mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t checkpoint_every,
@@ -842,7 +931,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
           "adjoint");
   hipEvent_t e0 = c->prof.next(), e1 = c->prof.next();
   prof_mark(&c->prof, e0, c->stream);
-  HIP_TRY(c, launch_adjoint(c->d_systems, dtype_complex(sy.dtype), sy.Npad,
+  HIP_TRY(c, launch_adjoint(c->d_systems, dtype_complex(sy.dtype), sy.ell_w > 0, sy.Npad,
                             (const TrajIn*)(base + o_traj), B, (const double*)(base + o_w),
                             (double*)(base + o_part), (double*)(base + o_g),
                             (double*)(base + o_P), (double*)(base + o_s), stride, S,

@@ -24,7 +24,7 @@ inline int dtype_bytes(int d) { return d == C128 ? 16 : (d == R32 ? 4 : 8); }
 struct DevSystem {
   int32_t N, K, Npad, dtype;
   int32_t jx_w;              // ELL width of J_x (0 when there is no Coriolis term)
-  int32_t pad0;
+  int32_t ell_w;             // sparse tables: kept elements per column (0: dense tables)
   double mu;
   const double* R;           // [K]
   const double* E;           // [N]
@@ -32,6 +32,7 @@ struct DevSystem {
   const void* M2;            // [K][N][Npad] natural-spline second derivatives
   const int32_t* jx_col;     // [N][jx_w], padding entries point at the row itself
   const double* jx_val;      // [N][jx_w], padding entries are 0
+  const int32_t* ell_col;    // sparse tables: [ell_w][Npad] stored row of each slot
   const double* drv;         // [K] driving potential U(R_k) of decoupled (AT) dynamics, or null
   const double* drv2;        // [K] its natural-spline second derivatives
   int64_t knot_stride;       // N * Npad elements
@@ -116,6 +117,17 @@ inline void prof_mark(Prof* p, hipEvent_t e, hipStream_t s) {
 }
 
 // ---- launchers (defined in the .hip files) ----------------------------------
+
+// Sparse (ELL) tables: pattern of the elements whose magnitude exceeds thr at
+// some knot (amax [N][N] scratch, cnt [N] kept per column), the slot lists
+// col [W][Npad], and the gather of dense storage [K][N][Npad] into [K][W][Npad].
+hipError_t launch_ell_pattern(const double* M_in, int N, int K, int ncomp, double thr,
+                              double* amax, int* cnt, hipStream_t s);
+hipError_t launch_ell_fill(const double* amax, int N, int Npad, int W, double thr, int32_t* col,
+                           hipStream_t s);
+hipError_t launch_ell_gather(const void* D, const void* D2, const int32_t* col, const int* cnt,
+                             int N, int Npad, int K, int W, int ncomp, int dtype, void* E,
+                             void* E2, hipStream_t s);
 
 // Table preparation: from FP64 input (device, [K][N][N], real or complex
 // interleaved) write storage tables and their natural-spline second
@@ -227,7 +239,8 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
 // the parametric form enter as nonzero lists: entries goff[t] .. goff[t+1]-1,
 // gent = row | col << 16, gval the values.
 int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S);
-hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, int Npad, const TrajIn* d_traj,
+hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
+                          const TrajIn* d_traj,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const uint32_t* gent, const double* gval,

@@ -152,6 +152,78 @@ __global__ void xsec_kernel(int64_t B, const double* __restrict__ bpar,
   sigma[i] = cnt > 0.0 ? 2.0 * M_PI * b_max / cnt * s : 0.0;
 }
 
+// ---- sparse (ELL) layout of the tables ---------------------------------------
+//
+// An element (m, n) of the stored matrices is kept when its magnitude exceeds
+// `thr` at some knot, in either (m, n) or (n, m) (the input is Hermitian to
+// rounding; the test is made symmetric so that column n of the stored matrix
+// lists the same channels as row n).  Column n's kept rows m, ascending, are
+// col[q][n], q < cnt[n]; the values of slot q are the stored element (m, n) of
+// M and of its spline curvature, so a kernel that streams "stored row" q reads
+// exactly what the dense kernel reads for stored row m = col[q][n].
+
+// amax[m][n] = max over knots of |M_k(m, n)| (FP64 input [K][N][N][ncomp])
+__global__ void ell_amax(const double* __restrict__ M, int N, int K, int ncomp,
+                         double* __restrict__ amax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t NN = (int64_t)N * N;
+  if (i >= NN) return;
+  double a = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double* e = M + ((int64_t)k * NN + i) * ncomp;
+    const double v = ncomp == 2 ? sqrt(e[0] * e[0] + e[1] * e[1]) : fabs(e[0]);
+    a = fmax(a, v);
+  }
+  amax[i] = a;
+}
+
+__device__ __forceinline__ bool ell_keep(const double* amax, int N, int m, int n, double thr) {
+  return amax[(int64_t)m * N + n] > thr || amax[(int64_t)n * N + m] > thr;
+}
+
+__global__ void ell_count(const double* __restrict__ amax, int N, double thr,
+                          int* __restrict__ cnt) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int c = 0;
+  for (int m = 0; m < N; ++m) c += ell_keep(amax, N, m, n, thr);
+  cnt[n] = c;
+}
+
+// col[q][n] for q < W and n < Npad; unused slots (and padding columns) point at
+// row 0 with zero values
+__global__ void ell_fill(const double* __restrict__ amax, int N, int Npad, int W, double thr,
+                         int32_t* __restrict__ col) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Npad) return;
+  int q = 0;
+  if (n < N)
+    for (int m = 0; m < N && q < W; ++m)
+      if (ell_keep(amax, N, m, n, thr)) col[(int64_t)q++ * Npad + n] = m;
+  for (; q < W; ++q) col[(int64_t)q * Npad + n] = 0;
+}
+
+// E[k][q][n] = D[k][col[q][n]][n] for kept slots, 0 otherwise (both slices of the
+// storage type; ncomp reals per element)
+template <typename S>
+__global__ void ell_gather(const S* __restrict__ D, const S* __restrict__ D2,
+                           const int32_t* __restrict__ col, const int* __restrict__ cnt, int N,
+                           int Npad, int K, int W, int ncomp, S* __restrict__ E,
+                           S* __restrict__ E2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_knot = (int64_t)W * Npad;
+  if (i >= (int64_t)K * per_knot) return;
+  const int k = (int)(i / per_knot);
+  const int64_t r = i - (int64_t)k * per_knot;
+  const int q = (int)(r / Npad), n = (int)(r - (int64_t)q * Npad);
+  const bool kept = n < N && q < cnt[n];
+  const int64_t src = ((int64_t)k * N * Npad + (int64_t)col[(int64_t)q * Npad + n] * Npad + n) * ncomp;
+  for (int c = 0; c < ncomp; ++c) {
+    E[i * ncomp + c] = kept ? D[src + c] : (S)0;
+    E2[i * ncomp + c] = kept ? D2[src + c] : (S)0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_validate(const double* M_in, int N, int K, int ncomp,
@@ -182,6 +254,36 @@ hipError_t launch_spline_prepare(const double* M_in, const double* R, int N, int
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_ell_pattern(const double* M_in, int N, int K, int ncomp, double thr,
+                              double* amax, int* cnt, hipStream_t s) {
+  const int64_t NN = (int64_t)N * N;
+  ell_amax<<<(unsigned)((NN + 255) / 256), 256, 0, s>>>(M_in, N, K, ncomp, amax);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  ell_count<<<(unsigned)((N + 127) / 128), 128, 0, s>>>(amax, N, thr, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_ell_fill(const double* amax, int N, int Npad, int W, double thr, int32_t* col,
+                           hipStream_t s) {
+  ell_fill<<<(unsigned)((Npad + 127) / 128), 128, 0, s>>>(amax, N, Npad, W, thr, col);
+  return hipGetLastError();
+}
+
+hipError_t launch_ell_gather(const void* D, const void* D2, const int32_t* col, const int* cnt,
+                             int N, int Npad, int K, int W, int ncomp, int dtype, void* E,
+                             void* E2, hipStream_t s) {
+  const int64_t total = (int64_t)K * W * Npad;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (dtype_fp32(dtype))
+    ell_gather<float><<<blocks, 256, 0, s>>>((const float*)D, (const float*)D2, col, cnt, N, Npad,
+                                             K, W, ncomp, (float*)E, (float*)E2);
+  else
+    ell_gather<double><<<blocks, 256, 0, s>>>((const double*)D, (const double*)D2, col, cnt, N,
+                                              Npad, K, W, ncomp, (double*)E, (double*)E2);
+  return hipGetLastError();
 }
 
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b,

@@ -225,48 +225,73 @@ struct Rhs {
 #pragma unroll
     for (int r = 0; r < NR; ++r) { U[r] = make_double2(0.0, 0.0); V[r] = make_double2(0.0, 0.0); }
 
-    int mb = 0, me = N;   // stored rows this thread streams
+    // stored rows this thread streams: N rows of the dense tables, or the
+    // ell_w slots of the sparse ones (slot q of column n holds stored row
+    // col[q][n], so c is gathered per element instead of broadcast)
+    const int nst = sy.ell_w > 0 ? sy.ell_w : N;
+    int mb = 0, me = nst;
     if constexpr (SPLIT) {
       const int w = threadIdx.x >> 6;
-      mb = (N * w) / NW;
-      me = (N * (w + 1)) / NW;
+      mb = (nst * w) / NW;
+      me = (nst * (w + 1)) / NW;
     }
-    for (int m0 = mb; m0 < me; m0 += (FP32 ? CHUNK : N)) {
-      const int m1 = FP32 ? min(me, m0 + CHUNK) : me;
-      F2 pu[NR], pv[NR];
+    const auto rcol = slice_rsrc(sy.ell_col, (uint32_t)((int64_t)nst * Npad * 4));
+    auto stream = [&](auto sparse) {
+      constexpr bool ELL = decltype(sparse)::value;
+      for (int m0 = mb; m0 < me; m0 += (FP32 ? CHUNK : nst)) {
+        const int m1 = FP32 ? min(me, m0 + CHUNK) : me;
+        F2 pu[NR], pv[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        pu[r].x = pu[r].y = pv[r].x = pv[r].y = (F)0;
-      }
+        for (int r = 0; r < NR; ++r) {
+          pu[r].x = pu[r].y = pv[r].x = pv[r].y = (F)0;
+        }
 #pragma unroll UNR
-      for (int m = m0; m < m1; ++m) {
-        const CS cm = lds.c[m];
-        const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
-        // No lane guard: a lane whose column group lies past the last one reads
-        // into the next stored row (or past the slice, which returns zero) and
-        // its sums are never used, so the loads of consecutive m stay in flight
-        // together.
+        for (int m = m0; m < m1; ++m) {
+          CS cm;
+          if constexpr (!ELL) cm = lds.c[m];
+          const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
+          // No lane guard: a lane whose column group lies past the last one reads
+          // into the next stored row (or past the slice, which returns zero) and
+          // its sums are never used, so the loads of consecutive m stay in flight
+          // together.
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const uint32_t off = rowoff + (uint32_t)(rlane() + j * ROWW) * (uint32_t)sizeof(L);
-          const L v0 = load16<L>(rs0, off);
-          const L v1 = load16<L>(rs1, off);
-          const L v2 = load16<L>(rs2, off);
-          const L v3 = load16<L>(rs3, off);
-          F r0[VEC], i0[VEC], r1[VEC], i1[VEC], r2[VEC], i2[VEC], r3[VEC], i3[VEC];
-          split(v0, r0, i0); split(v1, r1, i1); split(v2, r2, i2); split(v3, r3, i3);
+          for (int j = 0; j < RPT; ++j) {
+            const uint32_t grp = (uint32_t)(rlane() + j * ROWW);
+            const uint32_t off = rowoff + grp * (uint32_t)sizeof(L);
+            const L v0 = load16<L>(rs0, off);
+            const L v1 = load16<L>(rs1, off);
+            const L v2 = load16<L>(rs2, off);
+            const L v3 = load16<L>(rs3, off);
+            F r0[VEC], i0[VEC], r1[VEC], i1[VEC], r2[VEC], i2[VEC], r3[VEC], i3[VEC];
+            split(v0, r0, i0); split(v1, r1, i1); split(v2, r2, i2); split(v3, r3, i3);
+            int cidx[VEC];
+            if constexpr (ELL) {
+              const uint32_t coff = ((uint32_t)m * (uint32_t)Npad + grp * VEC) * 4u;
+              if constexpr (VEC == 2) {
+                const int2 cc = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(rcol, coff, 0, 0));
+                cidx[0] = cc.x;
+                cidx[1] = cc.y;
+              } else {
+                cidx[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, coff, 0, 0);
+              }
+            }
 #pragma unroll
-          for (int q = 0; q < VEC; ++q)
-            elem<CPLX, F, F2>(pu[j * VEC + q], pv[j * VEC + q], r0[q], i0[q], r1[q], i1[q],
-                              r2[q], i2[q], r3[q], i3[q], w, d, cm);
+            for (int q = 0; q < VEC; ++q) {
+              if constexpr (ELL) cm = lds.c[cidx[q]];
+              elem<CPLX, F, F2>(pu[j * VEC + q], pv[j * VEC + q], r0[q], i0[q], r1[q], i1[q],
+                                r2[q], i2[q], r3[q], i3[q], w, d, cm);
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          U[r].x += (double)pu[r].x; U[r].y += (double)pu[r].y;
+          V[r].x += (double)pv[r].x; V[r].y += (double)pv[r].y;
         }
       }
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        U[r].x += (double)pu[r].x; U[r].y += (double)pu[r].y;
-        V[r].x += (double)pv[r].x; V[r].y += (double)pv[r].y;
-      }
-    }
+    };
+    if (sy.ell_w > 0) stream(std::true_type{});
+    else stream(std::false_type{});
 
     if constexpr (SPLIT) {
       // every wave's partial sums of all rows, added in wave order

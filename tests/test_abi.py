@@ -43,6 +43,6 @@ def test_null_context_calls_fail_cleanly():
 def test_struct_layouts_match_header():
     """The ctypes mirrors have the sizes the C compiler gives the header's structs."""
     import paper_2312_02322_amd as mq
-    assert C.sizeof(mq.SystemDesc) == 80
+    assert C.sizeof(mq.SystemDesc) == 96
     assert C.sizeof(mq.BatchDesc) == 136   # the trailing int32 dynamics fits the padding
     assert C.sizeof(mq.BatchResult) == 88
