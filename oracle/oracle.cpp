@@ -657,3 +657,111 @@ int32_t oracle_cross_sections(int64_t B, int32_t N, const int32_t* init_level,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Coupling matrix of an asymmetric-top rotor + linear rotor (Section II, Eq. 17)
+//
+// With the potential expanded as V = sum_t v_t(R) tau_t (Eqs. 12-13), the matrix
+// (Eq. 6) is linear in the coefficients: M(R) = sum_t v_t(R) G_t.  G_t is Eq. 17
+// with v_t = 1: the sums over m1', m1'', k1'', k1' and eta are taken as they are
+// written there, the only rearrangement being that the k-sum (which does not
+// depend on m1', m1'' or eta) is evaluated once per element.  Eq. 18 is not used:
+// as printed, its summation index m1' stands for the projection of j1' in one
+// factor and of j1'' in another.  Elements between different m vanish (Eq. 5
+// couples n' -> n'' within one m).
+//
+// Clebsch-Gordan coefficients come from Racah's closed form, summed in long
+// double.
+
+static long double fact_ld(int n) {
+  long double f = 1.0L;
+  for (int i = 2; i <= n; ++i) f *= (long double)i;
+  return f;
+}
+
+// <j1 m1 j2 m2 | J M> (Condon-Shortley phase), integer arguments
+static double cg_racah(int j1, int m1, int j2, int m2, int J, int M) {
+  if (m1 + m2 != M) return 0.0;
+  if (J < std::abs(j1 - j2) || J > j1 + j2) return 0.0;
+  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(M) > J) return 0.0;
+  const long double pre =
+      (2 * J + 1) * fact_ld(J + j1 - j2) * fact_ld(J - j1 + j2) * fact_ld(j1 + j2 - J) /
+      fact_ld(j1 + j2 + J + 1) * fact_ld(J + M) * fact_ld(J - M) * fact_ld(j1 - m1) *
+      fact_ld(j1 + m1) * fact_ld(j2 - m2) * fact_ld(j2 + m2);
+  long double s = 0.0L;
+  const int kmin = std::max(0, std::max(j2 - J - m1, j1 - J + m2));
+  const int kmax = std::min(j1 + j2 - J, std::min(j1 - m1, j2 + m2));
+  for (int k = kmin; k <= kmax; ++k) {
+    const long double den = fact_ld(k) * fact_ld(j1 + j2 - J - k) * fact_ld(j1 - m1 - k) *
+                            fact_ld(j2 + m2 - k) * fact_ld(J - j2 + m1 + k) *
+                            fact_ld(J - j1 - m2 + k);
+    s += ((k & 1) ? -1.0L : 1.0L) / den;
+  }
+  return (double)(sqrtl(pre) * s);
+}
+
+extern "C" {
+
+double oracle_cg(int j1, int m1, int j2, int m2, int J, int M) {
+  return cg_racah(j1, m1, j2, m2, J, M);
+}
+
+// G[t][n''][n'] for every term t and channel pair.  Channels: total j, projection
+// m, rotor-1 state rot1 and linear-rotor j2; rotor-1 state r has angular momentum
+// rot1_j[r] and coefficients b[r * b_stride + k + j1] (Eq. 1).  Terms: (lam1, mu1,
+// lam2, lam) of Eq. 13.  Returns 0, or -1 for an index out of range.
+int oracle_coupling_angular(int N, const int* jt, const int* mt, const int* rot1,
+                            const int* j2t, int n1, const int* rot1_j, const double* b,
+                            int b_stride, int T, const int* lam1, const int* mu1,
+                            const int* lam2, const int* lam, double* G) {
+  for (int n = 0; n < N; ++n)
+    if (rot1[n] < 0 || rot1[n] >= n1 || 2 * rot1_j[rot1[n]] + 1 > b_stride) return -1;
+  const double pi = M_PI;
+#pragma omp parallel for collapse(2) schedule(dynamic)
+  for (int t = 0; t < T; ++t)
+    for (int f = 0; f < N; ++f) {                // final state n''
+      const int l1 = lam1[t], u1 = mu1[t], l2 = lam2[t], l = lam[t];
+      const int sgn = ((l1 + u1 + l2 + l) & 1) ? -1 : 1;
+      for (int i = 0; i < N; ++i) {              // initial state n'
+        double* out = G + ((int64_t)t * N + f) * N + i;
+        *out = 0.0;
+        if (mt[f] != mt[i]) continue;
+        const int m = mt[i];
+        const int ja = jt[i], j1a = rot1_j[rot1[i]], j2a = j2t[i];   // n'
+        const int jb = jt[f], j1b = rot1_j[rot1[f]], j2b = j2t[f];   // n''
+        const double* ba = b + (int64_t)rot1[i] * b_stride;
+        const double* bb = b + (int64_t)rot1[f] * b_stride;
+        // sum over k1'', k1' of b b [C(j1' k1' l1 mu1 | j1'' k1'') + s C(j1' k1' l1 -mu1 | j1'' k1'')]
+        double ksum = 0.0;
+        for (int kb = -j1b; kb <= j1b; ++kb)
+          for (int ka = -j1a; ka <= j1a; ++ka)
+            ksum += bb[kb + j1b] * ba[ka + j1a] *
+                    (cg_racah(j1a, ka, l1, u1, j1b, kb) + sgn * cg_racah(j1a, ka, l1, -u1, j1b, kb));
+        if (ksum == 0.0) continue;
+        const double pre = std::sqrt((2 * j1b + 1) / (8 * pi * pi)) *
+                           std::sqrt((2 * j1a + 1) / (8 * pi * pi)) *
+                           std::sqrt((2 * l1 + 1) / (4 * pi));
+        const double y2 = std::sqrt((2 * j2a + 1) * (2 * l2 + 1) / (4 * pi * (2 * j2b + 1))) *
+                          cg_racah(j2a, 0, l2, 0, j2b, 0);
+        const double d1 = 8 * pi * pi / (2 * j1b + 1);
+        double s = 0.0;
+        for (int m1a = -j1a; m1a <= j1a; ++m1a) {
+          const double ca = cg_racah(j1a, m1a, j2a, m - m1a, ja, m);
+          if (ca == 0.0) continue;
+          for (int m1b = -j1b; m1b <= j1b; ++m1b) {
+            const double cb = cg_racah(j1b, m1b, j2b, m - m1b, jb, m);
+            if (cb == 0.0) continue;
+            const int emax = std::min(l1, l2);
+            for (int eta = -emax; eta <= emax; ++eta)
+              s += ca * cb * ksum * cg_racah(l1, eta, l2, -eta, l, 0) * y2 *
+                   cg_racah(j2a, m - m1a, l2, -eta, j2b, m - m1b) * d1 *
+                   cg_racah(j1a, m1a, l1, eta, j1b, m1b);
+          }
+        }
+        *out = pre * s;
+      }
+    }
+  return 0;
+}
+
+}  // extern "C"

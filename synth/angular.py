@@ -74,6 +74,32 @@ def asymmetric_top_levels(j, A, B, C):
     return np.linalg.eigvalsh(H)
 
 
+def asymmetric_top_states(j, A, B, C):
+    """Energies (ascending, tau = -j..j) and eigenvectors of the rigid asymmetric top
+    for one j, in the basis of Section II, Eq. 1 (coefficients b_k, k = -j..j).
+
+    Same Hamiltonian matrix as asymmetric_top_levels.  Row tau + j of the returned
+    array holds b_k of level tau; each vector is normalised and its largest
+    component made positive so that the phases are reproducible.
+    """
+    n = 2 * j + 1
+    H = np.zeros((n, n))
+    jj = j * (j + 1)
+    for i, k in enumerate(range(-j, j + 1)):
+        H[i, i] = 0.5 * (B + C) * (jj - k * k) + A * k * k
+        if k + 2 <= j:
+            off = 0.25 * (B - C) * math.sqrt((jj - k * (k + 1)) * (jj - (k + 1) * (k + 2)))
+            H[i, i + 2] = off
+            H[i + 2, i] = off
+    E, V = np.linalg.eigh(H)
+    b = V.T.copy()
+    for r in range(n):
+        big = int(np.argmax(np.abs(b[r])))
+        if b[r, big] < 0:
+            b[r] = -b[r]
+    return E, b
+
+
 def jx_block(j):
     """Rows, cols, values of J_x on |j m>, m = -j..j (indices local to the block).
 
