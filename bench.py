@@ -61,11 +61,13 @@ def main():
                          "nonzero: the same gradient)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--workload", choices=["window", "large", "uneven", "at"], default="window",
+    ap.add_argument("--workload", choices=["window", "large", "uneven", "at", "coupling"],
+                    default="window",
                     help="window: N=969 mid-collision windows (default, the headline); "
                          "large: N=4096, 512 full collisions of 10,000 RK4 steps on the binned "
                          "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5; "
-                         "at: decoupled (AT) dynamics, 64 trajectories x 100 initial states")
+                         "at: decoupled (AT) dynamics, 64 trajectories x 100 initial states; "
+                         "coupling: build the N=6825 top + rotor tables (83 terms, 63 knots)")
     ap.add_argument("--large-n", type=int, default=4096)
     ap.add_argument("--large-traj", type=int, default=512)
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -103,6 +105,9 @@ def main():
         return
     if args.workload == "large":
         print(json.dumps(large_workload(args)), flush=True)
+        return
+    if args.workload == "coupling":
+        print(json.dumps(coupling_workload(args)), flush=True)
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_workload(args)), flush=True)
@@ -432,6 +437,69 @@ def at_workload(args, n_paths=64, n_init=100):
             "roofline": head["roofline"], "variants": res}
     if "C64" in P_of and "C128" in P_of:
         line["fp32_vs_fp64_max_abs_dP"] = float(np.max(np.abs(P_of["C64"] - P_of["C128"])))
+    return line
+
+
+def coupling_workload(args, cpu_rows=64):
+    """Coupling-matrix build (Section II, Eqs. 12-18): asymmetric top (H2O constants,
+    j1 <= 6, every tau1) + para-H2 (j2 = 0, 2, 4), all j and m: N = 6825 channels;
+    83 expansion terms from the ranges of the paper's potential; 63 knots from 3 to
+    30 bohr.  One step = one complete build of the FP64 tables [63][N][N] (23.5 GB)
+    from the expansion coefficients.  The unit counts the elements between channels
+    of equal m (the ones the potential couples), times the knots."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import coupling as CP
+    basis, ex = CP.config6()
+    N, T, K = basis.N, ex.T, ex.K
+    counts = np.bincount(basis.m - basis.m.min()).astype(np.float64)
+    elements = float(np.sum(counts ** 2)) * K
+    ctx = mq.Context(0)
+    for _ in range(args.warmup):
+        out = ctx.build_couplings(basis, ex)
+        del out
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.time()
+    for _ in range(args.steps):
+        out = ctx.build_couplings(basis, ex)
+        del out
+    torch.cuda.synchronize()
+    sec = (time.time() - t0) / args.steps
+    km, kn, kb = ctx.profile_read(with_bytes=True)
+    ctx.set_profiling(False)
+    ctx.close()
+    kms = km / kn
+    written = kb / kn
+    gbps = written / (kms * 1e-3) / 1e9
+    log("coupling: N=%d T=%d K=%d, %.1f ms per build, fill kernel %.2f ms (%.0f GB/s written, "
+        "%.1f%% of HBM)" % (N, T, K, sec * 1e3, kms, gbps, 100 * gbps / HBM_PEAK_GBPS))
+    line = {"metric": "coupling-matrix elements/s (equal-m pairs x knots)",
+            "value": elements / sec, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "coupling-matrix build, asymmetric top (j1<=6) + para-H2 "
+                                   "(j2<=4), N=%d channels, %d expansion terms, %d knots, FP64 "
+                                   "tables [K][N][N]" % (N, T, K),
+                       "N": N, "terms": T, "knots": K},
+            "roofline": {"kernel": "cpl_fill", "bound": "hbm", "achieved": gbps,
+                         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                         "traffic": None, "alg_bytes_per_launch": written, "launch_ms": kms,
+                         "launches_timed": kn}}
+    if not args.no_cpu:
+        import oracle
+        rows = np.linspace(0, N - 1, cpu_rows).astype(np.int64)
+        t0 = time.time()
+        oracle.coupling_tables(basis, ex, rows=rows)
+        csec = time.time() - t0
+        cel = float(np.sum(counts[basis.m[rows] - basis.m.min()])) * K
+        line["cpu_baseline"] = {"value": cel / csec, "unit": "elements/s",
+                                "cores": oracle.threads(), "kind": "oracle",
+                                "sample": "%d of the %d rows (Eq. 17 sums), %.1f s"
+                                          % (cpu_rows, N, csec)}
+        log("coupling: oracle %.3g elements/s on %d rows (%.1f s, %d threads)"
+            % (cel / csec, cpu_rows, csec, oracle.threads()))
     return line
 
 

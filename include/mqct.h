@@ -322,6 +322,60 @@ mqct_status mqct_set_option(mqct_context* ctx, int32_t option, int64_t value);
 const char* mqct_tuning_report(mqct_context* ctx);
 
 /*
+ * Coupling-matrix builder for an asymmetric-top rotor + linear rotor (paper
+ * Section II, Eqs. 12-18).  The potential is given by its expansion
+ * V(R, angles) = sum_t v_t(R) tau_t (Eq. 12) over the angular functions of
+ * Eq. 13, labelled t = (lam1, mu1, lam2, lam); the channels are the coupled
+ * states of Eq. 3.  The builder writes, on the context stream,
+ *   M_out[k][n''][n'] = <n'' m | V(R_k) | n' m>   (Eq. 6 by Eq. 17), zero between
+ *                       channels of different m (Eq. 5 couples n' -> n'' within m)
+ *   G_out[t][n''][n'] = the same element for v_t = 1 and every other v zero
+ * in FP64, row n'' major.  Either output may be NULL (not both); both are
+ * device memory the caller owns: M_out holds K*N*N doubles, G_out T*N*N.
+ * M_out is what mqct_system_load takes as a device table (MQCT_MEM_DEVICE, real
+ * input); the G_out and v rows are a parametric form for
+ * mqct_system_set_params (radial = v, gidx = t, G = G_out copied to the host).
+ * The call returns when both outputs are written.
+ *
+ * All descriptor arrays are host memory:
+ *   N                  channels; j[N], m[N] total angular momentum and its
+ *                      projection; rot1[N] index of the channel's rotor-1 state;
+ *                      j2[N] the linear rotor's angular momentum.
+ *                      |j1 - j2| <= j <= j1 + j2, |m| <= j.
+ *   n_rot1, rot1_j     rotor-1 states and their j1 (0..40);
+ *   b, b_stride        coefficients of Eq. 1: b[r * b_stride + k + j1] for
+ *                      k = -j1..j1 (b_stride >= 2 j1 + 1), real;
+ *   T, lam1, mu1,      expansion terms: 0 <= lam1, lam2 <= 20, |mu1| <= lam1,
+ *   lam2, lam          |lam1 - lam2| <= lam <= lam1 + lam2;
+ *   K, v               radial coefficients v[t * K + k] (hartree) at the knots.
+ * j2 <= 40.  Errors: MQCT_ERR_ARG (bad sizes, indices, angular momenta, null
+ * pointers), MQCT_ERR_NONFINITE (b or v), MQCT_ERR_OOM / MQCT_ERR_DEVICE.
+ * The Clebsch-Gordan, 6j and 9j coefficients are formed in FP64 from
+ * log-factorials; their relative error grows with the angular momenta (about
+ * 1e-14 at j ~ 10).
+ */
+typedef struct {
+  int32_t N;
+  const int32_t* j;
+  const int32_t* m;
+  const int32_t* rot1;
+  const int32_t* j2;
+  int32_t n_rot1;
+  const int32_t* rot1_j;
+  const double* b;
+  int32_t b_stride;
+  int32_t T;
+  const int32_t* lam1;
+  const int32_t* mu1;
+  const int32_t* lam2;
+  const int32_t* lam;
+  int32_t K;
+  const double* v;
+} mqct_coupling_desc;
+mqct_status mqct_coupling_build(mqct_context* ctx, const mqct_coupling_desc* desc,
+                                double* M_out, double* G_out);
+
+/*
  * Optional timing of the dominant step kernel of later runs: the fused
  * per-trajectory RK4 kernel, the table x columns product of the binned
  * schedule, or each replayed chunk of the work-list schedule.  HIP events are
@@ -334,7 +388,9 @@ const char* mqct_tuning_report(mqct_context* ctx);
  *                 N x Npad stored elements per right-hand side (4 per step plus
  *                 the final diagnostic one); binned product, the value and
  *                 second-derivative slices of every occupied knot once per stage
- *                 (counted on the device); 0 for the work-list schedule.
+ *                 (counted on the device); 0 for the work-list schedule;
+ *                 for mqct_coupling_build (whose fill kernel is timed), the
+ *                 bytes it wrote (M_out and G_out).
  * and resets them.  Timing adds two event records per timed launch.
  */
 mqct_status mqct_set_profiling(mqct_context* ctx, int32_t enable);

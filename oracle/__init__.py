@@ -59,7 +59,7 @@ def lib():
         _lib.oracle_cg.argtypes = [i32] * 6
         _lib.oracle_cg.restype = d
         _lib.oracle_coupling_angular.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, i32, i32,
-                                                 vp, vp, vp, vp, vp]
+                                                 vp, vp, vp, vp, i32, vp, vp]
         _lib.oracle_coupling_angular.restype = i32
     return _lib
 
@@ -213,27 +213,31 @@ def cg(j1, m1, j2, m2, J, M):
     return float(lib().oracle_cg(j1, m1, j2, m2, J, M))
 
 
-def coupling_angular(basis, lam1, mu1, lam2, lam):
+def coupling_angular(basis, lam1, mu1, lam2, lam, rows=None):
     """G[t, n'', n']: Eq. 17 with v_t = 1 for each term t = (lam1, mu1, lam2, lam).
 
     basis: channels (j, m, rot1, j2) and rotor-1 states (rot1_j, b) as built by
-    synth.coupling.top_rotor_basis."""
+    synth.coupling.top_rotor_basis.  rows: only these final states n'' (the
+    result is then G[t, q, n'] for n'' = rows[q])."""
     i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
     j, m, r1, j2 = i32(basis.j), i32(basis.m), i32(basis.rot1), i32(basis.j2)
     rj, b = i32(basis.rot1_j), _f64(basis.b)
     l1, u1, l2, l = i32(lam1), i32(mu1), i32(lam2), i32(lam)
     N, T = j.shape[0], l1.shape[0]
-    G = np.empty((T, N, N))
+    rr = None if rows is None else i32(rows)
+    nr = N if rr is None else rr.shape[0]
+    G = np.empty((T, nr, N))
     rc = lib().oracle_coupling_angular(N, _p(j), _p(m), _p(r1), _p(j2), rj.shape[0], _p(rj),
                                        _p(b), b.shape[1], T, _p(l1), _p(u1), _p(l2), _p(l),
-                                       _p(G))
+                                       nr, _p(rr), _p(G))
     if rc != 0:
-        raise ValueError("coupling_angular: rotor-1 index or b layout out of range")
+        raise ValueError("coupling_angular: index or b layout out of range")
     return G
 
 
-def coupling_tables(basis, expansion):
+def coupling_tables(basis, expansion, rows=None):
     """M[k, n'', n'] = sum_t v_t(R_k) G_t (Eq. 12 into Eq. 17), and the G_t."""
-    G = coupling_angular(basis, expansion.lam1, expansion.mu1, expansion.lam2, expansion.lam)
+    G = coupling_angular(basis, expansion.lam1, expansion.mu1, expansion.lam2, expansion.lam,
+                         rows=rows)
     M = np.einsum("tk,tab->kab", np.asarray(expansion.v, np.float64), G)
     return M, G

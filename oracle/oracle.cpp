@@ -706,24 +706,31 @@ double oracle_cg(int j1, int m1, int j2, int m2, int J, int M) {
   return cg_racah(j1, m1, j2, m2, J, M);
 }
 
-// G[t][n''][n'] for every term t and channel pair.  Channels: total j, projection
-// m, rotor-1 state rot1 and linear-rotor j2; rotor-1 state r has angular momentum
-// rot1_j[r] and coefficients b[r * b_stride + k + j1] (Eq. 1).  Terms: (lam1, mu1,
-// lam2, lam) of Eq. 13.  Returns 0, or -1 for an index out of range.
+// G[t][q][n'] for every term t, the final states n'' = rows[q] (q < nrows; all
+// N in order when rows is null) and every initial state n'.  Channels: total j,
+// projection m, rotor-1 state rot1 and linear-rotor j2; rotor-1 state r has
+// angular momentum rot1_j[r] and coefficients b[r * b_stride + k + j1] (Eq. 1).
+// Terms: (lam1, mu1, lam2, lam) of Eq. 13.  Returns 0, or -1 for an index out of
+// range.
 int oracle_coupling_angular(int N, const int* jt, const int* mt, const int* rot1,
                             const int* j2t, int n1, const int* rot1_j, const double* b,
                             int b_stride, int T, const int* lam1, const int* mu1,
-                            const int* lam2, const int* lam, double* G) {
+                            const int* lam2, const int* lam, int nrows, const int* rows,
+                            double* G) {
   for (int n = 0; n < N; ++n)
     if (rot1[n] < 0 || rot1[n] >= n1 || 2 * rot1_j[rot1[n]] + 1 > b_stride) return -1;
+  if (!rows) nrows = N;
+  for (int q = 0; q < nrows; ++q)
+    if (rows && (rows[q] < 0 || rows[q] >= N)) return -1;
   const double pi = M_PI;
 #pragma omp parallel for collapse(2) schedule(dynamic)
   for (int t = 0; t < T; ++t)
-    for (int f = 0; f < N; ++f) {                // final state n''
+    for (int q = 0; q < nrows; ++q) {
+      const int f = rows ? rows[q] : q;          // final state n''
       const int l1 = lam1[t], u1 = mu1[t], l2 = lam2[t], l = lam[t];
       const int sgn = ((l1 + u1 + l2 + l) & 1) ? -1 : 1;
       for (int i = 0; i < N; ++i) {              // initial state n'
-        double* out = G + ((int64_t)t * N + f) * N + i;
+        double* out = G + ((int64_t)t * nrows + q) * N + i;
         *out = 0.0;
         if (mt[f] != mt[i]) continue;
         const int m = mt[i];

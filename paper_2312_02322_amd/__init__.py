@@ -34,7 +34,16 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_load", "mqct_system_bytes", "mqct_system_free", "mqct_run",
            "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
            "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
-           "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver"]
+           "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
+           "mqct_coupling_build"]
+
+
+class CouplingDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("j", C.c_void_p), ("m", C.c_void_p), ("rot1", C.c_void_p),
+                ("j2", C.c_void_p), ("n_rot1", C.c_int32), ("rot1_j", C.c_void_p),
+                ("b", C.c_void_p), ("b_stride", C.c_int32), ("T", C.c_int32),
+                ("lam1", C.c_void_p), ("mu1", C.c_void_p), ("lam2", C.c_void_p),
+                ("lam", C.c_void_p), ("K", C.c_int32), ("v", C.c_void_p)]
 
 
 class MQCTError(RuntimeError):
@@ -112,6 +121,8 @@ def lib():
         L.mqct_set_option.restype = i32
         L.mqct_tuning_report.argtypes = [vp]
         L.mqct_tuning_report.restype = C.c_char_p
+        L.mqct_coupling_build.argtypes = [vp, C.POINTER(CouplingDesc), vp, vp]
+        L.mqct_coupling_build.restype = i32
         _lib = L
     return _lib
 
@@ -356,6 +367,33 @@ class Context:
         self._check(lib().mqct_adjoint(self.h, C.byref(bd), int(checkpoint_every), w.ctypes.data,
                                        g.ctypes.data, P.ctypes.data))
         return g, P.reshape(B, N)
+
+    def build_couplings(self, basis, expansion, tables=True, angular=False):
+        """Coupling matrices of an asymmetric top + linear rotor (Eqs. 12-18) on the GPU.
+
+        basis: channels j, m, rot1, j2 and rotor-1 states rot1_j, b (b_k at column
+        k + j1); expansion: terms lam1, mu1, lam2, lam and radial coefficients v[T, K]
+        (hartree).  Returns {"M": [K, N, N]} and/or {"G": [T, N, N]} as FP64 CUDA
+        tensors, ready for load_system(M=...) and set_params."""
+        torch = self.torch
+        i32 = lambda a: _host(a, np.int32)
+        j, m, r1, j2 = i32(basis.j), i32(basis.m), i32(basis.rot1), i32(basis.j2)
+        rj, b = i32(basis.rot1_j), _host(basis.b, np.float64)
+        l1, u1, l2, l = (i32(expansion.lam1), i32(expansion.mu1), i32(expansion.lam2),
+                         i32(expansion.lam))
+        v = _host(expansion.v, np.float64)
+        N, T, K = j.shape[0], l1.shape[0], v.shape[1]
+        out = {}
+        if tables:
+            out["M"] = torch.empty((K, N, N), dtype=torch.float64, device=self.device)
+        if angular:
+            out["G"] = torch.empty((T, N, N), dtype=torch.float64, device=self.device)
+        d = CouplingDesc(N, _ptr(j), _ptr(m), _ptr(r1), _ptr(j2), rj.shape[0], _ptr(rj),
+                         _ptr(b), b.shape[1], T, _ptr(l1), _ptr(u1), _ptr(l2), _ptr(l), K,
+                         _ptr(v))
+        self._check(lib().mqct_coupling_build(self.h, C.byref(d), _ptr(out.get("M")),
+                                              _ptr(out.get("G"))))
+        return out
 
     def set_option(self, name, value=1):
         """Work-list schedule options: graphs, autotune, chunk, reset_tuning, tail."""

@@ -1011,6 +1011,108 @@ const char* mqct_tuning_report(mqct_context* c) {
   return c->report.c_str();
 }
 
+mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, double* M_out,
+                                double* G_out) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!d) return fail(c, MQCT_ERR_ARG, "coupling_build: null descriptor");
+  if (!M_out && !G_out) return fail(c, MQCT_ERR_ARG, "coupling_build: no output requested");
+  const int N = d->N, T = d->T, K = d->K, n1 = d->n_rot1, bs = d->b_stride;
+  if (N < 1 || T < 1 || K < 1 || n1 < 1 || bs < 1)
+    return fail(c, MQCT_ERR_ARG, "coupling_build: need N, T, K, n_rot1, b_stride >= 1");
+  if (!d->j || !d->m || !d->rot1 || !d->j2 || !d->rot1_j || !d->b || !d->lam1 || !d->mu1 ||
+      !d->lam2 || !d->lam || !d->v)
+    return fail(c, MQCT_ERR_ARG, "coupling_build: null array");
+  constexpr int JMAX = 40, LMAX = 20;
+  for (int r = 0; r < n1; ++r)
+    if (d->rot1_j[r] < 0 || d->rot1_j[r] > JMAX || 2 * d->rot1_j[r] + 1 > bs)
+      return fail(c, MQCT_ERR_ARG, "coupling_build: rotor-1 state %d: j1 out of 0..%d or "
+                  "b_stride too small", r, JMAX);
+  if (!finite_arr(d->b, (int64_t)n1 * bs) || !finite_arr(d->v, (int64_t)T * K))
+    return fail(c, MQCT_ERR_NONFINITE, "coupling_build: non-finite b or v");
+  std::map<std::pair<int, std::pair<int, int>>, int> jl;
+  std::vector<int32_t> jl_j1, jl_j2, jl_j, chan_J(N);
+  for (int n = 0; n < N; ++n) {
+    const int r = d->rot1[n], j2 = d->j2[n], j = d->j[n], m = d->m[n];
+    if (r < 0 || r >= n1) return fail(c, MQCT_ERR_ARG, "coupling_build: rot1[%d] out of range", n);
+    const int j1 = d->rot1_j[r];
+    if (j2 < 0 || j2 > JMAX || j < std::abs(j1 - j2) || j > j1 + j2 || std::abs(m) > j)
+      return fail(c, MQCT_ERR_ARG, "coupling_build: channel %d: need 0 <= j2 <= %d, "
+                  "|j1-j2| <= j <= j1+j2, |m| <= j", n, JMAX);
+    auto key = std::make_pair(j1, std::make_pair(j2, j));
+    auto it = jl.find(key);
+    if (it == jl.end()) {
+      it = jl.emplace(key, (int)jl_j1.size()).first;
+      jl_j1.push_back(j1);
+      jl_j2.push_back(j2);
+      jl_j.push_back(j);
+    }
+    chan_J[n] = it->second;
+  }
+  const int nJ = (int)jl_j1.size();
+  std::vector<int32_t> perm(T);
+  for (int t = 0; t < T; ++t) {
+    const int l1 = d->lam1[t], u = d->mu1[t], l2 = d->lam2[t], l = d->lam[t];
+    if (l1 < 0 || l1 > LMAX || l2 < 0 || l2 > LMAX || std::abs(u) > l1 || l < std::abs(l1 - l2) ||
+        l > l1 + l2)
+      return fail(c, MQCT_ERR_ARG, "coupling_build: term %d: need 0 <= lam1, lam2 <= %d, "
+                  "|mu1| <= lam1, |lam1-lam2| <= lam <= lam1+lam2", t, LMAX);
+    perm[t] = t;
+  }
+  // terms sorted by lam: the fill kernel forms C(j' m lam 0 | j'' m) once per lam
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int a, int b) { return d->lam[a] < d->lam[b]; });
+  std::vector<int32_t> ints;
+  auto put = [&](const int32_t* p, int n) {
+    const size_t o = ints.size();
+    ints.insert(ints.end(), p, p + n);
+    return o;
+  };
+  std::vector<int32_t> tl1(T), tmu(T), tl2(T), tl(T);
+  std::vector<double> vs((size_t)T * K);
+  for (int t = 0; t < T; ++t) {
+    const int u = perm[t];
+    tl1[t] = d->lam1[u]; tmu[t] = d->mu1[u]; tl2[t] = d->lam2[u]; tl[t] = d->lam[u];
+    memcpy(&vs[(size_t)t * K], d->v + (size_t)u * K, (size_t)K * 8);
+  }
+  std::vector<int32_t> chan_r(d->rot1, d->rot1 + N), chan_j(d->j, d->j + N), chan_m(d->m, d->m + N);
+  const size_t o_cJ = put(chan_J.data(), N), o_cr = put(chan_r.data(), N),
+               o_cj = put(chan_j.data(), N), o_cm = put(chan_m.data(), N),
+               o_j1 = put(jl_j1.data(), nJ), o_j2 = put(jl_j2.data(), nJ),
+               o_jj = put(jl_j.data(), nJ), o_rj = put(d->rot1_j, n1),
+               o_t1 = put(tl1.data(), T), o_tm = put(tmu.data(), T), o_t2 = put(tl2.data(), T),
+               o_tl = put(tl.data(), T), o_tu = put(perm.data(), T);
+  const size_t ibytes = (ints.size() * 4 + 255) / 256 * 256;
+  const size_t n_b = (size_t)n1 * bs, n_v = (size_t)T * K, n_lf = 256;
+  const size_t n_K = (size_t)T * n1 * n1, n_F = (size_t)T * nJ * nJ;
+  const size_t total = ibytes + (n_b + n_v + n_lf + n_K + n_F) * 8;
+  HIP_TRY(c, hipSetDevice(c->device), "coupling_build");
+  char* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, total);
+  if (e != hipSuccess) return hip_fail(c, e, "coupling_build: workspace");
+  int32_t* di = (int32_t*)buf;
+  double* dd = (double*)(buf + ibytes);
+  double *db = dd, *dv = db + n_b, *dlf = dv + n_v, *dK = dlf + n_lf, *dF = dK + n_K;
+  if ((e = hipMemcpy(di, ints.data(), ints.size() * 4, hipMemcpyHostToDevice)) == hipSuccess &&
+      (e = hipMemcpy(db, d->b, n_b * 8, hipMemcpyHostToDevice)) == hipSuccess)
+    e = hipMemcpy(dv, vs.data(), n_v * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    CouplingDev dev{N, T, K, n1, nJ, bs, di + o_cJ, di + o_cr, di + o_cj, di + o_cm,
+                    di + o_j1, di + o_j2, di + o_jj, di + o_rj, db, di + o_t1, di + o_tm,
+                    di + o_t2, di + o_tl, di + o_tu, dv, dlf, dK, dF};
+    e = launch_coupling(dev, M_out, G_out, &c->prof, c->stream);
+    if (e == hipErrorInvalidValue) {
+      hipFree(buf);
+      return fail(c, MQCT_ERR_ARG, "coupling_build: N too large for one launch");
+    }
+    if (e == hipSuccess && c->prof.on)
+      c->prof.bytes += ((M_out ? (double)K : 0.0) + (G_out ? (double)T : 0.0)) * N * (double)N * 8.0;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(buf);
+  if (e != hipSuccess) return hip_fail(c, e, "coupling_build");
+  return MQCT_OK;
+}
+
 mqct_status mqct_set_profiling(mqct_context* c, int32_t enable) {
   if (!c) return MQCT_ERR_ARG;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "set_profiling");

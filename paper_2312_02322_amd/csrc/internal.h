@@ -116,6 +116,31 @@ inline void prof_mark(Prof* p, hipEvent_t e, hipStream_t s) {
   if (p && e) (void)hipEventRecord(e, s);
 }
 
+// Device view of a coupling-matrix build (coupling.hip).  Channels n have a
+// (j1, j2, j) level chan_J, a rotor-1 state chan_r, total j and projection m;
+// terms are sorted by lam (t_user maps back to the caller's order).
+struct CouplingDev {
+  int N, T, K, n1, nJ, b_stride;
+  const int* chan_J;
+  const int* chan_r;
+  const int* chan_j;
+  const int* chan_m;
+  const int* jl_j1;
+  const int* jl_j2;
+  const int* jl_j;
+  const int* rot_j;
+  const double* b;       // [n1][b_stride], b_k at k + j1
+  const int* t_l1;
+  const int* t_mu;
+  const int* t_l2;
+  const int* t_l;
+  const int* t_user;
+  const double* v;       // [T][K], sorted order
+  double* lf;            // [256] log-factorials
+  double* Kr;            // [T][n1][n1] rotor-1 factors
+  double* F;             // [T][nJ][nJ] level factors
+};
+
 // ---- launchers (defined in the .hip files) ----------------------------------
 
 // Sparse (ELL) tables: pattern of the elements whose magnitude exceeds thr at
@@ -256,5 +281,9 @@ hipError_t launch_spline_rows(const double* y, const double* x, int K, int ncol,
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,
                        const int32_t* level_of_channel, int n_levels, double b_max,
                        double* level_sums /*[B][n_levels]*/, double* sigma, hipStream_t s);
+
+// coupling-matrix build: M [K][N][N] and/or G [T][N][N] (device, either may be null)
+hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* prof,
+                           hipStream_t s);
 
 }  // namespace mqct

@@ -70,14 +70,17 @@ class Expansion:
 
 
 def top_rotor_basis(j1max=2, j2_values=(0, 2), rot=H2O_ABC_CM, B2_cm=H2_B_CM, jmax=None,
-                    m_values=None):
-    """Channels |j1 tau1 j2 j m> for j1 <= j1max (every tau1), j2 in j2_values,
-    |j1 - j2| <= j <= j1 + j2 (and j <= jmax), m = -j..j (or the given m only).
-    Ordered by level (j1, tau1, j2, j), then m."""
+                    m_values=None, rot1_states=None, order="level"):
+    """Channels |j1 tau1 j2 j m> for j1 <= j1max (every tau1, or only the (j1, tau1)
+    pairs in rot1_states), j2 in j2_values, |j1 - j2| <= j <= j1 + j2 (and j <=
+    jmax), m = -j..j (or the given m only).  order="level": by level (j1, tau1, j2,
+    j), then m; order="m": by m, then level (each m block contiguous)."""
     rot1_j, rot1_tau, rot1_E, bl = [], [], [], []
     for j1 in range(j1max + 1):
         E1, b1 = asymmetric_top_states(j1, *rot)
         for t in range(2 * j1 + 1):
+            if rot1_states is not None and (j1, t - j1) not in rot1_states:
+                continue
             row = np.zeros(2 * j1max + 1)
             row[:2 * j1 + 1] = b1[t]
             rot1_j.append(j1)
@@ -105,8 +108,15 @@ def top_rotor_basis(j1max=2, j2_values=(0, 2), rot=H2O_ABC_CM, B2_cm=H2_B_CM, jm
                     jr += [off + a for a in rr]; jc += [off + a for a in cc]; jv += vv
                 n_lev += 1
     i32 = lambda a: np.array(a, np.int32)
+    j, m, r1, j2, E, lev, jr, jc = (np.array(a) for a in (j, m, r1, j2, E, lev, jr, jc))
+    if order == "m":
+        p = np.lexsort((lev, m))               # new position -> old channel
+        inv = np.empty_like(p)
+        inv[p] = np.arange(p.size)
+        j, m, r1, j2, E, lev = (a[p] for a in (j, m, r1, j2, E, lev))
+        jr, jc = inv[jr.astype(np.int64)] if jr.size else jr, inv[jc.astype(np.int64)] if jc.size else jc
     return CouplingBasis(i32(j), i32(m), i32(r1), i32(j2), i32(rot1_j), i32(rot1_tau),
-                         np.array(bl), U.cm_to_hartree(np.array(E)), i32(jr), i32(jc),
+                         np.array(bl), U.cm_to_hartree(np.array(E, np.float64)), i32(jr), i32(jc),
                          np.array(jv, np.float64), i32(lev), n_lev)
 
 
@@ -162,10 +172,29 @@ def system_from_tables(basis, R_grid, M, mu_amu=1.8, name="top_rotor"):
                   n_levels=basis.n_levels)
 
 
-def config6(j1max=6, j2_values=(0, 2, 4), K=63, seed=0):
+# the levels j1_{kA kC} of Section II's check of Eq. 18, as (j1, tau1 = kA - kC)
+PAPER_CHECK_ROT1 = [(0, 0), (1, 0), (2, -2), (2, 0), (2, 2), (3, -2), (3, 0)]
+
+
+def paper_check_basis():
+    """The 14 (j1_{kA kC}, j2) combinations of Section II's check (j2 = 0, 2), all j, m."""
+    return top_rotor_basis(3, (0, 2), rot1_states=PAPER_CHECK_ROT1)
+
+
+def select_terms(terms, n, seed=0):
+    """n of the terms (the isotropic one always), drawn without replacement."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 6, 1000 + seed]))
+    iso = [i for i, t in enumerate(terms) if t == (0, 0, 0, 0)]
+    rest = [i for i in range(len(terms)) if i not in iso]
+    pick = sorted(iso + list(rng.choice(rest, size=n - len(iso), replace=False)))
+    return [terms[i] for i in pick]
+
+
+def config6(j1max=6, j2_values=(0, 2, 4), K=63, n_terms=83, seed=0):
     """Coupling-builder workload: H2O-like top, j1 <= 6 (every tau1) + para-H2, j2 <= 4,
-    all j and m; the expansion term set of Section II's test (l1 <= 9, mu1 <= 6,
-    l2 <= 6, l <= 11); 63 log-spaced radial points."""
-    basis = top_rotor_basis(j1max, j2_values)
-    terms = expansion_terms()
+    all j and m, channels ordered by m; 83 expansion terms drawn from the ranges of
+    Section II's potential (l1 <= 9, mu1 <= 6, l2 <= 6, l <= 11); 63 log-spaced radial
+    points from 3 to 30 bohr (Section III)."""
+    basis = top_rotor_basis(j1max, j2_values, order="m")
+    terms = select_terms(expansion_terms(), n_terms, seed)
     return basis, synthetic_expansion(terms, log_grid(K), seed)

@@ -37,6 +37,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.mqct_synchronize(None) == mq.ERR_ARG
     assert L.mqct_run(None, None, None) == mq.ERR_ARG
     assert L.mqct_system_load(None, None, None) == mq.ERR_ARG
+    assert L.mqct_coupling_build(None, None, None, None) == mq.ERR_ARG
     L.mqct_destroy(None)
 
 
@@ -46,3 +47,4 @@ def test_struct_layouts_match_header():
     assert C.sizeof(mq.SystemDesc) == 96
     assert C.sizeof(mq.BatchDesc) == 136   # the trailing int32 dynamics fits the padding
     assert C.sizeof(mq.BatchResult) == 88
+    assert C.sizeof(mq.CouplingDesc) == 120

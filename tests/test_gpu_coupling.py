@@ -1,0 +1,156 @@
+"""GPU parity of the coupling-matrix builder (Section II, Eqs. 12-18).
+
+The builder (one 9j symbol per level pair and term, one Clebsch-Gordan
+coefficient in m per element) against the oracle's Eq. 17 sums (pinned to the
+direct quadrature of Eq. 11):
+
+* every term with lam1 <= 3, lam2 <= 2 (odd mu1 and lam2 included) on a top with
+  j1 <= 2 and a rotor with j2 <= 2, all j and m: angular factors and tables to
+  1e-13 of the largest element, both channel orderings;
+* the paper's own check basis (the 14 (j1_{kA kC}, j2) combinations of Section
+  II) at R = 7 and 8 bohr;
+* the 83-term, 63-knot workload (N = 6825) on sampled rows, and its structure
+  (symmetric, zero between different m) on the whole output;
+* tables built on the GPU propagate like the oracle's tables (RK4, 1e-9);
+* G alone, M and G together, argument errors.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import coupling as C
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+def say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context()
+    yield c
+    c.synchronize()
+    c.close()
+
+
+def all_terms(l1max, l2max):
+    return [(l1, mu1, l2, l) for l1 in range(l1max + 1) for mu1 in range(l1 + 1)
+            for l2 in range(l2max + 1) for l in range(abs(l1 - l2), l1 + l2 + 1)]
+
+
+@pytest.mark.parametrize("order", ["level", "m"])
+def test_all_low_order_terms_match_the_oracle(ctx, order):
+    basis = C.top_rotor_basis(2, (0, 1, 2), order=order)
+    ex = C.synthetic_expansion(all_terms(3, 2), C.log_grid(7), seed=1)
+    say("builder vs Eq. 17: N=%d T=%d K=%d order=%s" % (basis.N, ex.T, ex.K, order))
+    out = ctx.build_couplings(basis, ex, tables=True, angular=True)
+    M_o, G_o = oracle.coupling_tables(basis, ex)
+    G = out["G"].cpu().numpy()
+    M = out["M"].cpu().numpy()
+    eg = np.max(np.abs(G - G_o))
+    em = np.max(np.abs(M - M_o))
+    say("  max|dG| %.2e of %.2e, max|dM| %.2e of %.2e" % (eg, np.abs(G_o).max(), em,
+                                                          np.abs(M_o).max()))
+    assert eg < TOL * np.abs(G_o).max()
+    assert em < TOL * np.abs(M_o).max()
+
+
+def test_paper_check_basis(ctx):
+    basis = C.paper_check_basis()
+    terms = C.expansion_terms()
+    ex = C.synthetic_expansion(terms, np.array([7.0, 8.0]), seed=2)
+    say("paper check basis N=%d, %d terms, R = 7, 8 bohr" % (basis.N, ex.T))
+    M = ctx.build_couplings(basis, ex)["M"].cpu().numpy()
+    M_o, _ = oracle.coupling_tables(basis, ex)
+    err = np.max(np.abs(M - M_o))
+    say("  max|dM| %.2e of %.2e" % (err, np.abs(M_o).max()))
+    assert err < TOL * np.abs(M_o).max()
+
+
+def test_workload_83_terms_sampled_rows(ctx):
+    basis, ex = C.config6()
+    N = basis.N
+    say("workload N=%d T=%d K=%d: build, then 4 sampled rows against Eq. 17" % (N, ex.T, ex.K))
+    M = ctx.build_couplings(basis, ex)["M"]
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(N, size=4, replace=False))
+    M_o, _ = oracle.coupling_tables(basis, ex, rows=rows)
+    Mr = M[:, rows, :].cpu().numpy()
+    err = np.max(np.abs(Mr - M_o))
+    say("  rows %s: max|dM| %.2e of %.2e" % (rows.tolist(), err, np.abs(M_o).max()))
+    assert err < TOL * np.abs(M_o).max()
+    # structure of the whole output at three knots
+    torch = ctx.torch
+    m = torch.as_tensor(basis.m, device=M.device)
+    other_m = m[:, None] != m[None, :]
+    for k in (0, ex.K // 2, ex.K - 1):
+        Mk = M[k]
+        assert float((Mk - Mk.T).abs().max()) < TOL * float(Mk.abs().max())
+        assert float(Mk[other_m].abs().max()) == 0.0
+    del M
+    torch.cuda.empty_cache()
+
+
+def test_built_tables_propagate_like_the_oracle(ctx):
+    basis = C.top_rotor_basis(2, (0, 2))
+    R = np.linspace(3.0, 30.0, 120)
+    ex = C.synthetic_expansion(C.select_terms(C.expansion_terms(4, 2, 2, 6), 20, seed=3), R, seed=3)
+    out = ctx.build_couplings(basis, ex)
+    M_o, _ = oracle.coupling_tables(basis, ex)
+    s_gpu = C.system_from_tables(basis, R, out["M"])
+    s_o = C.system_from_tables(basis, R, M_o)
+    from synth import systems as S
+    rng = np.random.default_rng(3)
+    B = 6
+    b = S.mc_batch(s_o, B, 100.0, 8.0, np.zeros(B, np.int32), rng, n_steps=1500)
+    say("propagation on built tables: N=%d B=%d" % (basis.N, B))
+    sid = ctx.load_system(s_gpu)
+    g = ctx.run_host([sid] * B, [basis.N] * B, init_channel=b.init_channel, E_coll=b.E_coll,
+                     b=b.b, R0=b.R0, dt=b.dt, n_steps=b.n_steps, schedule="gemv")
+    o = oracle.OracleSystem(s_o).propagate(b)
+    assert not np.any(g["status"] & 8)          # stayed on the radial grid
+    err = np.max(np.abs(g["P"].reshape(B, basis.N) - o["P"]))
+    say("  max|dP| %.2e, max P off the initial channel %.2e" % (err, np.max(o["P"][:, 1:])))
+    assert err < 1e-9
+    assert np.max(o["P"][:, 1:]) > 1e-3           # the couplings do transfer population
+    ctx.free_system(sid)
+
+
+def test_outputs_and_errors(ctx, gpu_lib):
+    basis = C.top_rotor_basis(1, (0, 1))
+    ex = C.synthetic_expansion(all_terms(2, 1), C.log_grid(5), seed=4)
+    both = ctx.build_couplings(basis, ex, tables=True, angular=True)
+    g_only = ctx.build_couplings(basis, ex, tables=False, angular=True)["G"]
+    m_only = ctx.build_couplings(basis, ex, tables=True, angular=False)["M"]
+    assert ctx.torch.equal(both["G"], g_only)
+    assert ctx.torch.equal(both["M"], m_only)
+    # M = sum_t v_t G_t
+    v = ctx.torch.as_tensor(ex.v, device=m_only.device)
+    assert float((ctx.torch.einsum("tk,tab->kab", v, g_only) - m_only).abs().max()) < \
+        1e-13 * float(m_only.abs().max())
+    with pytest.raises(gpu_lib.MQCTError) as e:
+        ctx.build_couplings(basis, ex, tables=False, angular=False)
+    assert e.value.code == gpu_lib.ERR_ARG
+    bad = C.top_rotor_basis(1, (0, 1))
+    bad.j = bad.j.copy()
+    bad.j[3] = 5                                  # outside |j1 - j2| .. j1 + j2
+    with pytest.raises(gpu_lib.MQCTError) as e:
+        ctx.build_couplings(bad, ex)
+    assert e.value.code == gpu_lib.ERR_ARG
+    ex_bad = C.synthetic_expansion([(2, 3, 0, 2)], C.log_grid(5))   # |mu1| > lam1
+    with pytest.raises(gpu_lib.MQCTError) as e:
+        ctx.build_couplings(basis, ex_bad)
+    assert e.value.code == gpu_lib.ERR_ARG
+    ex_nan = C.synthetic_expansion(all_terms(1, 1), C.log_grid(5))
+    ex_nan.v = ex_nan.v.copy()
+    ex_nan.v[0, 0] = np.nan
+    with pytest.raises(gpu_lib.MQCTError) as e:
+        ctx.build_couplings(basis, ex_nan)
+    assert e.value.code == gpu_lib.ERR_NONFINITE
