@@ -440,7 +440,7 @@ def at_workload(args, n_paths=64, n_init=100):
     return line
 
 
-def coupling_workload(args, cpu_rows=64):
+def coupling_workload(args, cpu_rows=256):
     """Coupling-matrix build (Section II, Eqs. 12-18): asymmetric top (H2O constants,
     j1 <= 6, every tau1) + para-H2 (j2 = 0, 2, 4), all j and m: N = 6825 channels;
     83 expansion terms from the ranges of the paper's potential; 63 knots from 3 to

@@ -1062,47 +1062,85 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
   std::stable_sort(perm.begin(), perm.end(),
                    [&](int a, int b) { return d->lam[a] < d->lam[b]; });
   std::vector<int32_t> ints;
-  auto put = [&](const int32_t* p, int n) {
+  auto put = [&](const int32_t* p, size_t n) {
     const size_t o = ints.size();
     ints.insert(ints.end(), p, p + n);
     return o;
   };
   std::vector<int32_t> tl1(T), tmu(T), tl2(T), tl(T);
-  std::vector<double> vs((size_t)T * K);
+  const int KP = (K + CPL_KNOT_CHUNK - 1) / CPL_KNOT_CHUNK * CPL_KNOT_CHUNK;
+  std::vector<double> vs((size_t)T * KP, 0.0);
+  int cg_lmax = 0, cg_jmax = 0;
   for (int t = 0; t < T; ++t) {
     const int u = perm[t];
     tl1[t] = d->lam1[u]; tmu[t] = d->mu1[u]; tl2[t] = d->lam2[u]; tl[t] = d->lam[u];
-    memcpy(&vs[(size_t)t * K], d->v + (size_t)u * K, (size_t)K * 8);
+    memcpy(&vs[(size_t)t * KP], d->v + (size_t)u * K, (size_t)K * 8);
+    cg_lmax = std::max(cg_lmax, tl[t]);
   }
+  for (int n = 0; n < N; ++n) cg_jmax = std::max(cg_jmax, (int)d->j[n]);
   std::vector<int32_t> chan_r(d->rot1, d->rot1 + N), chan_j(d->j, d->j + N), chan_m(d->m, d->m + N);
+  // channels grouped by m (the potential couples only equal m), and the fill
+  // kernel's work list: per row, tiles of 256 channels of the row's group
+  std::map<int, int> gid;
+  for (int n = 0; n < N; ++n) gid.emplace(d->m[n], 0);
+  int ng = 0;
+  for (auto& kv : gid) kv.second = ng++;
+  std::vector<int32_t> chan_grp(N), grp_off(ng + 1, 0), grp_list(N);
+  for (int n = 0; n < N; ++n) {
+    chan_grp[n] = gid[d->m[n]];
+    ++grp_off[chan_grp[n] + 1];
+  }
+  for (int g = 0; g < ng; ++g) grp_off[g + 1] += grp_off[g];
+  {
+    std::vector<int32_t> fillp(grp_off.begin(), grp_off.end() - 1);
+    for (int n = 0; n < N; ++n) grp_list[fillp[chan_grp[n]]++] = n;
+  }
+  std::vector<int32_t> work;
+  for (int n = 0; n < N; ++n) {
+    const int cnt = grp_off[chan_grp[n] + 1] - grp_off[chan_grp[n]];
+    for (int tile = 0; tile * 256 < cnt; ++tile) {
+      work.push_back(n);
+      work.push_back(tile);
+    }
+  }
+  const int64_t n_work = (int64_t)work.size() / 2;
+  if (n_work > 0x7fffffffLL)
+    return fail(c, MQCT_ERR_ARG, "coupling_build: too many channels for one launch");
   const size_t o_cJ = put(chan_J.data(), N), o_cr = put(chan_r.data(), N),
                o_cj = put(chan_j.data(), N), o_cm = put(chan_m.data(), N),
                o_j1 = put(jl_j1.data(), nJ), o_j2 = put(jl_j2.data(), nJ),
                o_jj = put(jl_j.data(), nJ), o_rj = put(d->rot1_j, n1),
                o_t1 = put(tl1.data(), T), o_tm = put(tmu.data(), T), o_t2 = put(tl2.data(), T),
-               o_tl = put(tl.data(), T), o_tu = put(perm.data(), T);
+               o_tl = put(tl.data(), T), o_tu = put(perm.data(), T),
+               o_cg = put(chan_grp.data(), N), o_go = put(grp_off.data(), ng + 1),
+               o_gl = put(grp_list.data(), N);
+  if (ints.size() & 1) ints.push_back(0);      // the work list is read as int2
+  const size_t o_wk = put(work.data(), work.size());
   const size_t ibytes = (ints.size() * 4 + 255) / 256 * 256;
-  const size_t n_b = (size_t)n1 * bs, n_v = (size_t)T * K, n_lf = 256;
+  const size_t n_b = (size_t)n1 * bs, n_v = (size_t)T * KP, n_lf = 256;
   const size_t n_K = (size_t)T * n1 * n1, n_F = (size_t)T * nJ * nJ;
-  const size_t total = ibytes + (n_b + n_v + n_lf + n_K + n_F) * 8;
+  const size_t n_cg = (size_t)(cg_jmax + 1) * (cg_jmax + 1) * (2 * cg_jmax + 1) * (cg_lmax + 1);
+  const size_t total = ibytes + (n_b + n_v + n_lf + n_K + n_F + n_cg) * 8;
   HIP_TRY(c, hipSetDevice(c->device), "coupling_build");
   char* buf = nullptr;
   hipError_t e = hipMalloc((void**)&buf, total);
   if (e != hipSuccess) return hip_fail(c, e, "coupling_build: workspace");
   int32_t* di = (int32_t*)buf;
   double* dd = (double*)(buf + ibytes);
-  double *db = dd, *dv = db + n_b, *dlf = dv + n_v, *dK = dlf + n_lf, *dF = dK + n_K;
+  double *db = dd, *dv = db + n_b, *dlf = dv + n_v, *dK = dlf + n_lf, *dF = dK + n_K,
+         *dcg = dF + n_F;
   if ((e = hipMemcpy(di, ints.data(), ints.size() * 4, hipMemcpyHostToDevice)) == hipSuccess &&
       (e = hipMemcpy(db, d->b, n_b * 8, hipMemcpyHostToDevice)) == hipSuccess)
     e = hipMemcpy(dv, vs.data(), n_v * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     CouplingDev dev{N, T, K, n1, nJ, bs, di + o_cJ, di + o_cr, di + o_cj, di + o_cm,
                     di + o_j1, di + o_j2, di + o_jj, di + o_rj, db, di + o_t1, di + o_tm,
-                    di + o_t2, di + o_tl, di + o_tu, dv, dlf, dK, dF};
+                    di + o_t2, di + o_tl, di + o_tu, dv, dlf, dK, dF, di + o_cg, di + o_go,
+                    di + o_gl, (const int2*)(di + o_wk), n_work, KP, cg_jmax, cg_lmax, dcg};
     e = launch_coupling(dev, M_out, G_out, &c->prof, c->stream);
     if (e == hipErrorInvalidValue) {
       hipFree(buf);
-      return fail(c, MQCT_ERR_ARG, "coupling_build: N too large for one launch");
+      return fail(c, MQCT_ERR_ARG, "coupling_build: output too large for one launch");
     }
     if (e == hipSuccess && c->prof.on)
       c->prof.bytes += ((M_out ? (double)K : 0.0) + (G_out ? (double)T : 0.0)) * N * (double)N * 8.0;

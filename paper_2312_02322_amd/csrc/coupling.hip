@@ -21,16 +21,20 @@
 //   cpl_lfact  log-factorials (the Racah sums below run in the log domain);
 //   cpl_rotor  K_t for every pair of rotor-1 states;
 //   cpl_jlevel F_t for every pair of (j1, j2, j) levels (9j from three 6j);
-//   cpl_fill   one thread per output column n' of a row n'': for the columns of
-//              the row's m, the coefficients C(j' m lam 0 | j'' m) (recomputed
-//              only when lam changes: terms are sorted by lam), then
-//              M[k][n''][n'] = sum_t v_t(R_k) G_t for a chunk of knots at a time
-//              with v staged in LDS; every other column gets zeros.  The output
-//              is written row by row with consecutive lanes on consecutive
-//              columns, so the zeros stream at full write bandwidth.
+//   cpl_zero   the outputs cleared with 16-byte stores (most elements couple
+//              channels of different m and stay zero);
+//   cpl_cgm    the coefficients C(j' m lam 0 | j'' m) for every j', j'', m and lam
+//              that occur;
+//   cpl_fill   one work item per row n'' and 256 of the channels n' that share its
+//              m: per lane g_t = F K C gathered for a chunk of terms, then M[k][n''][n']
+//              = sum_t v_t(R_k) g_t for a chunk of knots (v by scalar loads).  With
+//              channels ordered by m the lanes of a work item write consecutive
+//              columns.
 #include "internal.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace mqct {
 
@@ -38,8 +42,8 @@ namespace {
 
 constexpr int LF_N = 256;        // log-factorial table: arguments up to 255
 constexpr int FILL_BLOCK = 256;
-constexpr int FILL_KC = 32;      // knots per accumulation chunk (registers)
-constexpr int FILL_TC = 32;      // terms per LDS stage
+constexpr int FILL_KC = CPL_KNOT_CHUNK;   // knots per accumulation chunk (registers)
+constexpr int FILL_TC = 8;       // terms whose factors are gathered together
 
 __device__ inline bool tri(int a, int b, int c) { return c >= abs(a - b) && c <= a + b; }
 
@@ -100,13 +104,14 @@ __global__ void cpl_lfact(double* __restrict__ lf) {
   if (i < LF_N) lf[i] = lgamma((double)i + 1.0);
 }
 
-// K[t][rb][ra]: the rotor-1 factor between rotor-1 states ra (initial) and rb (final)
+// K[rb][ra][t]: the rotor-1 factor between rotor-1 states ra (initial) and rb (final)
 __global__ void cpl_rotor(CouplingDev d) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nn = (int64_t)d.n1 * d.n1;
   if (i >= (int64_t)d.T * nn) return;
-  const int t = (int)(i / nn);
-  const int rb = (int)((i - t * nn) / d.n1), ra = (int)(i - t * nn - (int64_t)rb * d.n1);
+  const int t = (int)(i % d.T);
+  const int64_t pr = i / d.T;
+  const int rb = (int)(pr / d.n1), ra = (int)(pr - (int64_t)rb * d.n1);
   const int l1 = d.t_l1[t], mu = d.t_mu[t], l2 = d.t_l2[t], l = d.t_l[t];
   const double s = ((l1 + mu + l2 + l) & 1) ? -1.0 : 1.0;
   const int ja = d.rot_j[ra], jb = d.rot_j[rb];
@@ -124,13 +129,14 @@ __global__ void cpl_rotor(CouplingDev d) {
   d.Kr[i] = acc;
 }
 
-// F[t][Jb][Ja] between (j1, j2, j) levels Ja (initial) and Jb (final)
+// F[Jb][Ja][t] between (j1, j2, j) levels Ja (initial) and Jb (final)
 __global__ void cpl_jlevel(CouplingDev d) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nn = (int64_t)d.nJ * d.nJ;
   if (i >= (int64_t)d.T * nn) return;
-  const int t = (int)(i / nn);
-  const int Jb = (int)((i - t * nn) / d.nJ), Ja = (int)(i - t * nn - (int64_t)Jb * d.nJ);
+  const int t = (int)(i % d.T);
+  const int64_t pr = i / d.T;
+  const int Jb = (int)(pr / d.nJ), Ja = (int)(pr - (int64_t)Jb * d.nJ);
   const int l1 = d.t_l1[t], l2 = d.t_l2[t], l = d.t_l[t];
   const int j1a = d.jl_j1[Ja], j2a = d.jl_j2[Ja], ja = d.jl_j[Ja];
   const int j1b = d.jl_j1[Jb], j2b = d.jl_j2[Jb], jb = d.jl_j[Jb];
@@ -144,73 +150,95 @@ __global__ void cpl_jlevel(CouplingDev d) {
   d.F[i] = f;
 }
 
-// M[k][nb][na] (and G[t][nb][na] when asked) for one row nb and FILL_BLOCK columns
+// zero n doubles, one 16-byte store per thread from the first 16-byte boundary
+// (single elements before it and after the last pair)
+__global__ void __launch_bounds__(256) cpl_zero(double* __restrict__ p, int64_t n) {
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  const int64_t head = ((uintptr_t)p & 15) ? 1 : 0;
+  const int64_t pairs = (n - head) >> 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < pairs) ((dv2*)(p + head))[i] = dv2{0.0, 0.0};
+  if (i == 0) {
+    if (head) p[0] = 0.0;
+    if ((n - head) & 1) p[n - 1] = 0.0;
+  }
+}
+
+// C(ja m lam 0 | jb m) for ja, jb <= JM, |m| <= JM, lam <= LM: cgt[((ja * (JM+1) +
+// jb) * (2 JM + 1) + m + JM) * (LM + 1) + lam]
+__global__ void cpl_cgm(CouplingDev d) {
+  const int JM = d.cg_jmax, LM = d.cg_lmax;
+  const int64_t total = (int64_t)(JM + 1) * (JM + 1) * (2 * JM + 1) * (LM + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int lam = (int)(i % (LM + 1));
+  int64_t r = i / (LM + 1);
+  const int m = (int)(r % (2 * JM + 1)) - JM;
+  r /= (2 * JM + 1);
+  const int jb = (int)(r % (JM + 1)), ja = (int)(r / (JM + 1));
+  d.cgt[i] = cg_dev(d.lf, ja, m, lam, 0, jb, m);
+}
+
+// One work item = (row nb, FILL_BLOCK consecutive entries of the list of channels
+// that share nb's m).  M[k][nb][na] (and G[t][nb][na] when asked) for those na.
+// Per chunk of FILL_TC terms a lane first gathers the chunk's factors (F, K and
+// the m-coefficient, all independent loads), then adds v_t(R_k) g_t into FILL_KC
+// knot accumulators; v (rows padded to a multiple of FILL_KC) is the same for
+// every lane and is read with uniform (scalar) loads.
 __global__ void __launch_bounds__(FILL_BLOCK)
-cpl_fill(CouplingDev d, int64_t tiles, double* __restrict__ M, double* __restrict__ G) {
-  __shared__ double vs[FILL_TC][FILL_KC];
-  const int64_t bid = blockIdx.x;
-  const int nb = (int)(bid / tiles);
-  const int na = (int)(bid - (int64_t)nb * tiles) * FILL_BLOCK + threadIdx.x;
-  const int N = d.N, T = d.T, K = d.K;
-  const bool in = na < N;
+cpl_fill(CouplingDev d, const int2* __restrict__ work, double* __restrict__ M,
+         double* __restrict__ G) {
+  const int2 w = work[blockIdx.x];
+  const int nb = w.x;
+  const int g = d.chan_grp[nb];
+  const int g0 = d.grp_off[g], cnt = d.grp_off[g + 1] - g0;
+  const int q = w.y * FILL_BLOCK + threadIdx.x;
+  if (q >= cnt) return;
+  const int na = d.grp_list[g0 + q];
+  const int N = d.N, T = d.T, K = d.K, KP = d.KP;
   const int mb = d.chan_m[nb];
-  const bool act = in && d.chan_m[na] == mb;
   const int64_t NN = (int64_t)N * N;
   const int64_t pos = (int64_t)nb * N + na;
-  if (!__syncthreads_or(act)) {
-    if (in) {
-      if (M)
-        for (int k = 0; k < K; ++k) M[k * NN + pos] = 0.0;
-      if (G)
-        for (int t = 0; t < T; ++t) G[t * NN + pos] = 0.0;
-    }
-    return;
-  }
   const int Jb = d.chan_J[nb], rb = d.chan_r[nb], jb = d.chan_j[nb];
-  const int Ja = act ? d.chan_J[na] : 0, ra = act ? d.chan_r[na] : 0;
-  const int ja = act ? d.chan_j[na] : 0;
-  const int64_t nJJ = (int64_t)d.nJ * d.nJ, n11 = (int64_t)d.n1 * d.n1;
-  const double* Fp = d.F + (int64_t)Jb * d.nJ + Ja;       // + t * nJJ
-  const double* Kp = d.Kr + (int64_t)rb * d.n1 + ra;      // + t * n11
-  if (in && !act && G)
-    for (int t = 0; t < T; ++t) G[t * NN + pos] = 0.0;
+  const int Ja = d.chan_J[na], ra = d.chan_r[na], ja = d.chan_j[na];
+  const double* Fp = d.F + ((int64_t)Jb * d.nJ + Ja) * T;     // + t
+  const double* Kp = d.Kr + ((int64_t)rb * d.n1 + ra) * T;    // + t
+  const int JM = d.cg_jmax;
+  const double* Cp =
+      d.cgt + (((int64_t)ja * (JM + 1) + jb) * (2 * JM + 1) + mb + JM) * (d.cg_lmax + 1);
+  const double* __restrict__ v = d.v;
   // G alone: one pass over the terms
   const int kpasses = M ? K : 1;
   for (int k0 = 0; k0 < kpasses; k0 += FILL_KC) {
     double acc[FILL_KC];
 #pragma unroll
-    for (int q = 0; q < FILL_KC; ++q) acc[q] = 0.0;
-    int cur = -1;
-    double c = 0.0;
+    for (int u = 0; u < FILL_KC; ++u) acc[u] = 0.0;
     for (int t0 = 0; t0 < T; t0 += FILL_TC) {
-      __syncthreads();
-      if (M)
-        for (int e = threadIdx.x; e < FILL_TC * FILL_KC; e += FILL_BLOCK) {
-          const int tt = e / FILL_KC, kk = e - tt * FILL_KC;
-          const int t = t0 + tt, k = k0 + kk;
-          vs[tt][kk] = (t < T && k < K) ? d.v[(int64_t)t * K + k] : 0.0;
-        }
-      __syncthreads();
-      if (!act) continue;
-      const int t1 = min(T, t0 + FILL_TC);
-      for (int t = t0; t < t1; ++t) {
-        const int l = d.t_l[t];
-        if (l != cur) {
-          cur = l;
-          c = cg_dev(d.lf, ja, mb, l, 0, jb, mb);
-        }
-        const double g = Fp[t * nJJ] * Kp[t * n11] * c;
-        if (G && k0 == 0) G[(int64_t)d.t_user[t] * NN + pos] = g;
-        if (M) {
+      double gv[FILL_TC];
 #pragma unroll
-          for (int q = 0; q < FILL_KC; ++q) acc[q] = fma(vs[t - t0][q], g, acc[q]);
+      for (int i = 0; i < FILL_TC; ++i) {
+        const int t = min(t0 + i, T - 1);
+        gv[i] = Fp[t] * Kp[t] * Cp[d.t_l[t]];
+      }
+      if (G && k0 == 0) {
+#pragma unroll
+        for (int i = 0; i < FILL_TC; ++i)
+          if (t0 + i < T) G[(int64_t)d.t_user[t0 + i] * NN + pos] = gv[i];
+      }
+      if (M) {
+#pragma unroll
+        for (int i = 0; i < FILL_TC; ++i) {
+          if (t0 + i >= T) break;
+          const double* vt = v + (int64_t)(t0 + i) * KP + k0;
+#pragma unroll
+          for (int u = 0; u < FILL_KC; ++u) acc[u] = fma(vt[u], gv[i], acc[u]);
         }
       }
     }
-    if (M && in) {
+    if (M) {
 #pragma unroll
-      for (int q = 0; q < FILL_KC; ++q)
-        if (k0 + q < K) M[(k0 + q) * NN + pos] = act ? acc[q] : 0.0;
+      for (int u = 0; u < FILL_KC; ++u)
+        if (k0 + u < K) M[(k0 + u) * NN + pos] = acc[u];
     }
   }
 }
@@ -222,18 +250,28 @@ hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* pro
   cpl_lfact<<<1, LF_N, 0, s>>>(d.lf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int64_t ncg = (int64_t)(d.cg_jmax + 1) * (d.cg_jmax + 1) * (2 * d.cg_jmax + 1) *
+                      (d.cg_lmax + 1);
+  cpl_cgm<<<(unsigned)((ncg + 255) / 256), 256, 0, s>>>(d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t nr = (int64_t)d.T * d.n1 * d.n1;
   cpl_rotor<<<(unsigned)((nr + 255) / 256), 256, 0, s>>>(d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t nj = (int64_t)d.T * d.nJ * d.nJ;
   cpl_jlevel<<<(unsigned)((nj + 255) / 256), 256, 0, s>>>(d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t tiles = (d.N + FILL_BLOCK - 1) / FILL_BLOCK;
-  const int64_t blocks = tiles * d.N;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
   prof_mark(prof, e0, s);
-  cpl_fill<<<(unsigned)blocks, FILL_BLOCK, 0, s>>>(d, tiles, M, G);
+  const int64_t NN = (int64_t)d.N * d.N;
+  auto zero = [&](double* p, int64_t n) {
+    const int64_t blocks = ((n + 1) / 2 + 255) / 256;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    cpl_zero<<<(unsigned)blocks, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+  };
+  if (M && (e = zero(M, (int64_t)d.K * NN)) != hipSuccess) return e;
+  if (G && (e = zero(G, (int64_t)d.T * NN)) != hipSuccess) return e;
+  cpl_fill<<<(unsigned)d.n_work, FILL_BLOCK, 0, s>>>(d, d.work, M, G);
   prof_mark(prof, e1, s);
   return hipGetLastError();
 }

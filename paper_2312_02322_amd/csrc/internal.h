@@ -116,6 +116,9 @@ inline void prof_mark(Prof* p, hipEvent_t e, hipStream_t s) {
   if (p && e) (void)hipEventRecord(e, s);
 }
 
+// knots per accumulation chunk of the coupling fill kernel (v rows are padded to it)
+constexpr int CPL_KNOT_CHUNK = 32;
+
 // Device view of a coupling-matrix build (coupling.hip).  Channels n have a
 // (j1, j2, j) level chan_J, a rotor-1 state chan_r, total j and projection m;
 // terms are sorted by lam (t_user maps back to the caller's order).
@@ -135,10 +138,18 @@ struct CouplingDev {
   const int* t_l2;
   const int* t_l;
   const int* t_user;
-  const double* v;       // [T][K], sorted order
+  const double* v;       // [T][KP], sorted order, zero beyond K
   double* lf;            // [256] log-factorials
-  double* Kr;            // [T][n1][n1] rotor-1 factors
-  double* F;             // [T][nJ][nJ] level factors
+  double* Kr;            // [n1][n1][T] rotor-1 factors
+  double* F;             // [nJ][nJ][T] level factors
+  const int* chan_grp;   // [N] the channel's m group
+  const int* grp_off;    // [groups + 1] offsets into grp_list
+  const int* grp_list;   // [N] channels of each m group, ascending
+  const int2* work;      // [n_work] (row, tile of FILL_BLOCK entries of its m group)
+  int64_t n_work;
+  int KP;                // v row stride: K rounded up to the fill kernel's knot chunk
+  int cg_jmax, cg_lmax;  // extent of the C(j' m lam 0 | j'' m) table
+  double* cgt;           // that table
 };
 
 // ---- launchers (defined in the .hip files) ----------------------------------
