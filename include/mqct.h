@@ -322,6 +322,44 @@ mqct_status mqct_set_option(mqct_context* ctx, int32_t option, int64_t value);
 const char* mqct_tuning_report(mqct_context* ctx);
 
 /*
+ * Cross-section post-processing (paper Section III).  sigma[e][i][f] is the cross
+ * section for level i -> level f at the e-th collision energy (e < n_E; i, f < L),
+ * g[L] the level degeneracies (2 j1 + 1)(2 j2 + 1).
+ *   ratio[e][i][f] = g_i sigma_{i->f} / (g_f sigma_{f->i})   (the two sides of the
+ *                    microscopic-reversibility condition, Eq. 19; NaN where the
+ *                    right side is zero)
+ *   sym[e][i][f]   = (g_i sigma_{i->f} + g_f sigma_{f->i}) / 2   (Eq. 20)
+ * Either output may be NULL.  mem: where g, sigma, sym and ratio live
+ * (MQCT_MEM_HOST: copied in and out, the call returns when the outputs are
+ * written; MQCT_MEM_DEVICE: enqueued on the context stream).  Errors:
+ * MQCT_ERR_ARG (sizes, null pointers), MQCT_ERR_NONFINITE (host inputs).
+ */
+mqct_status mqct_xs_symmetrize(mqct_context* ctx, int32_t mem, int32_t n_E, int32_t L,
+                               const double* g, const double* sigma, double* sym, double* ratio);
+/*
+ * Rate coefficients from the symmetrised cross sections sym[e][i][f] (Eq. 20)
+ * computed at the collision energies U[n_E] (hartree, increasing, 2 <= n_E <= 64),
+ * by Maxwell-Boltzmann averaging (Section III, details in the paper's ref. 44).
+ * U is read as the symmetrised translational energy (the mean of the initial and
+ * final kinetic energies of a transition), so that with beta = k_B T (hartree)
+ *   k[t][i][f] = (1/g_i) sqrt(8/(pi mu)) beta^(-3/2) exp(-(E_f - E_i)/(2 beta))
+ *                * int s(U) U exp(-U/beta) dU
+ * obeys detailed balance for any s; s is the natural cubic spline through
+ * (U_e, sym_e) on [U_1, U_n], falls linearly to zero at the threshold
+ * |E_f - E_i| / 2 below U_1, and stays at sym(U_n) above U_n.  E[L] level energies
+ * (hartree), mu reduced mass (m_e), beta[n_T] > 0; k in bohr^3 per atomic unit of
+ * time (x 6.1265e-9 for cm^3/s).  The integral is taken up to 60 beta past the
+ * threshold by 8-point Gauss-Legendre on pieces no wider than beta, the rest in
+ * closed form.  mem as above (U, E, g, sym, beta and k in one space).  Errors:
+ * MQCT_ERR_ARG (sizes, U not increasing, g, mu or beta not positive),
+ * MQCT_ERR_NONFINITE.  Host inputs are validated; device inputs only by size.
+ */
+mqct_status mqct_rate_coefficients(mqct_context* ctx, int32_t mem, int32_t n_E, int32_t L,
+                                   const double* U, const double* E, const double* g,
+                                   const double* sym, double mu, int32_t n_T,
+                                   const double* beta, double* k);
+
+/*
  * Coupling-matrix builder for an asymmetric-top rotor + linear rotor (paper
  * Section II, Eqs. 12-18).  The potential is given by its expansion
  * V(R, angles) = sum_t v_t(R) tau_t (Eq. 12) over the angular functions of

@@ -35,7 +35,7 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
            "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
-           "mqct_coupling_build"]
+           "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients"]
 
 
 class CouplingDesc(C.Structure):
@@ -123,6 +123,10 @@ def lib():
         L.mqct_tuning_report.restype = C.c_char_p
         L.mqct_coupling_build.argtypes = [vp, C.POINTER(CouplingDesc), vp, vp]
         L.mqct_coupling_build.restype = i32
+        L.mqct_xs_symmetrize.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.mqct_xs_symmetrize.restype = i32
+        L.mqct_rate_coefficients.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, d, i32, vp, vp]
+        L.mqct_rate_coefficients.restype = i32
         _lib = L
     return _lib
 
@@ -394,6 +398,29 @@ class Context:
         self._check(lib().mqct_coupling_build(self.h, C.byref(d), _ptr(out.get("M")),
                                               _ptr(out.get("G"))))
         return out
+
+    def xs_symmetrize(self, sigma, g):
+        """Eq. 19 ratio and Eq. 20 symmetrised cross sections of sigma[n_E, L, L]
+        (host arrays in, host arrays out; computed on the GPU)."""
+        sigma = _host(sigma, np.float64)
+        g = _host(g, np.float64)
+        nE, L = sigma.shape[0], sigma.shape[1]
+        sym = np.empty_like(sigma)
+        ratio = np.empty_like(sigma)
+        self._check(lib().mqct_xs_symmetrize(self.h, MEM_HOST, nE, L, _ptr(g), _ptr(sigma),
+                                             _ptr(sym), _ptr(ratio)))
+        return sym, ratio
+
+    def rate_coefficients(self, U, sym, E_level, g, mu, beta):
+        """k[n_T, L, L] (bohr^3 per a.u. of time) from the symmetrised cross sections
+        sym[n_E, L, L] at the energies U[n_E]; beta = k_B T (hartree)."""
+        U, sym, E, g, beta = (_host(a, np.float64) for a in (U, sym, E_level, g, beta))
+        nE, L, nT = sym.shape[0], sym.shape[1], beta.shape[0]
+        k = np.empty((nT, L, L))
+        self._check(lib().mqct_rate_coefficients(self.h, MEM_HOST, nE, L, _ptr(U), _ptr(E),
+                                                 _ptr(g), _ptr(sym), float(mu), nT, _ptr(beta),
+                                                 _ptr(k)))
+        return k
 
     def set_option(self, name, value=1):
         """Work-list schedule options: graphs, autotune, chunk, reset_tuning, tail."""

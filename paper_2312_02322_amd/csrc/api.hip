@@ -1011,6 +1011,84 @@ const char* mqct_tuning_report(mqct_context* c) {
   return c->report.c_str();
 }
 
+mqct_status mqct_xs_symmetrize(mqct_context* c, int32_t mem, int32_t nE, int32_t L,
+                               const double* g, const double* sigma, double* sym, double* ratio) {
+  if (!c) return MQCT_ERR_ARG;
+  if (nE < 1 || L < 1 || !g || !sigma || (!sym && !ratio))
+    return fail(c, MQCT_ERR_ARG, "xs_symmetrize: need n_E, L >= 1, g, sigma and an output");
+  if (mem != MQCT_MEM_HOST && mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "xs_symmetrize: mem must be host or device");
+  const size_t n = (size_t)nE * L * L;
+  if (mem == MQCT_MEM_HOST && (!finite_arr(g, L) || !finite_arr(sigma, (int64_t)n)))
+    return fail(c, MQCT_ERR_NONFINITE, "xs_symmetrize: non-finite input");
+  HIP_TRY(c, hipSetDevice(c->device), "xs_symmetrize");
+  if (mem == MQCT_MEM_DEVICE) {
+    HIP_TRY(c, launch_xs_symmetrize(nE, L, g, sigma, sym, ratio, c->stream), "xs_symmetrize");
+    return MQCT_OK;
+  }
+  mqct_status st;
+  const size_t need = (L + 3 * n) * 8;
+  if ((st = ensure(c, c->xs[1], need, "xs_symmetrize")) != MQCT_OK) return st;
+  double* dg = (double*)c->xs[1].p;
+  double *ds = dg + L, *dy = ds + n, *dr = dy + n;
+  HIP_TRY(c, hipMemcpyAsync(dg, g, L * 8, hipMemcpyHostToDevice, c->stream), "xs_symmetrize");
+  HIP_TRY(c, hipMemcpyAsync(ds, sigma, n * 8, hipMemcpyHostToDevice, c->stream), "xs_symmetrize");
+  HIP_TRY(c, launch_xs_symmetrize(nE, L, dg, ds, sym ? dy : nullptr, ratio ? dr : nullptr,
+                                  c->stream), "xs_symmetrize");
+  if (sym) HIP_TRY(c, hipMemcpyAsync(sym, dy, n * 8, hipMemcpyDeviceToHost, c->stream), "xs_symmetrize");
+  if (ratio) HIP_TRY(c, hipMemcpyAsync(ratio, dr, n * 8, hipMemcpyDeviceToHost, c->stream), "xs_symmetrize");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "xs_symmetrize");
+  return MQCT_OK;
+}
+
+mqct_status mqct_rate_coefficients(mqct_context* c, int32_t mem, int32_t nE, int32_t L,
+                                   const double* U, const double* E, const double* g,
+                                   const double* sym, double mu, int32_t nT, const double* beta,
+                                   double* k) {
+  if (!c) return MQCT_ERR_ARG;
+  if (nE < 2 || nE > 64 || L < 1 || nT < 1 || !U || !E || !g || !sym || !beta || !k)
+    return fail(c, MQCT_ERR_ARG, "rate_coefficients: need 2 <= n_E <= 64, L, n_T >= 1 and "
+                "every array");
+  if (mem != MQCT_MEM_HOST && mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "rate_coefficients: mem must be host or device");
+  if (!(mu > 0.0) || !isfinite(mu)) return fail(c, MQCT_ERR_ARG, "rate_coefficients: mu must be > 0");
+  const size_t n = (size_t)nE * L * L, nk = (size_t)nT * L * L;
+  if (mem == MQCT_MEM_HOST) {
+    if (!finite_arr(U, nE) || !finite_arr(E, L) || !finite_arr(g, L) ||
+        !finite_arr(sym, (int64_t)n) || !finite_arr(beta, nT))
+      return fail(c, MQCT_ERR_NONFINITE, "rate_coefficients: non-finite input");
+    for (int e = 1; e < nE; ++e)
+      if (!(U[e] > U[e - 1])) return fail(c, MQCT_ERR_ARG, "rate_coefficients: U must increase");
+    for (int i = 0; i < L; ++i)
+      if (!(g[i] > 0.0)) return fail(c, MQCT_ERR_ARG, "rate_coefficients: g must be > 0");
+    for (int t = 0; t < nT; ++t)
+      if (!(beta[t] > 0.0)) return fail(c, MQCT_ERR_ARG, "rate_coefficients: beta must be > 0");
+  }
+  HIP_TRY(c, hipSetDevice(c->device), "rate_coefficients");
+  if (mem == MQCT_MEM_DEVICE) {
+    HIP_TRY(c, launch_xs_rates(nE, L, nT, U, E, g, sym, mu, beta, k, c->stream),
+            "rate_coefficients");
+    return MQCT_OK;
+  }
+  mqct_status st;
+  const size_t need = (nE + 2 * L + n + nT + nk) * 8;
+  if ((st = ensure(c, c->xs[2], need, "rate_coefficients")) != MQCT_OK) return st;
+  double* dU = (double*)c->xs[2].p;
+  double *dE = dU + nE, *dg = dE + L, *dy = dg + L, *db = dy + n, *dk = db + nT;
+  HIP_TRY(c, hipMemcpyAsync(dU, U, nE * 8, hipMemcpyHostToDevice, c->stream), "rate_coefficients");
+  HIP_TRY(c, hipMemcpyAsync(dE, E, L * 8, hipMemcpyHostToDevice, c->stream), "rate_coefficients");
+  HIP_TRY(c, hipMemcpyAsync(dg, g, L * 8, hipMemcpyHostToDevice, c->stream), "rate_coefficients");
+  HIP_TRY(c, hipMemcpyAsync(dy, sym, n * 8, hipMemcpyHostToDevice, c->stream), "rate_coefficients");
+  HIP_TRY(c, hipMemcpyAsync(db, beta, nT * 8, hipMemcpyHostToDevice, c->stream), "rate_coefficients");
+  hipEvent_t e0 = c->prof.next(), e1 = c->prof.next();
+  prof_mark(&c->prof, e0, c->stream);
+  HIP_TRY(c, launch_xs_rates(nE, L, nT, dU, dE, dg, dy, mu, db, dk, c->stream), "rate_coefficients");
+  prof_mark(&c->prof, e1, c->stream);
+  HIP_TRY(c, hipMemcpyAsync(k, dk, nk * 8, hipMemcpyDeviceToHost, c->stream), "rate_coefficients");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "rate_coefficients");
+  return MQCT_OK;
+}
+
 mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, double* M_out,
                                 double* G_out) {
   if (!c) return MQCT_ERR_ARG;

@@ -293,6 +293,13 @@ hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const
                        const int32_t* level_of_channel, int n_levels, double b_max,
                        double* level_sums /*[B][n_levels]*/, double* sigma, hipStream_t s);
 
+// cross-section post-processing (postproc.hip), device pointers
+hipError_t launch_xs_symmetrize(int nE, int L, const double* g, const double* sigma, double* sym,
+                                double* ratio, hipStream_t s);
+hipError_t launch_xs_rates(int nE, int L, int nT, const double* U, const double* E,
+                           const double* g, const double* sym, double mu, const double* beta,
+                           double* k, hipStream_t s);
+
 // coupling-matrix build: M [K][N][N] and/or G [T][N][N] (device, either may be null)
 hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* prof,
                            hipStream_t s);
