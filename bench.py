@@ -16,6 +16,7 @@ bytes / measured kernel time), the FP32 - FP64 probability difference, and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -61,13 +62,16 @@ def main():
                          "nonzero: the same gradient)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--workload", choices=["window", "large", "uneven", "at", "coupling"],
+    ap.add_argument("--workload", choices=["window", "large", "uneven", "at", "coupling",
+                                           "rates"],
                     default="window",
                     help="window: N=969 mid-collision windows (default, the headline); "
                          "large: N=4096, 512 full collisions of 10,000 RK4 steps on the binned "
                          "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5; "
                          "at: decoupled (AT) dynamics, 64 trajectories x 100 initial states; "
-                         "coupling: build the N=6825 top + rotor tables (83 terms, 63 knots)")
+                         "coupling: build the N=6825 top + rotor tables (83 terms, 63 knots); "
+                         "rates: Eq. 20 and rate coefficients for 1032 levels, 10 energies, "
+                         "20 temperatures")
     ap.add_argument("--large-n", type=int, default=4096)
     ap.add_argument("--large-traj", type=int, default=512)
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -108,6 +112,9 @@ def main():
         return
     if args.workload == "coupling":
         print(json.dumps(coupling_workload(args)), flush=True)
+        return
+    if args.workload == "rates":
+        print(json.dumps(rates_workload(args)), flush=True)
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_workload(args)), flush=True)
@@ -500,6 +507,82 @@ def coupling_workload(args, cpu_rows=256):
                                           % (cpu_rows, N, csec)}
         log("coupling: oracle %.3g elements/s on %d rows (%.1f s, %d threads)"
             % (cel / csec, cpu_rows, csec, oracle.threads()))
+    return line
+
+
+def rates_workload(args, L=1032, n_T=20, cpu_pairs=600):
+    """Post-processing (Section III): 1032 non-degenerate levels (the paper's count for
+    an o/p-H2O + p-H2 symmetry), cross sections at the paper's ten collision energies
+    (20 - 12000 cm^-1), Eq. 20 symmetrisation, then rate coefficients at 20
+    temperatures from 10 to 2000 K: 2.1e7 Maxwell-Boltzmann integrals.  Level
+    energies and degeneracies are synthetic (0 - 8000 cm^-1, g = (2j1+1)(2j2+1) with
+    j1 <= 28, j2 <= 10); cross sections smooth positive functions of U.  One step =
+    Eq. 20 + all rates, inputs and outputs in device memory."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import units as UU
+    rng = np.random.default_rng(np.random.SeedSequence([231202322, 7]))
+    U = UU.cm_to_hartree(np.array([20.0, 41.28, 84.0, 170.47, 346.41, 703.89, 1430.0, 2906.3,
+                                   5906.0, 12000.0]))
+    E = np.sort(UU.cm_to_hartree(8000.0 * rng.random(L)))
+    g = ((2 * rng.integers(0, 29, L) + 1) * (2 * rng.integers(0, 11, L) + 1)).astype(float)
+    A = rng.random((L, L)) * 30.0
+    p = 0.2 + 0.6 * rng.random((L, L))
+    Uc = UU.cm_to_hartree(3000.0 + 6000.0 * rng.random((L, L)))
+    sigma = A[None] * (U[:, None, None] / U[0]) ** p[None] * np.exp(-U[:, None, None] / Uc[None])
+    T = np.geomspace(10.0, 2000.0, n_T)
+    beta = 3.166811563e-6 * T
+    mu = UU.amu_to_me(1.8)
+    dev = torch.device("cuda", 0)
+    td = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    dU, dE, dg, dsig, db = td(U), td(E), td(g), td(sigma), td(beta)
+    dsym = torch.empty_like(dsig)
+    dk = torch.empty((n_T, L, L), dtype=torch.float64, device=dev)
+    ctx = mq.Context(0)
+    L_ = mq.lib()
+    P = lambda t: C.c_void_p(t.data_ptr())
+
+    def step():
+        ctx._check(L_.mqct_xs_symmetrize(ctx.h, mq.MEM_DEVICE, U.size, L, P(dg), P(dsig), P(dsym),
+                                         None))
+        ctx._check(L_.mqct_rate_coefficients(ctx.h, mq.MEM_DEVICE, U.size, L, P(dU), P(dE), P(dg),
+                                             P(dsym), mu, n_T, P(db), P(dk)))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ctx.close()
+    n_int = n_T * L * L
+    log("rates: %d levels, %d temperatures: %.2f ms per step, %.3g rate coefficients/s"
+        % (L, n_T, ms, n_int / (ms * 1e-3)))
+    line = {"metric": "rate coefficients/s (Maxwell-Boltzmann integrals of Eq. 20 cross "
+                      "sections)", "value": n_int / (ms * 1e-3), "unit": "rates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "%d levels x %d collision energies -> Eq. 20 -> rate "
+                                   "coefficients at %d temperatures" % (L, U.size, n_T),
+                       "levels": L, "energies": int(U.size), "temperatures": n_T}}
+    if not args.no_cpu:
+        from oracle import postproc as PP
+        sym = PP.symmetrize(sigma, g)
+        pick = rng.integers(0, L, (cpu_pairs // n_T + 1, 2))
+        pairs = [tuple(x) for x in pick]
+        t0 = time.time()
+        PP.rate_coefficients(U, sym, E, g, mu, beta, pairs=pairs)
+        csec = time.time() - t0
+        line["cpu_baseline"] = {"value": len(pairs) * n_T / csec, "unit": "rates/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "%d transitions x %d temperatures (scipy quad), %.1f s"
+                                          % (len(pairs), n_T, csec)}
     return line
 
 

@@ -348,8 +348,8 @@ mqct_status mqct_xs_symmetrize(mqct_context* ctx, int32_t mem, int32_t n_E, int3
  * (U_e, sym_e) on [U_1, U_n], falls linearly to zero at the threshold
  * |E_f - E_i| / 2 below U_1, and stays at sym(U_n) above U_n.  E[L] level energies
  * (hartree), mu reduced mass (m_e), beta[n_T] > 0; k in bohr^3 per atomic unit of
- * time (x 6.1265e-9 for cm^3/s).  The integral is taken up to 60 beta past the
- * threshold by 8-point Gauss-Legendre on pieces no wider than beta, the rest in
+ * time (x 6.1265e-9 for cm^3/s).  The integral is taken up to 40 beta past the
+ * threshold by 8-point Gauss-Legendre on pieces no wider than 2 beta, the rest in
  * closed form.  mem as above (U, E, g, sym, beta and k in one space).  Errors:
  * MQCT_ERR_ARG (sizes, U not increasing, g, mu or beta not positive),
  * MQCT_ERR_NONFINITE.  Host inputs are validated; device inputs only by size.
