@@ -34,8 +34,8 @@ MFMA_PEAK_TFLOPS = {"C64": 157.3, "C128": 78.6}   # dense FP32 / FP64 matrix pea
 # WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (profiles/).
 # Valid only for the kernel source file and workload they were taken on.
 MEASURED_TRAFFIC = {
-    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "e8e90551296eb8ef",
-                        "bytes": 4.471e9, "window": 10, "trajectories": 4096},
+    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "ecc15788f2ff3741",
+                        "bytes": 3.065e9, "window": 10, "trajectories": 4096},
 }
 
 

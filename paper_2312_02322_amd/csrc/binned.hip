@@ -33,7 +33,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TB = 32;     // trajectories per GEMM work item (2 TB real columns), a multiple of 8
+constexpr int TB = 64;     // trajectories per GEMM work item (2 TB real columns), a multiple of 8
 constexpr int NT = 256;    // threads of the per-trajectory kernels
 constexpr int NWT = NT / 64;
 
