@@ -412,7 +412,15 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
   const int item = w / nrb, rb = w - item * nrb;
   const int4 it = ws.items[item];
   const DevSystem sy = systems[ws.traj[0].sys];
-  gemm_dispatch<DT, TB / 8>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
+  if constexpr (DT == R64) {
+    // real FP64 tables: at most four column blocks per pass (eight would spill)
+    for (int c0 = 0; c0 < it.z; c0 += 32) {
+      const int cnt = min(32, it.z - c0);
+      gemm_dispatch<DT, 4>(ws, sy, rb, it.x, it.y + c0, cnt, (cnt + 7) >> 3);
+    }
+  } else {
+    gemm_dispatch<DT, TB / 8>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
+  }
 }
 
 // Combine the two knots' contributions, add the Coriolis term, reduce the
