@@ -208,6 +208,7 @@ struct QWS {
   double2* amp;        // [n][npad] amplitudes
   double2* kst;        // [n][8][npad] DP5 stage derivatives and fifth-order solution
   int32_t* list;       // [n] work list (class-local indices of unfinished trajectories)
+  int32_t* list2;      // [n] scratch of the compaction
   int32_t* count;      // [1] entries on the work list
 };
 

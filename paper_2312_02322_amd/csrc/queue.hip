@@ -50,42 +50,49 @@ constexpr int64_t TAIL_SAMPLE = 32;
 constexpr size_t LDS_MAX = 160 * 1024;
 constexpr int CT = 1024;   // threads of the compaction kernel
 
-// Stable in-place compaction of the work list: entries whose trajectory is
-// done are dropped.  The list is processed in chunks of CT entries in order;
-// within a chunk every entry is read before any is written, and a kept entry
-// moves to a position no later than its own, so no unread entry is overwritten.
-__global__ void __launch_bounds__(CT) q_compact(int32_t* list, int32_t* count,
+// Compaction of the work list: entries whose trajectory is done are dropped and
+// the rest are ordered by their current R (buckets of 1/4 bohr, by counting
+// sort; the order within a bucket is whatever the atomics give).  Trajectories
+// at nearly the same R read the same table slices, so workgroups that run at the
+// same time then share them through the caches.  Each trajectory's arithmetic
+// does not depend on its position in the list, so the results are the same for
+// any order.
+constexpr int QBK = 1024;
+__device__ __forceinline__ int r_bucket(double R) {
+  const double x = R * 4.0;
+  return (x >= 0.0 && x < (double)QBK) ? (int)x : (x >= (double)QBK ? QBK - 1 : 0);
+}
+
+__global__ void __launch_bounds__(CT) q_compact(int32_t* list, int32_t* tmp, int32_t* count,
                                                const QState* __restrict__ st) {
-  __shared__ int32_t wsum[CT / 64];
-  __shared__ int32_t base;
+  __shared__ int32_t cur[QBK];
+  __shared__ int32_t kept;
   const int n = *count;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) base = 0;
+  for (int b = threadIdx.x; b < QBK; b += CT) cur[b] = 0;
   __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += CT) {
-    const int p = c0 + threadIdx.x;
-    int v = 0;
-    bool keep = false;
-    if (p < n) {
-      v = list[p];
-      keep = !(st[v].flags & Q_DONE);
-    }
-    const unsigned long long m = __ballot(keep);
-    const int before = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __popcll(m);
-    __syncthreads();
-    int off = base;
-    for (int q = 0; q < w; ++q) off += wsum[q];
-    if (keep) list[off + before] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int q = 0; q < CT / 64; ++q) tot += wsum[q];
-      base += tot;
-    }
-    __syncthreads();
+  for (int p = threadIdx.x; p < n; p += CT) {
+    const int v = list[p];
+    if (!(st[v].flags & Q_DONE)) atomicAdd(&cur[r_bucket(st[v].yc[0])], 1);
   }
-  if (threadIdx.x == 0) *count = base;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < QBK; ++b) {
+      const int c = cur[b];
+      cur[b] = acc;
+      acc += c;
+    }
+    kept = acc;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < n; p += CT) {
+    const int v = list[p];
+    if (!(st[v].flags & Q_DONE)) tmp[atomicAdd(&cur[r_bucket(st[v].yc[0])], 1)] = v;
+  }
+  __syncthreads();
+  const int k = kept;
+  for (int p = threadIdx.x; p < k; p += CT) list[p] = tmp[p];
+  if (threadIdx.x == 0) *count = k;
 }
 
 // Work list = all sample slots, count = n (used by the autotuner's copies).
@@ -98,7 +105,7 @@ __global__ void q_iota(int32_t* list, int32_t* count, int n) {
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t class_bytes(int64_t n, int npad, int method) {
-  size_t s = al((size_t)n * sizeof(QState)) + al((size_t)n * npad * 16) + al((size_t)n * 4);
+  size_t s = al((size_t)n * sizeof(QState)) + al((size_t)n * npad * 16) + 2 * al((size_t)n * 4);
   if (method == 1) s += al((size_t)n * 8 * npad * 16);
   return s;
 }
@@ -111,6 +118,7 @@ QWS carve(char*& p, int64_t n, int npad, int method, const TrajIn* traj) {
   w.st = (QState*)p; p += al((size_t)n * sizeof(QState));
   w.amp = (double2*)p; p += al((size_t)n * npad * 16);
   w.list = (int32_t*)p; p += al((size_t)n * 4);
+  w.list2 = (int32_t*)p; p += al((size_t)n * 4);
   if (method == 1) { w.kst = (double2*)p; p += al((size_t)n * 8 * npad * 16); }
   return w;
 }
@@ -358,7 +366,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     hipError_t err;
     for (int j = 0; j < chunk; ++j)
       if ((err = launch(ks.step[method], r.grid, ks.block, lds, st, a)) != hipSuccess) return err;
-    q_compact<<<1, CT, 0, st>>>(r.ws.list, r.ws.count, r.ws.st);
+    q_compact<<<1, CT, 0, st>>>(r.ws.list, r.ws.list2, r.ws.count, r.ws.st);
     return hipGetLastError();
   };
   auto drop_graph = [](ClassRun& r) {

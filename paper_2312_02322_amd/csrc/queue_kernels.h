@@ -11,8 +11,10 @@
 //           error estimate and the accept/reject decision).  A trajectory that
 //           finishes evaluates its end state once more for the diagnostics and
 //           writes its results.
-//   compact one workgroup: removes finished trajectories from the work list
-//           (stable, in place) and updates the active count.
+//   compact one workgroup: removes finished trajectories from the work list,
+//           orders the rest by R (counting sort over 1/4-bohr buckets, so that
+//           concurrent workgroups read the same table slices) and updates the
+//           active count.
 //
 // The launches read the active count from device memory, so a fixed grid can
 // be replayed (HIP graph) while the list shrinks: workgroups past the count
