@@ -389,8 +389,9 @@ mqct_status mqct_rate_coefficients(mqct_context* ctx, int32_t mem, int32_t n_E, 
  * j2 <= 40.  Errors: MQCT_ERR_ARG (bad sizes, indices, angular momenta, null
  * pointers), MQCT_ERR_NONFINITE (b or v), MQCT_ERR_OOM / MQCT_ERR_DEVICE.
  * The Clebsch-Gordan, 6j and 9j coefficients are formed in FP64 from
- * log-factorials; their relative error grows with the angular momenta (about
- * 1e-14 at j ~ 10).
+ * log-factorials; their relative error grows with the angular momenta (measured
+ * against long-double sums: 2e-14 of the largest element for j <= 13, 3e-13 for
+ * j <= 28).
  */
 typedef struct {
   int32_t N;

@@ -74,6 +74,30 @@ def test_paper_check_basis(ctx):
     assert err < TOL * np.abs(M_o).max()
 
 
+@pytest.mark.parametrize("case", ["j13", "j28"])
+def test_high_angular_momenta(ctx, case):
+    """Rotor-1 states up to j1 = 9 (total j up to 13) and up to j1 = 24 (j up to 28,
+    the paper's water basis reaches j1 = 28): the log-domain Racah sums against the
+    oracle's long-double ones, with terms over the paper's lam ranges."""
+    if case == "j13":
+        rot1 = [(8, -8), (8, 3), (9, 0), (9, 9), (7, -1)]
+        basis = C.top_rotor_basis(9, (0, 4), rot1_states=rot1, m_values=(-3, 0, 5))
+        tol = 1e-12                 # measured 2.0e-14
+    else:
+        rot1 = [(20, -20), (20, 5), (24, 0), (24, 24), (22, -3)]
+        basis = C.top_rotor_basis(24, (0, 4), rot1_states=rot1, m_values=(-2, 7))
+        tol = 2e-12                 # measured 2.7e-13
+    ex = C.synthetic_expansion(C.select_terms(C.expansion_terms(), 20, seed=9), np.array([6.0, 7.0, 9.0]),
+                               seed=9)
+    say("high j (%s): N=%d, j <= %d" % (case, basis.N, basis.j.max()))
+    out = ctx.build_couplings(basis, ex, tables=True, angular=True)
+    M_o, G_o = oracle.coupling_tables(basis, ex)
+    em = np.max(np.abs(out["M"].cpu().numpy() - M_o)) / np.abs(M_o).max()
+    eg = np.max(np.abs(out["G"].cpu().numpy() - G_o)) / np.abs(G_o).max()
+    say("  relative max|dM| %.2e, max|dG| %.2e" % (em, eg))
+    assert em < tol and eg < tol
+
+
 def test_workload_83_terms_sampled_rows(ctx):
     basis, ex = C.config6()
     N = basis.N
