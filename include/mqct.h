@@ -413,6 +413,26 @@ typedef struct {
 } mqct_coupling_desc;
 mqct_status mqct_coupling_build(mqct_context* ctx, const mqct_coupling_desc* desc,
                                 double* M_out, double* G_out);
+/*
+ * Screened build for bases too large for the dense tables (Section III: the
+ * matrix was computed at two distances in the interaction region, the elements
+ * above 1 cm^-1 were kept and only those were computed on the radial grid).
+ * Every element of equal m is evaluated at n_screen radii, given by the
+ * expansion coefficients there (v_screen[t * n_screen + s], host, 1 <= n_screen
+ * <= 8); it is kept when max_s |M(R_s)| > drop_below (hartree).  The kept
+ * elements are written to device memory in an unspecified order:
+ *   rows[i], cols[i]        row n'' and column n' of kept element i;
+ *   values[k * capacity + i] its value at knot k (from desc->v), k < K.
+ * *n_kept (host) receives the number of kept elements.  When it exceeds
+ * capacity nothing is written beyond capacity and the call fails with
+ * MQCT_ERR_ARG (call again with capacity >= *n_kept; capacity 0 only counts).
+ * The call returns when the outputs are written.  Other errors as for
+ * mqct_coupling_build.
+ */
+mqct_status mqct_coupling_build_sparse(mqct_context* ctx, const mqct_coupling_desc* desc,
+                                       int32_t n_screen, const double* v_screen,
+                                       double drop_below, int64_t capacity, int32_t* rows,
+                                       int32_t* cols, double* values, int64_t* n_kept);
 
 /*
  * Optional timing of the dominant step kernel of later runs: the fused

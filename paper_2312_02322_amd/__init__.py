@@ -35,7 +35,8 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_cross_sections", "mqct_set_profiling", "mqct_profile_read",
            "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
-           "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients"]
+           "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients",
+           "mqct_coupling_build_sparse"]
 
 
 class CouplingDesc(C.Structure):
@@ -123,6 +124,9 @@ def lib():
         L.mqct_tuning_report.restype = C.c_char_p
         L.mqct_coupling_build.argtypes = [vp, C.POINTER(CouplingDesc), vp, vp]
         L.mqct_coupling_build.restype = i32
+        L.mqct_coupling_build_sparse.argtypes = [vp, C.POINTER(CouplingDesc), i32, vp, d, i64,
+                                                 vp, vp, vp, C.POINTER(i64)]
+        L.mqct_coupling_build_sparse.restype = i32
         L.mqct_xs_symmetrize.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.mqct_xs_symmetrize.restype = i32
         L.mqct_rate_coefficients.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, d, i32, vp, vp]
@@ -398,6 +402,41 @@ class Context:
         self._check(lib().mqct_coupling_build(self.h, C.byref(d), _ptr(out.get("M")),
                                               _ptr(out.get("G"))))
         return out
+
+    def build_couplings_sparse(self, basis, expansion, v_screen, drop_below, capacity=None):
+        """Screened build (mqct_coupling_build_sparse): the equal-m elements whose
+        largest |M| at the screening radii (v_screen [T, S], hartree) exceeds
+        drop_below, as device tensors rows [n], cols [n] (int32) and values [K, n]
+        (FP64).  capacity None: count first, then build with the exact capacity."""
+        torch = self.torch
+        i32 = lambda a: _host(a, np.int32)
+        j, m, r1, j2 = i32(basis.j), i32(basis.m), i32(basis.rot1), i32(basis.j2)
+        rj, b = i32(basis.rot1_j), _host(basis.b, np.float64)
+        l1, u1, l2, l = (i32(expansion.lam1), i32(expansion.mu1), i32(expansion.lam2),
+                         i32(expansion.lam))
+        v = _host(expansion.v, np.float64)
+        vs = _host(v_screen, np.float64)
+        N, T, K = j.shape[0], l1.shape[0], v.shape[1]
+        d = CouplingDesc(N, _ptr(j), _ptr(m), _ptr(r1), _ptr(j2), rj.shape[0], _ptr(rj),
+                         _ptr(b), b.shape[1], T, _ptr(l1), _ptr(u1), _ptr(l2), _ptr(l), K,
+                         _ptr(v))
+        n = C.c_int64()
+        if capacity is None:
+            code = lib().mqct_coupling_build_sparse(self.h, C.byref(d), vs.shape[1], _ptr(vs),
+                                                    float(drop_below), 0, None, None, None,
+                                                    C.byref(n))
+            if code not in (OK, ERR_ARG) or (code == ERR_ARG and n.value == 0):
+                self._check(code)
+            capacity = n.value
+        cap = max(int(capacity), 1)
+        rows = torch.empty(cap, dtype=torch.int32, device=self.device)
+        cols = torch.empty(cap, dtype=torch.int32, device=self.device)
+        vals = torch.empty((K, cap), dtype=torch.float64, device=self.device)
+        self._check(lib().mqct_coupling_build_sparse(self.h, C.byref(d), vs.shape[1], _ptr(vs),
+                                                     float(drop_below), cap, _ptr(rows),
+                                                     _ptr(cols), _ptr(vals), C.byref(n)))
+        k = n.value
+        return {"rows": rows[:k], "cols": cols[:k], "values": vals[:, :k], "n_kept": k}
 
     def xs_symmetrize(self, sigma, g):
         """Eq. 19 ratio and Eq. 20 symmetrised cross sections of sigma[n_E, L, L]

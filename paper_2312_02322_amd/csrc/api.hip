@@ -1089,33 +1089,38 @@ mqct_status mqct_rate_coefficients(mqct_context* c, int32_t mem, int32_t nE, int
   return MQCT_OK;
 }
 
-mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, double* M_out,
-                                double* G_out) {
-  if (!c) return MQCT_ERR_ARG;
-  if (!d) return fail(c, MQCT_ERR_ARG, "coupling_build: null descriptor");
-  if (!M_out && !G_out) return fail(c, MQCT_ERR_ARG, "coupling_build: no output requested");
+namespace {
+
+// Validation and device set-up shared by the dense and the screened builds: the
+// (j1, j2, j) levels, terms sorted by lam, channels grouped by m, the work list
+// (per row, tiles of 256 channels of the row's m group), and one device
+// workspace holding them with the factor arrays.  On success *buf owns it.
+mqct_status coupling_setup(mqct_context* c, const mqct_coupling_desc* d, const char* what,
+                           CouplingDev& dev, char** buf) {
+  *buf = nullptr;
+  if (!d) return fail(c, MQCT_ERR_ARG, "%s: null descriptor", what);
   const int N = d->N, T = d->T, K = d->K, n1 = d->n_rot1, bs = d->b_stride;
   if (N < 1 || T < 1 || K < 1 || n1 < 1 || bs < 1)
-    return fail(c, MQCT_ERR_ARG, "coupling_build: need N, T, K, n_rot1, b_stride >= 1");
+    return fail(c, MQCT_ERR_ARG, "%s: need N, T, K, n_rot1, b_stride >= 1", what);
   if (!d->j || !d->m || !d->rot1 || !d->j2 || !d->rot1_j || !d->b || !d->lam1 || !d->mu1 ||
       !d->lam2 || !d->lam || !d->v)
-    return fail(c, MQCT_ERR_ARG, "coupling_build: null array");
+    return fail(c, MQCT_ERR_ARG, "%s: null array", what);
   constexpr int JMAX = 40, LMAX = 20;
   for (int r = 0; r < n1; ++r)
     if (d->rot1_j[r] < 0 || d->rot1_j[r] > JMAX || 2 * d->rot1_j[r] + 1 > bs)
-      return fail(c, MQCT_ERR_ARG, "coupling_build: rotor-1 state %d: j1 out of 0..%d or "
-                  "b_stride too small", r, JMAX);
+      return fail(c, MQCT_ERR_ARG, "%s: rotor-1 state %d: j1 out of 0..%d or b_stride too small",
+                  what, r, JMAX);
   if (!finite_arr(d->b, (int64_t)n1 * bs) || !finite_arr(d->v, (int64_t)T * K))
-    return fail(c, MQCT_ERR_NONFINITE, "coupling_build: non-finite b or v");
+    return fail(c, MQCT_ERR_NONFINITE, "%s: non-finite b or v", what);
   std::map<std::pair<int, std::pair<int, int>>, int> jl;
   std::vector<int32_t> jl_j1, jl_j2, jl_j, chan_J(N);
   for (int n = 0; n < N; ++n) {
     const int r = d->rot1[n], j2 = d->j2[n], j = d->j[n], m = d->m[n];
-    if (r < 0 || r >= n1) return fail(c, MQCT_ERR_ARG, "coupling_build: rot1[%d] out of range", n);
+    if (r < 0 || r >= n1) return fail(c, MQCT_ERR_ARG, "%s: rot1[%d] out of range", what, n);
     const int j1 = d->rot1_j[r];
     if (j2 < 0 || j2 > JMAX || j < std::abs(j1 - j2) || j > j1 + j2 || std::abs(m) > j)
-      return fail(c, MQCT_ERR_ARG, "coupling_build: channel %d: need 0 <= j2 <= %d, "
-                  "|j1-j2| <= j <= j1+j2, |m| <= j", n, JMAX);
+      return fail(c, MQCT_ERR_ARG, "%s: channel %d: need 0 <= j2 <= %d, |j1-j2| <= j <= j1+j2, "
+                  "|m| <= j", what, n, JMAX);
     auto key = std::make_pair(j1, std::make_pair(j2, j));
     auto it = jl.find(key);
     if (it == jl.end()) {
@@ -1132,11 +1137,12 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
     const int l1 = d->lam1[t], u = d->mu1[t], l2 = d->lam2[t], l = d->lam[t];
     if (l1 < 0 || l1 > LMAX || l2 < 0 || l2 > LMAX || std::abs(u) > l1 || l < std::abs(l1 - l2) ||
         l > l1 + l2)
-      return fail(c, MQCT_ERR_ARG, "coupling_build: term %d: need 0 <= lam1, lam2 <= %d, "
-                  "|mu1| <= lam1, |lam1-lam2| <= lam <= lam1+lam2", t, LMAX);
+      return fail(c, MQCT_ERR_ARG, "%s: term %d: need 0 <= lam1, lam2 <= %d, |mu1| <= lam1, "
+                  "|lam1-lam2| <= lam <= lam1+lam2", what, t, LMAX);
     perm[t] = t;
   }
-  // terms sorted by lam: the fill kernel forms C(j' m lam 0 | j'' m) once per lam
+  // terms sorted by lam (kept from the first form of the fill kernel; the order of
+  // the sums over t is then the same in every kernel)
   std::stable_sort(perm.begin(), perm.end(),
                    [&](int a, int b) { return d->lam[a] < d->lam[b]; });
   std::vector<int32_t> ints;
@@ -1157,8 +1163,6 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
   }
   for (int n = 0; n < N; ++n) cg_jmax = std::max(cg_jmax, (int)d->j[n]);
   std::vector<int32_t> chan_r(d->rot1, d->rot1 + N), chan_j(d->j, d->j + N), chan_m(d->m, d->m + N);
-  // channels grouped by m (the potential couples only equal m), and the fill
-  // kernel's work list: per row, tiles of 256 channels of the row's group
   std::map<int, int> gid;
   for (int n = 0; n < N; ++n) gid.emplace(d->m[n], 0);
   int ng = 0;
@@ -1173,8 +1177,15 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
     std::vector<int32_t> fillp(grp_off.begin(), grp_off.end() - 1);
     for (int n = 0; n < N; ++n) grp_list[fillp[chan_grp[n]]++] = n;
   }
+  // rows taken level by level ((j1, j2, j) of the row, then m): consecutive work
+  // items then read the same row of level factors
+  std::vector<int32_t> order(N);
+  for (int n = 0; n < N; ++n) order[n] = n;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return chan_J[a] != chan_J[b] ? chan_J[a] < chan_J[b] : d->m[a] < d->m[b];
+  });
   std::vector<int32_t> work;
-  for (int n = 0; n < N; ++n) {
+  for (int n : order) {
     const int cnt = grp_off[chan_grp[n] + 1] - grp_off[chan_grp[n]];
     for (int tile = 0; tile * 256 < cnt; ++tile) {
       work.push_back(n);
@@ -1183,7 +1194,7 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
   }
   const int64_t n_work = (int64_t)work.size() / 2;
   if (n_work > 0x7fffffffLL)
-    return fail(c, MQCT_ERR_ARG, "coupling_build: too many channels for one launch");
+    return fail(c, MQCT_ERR_ARG, "%s: too many channels for one launch", what);
   const size_t o_cJ = put(chan_J.data(), N), o_cr = put(chan_r.data(), N),
                o_cj = put(chan_j.data(), N), o_cm = put(chan_m.data(), N),
                o_j1 = put(jl_j1.data(), nJ), o_j2 = put(jl_j2.data(), nJ),
@@ -1199,33 +1210,107 @@ mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, do
   const size_t n_K = (size_t)T * n1 * n1, n_F = (size_t)T * nJ * nJ;
   const size_t n_cg = (size_t)(cg_jmax + 1) * (cg_jmax + 1) * (2 * cg_jmax + 1) * (cg_lmax + 1);
   const size_t total = ibytes + (n_b + n_v + n_lf + n_K + n_F + n_cg) * 8;
-  HIP_TRY(c, hipSetDevice(c->device), "coupling_build");
-  char* buf = nullptr;
-  hipError_t e = hipMalloc((void**)&buf, total);
-  if (e != hipSuccess) return hip_fail(c, e, "coupling_build: workspace");
-  int32_t* di = (int32_t*)buf;
-  double* dd = (double*)(buf + ibytes);
+  HIP_TRY(c, hipSetDevice(c->device), what);
+  char* w = nullptr;
+  hipError_t e = hipMalloc((void**)&w, total);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  int32_t* di = (int32_t*)w;
+  double* dd = (double*)(w + ibytes);
   double *db = dd, *dv = db + n_b, *dlf = dv + n_v, *dK = dlf + n_lf, *dF = dK + n_K,
          *dcg = dF + n_F;
   if ((e = hipMemcpy(di, ints.data(), ints.size() * 4, hipMemcpyHostToDevice)) == hipSuccess &&
       (e = hipMemcpy(db, d->b, n_b * 8, hipMemcpyHostToDevice)) == hipSuccess)
     e = hipMemcpy(dv, vs.data(), n_v * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) {
-    CouplingDev dev{N, T, K, n1, nJ, bs, di + o_cJ, di + o_cr, di + o_cj, di + o_cm,
+  if (e != hipSuccess) {
+    hipFree(w);
+    return hip_fail(c, e, what);
+  }
+  dev = CouplingDev{N, T, K, n1, nJ, bs, di + o_cJ, di + o_cr, di + o_cj, di + o_cm,
                     di + o_j1, di + o_j2, di + o_jj, di + o_rj, db, di + o_t1, di + o_tm,
                     di + o_t2, di + o_tl, di + o_tu, dv, dlf, dK, dF, di + o_cg, di + o_go,
                     di + o_gl, (const int2*)(di + o_wk), n_work, KP, cg_jmax, cg_lmax, dcg};
-    e = launch_coupling(dev, M_out, G_out, &c->prof, c->stream);
-    if (e == hipErrorInvalidValue) {
-      hipFree(buf);
-      return fail(c, MQCT_ERR_ARG, "coupling_build: output too large for one launch");
-    }
-    if (e == hipSuccess && c->prof.on)
-      c->prof.bytes += ((M_out ? (double)K : 0.0) + (G_out ? (double)T : 0.0)) * N * (double)N * 8.0;
+  *buf = w;
+  return MQCT_OK;
+}
+
+}  // namespace
+
+mqct_status mqct_coupling_build(mqct_context* c, const mqct_coupling_desc* d, double* M_out,
+                                double* G_out) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!M_out && !G_out) return fail(c, MQCT_ERR_ARG, "coupling_build: no output requested");
+  CouplingDev dev;
+  char* buf = nullptr;
+  mqct_status st = coupling_setup(c, d, "coupling_build", dev, &buf);
+  if (st != MQCT_OK) return st;
+  hipError_t e = launch_coupling(dev, M_out, G_out, &c->prof, c->stream);
+  if (e == hipErrorInvalidValue) {
+    hipFree(buf);
+    return fail(c, MQCT_ERR_ARG, "coupling_build: output too large for one launch");
   }
+  if (e == hipSuccess && c->prof.on)
+    c->prof.bytes += ((M_out ? (double)dev.K : 0.0) + (G_out ? (double)dev.T : 0.0)) * dev.N *
+                     (double)dev.N * 8.0;
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   hipFree(buf);
   if (e != hipSuccess) return hip_fail(c, e, "coupling_build");
+  return MQCT_OK;
+}
+
+mqct_status mqct_coupling_build_sparse(mqct_context* c, const mqct_coupling_desc* d,
+                                       int32_t n_screen, const double* v_screen,
+                                       double drop_below, int64_t capacity, int32_t* rows,
+                                       int32_t* cols, double* values, int64_t* n_kept) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!n_kept || n_screen < 1 || n_screen > CPL_MAX_SCREEN || !v_screen || capacity < 0 ||
+      (capacity > 0 && (!rows || !cols || !values)))
+    return fail(c, MQCT_ERR_ARG, "coupling_build_sparse: need 1 <= n_screen <= %d, v_screen, "
+                "n_kept, and rows, cols, values when capacity > 0", CPL_MAX_SCREEN);
+  if (!(drop_below >= 0.0) || !isfinite(drop_below))
+    return fail(c, MQCT_ERR_ARG, "coupling_build_sparse: drop_below must be finite and >= 0");
+  *n_kept = 0;
+  if (d && d->T >= 1 && !finite_arr(v_screen, (int64_t)d->T * n_screen))
+    return fail(c, MQCT_ERR_NONFINITE, "coupling_build_sparse: non-finite v_screen");
+  CouplingDev dev;
+  char* buf = nullptr;
+  mqct_status st = coupling_setup(c, d, "coupling_build_sparse", dev, &buf);
+  if (st != MQCT_OK) return st;
+  // screening coefficients in the sorted term order, and the kept-element counter
+  std::vector<double> vs((size_t)dev.T * n_screen);
+  std::vector<int32_t> perm(dev.T);
+  HIP_TRY(c, hipMemcpy(perm.data(), dev.t_user, (size_t)dev.T * 4, hipMemcpyDeviceToHost),
+          "coupling_build_sparse");
+  for (int t = 0; t < dev.T; ++t)
+    for (int q = 0; q < n_screen; ++q) vs[(size_t)t * n_screen + q] = v_screen[(size_t)perm[t] * n_screen + q];
+  char* sbuf = nullptr;
+  hipError_t e = hipMalloc((void**)&sbuf, 256 + vs.size() * 8);
+  if (e == hipSuccess) {
+    unsigned long long* cnt = (unsigned long long*)sbuf;
+    double* dvs = (double*)(sbuf + 256);
+    e = hipMemcpy(dvs, vs.data(), vs.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, 8, c->stream);
+    hipEvent_t e0 = c->prof.next(), e1 = c->prof.next();
+    prof_mark(&c->prof, e0, c->stream);
+    if (e == hipSuccess)
+      e = launch_coupling_screen(dev, n_screen, dvs, drop_below, capacity, cnt, rows, cols,
+                                 c->stream);
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) {
+      *n_kept = (int64_t)h;
+      if ((int64_t)h <= capacity && h > 0)
+        e = launch_coupling_values(dev, (int64_t)h, rows, cols, capacity, values, c->stream);
+      prof_mark(&c->prof, e1, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+  }
+  if (sbuf) hipFree(sbuf);
+  hipFree(buf);
+  if (e != hipSuccess) return hip_fail(c, e, "coupling_build_sparse");
+  if (*n_kept > capacity)
+    return fail(c, MQCT_ERR_ARG, "coupling_build_sparse: %lld elements kept, capacity %lld",
+                (long long)*n_kept, (long long)capacity);
   return MQCT_OK;
 }
 

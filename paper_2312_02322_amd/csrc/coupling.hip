@@ -43,6 +43,7 @@ namespace {
 constexpr int LF_N = 256;        // log-factorial table: arguments up to 255
 constexpr int FILL_BLOCK = 256;
 constexpr int FILL_KC = CPL_KNOT_CHUNK;   // knots per accumulation chunk (registers)
+constexpr int NXCD = 8;          // accelerator dies of the device, each with its own L2
 constexpr int FILL_TC = 8;       // terms whose factors are gathered together
 
 __device__ inline bool tri(int a, int b, int c) { return c >= abs(a - b) && c <= a + b; }
@@ -179,6 +180,34 @@ __global__ void cpl_cgm(CouplingDev d) {
   d.cgt[i] = cg_dev(d.lf, ja, m, lam, 0, jb, m);
 }
 
+// Per element (nb, na) of equal m: pointers to its level factors F[Jb][Ja][.],
+// rotor-1 factors K[rb][ra][.] and m-coefficients C(ja m . 0 | jb m); g_t is
+// F[t] K[t] C[lam_t] for every kernel that forms it.
+struct GPtr {
+  const double* F;
+  const double* Kr;
+  const double* C;
+};
+__device__ __forceinline__ GPtr gptr(const CouplingDev& d, int nb, int na) {
+  const int T = d.T, JM = d.cg_jmax, mb = d.chan_m[nb];
+  const int Jb = d.chan_J[nb], rb = d.chan_r[nb], jb = d.chan_j[nb];
+  const int Ja = d.chan_J[na], ra = d.chan_r[na], ja = d.chan_j[na];
+  GPtr p;
+  p.F = d.F + ((int64_t)Jb * d.nJ + Ja) * T;
+  p.Kr = d.Kr + ((int64_t)rb * d.n1 + ra) * T;
+  p.C = d.cgt + (((int64_t)ja * (JM + 1) + jb) * (2 * JM + 1) + mb + JM) * (d.cg_lmax + 1);
+  return p;
+}
+// g_t for the FILL_TC terms from t0 (indices past the last term repeat it)
+__device__ __forceinline__ void gather_g(const CouplingDev& d, const GPtr& p, int t0,
+                                         double (&gv)[FILL_TC]) {
+#pragma unroll
+  for (int i = 0; i < FILL_TC; ++i) {
+    const int t = min(t0 + i, d.T - 1);
+    gv[i] = p.F[t] * p.Kr[t] * p.C[d.t_l[t]];
+  }
+}
+
 // One work item = (row nb, FILL_BLOCK consecutive entries of the list of channels
 // that share nb's m).  M[k][nb][na] (and G[t][nb][na] when asked) for those na.
 // Per chunk of FILL_TC terms a lane first gathers the chunk's factors (F, K and
@@ -196,16 +225,9 @@ cpl_fill(CouplingDev d, const int2* __restrict__ work, double* __restrict__ M,
   if (q >= cnt) return;
   const int na = d.grp_list[g0 + q];
   const int N = d.N, T = d.T, K = d.K, KP = d.KP;
-  const int mb = d.chan_m[nb];
   const int64_t NN = (int64_t)N * N;
   const int64_t pos = (int64_t)nb * N + na;
-  const int Jb = d.chan_J[nb], rb = d.chan_r[nb], jb = d.chan_j[nb];
-  const int Ja = d.chan_J[na], ra = d.chan_r[na], ja = d.chan_j[na];
-  const double* Fp = d.F + ((int64_t)Jb * d.nJ + Ja) * T;     // + t
-  const double* Kp = d.Kr + ((int64_t)rb * d.n1 + ra) * T;    // + t
-  const int JM = d.cg_jmax;
-  const double* Cp =
-      d.cgt + (((int64_t)ja * (JM + 1) + jb) * (2 * JM + 1) + mb + JM) * (d.cg_lmax + 1);
+  const GPtr gp = gptr(d, nb, na);
   const double* __restrict__ v = d.v;
   // G alone: one pass over the terms
   const int kpasses = M ? K : 1;
@@ -215,11 +237,7 @@ cpl_fill(CouplingDev d, const int2* __restrict__ work, double* __restrict__ M,
     for (int u = 0; u < FILL_KC; ++u) acc[u] = 0.0;
     for (int t0 = 0; t0 < T; t0 += FILL_TC) {
       double gv[FILL_TC];
-#pragma unroll
-      for (int i = 0; i < FILL_TC; ++i) {
-        const int t = min(t0 + i, T - 1);
-        gv[i] = Fp[t] * Kp[t] * Cp[d.t_l[t]];
-      }
+      gather_g(d, gp, t0, gv);
       if (G && k0 == 0) {
 #pragma unroll
         for (int i = 0; i < FILL_TC; ++i)
@@ -243,10 +261,103 @@ cpl_fill(CouplingDev d, const int2* __restrict__ work, double* __restrict__ M,
   }
 }
 
+// Screening: an element of equal m is kept when max_s |M(R_s)| > thr over the
+// screening radii, M(R_s) = sum_t vs[t][s] g_t.  Kept elements take slots of
+// (rows, cols) in the order the per-wave atomics give (one atomic per wave);
+// slots past the capacity are counted but not written.
+__global__ void __launch_bounds__(FILL_BLOCK)
+cpl_screen(CouplingDev d, const int2* __restrict__ work, int S, const double* __restrict__ vs,
+           double thr, int64_t capacity, unsigned long long* __restrict__ count,
+           int32_t* __restrict__ rows, int32_t* __restrict__ cols) {
+  // workgroup ids go to the dies round-robin; give each die one contiguous share
+  // of the work list (ordered by the rows' levels) so that its L2 holds the
+  // level-factor rows those items read
+  const int64_t per = (d.n_work + NXCD - 1) / NXCD;
+  const int64_t wi = (int64_t)(blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  if (blockIdx.x / NXCD >= per || wi >= d.n_work) return;
+  const int2 w = work[wi];
+  const int nb = w.x;
+  const int g = d.chan_grp[nb];
+  const int g0 = d.grp_off[g], cnt = d.grp_off[g + 1] - g0;
+  const int q = w.y * FILL_BLOCK + threadIdx.x;
+  const bool act = q < cnt;
+  const int na = act ? d.grp_list[g0 + q] : nb;
+  bool keep = false;
+  if (act) {
+    const GPtr gp = gptr(d, nb, na);
+    double acc[CPL_MAX_SCREEN];
+#pragma unroll
+    for (int u = 0; u < CPL_MAX_SCREEN; ++u) acc[u] = 0.0;
+    for (int t0 = 0; t0 < d.T; t0 += FILL_TC) {
+      double gv[FILL_TC];
+      gather_g(d, gp, t0, gv);
+#pragma unroll
+      for (int i = 0; i < FILL_TC; ++i) {
+        if (t0 + i >= d.T) break;
+        const double* vt = vs + (int64_t)(t0 + i) * S;
+#pragma unroll
+        for (int u = 0; u < CPL_MAX_SCREEN; ++u)
+          if (u < S) acc[u] = fma(vt[u], gv[i], acc[u]);
+      }
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int u = 0; u < CPL_MAX_SCREEN; ++u)
+      if (u < S) mx = fmax(mx, fabs(acc[u]));
+    keep = mx > thr;
+  }
+  const unsigned long long bal = __ballot(keep);
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0 && bal) base = atomicAdd(count, (unsigned long long)__popcll(bal));
+  const int lo = __shfl((int)(base & 0xffffffffull), 0, 64);
+  const int hi = __shfl((int)(base >> 32), 0, 64);
+  base = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  if (keep) {
+    const int64_t idx = (int64_t)(base + __popcll(bal & ((1ull << lane) - 1ull)));
+    if (idx < capacity) {
+      rows[idx] = nb;
+      cols[idx] = na;
+    }
+  }
+}
+
+// Values of the kept elements at every knot: values[k * capacity + i] for the
+// element (rows[i], cols[i]), one thread per element.
+__global__ void __launch_bounds__(256)
+cpl_values(CouplingDev d, int64_t n, const int32_t* __restrict__ rows,
+           const int32_t* __restrict__ cols, int64_t capacity, double* __restrict__ values) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const GPtr gp = gptr(d, rows[i], cols[i]);
+  const int T = d.T, K = d.K, KP = d.KP;
+  const double* __restrict__ v = d.v;
+  for (int k0 = 0; k0 < K; k0 += FILL_KC) {
+    double acc[FILL_KC];
+#pragma unroll
+    for (int u = 0; u < FILL_KC; ++u) acc[u] = 0.0;
+    for (int t0 = 0; t0 < T; t0 += FILL_TC) {
+      double gv[FILL_TC];
+      gather_g(d, gp, t0, gv);
+#pragma unroll
+      for (int j = 0; j < FILL_TC; ++j) {
+        if (t0 + j >= T) break;
+        const double* vt = v + (int64_t)(t0 + j) * KP + k0;
+#pragma unroll
+        for (int u = 0; u < FILL_KC; ++u) acc[u] = fma(vt[u], gv[j], acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < FILL_KC; ++u)
+      if (k0 + u < K) values[(int64_t)(k0 + u) * capacity + i] = acc[u];
+  }
+}
+
 }  // namespace
 
-hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* prof,
-                           hipStream_t s) {
+namespace {
+
+hipError_t launch_factors(const CouplingDev& d, hipStream_t s) {
   cpl_lfact<<<1, LF_N, 0, s>>>(d.lf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -258,8 +369,17 @@ hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* pro
   cpl_rotor<<<(unsigned)((nr + 255) / 256), 256, 0, s>>>(d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t nj = (int64_t)d.T * d.nJ * d.nJ;
+  if ((nj + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
   cpl_jlevel<<<(unsigned)((nj + 255) / 256), 256, 0, s>>>(d);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* prof,
+                           hipStream_t s) {
+  hipError_t e = launch_factors(d, s);
+  if (e != hipSuccess) return e;
   hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
   prof_mark(prof, e0, s);
   const int64_t NN = (int64_t)d.N * d.N;
@@ -273,6 +393,28 @@ hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* pro
   if (G && (e = zero(G, (int64_t)d.T * NN)) != hipSuccess) return e;
   cpl_fill<<<(unsigned)d.n_work, FILL_BLOCK, 0, s>>>(d, d.work, M, G);
   prof_mark(prof, e1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_coupling_screen(const CouplingDev& d, int S, const double* vs, double thr,
+                                  int64_t capacity, unsigned long long* count, int32_t* rows,
+                                  int32_t* cols, hipStream_t s) {
+  if (S < 1 || S > CPL_MAX_SCREEN) return hipErrorInvalidValue;
+  hipError_t e = launch_factors(d, s);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (d.n_work + NXCD - 1) / NXCD * NXCD;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  cpl_screen<<<(unsigned)blocks, FILL_BLOCK, 0, s>>>(d, d.work, S, vs, thr, capacity, count, rows,
+                                                      cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_coupling_values(const CouplingDev& d, int64_t n, const int32_t* rows,
+                                  const int32_t* cols, int64_t capacity, double* values,
+                                  hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  cpl_values<<<(unsigned)blocks, 256, 0, s>>>(d, n, rows, cols, capacity, values);
   return hipGetLastError();
 }
 

@@ -304,5 +304,16 @@ hipError_t launch_xs_rates(int nE, int L, int nT, const double* U, const double*
 // coupling-matrix build: M [K][N][N] and/or G [T][N][N] (device, either may be null)
 hipError_t launch_coupling(const CouplingDev& d, double* M, double* G, Prof* prof,
                            hipStream_t s);
+// screened build: factors, then the equal-m elements whose largest |M| over the
+// S screening radii (coefficients vs [T][S], sorted term order) exceeds thr,
+// counted in *count and listed in rows / cols up to capacity; then their values
+// at the K knots, values[k * capacity + i]
+constexpr int CPL_MAX_SCREEN = 8;
+hipError_t launch_coupling_screen(const CouplingDev& d, int S, const double* vs, double thr,
+                                  int64_t capacity, unsigned long long* count, int32_t* rows,
+                                  int32_t* cols, hipStream_t s);
+hipError_t launch_coupling_values(const CouplingDev& d, int64_t n, const int32_t* rows,
+                                  const int32_t* cols, int64_t capacity, double* values,
+                                  hipStream_t s);
 
 }  // namespace mqct

@@ -70,16 +70,20 @@ class Expansion:
 
 
 def top_rotor_basis(j1max=2, j2_values=(0, 2), rot=H2O_ABC_CM, B2_cm=H2_B_CM, jmax=None,
-                    m_values=None, rot1_states=None, order="level"):
+                    m_values=None, rot1_states=None, order="level", e_max_cm=None,
+                    tau_parity=None):
     """Channels |j1 tau1 j2 j m> for j1 <= j1max (every tau1, or only the (j1, tau1)
-    pairs in rot1_states), j2 in j2_values, |j1 - j2| <= j <= j1 + j2 (and j <=
-    jmax), m = -j..j (or the given m only).  order="level": by level (j1, tau1, j2,
-    j), then m; order="m": by m, then level (each m block contiguous)."""
+    pairs in rot1_states, or only tau1 of the given parity), j2 in j2_values, rotational
+    energy below e_max_cm if given, |j1 - j2| <= j <= j1 + j2 (and j <= jmax),
+    m = -j..j (or the given m only).  order="level": by level (j1, tau1, j2, j), then
+    m; order="m": by m, then level (each m block contiguous)."""
     rot1_j, rot1_tau, rot1_E, bl = [], [], [], []
     for j1 in range(j1max + 1):
         E1, b1 = asymmetric_top_states(j1, *rot)
         for t in range(2 * j1 + 1):
             if rot1_states is not None and (j1, t - j1) not in rot1_states:
+                continue
+            if tau_parity is not None and (t - j1) % 2 != tau_parity:
                 continue
             row = np.zeros(2 * j1max + 1)
             row[:2 * j1 + 1] = b1[t]
@@ -92,6 +96,8 @@ def top_rotor_basis(j1max=2, j2_values=(0, 2), rot=H2O_ABC_CM, B2_cm=H2_B_CM, jm
     n_lev = 0
     for r in range(len(rot1_j)):
         for jb in j2_values:
+            if e_max_cm is not None and rot1_E[r] + B2_cm * jb * (jb + 1) >= e_max_cm:
+                continue
             for jt in range(abs(rot1_j[r] - jb), rot1_j[r] + jb + 1):
                 if jmax is not None and jt > jmax:
                     continue
@@ -170,6 +176,24 @@ def system_from_tables(basis, R_grid, M, mu_amu=1.8, name="top_rotor"):
                   jx_row=basis.jx_row, jx_col=basis.jx_col, jx_val=basis.jx_val,
                   mu=U.amu_to_me(mu_amu), level_of_channel=basis.level_of_channel,
                   n_levels=basis.n_levels)
+
+
+# Screening threshold for the paper-size build with this module's synthetic
+# expansion.  The paper keeps |M| > 1 cm^-1 of its ab-initio potential (14.6 M of
+# about 0.5 B elements); the synthetic potential is about twenty times weaker at
+# the screening distances (its isotropic well is a few cm^-1 deep against some
+# 200 cm^-1 for H2O + H2), so the threshold is scaled with it: 0.05 cm^-1 keeps a
+# number of elements of the paper's order.
+PAPER_SCALE_DROP_CM = 0.05
+PAPER_SCREEN_R = (6.03, 7.11)        # bohr, Section III
+
+
+def para_h2o_para_h2_basis(e_max_cm=8000.0, j1max=28, j2max=10, order="m"):
+    """Section III's p-H2O + p-H2 basis: para-H2O (tau1 = kA - kC even) up to j1 = 28,
+    para-H2 (even j2) up to 10, rotational energy below 8000 cm^-1, all j and m (rigid
+    rotors with the H2O and H2 constants: 1034 levels, 206,350 states)."""
+    return top_rotor_basis(j1max, tuple(range(0, j2max + 1, 2)), order=order,
+                           e_max_cm=e_max_cm, tau_parity=0)
 
 
 # the levels j1_{kA kC} of Section II's check of Eq. 18, as (j1, tau1 = kA - kC)

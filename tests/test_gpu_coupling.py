@@ -178,3 +178,90 @@ def test_outputs_and_errors(ctx, gpu_lib):
     with pytest.raises(gpu_lib.MQCTError) as e:
         ctx.build_couplings(basis, ex_nan)
     assert e.value.code == gpu_lib.ERR_NONFINITE
+
+
+# ---------------------------------------------------------------- screened build
+
+SCREEN_R = np.array([6.03, 7.11])           # the two distances of Section III's screening
+
+
+def pair_values(basis, ex, pairs):
+    """The oracle's Eq. 17 for single elements: a two-channel basis per pair."""
+    out = []
+    for f, i in pairs:
+        sub = C.CouplingBasis(basis.j[[f, i]], basis.m[[f, i]], basis.rot1[[f, i]],
+                              basis.j2[[f, i]], basis.rot1_j, basis.rot1_tau, basis.b,
+                              basis.E[[f, i]], np.zeros(0, np.int32), np.zeros(0, np.int32),
+                              np.zeros(0), np.zeros(2, np.int32), 2)
+        M, _ = oracle.coupling_tables(sub, ex)
+        out.append(M[:, 0, 1])
+    return np.array(out).T                      # [K, pairs]
+
+
+def screen_expansion(terms, seed):
+    ex = C.synthetic_expansion(terms, C.log_grid(63), seed=seed)
+    scr = C.synthetic_expansion(terms, SCREEN_R, seed=seed)
+    return ex, scr.v
+
+
+def test_screened_build_matches_the_oracle(ctx):
+    basis = C.top_rotor_basis(3, (0, 2), order="m")
+    terms = C.select_terms(C.expansion_terms(), 40, seed=5)
+    ex, vs = screen_expansion(terms, 5)
+    thr = C.U.cm_to_hartree(1.0)
+    say("screened build: N=%d, %d terms, drop below 1 cm^-1" % (basis.N, len(terms)))
+    out = ctx.build_couplings_sparse(basis, ex, vs, thr)
+    scr = C.synthetic_expansion(terms, SCREEN_R, seed=5)
+    M_s, _ = oracle.coupling_tables(basis, scr)
+    amax = np.abs(M_s).max(axis=0)
+    same_m = basis.m[:, None] == basis.m[None, :]
+    keep_o = same_m & (amax > thr)
+    border = np.abs(amax - thr) < 1e-9 * thr
+    rows = out["rows"].cpu().numpy()
+    cols = out["cols"].cpu().numpy()
+    keep_g = np.zeros_like(keep_o)
+    keep_g[rows, cols] = True
+    assert len(set(zip(rows.tolist(), cols.tolist()))) == out["n_kept"]      # no duplicates
+    assert np.array_equal(keep_g & ~border, keep_o & ~border)
+    say("  kept %d of %d equal-m elements" % (out["n_kept"], int(same_m.sum())))
+    M_o, _ = oracle.coupling_tables(basis, ex)
+    vals = out["values"].cpu().numpy()
+    err = np.max(np.abs(vals - M_o[:, rows, cols]))
+    assert err < TOL * np.abs(M_o).max()
+    # capacity too small: counted, nothing past the capacity, ERR_ARG
+    import paper_2312_02322_amd as mq
+    with pytest.raises(mq.MQCTError) as e:
+        ctx.build_couplings_sparse(basis, ex, vs, thr, capacity=out["n_kept"] - 1)
+    assert e.value.code == mq.ERR_ARG
+
+
+def test_screened_build_at_the_papers_size(ctx):
+    """Section III's p-H2O + p-H2 basis (206,350 states, 1.2e9 equal-m elements)
+    with 83 terms: the screened build, checked on sampled kept and dropped elements."""
+    basis = C.para_h2o_para_h2_basis()
+    terms = C.select_terms(C.expansion_terms(), 83, seed=0)
+    ex, vs = screen_expansion(terms, 0)
+    thr = C.U.cm_to_hartree(C.PAPER_SCALE_DROP_CM)
+    import time
+    torch = ctx.torch
+    torch.cuda.synchronize()
+    t0 = time.time()
+    out = ctx.build_couplings_sparse(basis, ex, vs, thr)
+    torch.cuda.synchronize()
+    sec = time.time() - t0
+    n = out["n_kept"]
+    say("paper-size screened build: N=%d, %d terms, %d kept, %.1f s" % (basis.N, len(terms), n,
+                                                                         sec))
+    rng = np.random.default_rng(3)
+    pick = rng.choice(n, size=12, replace=False)
+    rows = out["rows"][pick].cpu().numpy()
+    cols = out["cols"][pick].cpu().numpy()
+    assert np.all(basis.m[rows] == basis.m[cols])
+    ref = pair_values(basis, ex, list(zip(rows, cols)))
+    got = out["values"][:, pick].cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say("  12 kept elements against Eq. 17: relative %.2e" % err)
+    assert err < 1e-11
+    scr = pair_values(basis, C.synthetic_expansion(terms, SCREEN_R, seed=0),
+                      list(zip(rows, cols)))
+    assert np.all(np.abs(scr).max(axis=0) > thr)
