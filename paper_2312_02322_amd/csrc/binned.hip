@@ -45,7 +45,9 @@ struct BinWS {
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
   double2* c64;           // [B][Npad] c = e^{-iEt} a at the current stage, FP64
   void* cst;              // [B][2][KR] the two real columns of c in the table precision
-  double4* uv;            // [2][B][Npad] (Re u, Im u, Re v, Im v) from the left / right knot
+  void* uv;               // [2][B][Npad][4] in the table precision, left / right knot:
+                          // (zA_re, zB_re, zA_im, zB_im), the value (A) and second-
+                          // derivative (B) slices times c, before the spline weights
   double* ycl;            // [B][4] R, Phi, P_R, P_Phi at the start of the step
   double* kcl;            // [B][4] classical derivative of the last stage
   double* acl;            // [B][4] classical accumulator
@@ -178,35 +180,62 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
 }
 
 // Bin offsets and the GEMM work list; resets the counters for the next stage.
+// The work items are listed by their number of 8-trajectory column blocks,
+// largest first: the product workgroups of the large items start first and the
+// short ones fill the end of the launch.  (The order within one size class is
+// that of the slot counters and does not affect any result: every item writes
+// its own outputs.)  One workgroup of 1024 threads, two knots per thread.
 __global__ void __launch_bounds__(1024) bin_scan(BinWS ws) {
-  const int K = ws.K;
-  __shared__ int ioff_s[2049];
-  if (threadIdx.x == 0) {
-    int off = 0, io = 0, occupied = 0;
-    for (int g = 0; g < K; ++g) {
-      const int c = ws.cnt[g];
-      ws.offset[g] = off;
-      ioff_s[g] = io;
-      off += c;
-      io += (c + TB - 1) / TB;
-      occupied += c > 0;
+  constexpr int NCLS = TB / 8;                 // column-block classes 1..NCLS
+  const int K = ws.K, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ int wsum[16];
+  __shared__ int ncls[NCLS + 1], cur[NCLS + 1];
+  __shared__ int occupied;
+  if (t <= NCLS) ncls[t] = 0;
+  if (t == 0) occupied = 0;
+  const int g0 = 2 * t, g1 = 2 * t + 1;
+  const int c0 = g0 < K ? ws.cnt[g0] : 0, c1 = g1 < K ? ws.cnt[g1] : 0;
+  // exclusive prefix of the bin sizes: within the wave, then across waves
+  int incl = c0 + c1;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  const int off0 = base + incl - c0 - c1, off1 = off0 + c0;
+  if (g0 < K) ws.offset[g0] = off0;
+  if (g1 < K) ws.offset[g1] = off1;
+  const int cls0 = ((c0 % TB) + 7) >> 3, cls1 = ((c1 % TB) + 7) >> 3;   // 0: no partial item
+  if (c0 / TB + c1 / TB) atomicAdd(&ncls[NCLS], c0 / TB + c1 / TB);
+  if (cls0) atomicAdd(&ncls[cls0], 1);
+  if (cls1) atomicAdd(&ncls[cls1], 1);
+  if ((c0 > 0) + (c1 > 0)) atomicAdd(&occupied, (c0 > 0) + (c1 > 0));
+  __syncthreads();
+  if (t == 0) {
+    int io = 0;
+    for (int c = NCLS; c >= 1; --c) {
+      cur[c] = io;
+      io += ncls[c];
     }
-    ioff_s[K] = io;
     *ws.n_items = io;
     *ws.occ += (unsigned long long)occupied;
   }
   __syncthreads();
-  for (int g = threadIdx.x; g < K; g += blockDim.x) {
-    const int c = ws.cnt[g];
-    const int base = ioff_s[g];
-    for (int q = 0; q * TB < c; ++q)
-      ws.items[base + q] = make_int4(g, ws.offset[g] + q * TB, min(TB, c - q * TB), 0);
-  }
-  __syncthreads();
-  for (int g = threadIdx.x; g < K; g += blockDim.x) {
-    ws.cnt[g] = 0;
-    ws.cursor[g] = 0;
-  }
+  auto emit = [&](int g, int c, int off, int cls) {
+    const int nf = c / TB;
+    if (nf) {
+      const int p = atomicAdd(&cur[NCLS], nf);
+      for (int q = 0; q < nf; ++q) ws.items[p + q] = make_int4(g, off + q * TB, TB, 0);
+    }
+    if (cls) ws.items[atomicAdd(&cur[cls], 1)] = make_int4(g, off + nf * TB, c - nf * TB, 0);
+  };
+  if (g0 < K) emit(g0, c0, off0, cls0);
+  if (g1 < K) emit(g1, c1, off1, cls1);
+  if (g0 < K) { ws.cnt[g0] = 0; ws.cursor[g0] = 0; }
+  if (g1 < K) { ws.cnt[g1] = 0; ws.cursor[g1] = 0; }
 }
 
 __global__ void bin_scatter(BinWS ws) {
@@ -283,7 +312,10 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   const auto rA = slice_rsrc((const S*)sy.M + (int64_t)g * ks * NCOMP, sbytes);
   const auto rB = slice_rsrc((const S*)sy.M2 + (int64_t)g * ks * NCOMP, sbytes);
   const uint32_t rowbytes = (uint32_t)(Npad * NCOMP * sizeof(S));
-  const int KR = Npad * NCOMP;   // real K extent (zero-padded past N)
+  const int KR = Npad * NCOMP;   // stored real K extent (zero-padded past N)
+  // the products stop at the first 16-multiple past the N * NCOMP stored reals:
+  // the steps beyond would add exact zeros
+  const int KE = (N * NCOMP + 15) & ~15;
 
   // this lane's real column in each column block
   const S* col[NX];
@@ -337,30 +369,29 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   };
   // K steps past the last one reload that step's operands (unused) rather than branch
 #pragma unroll
-  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KR - 16), a[j], bv[j]);
-  for (int k0 = 0; k0 < KR; k0 += 16 * PF * GEMM_UF) {
+  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KE - 16), a[j], bv[j]);
+  for (int k0 = 0; k0 < KE; k0 += 16 * PF * GEMM_UF) {
 #pragma unroll
     for (int j = 0; j < PF * GEMM_UF; ++j) {
       const int kl = k0 + 16 * (j + PF - 1);
-      load(kl < KR ? kl : KR - 16, a[(j + PF - 1) % PF], bv[(j + PF - 1) % PF]);
+      load(kl < KE ? kl : KE - 16, a[(j + PF - 1) % PF], bv[(j + PF - 1) % PF]);
       // keep the loads ahead of the products (and the waits for them behind)
       __builtin_amdgcn_sched_barrier(0);
-      if (k0 + 16 * j < KR) mma(a[j % PF], bv[j % PF]);
+      if (k0 + 16 * j < KE) mma(a[j % PF], bv[j % PF]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 
-  // epilogue: apply this column's spline weights (left or right knot)
+  // epilogue: both slices' products of this column (left or right knot); the
+  // spline weights are applied in FP64 where the two knots are combined
 #pragma unroll
   for (int cb = 0; cb < NX; ++cb) {
     const int jt = (cb * 16 + c16) >> 1;
     if (jt >= count) continue;
     const int e = ws.list[start + jt];
     const int b = e >> 1, side = e & 1;
-    const double* w = ws.wts + (int64_t)b * 8;
-    const double wA = side ? w[1] : w[0], wB = side ? w[3] : w[2];
-    const double dA = side ? w[5] : w[4], dB = side ? w[7] : w[6];
-    double* o = (double*)(ws.uv + ((int64_t)side * ws.B + b) * Npad);
+    using S2 = typename std::conditional<FP32, float2, double2>::type;
+    S2* o = (S2*)((S*)ws.uv + ((int64_t)side * ws.B + b) * Npad * 4) + part;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -368,9 +399,10 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
         // D rows of lane group q: 4q + i (f32 form), q + 4i (f64 form)
         const int n = row0 + r * 16 + (FP32 ? 4 * q + i : q + 4 * i);
         if (n < N) {
-          const double z = (double)acc[r][0][cb][i], z2 = (double)acc[r][1][cb][i];
-          o[(int64_t)n * 4 + part] = wA * z + wB * z2;
-          o[(int64_t)n * 4 + 2 + part] = dA * z + dB * z2;
+          S2 z;
+          z.x = acc[r][0][cb][i];
+          z.y = acc[r][1][cb][i];
+          o[(int64_t)n * 2] = z;
         }
       }
   }
@@ -396,20 +428,19 @@ constexpr int NXCD = 8;    // accelerator dies (each with its own L2) of the dev
 // resident workgroups per CU.
 constexpr size_t GEMM_LDS_CAP = 96 * 1024;
 
-// Work w = item * nrb + row block, items ordered by knot.  Workgroups are
-// handed to the dies round-robin by id, so die x receives ids x, x + 8, ...;
-// mapping those to one contiguous share of the work list keeps the row blocks
-// of an item (which read the same columns) and the items of one knot (which
-// read the same table rows) on one die's L2.
+// Work items are dealt to the dies round-robin (item i to die i mod 8), and the
+// row blocks of one item run on one die, one after another: they read the same
+// amplitude columns, which then stay in that die's L2.  Workgroups are handed
+// to the dies round-robin by id, so die x receives ids x, x + 8, ...: its
+// j-th workgroup takes row block j mod nrb of item x + 8 (j / nrb).  The items
+// arrive largest first, so every die starts on its long items and ends on its
+// short ones.
 template <int DT>
 __global__ void __launch_bounds__(256)
 bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
-  const int total = *ws.n_items * nrb;
-  const int per = (total + NXCD - 1) / NXCD;
   const int x = blockIdx.x % NXCD, jj = blockIdx.x / NXCD;
-  const int w = x * per + jj;
-  if (jj >= per || w >= total) return;
-  const int item = w / nrb, rb = w - item * nrb;
+  const int item = x + NXCD * (jj / nrb), rb = jj % nrb;
+  if (item >= *ws.n_items) return;
   const int4 it = ws.items[item];
   const DevSystem sy = systems[ws.traj[0].sys];
   if constexpr (DT == R64) {
@@ -423,8 +454,10 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
   }
 }
 
-// Combine the two knots' contributions, add the Coriolis term, reduce the
-// mean-field force and torque, and advance the RK4 accumulators.
+// Combine the two knots' contributions with the spline weights, add the
+// Coriolis term, reduce the mean-field force and torque, and advance the RK4
+// accumulators.  S: the table precision (that of the stored products).
+template <typename S>
 __global__ void __launch_bounds__(NT)
 bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag,
             TrajOut out) {
@@ -443,11 +476,23 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   const double phidot = ys[3] / (mu * R * R);
   const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
   double sums[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* wt = ws.wts + (int64_t)b * 8;
+  const double w0 = wt[0], w1 = wt[1], w2 = wt[2], w3 = wt[3];
+  const double d0 = wt[4], d1 = wt[5], d2 = wt[6], d3 = wt[7];
+  using S4 = typename std::conditional<sizeof(S) == 4, float4, double4>::type;
+  const S4* uvl = (const S4*)ws.uv;
   for (int n = threadIdx.x; n < N; n += NT) {
     const int64_t o = (int64_t)b * Npad + n;
-    const double4 L = ws.uv[o], Rr = ws.uv[(int64_t)ws.B * Npad + o];
-    const double2 u = make_double2(L.x + Rr.x, L.y + Rr.y);
-    const double2 v = make_double2(L.z + Rr.z, L.w + Rr.w);
+    const S4 L = uvl[o], Rr = uvl[(int64_t)ws.B * Npad + o];
+    // left knot: weights w0, w2 (d0, d2); right knot: w1, w3 (d1, d3)
+    const double2 u = make_double2((w0 * (double)L.x + w2 * (double)L.y) +
+                                       (w1 * (double)Rr.x + w3 * (double)Rr.y),
+                                   (w0 * (double)L.z + w2 * (double)L.w) +
+                                       (w1 * (double)Rr.z + w3 * (double)Rr.w));
+    const double2 v = make_double2((d0 * (double)L.x + d2 * (double)L.y) +
+                                       (d1 * (double)Rr.x + d3 * (double)Rr.y),
+                                   (d0 * (double)L.z + d2 * (double)L.w) +
+                                       (d1 * (double)Rr.z + d3 * (double)Rr.w));
     const double2 c = ws.c64[o];
     double2 xc = make_double2(0.0, 0.0);
     for (int qq = 0; qq < sy.jx_w; ++qq) {
@@ -560,7 +605,7 @@ size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
   size_t s = 0;
   s += 4 * al(v * 16);                    // a0, kv, acc, c64
   s += al(v * 2 * 2 * (fp32 ? 4 : 8));    // cst (two real columns, complex worst case)
-  s += al(2 * v * 32);                    // uv
+  s += al(2 * v * 4 * (fp32 ? 4 : 8));    // uv
   s += 4 * al((size_t)B * 32);            // ycl kcl acl ysb
   s += al((size_t)B * 64) + al((size_t)B * 8) + al((size_t)B * 32);   // wts tst diag
   s += 3 * al((size_t)B * 4);             // kb status done
@@ -586,7 +631,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   ws.acc = (double2*)take(v * 16);
   ws.c64 = (double2*)take(v * 16);
   ws.cst = take(v * 2 * 2 * (fp32 ? 4 : 8));
-  ws.uv = (double4*)take(2 * v * 32);
+  ws.uv = take(2 * v * 4 * (fp32 ? 4 : 8));
   ws.ycl = (double*)take((size_t)B * 32);
   ws.kcl = (double*)take((size_t)B * 32);
   ws.acl = (double*)take((size_t)B * 32);
@@ -609,7 +654,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   const bool cplx = dtype_complex(hs.dtype);
   const int rows_per_block = 2 * 4 * 16;
   const int nrb = (hs.N + rows_per_block - 1) / rows_per_block;
-  const int64_t gblocks = ((int64_t)nrb * max_items + NXCD - 1) / NXCD * NXCD;
+  const int64_t gblocks = (int64_t)(max_items + NXCD - 1) / NXCD * nrb * NXCD;
   const dim3 ggrid((unsigned)gblocks);
   hipError_t e;
   bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
@@ -631,7 +676,8 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
     else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
     else bin_gemm<R64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
     prof_mark(prof, e1, s);
-    bin_combine<<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
+    if (fp32) bin_combine<float><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
+    else bin_combine<double><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
     return hipGetLastError();
   };
   (void)cplx;
