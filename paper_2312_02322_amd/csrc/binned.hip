@@ -17,14 +17,17 @@
 // ...); each trajectory therefore contributes two real columns and the table
 // is read exactly as stored.
 //
-// Per stage: prep (stage state, interval, weights, phases, c columns, bin
-// counts) -> scan (bin offsets and GEMM work list) -> scatter (bin lists) ->
-// gemm (per knot and 32-trajectory tile) -> combine (J_x, force, torque,
-// derivatives, RK4 accumulation).  The right-hand side is the same as the
-// per-trajectory kernels' (Eqs. 5 and 7-10).
+// Per stage: scan (bin offsets and GEMM work list) -> scatter (bin lists) ->
+// gemm (per knot and 64-trajectory tile) -> combine (J_x, force, torque,
+// derivatives, RK4 accumulation, then the following stage's state: interval,
+// weights, phases, c columns and bin counts).  A separate prep kernel sets up
+// the first stage and the final diagnostic evaluation.  The right-hand side is
+// the same as the per-trajectory kernels' (Eqs. 5 and 7-10).
 #include "device.h"
 
 #include <math.h>
+
+#include <type_traits>
 
 namespace mqct {
 
@@ -43,7 +46,8 @@ struct BinWS {
   double2* a0;            // [B][Npad] amplitudes at the start of the step
   double2* kv;            // [B][Npad] derivative of the last stage
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
-  double2* c64;           // [B][Npad] c = e^{-iEt} a at the current stage, FP64
+  double2* c64;           // [B][Npad] c = e^{-iEt} a of the stage in the combine, FP64,
+                          // when Npad is too large for LDS
   void* cst;              // [B][2][KR] the two real columns of c in the table precision
   void* uv;               // [2][B][Npad][4] in the table precision, left / right knot:
                           // (zA_re, zB_re, zA_im, zB_im), the value (A) and second-
@@ -117,12 +121,45 @@ __global__ void bin_zero(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// Stage state of every trajectory: classical stage values, interval and
-// weights, phases and the c columns; adds the trajectory to the counts of its
-// two knots.  diag = 1: the final diagnostic evaluation at the end state.
-// The two real columns of a trajectory (KR = 2 Npad reals for complex tables,
-// Npad for real ones): complex tables take (Re c_n, -Im c_n) and (Im c_n, Re c_n)
-// at reals 2n, 2n+1; real tables take Re c_n and Im c_n.
+// Interval, spline weights, stage state and time of trajectory b at a stage,
+// and its entries in the counts of its two knots (one thread).
+__device__ __forceinline__ void stage_setup(const BinWS& ws, const DevSystem& sy, int b,
+                                            const double (&ys)[4], double t, bool count_below) {
+  const Spl sp = spline_at(sy.R, sy.K, ys[0]);
+  for (int i = 0; i < 4; ++i) ws.ysb[b * 4 + i] = ys[i];
+  double* w = ws.wts + (int64_t)b * 8;
+  w[0] = sp.w0; w[1] = sp.w1; w[2] = sp.w2; w[3] = sp.w3;
+  w[4] = sp.d0; w[5] = sp.d1; w[6] = sp.d2; w[7] = sp.d3;
+  ws.tst[b] = t;
+  ws.kb[b] = sp.k;
+  atomicAdd(&ws.cnt[sp.k], 1);
+  atomicAdd(&ws.cnt[sp.k + 1], 1);
+  if (sp.below && count_below) ws.status[b] |= ST_BELOW_GRID;
+}
+
+// Element n of the two real columns of c in the table precision (KR = 2 Npad
+// reals for complex tables, Npad for real ones): complex tables take
+// (Re c_n, -Im c_n) and (Im c_n, Re c_n) at reals 2n, 2n+1; real tables take
+// Re c_n and Im c_n.
+template <typename S, bool CPLX>
+__device__ __forceinline__ void put_cols(const BinWS& ws, int b, int Npad, int n, double2 c) {
+  const int64_t KR = (CPLX ? 2 : 1) * (int64_t)Npad;
+  S* col0 = (S*)ws.cst + (int64_t)b * 2 * KR;
+  S* col1 = col0 + KR;
+  const S re = (S)c.x, im = (S)c.y;
+  if constexpr (CPLX) {
+    col0[2 * n] = re; col0[2 * n + 1] = -im;
+    col1[2 * n] = im; col1[2 * n + 1] = re;
+  } else {
+    col0[n] = re;
+    col1[n] = im;
+  }
+}
+
+// Stage state of every trajectory for the first stage of the run and for the
+// final diagnostic evaluation (diag = 1, at the end state): classical stage
+// values, interval and weights, the c columns, and the knot counts.  Every
+// other stage is prepared by the combine of the stage before it.
 template <typename S, bool CPLX>
 __global__ void __launch_bounds__(NT)
 bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag) {
@@ -142,21 +179,7 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
   const double t = tj.t0 + (double)jsteps * h + cf;
   double ys[4];
   for (int i = 0; i < 4; ++i) ys[i] = fma(cf, ws.kcl[b * 4 + i], ws.ycl[b * 4 + i]);
-  const Spl sp = spline_at(sy.R, sy.K, ys[0]);
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < 4; ++i) ws.ysb[b * 4 + i] = ys[i];
-    double* w = ws.wts + (int64_t)b * 8;
-    w[0] = sp.w0; w[1] = sp.w1; w[2] = sp.w2; w[3] = sp.w3;
-    w[4] = sp.d0; w[5] = sp.d1; w[6] = sp.d2; w[7] = sp.d3;
-    ws.tst[b] = t;
-    ws.kb[b] = sp.k;
-    atomicAdd(&ws.cnt[sp.k], 1);
-    atomicAdd(&ws.cnt[sp.k + 1], 1);
-    if (sp.below && !diag) ws.status[b] |= ST_BELOW_GRID;
-  }
-  const int64_t KR = (CPLX ? 2 : 1) * (int64_t)Npad;
-  S* col0 = (S*)ws.cst + (int64_t)b * 2 * KR;
-  S* col1 = col0 + KR;
+  if (threadIdx.x == 0) stage_setup(ws, sy, b, ys, t, !diag);
   for (int n = threadIdx.x; n < Npad; n += NT) {
     const int64_t o = (int64_t)b * Npad + n;
     double2 c = make_double2(0.0, 0.0);
@@ -167,15 +190,7 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
       sincos(sy.E[n] * t, &sn, &cs);
       c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
     }
-    ws.c64[o] = c;
-    const S re = (S)c.x, im = (S)c.y;
-    if constexpr (CPLX) {
-      col0[2 * n] = re; col0[2 * n + 1] = -im;
-      col1[2 * n] = im; col1[2 * n + 1] = re;
-    } else {
-      col0[n] = re;
-      col1[n] = im;
-    }
+    put_cols<S, CPLX>(ws, b, Npad, n, c);
   }
 }
 
@@ -456,11 +471,16 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
 
 // Combine the two knots' contributions with the spline weights, add the
 // Coriolis term, reduce the mean-field force and torque, and advance the RK4
-// accumulators.  S: the table precision (that of the stored products).
-template <typename S>
+// accumulators; with next = 1 also prepare the following stage of the step
+// sequence (its c columns, interval, weights and knot counts), so that the
+// amplitudes are read once per stage.  S, CPLX: the table precision and kind;
+// LDSC: c of this stage and its phases e^{-iEt} are held in LDS (Npad <= 2048),
+// else c is kept in ws.c64 and the phases are computed again.
+template <typename S, bool CPLX, bool LDSC>
 __global__ void __launch_bounds__(NT)
 bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag,
-            TrajOut out) {
+            int next, TrajOut out) {
+  extern __shared__ double2 c_lds[];   // [Npad] c, then [Npad] (cos Et, sin Et)
   __shared__ double red[NWT * 8];
   const int b = blockIdx.x;
   if (ws.kb[b] < 0) return;
@@ -475,7 +495,30 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   const double R = ys[0];
   const double phidot = ys[3] / (mu * R * R);
   const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+  double2* cb = LDSC ? c_lds : ws.c64 + (int64_t)b * Npad;
+  double2* ph = c_lds + Npad;
   double sums[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // c = e^{-iEt} (a0 + cf k) of this stage, for the products with J_x; the
+  // rotational energy and the norm
+  for (int n = threadIdx.x; n < N; n += NT) {
+    const int64_t o = (int64_t)b * Npad + n;
+    const double2 a = ws.a0[o], k = ws.kv[o];
+    const double2 cur = make_double2(fma(cf, k.x, a.x), fma(cf, k.y, a.y));
+    double sn, cs;
+    sincos(sy.E[n] * t, &sn, &cs);
+    cb[n] = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+    if constexpr (LDSC) ph[n] = make_double2(cs, sn);
+    const double pn = cur.x * cur.x + cur.y * cur.y;
+    sums[3] += sy.E[n] * pn;
+    sums[4] += pn;
+  }
+  __syncthreads();
+  // the following stage: step jn, stage stn, time tn
+  const int stn = st == 3 ? 0 : st + 1;
+  const int64_t jn = st == 3 ? j + 1 : j;
+  const double cfn = stage_frac(stn) * h;
+  const double tn = tj.t0 + (double)jn * h + cfn;
+  const bool same_t = tn == t;
   const double* wt = ws.wts + (int64_t)b * 8;
   const double w0 = wt[0], w1 = wt[1], w2 = wt[2], w3 = wt[3];
   const double d0 = wt[4], d1 = wt[5], d2 = wt[6], d3 = wt[7];
@@ -493,27 +536,29 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
                                        (d1 * (double)Rr.x + d3 * (double)Rr.y),
                                    (d0 * (double)L.z + d2 * (double)L.w) +
                                        (d1 * (double)Rr.z + d3 * (double)Rr.w));
-    const double2 c = ws.c64[o];
+    const double2 c = cb[n];
     double2 xc = make_double2(0.0, 0.0);
     for (int qq = 0; qq < sy.jx_w; ++qq) {
       const int col = sy.jx_col[(int64_t)n * sy.jx_w + qq];
       const double jv = sy.jx_val[(int64_t)n * sy.jx_w + qq];
-      const double2 cm = ws.c64[(int64_t)b * Npad + col];
+      const double2 cm = cb[col];
       xc.x = fma(jv, cm.x, xc.x);
       xc.y = fma(jv, cm.y, xc.y);
     }
-    const double2 a = ws.a0[o], kold = ws.kv[o];
-    const double2 cur = make_double2(fma(cf, kold.x, a.x), fma(cf, kold.y, a.y));
     sums[0] += c.x * v.x + c.y * v.y;
     sums[1] += xc.x * u.y - xc.y * u.x;
     sums[2] += c.x * u.x + c.y * u.y;
-    const double pn = cur.x * cur.x + cur.y * cur.y;
-    sums[3] += sy.E[n] * pn;
-    sums[4] += pn;
     sums[5] += c.x * xc.x + c.y * xc.y;
     if (!diag) {
+      const double2 a = ws.a0[o];
       double sn, cs;
-      sincos(sy.E[n] * t, &sn, &cs);
+      if constexpr (LDSC) {
+        const double2 p = ph[n];
+        cs = p.x;
+        sn = p.y;
+      } else {
+        sincos(sy.E[n] * t, &sn, &cs);
+      }
       const double gx = u.x + phidot * xc.x, gy = u.y + phidot * xc.y;
       const double yx = cs * gx - sn * gy, yy = cs * gy + sn * gx;
       const double2 k = make_double2(yy, -yx);
@@ -521,11 +566,21 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
       ac.x = fma(wgt, k.x, ac.x);
       ac.y = fma(wgt, k.y, ac.y);
       ws.kv[o] = k;
+      double2 base = a;
       if (st == 3) {
         const double h6 = h / 6.0;
-        ws.a0[o] = make_double2(a.x + h6 * ac.x, a.y + h6 * ac.y);
+        base = make_double2(a.x + h6 * ac.x, a.y + h6 * ac.y);
+        ws.a0[o] = base;
       } else {
         ws.acc[o] = ac;
+      }
+      if (next) {
+        // the following stage's amplitudes and c columns
+        const double2 curn = make_double2(fma(cfn, k.x, base.x), fma(cfn, k.y, base.y));
+        double snn = sn, csn = cs;
+        if (!same_t) sincos(sy.E[n] * tn, &snn, &csn);
+        put_cols<S, CPLX>(ws, b, Npad, n, make_double2(csn * curn.x + snn * curn.y,
+                                                       csn * curn.y - snn * curn.x));
       }
     }
   }
@@ -592,6 +647,19 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
         ws.status[b] |= ST_NONFINITE;
         ws.done[b] = (int)(j + 1);
       }
+    }
+  }
+  if (!next) return;
+  // every thread has read this stage's weights and state before thread 0
+  // overwrites them with the following stage's
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (jn < tj.n_steps && ws.done[b] < 0) {
+      double yn[4];
+      for (int i = 0; i < 4; ++i) yn[i] = fma(cfn, ws.kcl[b * 4 + i], ws.ycl[b * 4 + i]);
+      stage_setup(ws, sy, b, yn, tn, true);
+    } else {
+      ws.kb[b] = -1;
     }
   }
 }
@@ -662,11 +730,22 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cursor, hs.K);
   bin_zero<<<1, 256, 0, s>>>((int*)ws.occ, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  auto stage = [&](int64_t j, int st, int diag) -> hipError_t {
+  auto prep = [&](int64_t j, int st, int diag) {
     if (hs.dtype == C64) bin_prep<float, true><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
     else if (hs.dtype == C128) bin_prep<double, true><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
     else if (hs.dtype == R32) bin_prep<float, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
     else bin_prep<double, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag);
+  };
+  // c of a stage and its phases in LDS when they fit the default 64 KiB
+  const bool ldsc = (size_t)hs.Npad * 32 <= 65536;
+  const size_t clds = ldsc ? (size_t)hs.Npad * 32 : 0;
+  auto combine = [&](auto sc, auto cx, int64_t j, int st, int diag, int next) {
+    using S = decltype(sc);
+    constexpr bool CX = decltype(cx)::value;
+    if (ldsc) bin_combine<S, CX, true><<<B, NT, clds, s>>>(ws, d_systems, j, st, diag, next, out);
+    else bin_combine<S, CX, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, next, out);
+  };
+  auto stage = [&](int64_t j, int st, int diag, int next) -> hipError_t {
     bin_scan<<<1, 1024, 0, s>>>(ws);
     bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
     hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
@@ -676,15 +755,21 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
     else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
     else bin_gemm<R64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
     prof_mark(prof, e1, s);
-    if (fp32) bin_combine<float><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
-    else bin_combine<double><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, out);
+    if (hs.dtype == C64) combine(0.0f, std::true_type{}, j, st, diag, next);
+    else if (hs.dtype == C128) combine(0.0, std::true_type{}, j, st, diag, next);
+    else if (hs.dtype == R32) combine(0.0f, std::false_type{}, j, st, diag, next);
+    else combine(0.0, std::false_type{}, j, st, diag, next);
     return hipGetLastError();
   };
   (void)cplx;
+  // the first stage is prepared on its own, every later one by the combine of
+  // the stage before it, the final diagnostic evaluation on its own again
+  if (max_steps > 0) prep(0, 0, 0);
   for (int64_t j = 0; j < max_steps; ++j)
     for (int st = 0; st < 4; ++st)
-      if ((e = stage(j, st, 0)) != hipSuccess) return e;
-  if ((e = stage(max_steps, 0, 1)) != hipSuccess) return e;
+      if ((e = stage(j, st, 0, !(j == max_steps - 1 && st == 3))) != hipSuccess) return e;
+  prep(max_steps, 0, 1);
+  if ((e = stage(max_steps, 0, 1, 0)) != hipSuccess) return e;
   // algorithmic table bytes of the timed products: each occupied knot's value
   // and second-derivative slices, read once per stage
   unsigned long long* slot =

@@ -130,3 +130,33 @@ def test_profiled_table_bytes(ctx):
         say("  %s: %d launches, %.0f bytes (expected %d)" % (sched, n, by, expect))
         assert n > 0 and by == expect
     ctx.free_system(sid)
+
+
+def test_binned_wide_system_c_outside_lds(ctx):
+    """N = 2100 (padded past 2048 columns): the combine keeps c in device memory
+    instead of LDS.  Channels come in degenerate pairs (2i, 2i+1) coupled by a
+    real-symmetric J_x, so every row's Coriolis term reads c of another row.
+    Binned against the per-trajectory schedule (both FP64 tables) and against
+    the oracle."""
+    s = S.large_random_system(N=2100, K=12, cfg_index=7)
+    s.E = np.repeat(s.E[0::2], 2)
+    s.level_of_channel = (np.arange(s.N) // 2).astype(np.int32)
+    s.n_levels = s.N // 2
+    n = np.arange(0, s.N, 2, dtype=np.int32)
+    s.jx_row = np.concatenate([n, n + 1])
+    s.jx_col = np.concatenate([n + 1, n])
+    s.jx_val = np.tile(0.5 + 0.25 * np.cos(n), 2)
+    rng = np.random.default_rng(21)
+    b = S.mc_batch(s, 3, 600.0, 6.0, [0, 1000, 2099], rng, n_steps=12, dt=20.0,
+                   R0_bohr=0.5 * (s.R_grid[6] + s.R_grid[7]))
+    say("binned N=%d (c outside LDS), %d trajectories x %d steps" % (s.N, b.B, 12))
+    sid = ctx.load_system(s, storage="C128")
+    gb = run(ctx, sid, s, b, "binned")
+    gg = run(ctx, sid, s, b, "gemv")
+    ctx.free_system(sid)
+    d = np.max(np.abs(gb["P"] - gg["P"]))
+    say("  max|P_binned - P_gemv| = %.3e" % d)
+    assert d < 1e-12
+    assert np.max(np.abs(gb["classical"] - gg["classical"]) / (1 + np.abs(gg["classical"]))) < 1e-12
+    o = oracle.OracleSystem(s).propagate(b.subset([1]))
+    assert np.max(np.abs(gb["P"][1] - o["P"][0])) < 1e-9
