@@ -44,7 +44,7 @@ struct BinWS {
   int B, N, Npad, K;
   const TrajIn* traj;     // [B], batch order
   double2* a0;            // [B][Npad] amplitudes at the start of the step
-  double2* kv;            // [B][Npad] derivative of the last stage
+  double2* cur;           // [B][Npad] amplitudes at the current stage, a0 + cf k
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
   double2* c64;           // [B][Npad] c = e^{-iEt} a of the stage in the combine, FP64,
                           // when Npad is too large for LDS
@@ -89,7 +89,7 @@ bin_init(BinWS ws, const DevSystem* __restrict__ systems, const double* __restri
     }
     const int64_t o = (int64_t)b * Npad + n;
     ws.a0[o] = v;
-    ws.kv[o] = make_double2(0.0, 0.0);
+    ws.cur[o] = v;
     ws.acc[o] = make_double2(0.0, 0.0);
   }
   if (threadIdx.x == 0) {
@@ -158,8 +158,9 @@ __device__ __forceinline__ void put_cols(const BinWS& ws, int b, int Npad, int n
 
 // Stage state of every trajectory for the first stage of the run and for the
 // final diagnostic evaluation (diag = 1, at the end state): classical stage
-// values, interval and weights, the c columns, and the knot counts.  Every
-// other stage is prepared by the combine of the stage before it.
+// values, interval and weights, the stage amplitudes and c columns, and the
+// knot counts.  Both begin a step (st = 0), where the stage amplitudes are a0.
+// Every other stage is prepared by the combine of the stage before it.
 template <typename S, bool CPLX>
 __global__ void __launch_bounds__(NT)
 bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int diag) {
@@ -184,11 +185,11 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
     const int64_t o = (int64_t)b * Npad + n;
     double2 c = make_double2(0.0, 0.0);
     if (n < N) {
-      const double2 a = ws.a0[o], k = ws.kv[o];
-      const double2 cur = make_double2(fma(cf, k.x, a.x), fma(cf, k.y, a.y));
+      const double2 a = ws.a0[o];
+      ws.cur[o] = a;
       double sn, cs;
       sincos(sy.E[n] * t, &sn, &cs);
-      c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+      c = make_double2(cs * a.x + sn * a.y, cs * a.y - sn * a.x);
     }
     put_cols<S, CPLX>(ws, b, Npad, n, c);
   }
@@ -488,7 +489,6 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   const DevSystem sy = systems[tj.sys];
   const int N = sy.N, Npad = sy.Npad;
   const double mu = sy.mu, h = tj.dt;
-  const double cf = diag ? 0.0 : stage_frac(st) * h;
   double ys[4];
   for (int i = 0; i < 4; ++i) ys[i] = ws.ysb[b * 4 + i];
   const double t = ws.tst[b];
@@ -501,9 +501,7 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   // c = e^{-iEt} (a0 + cf k) of this stage, for the products with J_x; the
   // rotational energy and the norm
   for (int n = threadIdx.x; n < N; n += NT) {
-    const int64_t o = (int64_t)b * Npad + n;
-    const double2 a = ws.a0[o], k = ws.kv[o];
-    const double2 cur = make_double2(fma(cf, k.x, a.x), fma(cf, k.y, a.y));
+    const double2 cur = ws.cur[(int64_t)b * Npad + n];
     double sn, cs;
     sincos(sy.E[n] * t, &sn, &cs);
     cb[n] = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
@@ -565,7 +563,6 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
       double2 ac = st == 0 ? make_double2(0.0, 0.0) : ws.acc[o];
       ac.x = fma(wgt, k.x, ac.x);
       ac.y = fma(wgt, k.y, ac.y);
-      ws.kv[o] = k;
       double2 base = a;
       if (st == 3) {
         const double h6 = h / 6.0;
@@ -577,6 +574,7 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
       if (next) {
         // the following stage's amplitudes and c columns
         const double2 curn = make_double2(fma(cfn, k.x, base.x), fma(cfn, k.y, base.y));
+        ws.cur[o] = curn;
         double snn = sn, csn = cs;
         if (!same_t) sincos(sy.E[n] * tn, &snn, &csn);
         put_cols<S, CPLX>(ws, b, Npad, n, make_double2(csn * curn.x + snn * curn.y,
@@ -671,7 +669,7 @@ inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
   const size_t v = (size_t)B * Npad;
   size_t s = 0;
-  s += 4 * al(v * 16);                    // a0, kv, acc, c64
+  s += 4 * al(v * 16);                    // a0, cur, acc, c64
   s += al(v * 2 * 2 * (fp32 ? 4 : 8));    // cst (two real columns, complex worst case)
   s += al(2 * v * 4 * (fp32 ? 4 : 8));    // uv
   s += 4 * al((size_t)B * 32);            // ycl kcl acl ysb
@@ -695,7 +693,7 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   auto take = [&](size_t bytes) { void* q = p; p += al(bytes); return q; };
   const size_t v = (size_t)B * hs.Npad;
   ws.a0 = (double2*)take(v * 16);
-  ws.kv = (double2*)take(v * 16);
+  ws.cur = (double2*)take(v * 16);
   ws.acc = (double2*)take(v * 16);
   ws.c64 = (double2*)take(v * 16);
   ws.cst = take(v * 2 * 2 * (fp32 ? 4 : 8));
