@@ -97,7 +97,7 @@ def main():
         print(json.dumps(read_bandwidth_probe()), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(trajectories shard trivially; see the design notes). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -45,7 +45,7 @@ enum {
   MQCT_ERR_NOT_HERMITIAN = -3, /* |M - M^H| > 1e-12 max|M| at some knot                */
   MQCT_ERR_OOM = -4,           /* device allocation failed                             */
   MQCT_ERR_DEVICE = -5,        /* a HIP runtime call failed                            */
-  MQCT_ERR_UNSUPPORTED = -6,   /* a valid request this build does not implement        */
+  MQCT_ERR_UNSUPPORTED = -6,   /* a valid request the library does not implement      */
   MQCT_ERR_STATE = -7          /* call out of order (e.g. unknown system id)           */
 };
 
