@@ -137,7 +137,7 @@ struct Adj {
     constexpr bool ell = ELL;
     const int nst = ell ? sy.ell_w : N;
     const double mu = sy.mu, R = Y.y[0], pphi = Y.y[3];
-    const Spl sp = spline_at(sy.R, sy.K, R);
+    const Spl sp = spline_at(sy.R, sy.K, R, sy.R_inv_h);
     double w[4], d[4], dd[4];
     weights(sp, w, d, dd, R, sy.R, sy.K);
     const double om = pphi / (mu * R * R);
@@ -193,7 +193,7 @@ struct Adj {
     constexpr bool ell = ELL;
     const int nst = ell ? sy.ell_w : N;
     const double mu = sy.mu, R = Y.y[0], pphi = Y.y[3];
-    const Spl sp = spline_at(sy.R, sy.K, R);
+    const Spl sp = spline_at(sy.R, sy.K, R, sy.R_inv_h);
     double w[4], d[4], dd[4];
     weights(sp, w, d, dd, R, sy.R, sy.K);
     const double om = pphi / (mu * R * R);

@@ -280,6 +280,14 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   SysHost sh;
   sh.dev.N = N; sh.dev.K = K; sh.dev.Npad = Npad; sh.dev.dtype = d->storage;
   sh.dev.jx_w = W; sh.dev.mu = d->mu; sh.dev.knot_stride = (int64_t)N * Npad;
+  {
+    // a uniform grid lets the interval lookup start from a guess one step off at most
+    const double hu = (d->R_grid[K - 1] - d->R_grid[0]) / (K - 1);
+    bool uniform = true;
+    for (int k = 0; k < K && uniform; ++k)
+      uniform = fabs(d->R_grid[k] - (d->R_grid[0] + k * hu)) <= 1e-9 * hu;
+    sh.dev.R_inv_h = uniform ? 1.0 / hu : 0.0;
+  }
   sh.table_bytes = 2 * store_elems * es;
 
   double* din = nullptr;

@@ -17,7 +17,11 @@ struct Spl {
   double w0, w1, w2, w3, d0, d1, d2, d3;
 };
 
-__device__ __forceinline__ Spl spline_at(const double* __restrict__ x, int K, double R) {
+// inv_h > 0: the knots are uniform with spacing 1 / inv_h, and the interval is
+// found from a guess and at most a step or two of correction instead of a
+// binary search (the same k: the largest one in [0, K-2] with x[k] <= R).
+__device__ __forceinline__ Spl spline_at(const double* __restrict__ x, int K, double R,
+                                         double inv_h = 0.0) {
   Spl s;
   s.below = R < x[0];
   if (R > x[K - 1]) {
@@ -28,10 +32,16 @@ __device__ __forceinline__ Spl spline_at(const double* __restrict__ x, int K, do
   }
   int lo = 0;
   if (!s.below) {
-    int hi = K - 2;           // largest k in [0, K-2] with x[k] <= R
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (x[mid] <= R) lo = mid; else hi = mid - 1;
+    if (inv_h > 0.0) {
+      lo = min(max((int)((R - x[0]) * inv_h), 0), K - 2);
+      while (lo > 0 && x[lo] > R) --lo;
+      while (lo < K - 2 && x[lo + 1] <= R) ++lo;
+    } else {
+      int hi = K - 2;           // largest k in [0, K-2] with x[k] <= R
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (x[mid] <= R) lo = mid; else hi = mid - 1;
+      }
     }
   }
   s.k = lo;

@@ -36,6 +36,7 @@ struct DevSystem {
   const double* drv;         // [K] driving potential U(R_k) of decoupled (AT) dynamics, or null
   const double* drv2;        // [K] its natural-spline second derivatives
   int64_t knot_stride;       // N * Npad elements
+  double R_inv_h;            // 1 / spacing when the R grid is uniform, else 0
 };
 
 // Per-trajectory launch record.

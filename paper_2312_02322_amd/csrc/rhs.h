@@ -187,7 +187,7 @@ struct Rhs {
                               double2 (&cur)[NR], Sums& tot, bool& below, const Lds<DT>& lds,
                               bool at = false) {
     const int N = sy.N, Npad = sy.Npad;
-    const Spl sp = spline_at(sy.R, sy.K, R);
+    const Spl sp = spline_at(sy.R, sy.K, R, sy.R_inv_h);
     below |= sp.below;
     const double phidot = uni(pphi / (sy.mu * R * R));
 
