@@ -125,7 +125,7 @@ __global__ void bin_zero(int* p, int n) {
 // and its entries in the counts of its two knots (one thread).
 __device__ __forceinline__ void stage_setup(const BinWS& ws, const DevSystem& sy, int b,
                                             const double (&ys)[4], double t, bool count_below) {
-  const Spl sp = spline_at(sy.R, sy.K, ys[0]);
+  const Spl sp = spline_at(sy.R, sy.K, ys[0], sy.R_inv_h);
   for (int i = 0; i < 4; ++i) ws.ysb[b * 4 + i] = ys[i];
   double* w = ws.wts + (int64_t)b * 8;
   w[0] = sp.w0; w[1] = sp.w1; w[2] = sp.w2; w[3] = sp.w3;
