@@ -160,3 +160,33 @@ def test_binned_wide_system_c_outside_lds(ctx):
     assert np.max(np.abs(gb["classical"] - gg["classical"]) / (1 + np.abs(gg["classical"]))) < 1e-12
     o = oracle.OracleSystem(s).propagate(b.subset([1]))
     assert np.max(np.abs(gb["P"][1] - o["P"][0])) < 1e-9
+
+
+@pytest.mark.parametrize("schedule", ["binned", "gemv"])
+def test_trajectory_that_overflows_stops_alone(ctx, schedule):
+    """Initial amplitudes of 1e200 in one trajectory overflow its norm and force in the
+    first step: it stops after that step with the non-finite status bit, while the
+    others sharing its bins run on as they do without it."""
+    (s,), b = S.config1(n_traj=4, n_steps=40)
+    say("%s: one overflowing trajectory among 4 (N=%d)" % (schedule, s.N))
+    sid = ctx.load_system(s)
+    a0 = np.zeros((b.B, s.N), np.complex128)
+    a0[np.arange(b.B), b.init_channel] = 1.0
+    a0[2, b.init_channel[2]] = 1e200
+    kw = dict(E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt, n_steps=b.n_steps, schedule=schedule)
+    g = ctx.run_host([sid] * b.B, [s.N] * b.B, a0=a0.reshape(-1), **kw)
+    keep = [0, 1, 3]
+    ref = ctx.run_host([sid] * 3, [s.N] * 3, a0=a0[keep].reshape(-1),
+                       **{k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in kw.items()})
+    ctx.free_system(sid)
+    nonfinite = gpu_status_bit("NONFINITE")
+    assert g["status"][2] & nonfinite and g["steps"][2] == 1
+    for i in keep:
+        assert not g["status"][i] & nonfinite and g["steps"][i] == b.n_steps[i]
+    P = g["P"].reshape(b.B, s.N)[keep]
+    assert np.max(np.abs(P - ref["P"].reshape(3, s.N))) == 0.0
+
+
+def gpu_status_bit(name):
+    import paper_2312_02322_amd as mq
+    return mq.STATUS[name]
