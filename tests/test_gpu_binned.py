@@ -162,11 +162,13 @@ def test_binned_wide_system_c_outside_lds(ctx):
     assert np.max(np.abs(gb["P"][1] - o["P"][0])) < 1e-9
 
 
-@pytest.mark.parametrize("schedule", ["binned", "gemv"])
+@pytest.mark.parametrize("schedule", ["binned", "gemv", "queue"])
 def test_trajectory_that_overflows_stops_alone(ctx, schedule):
     """Initial amplitudes of 1e200 in one trajectory overflow its norm and force in the
     first step: it stops after that step with the non-finite status bit, while the
-    others sharing its bins run on as they do without it."""
+    others (sharing its bins, on the binned schedule) run on as they do without it:
+    bit for bit on the binned and per-trajectory schedules; on the work-list
+    schedule, whose workgroup shape may change with the batch, to rounding."""
     (s,), b = S.config1(n_traj=4, n_steps=40)
     say("%s: one overflowing trajectory among 4 (N=%d)" % (schedule, s.N))
     sid = ctx.load_system(s)
@@ -184,7 +186,8 @@ def test_trajectory_that_overflows_stops_alone(ctx, schedule):
     for i in keep:
         assert not g["status"][i] & nonfinite and g["steps"][i] == b.n_steps[i]
     P = g["P"].reshape(b.B, s.N)[keep]
-    assert np.max(np.abs(P - ref["P"].reshape(3, s.N))) == 0.0
+    tol = 1e-13 if schedule == "queue" else 0.0
+    assert np.max(np.abs(P - ref["P"].reshape(3, s.N))) <= tol
 
 
 def gpu_status_bit(name):
