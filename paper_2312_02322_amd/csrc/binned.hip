@@ -717,7 +717,6 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   ws.n_items = (int*)take(16);
   ws.occ = (unsigned long long*)take(16);
 
-  const bool cplx = dtype_complex(hs.dtype);
   const int rows_per_block = 2 * 4 * 16;
   const int nrb = (hs.N + rows_per_block - 1) / rows_per_block;
   const int64_t gblocks = (int64_t)(max_items + NXCD - 1) / NXCD * nrb * NXCD;
@@ -759,7 +758,6 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
     else combine(0.0, std::false_type{}, j, st, diag, next);
     return hipGetLastError();
   };
-  (void)cplx;
   // the first stage is prepared on its own, every later one by the combine of
   // the stage before it, the final diagnostic evaluation on its own again
   if (max_steps > 0) prep(0, 0, 0);
