@@ -488,8 +488,6 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_QUEUE)
     return fail(c, MQCT_ERR_ARG, "run: unknown schedule %d", bd->schedule);
   const bool binned = bd->schedule == MQCT_SCHED_BINNED;
-  if (binned && bd->integrator != MQCT_RK4)
-    return fail(c, MQCT_ERR_UNSUPPORTED, "run: the binned schedule steps in lockstep (RK4 only)");
   if (binned) {
     for (int64_t b = 1; b < B; ++b)
       if (bd->system_id[b] != bd->system_id[0])
@@ -501,8 +499,9 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
                   "run: the binned schedule multiplies dense tables (system %d is sparse)", sid0);
   }
   const bool dp5 = bd->integrator == MQCT_DP5;
-  // DP5 always runs on the work-list schedule (trajectory lengths differ)
-  const bool queue = dp5 || bd->schedule == MQCT_SCHED_QUEUE;
+  // DP5 runs on the work-list schedule (trajectory lengths differ) unless the
+  // binned schedule is asked for
+  const bool queue = (dp5 && !binned) || bd->schedule == MQCT_SCHED_QUEUE;
   if (dp5) {
     if (!(bd->rtol > 0.0) || !(bd->atol > 0.0) || bd->max_steps < 1 || !(bd->h_min >= 0.0))
       return fail(c, MQCT_ERR_ARG, "run: DP5 needs rtol > 0, atol > 0, max_steps >= 1, h_min >= 0");
@@ -675,7 +674,17 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   out.status = (int32_t*)dp[6]; out.norm_err = (double*)dp[7]; out.energy_err = (double*)dp[8];
   out.angmom_err = (double*)dp[9];
 
-  if (binned) {
+  if (binned && dp5) {
+    const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
+    if (B > INT32_MAX) return fail(c, MQCT_ERR_UNSUPPORTED, "run: B too large for the binned schedule");
+    const DpCtl ctl{bd->rtol, bd->atol, bd->h_min, bd->max_steps};
+    const int64_t max_attempts = 4 * bd->max_steps + 256;
+    const size_t wsb = binned_dp5_workspace_bytes((int)B, hs.Npad, hs.K, dtype_fp32(hs.dtype));
+    if ((st = ensure(c, c->binws, wsb, "run: binned workspace")) != MQCT_OK) return st;
+    hipError_t e = run_binned_dp5(c->d_systems, hs, (const TrajIn*)c->traj.p, (int)B, d_a0, out,
+                                  ctl, max_attempts, c->binws.p, c->stream, &c->prof);
+    if (e != hipSuccess) return hip_fail(c, e, "run: binned DP5");
+  } else if (binned) {
     const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
     int64_t max_steps = 0;
     for (int64_t b = 0; b < B; ++b) max_steps = std::max(max_steps, c->h_traj[b].n_steps);

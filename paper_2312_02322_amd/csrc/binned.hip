@@ -664,6 +664,386 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
 
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+
+// ---- adaptive Dormand-Prince 5(4) on the binned product ----------------------
+//
+// Every unfinished trajectory makes one step attempt per round: six stage
+// evaluations (the first stage is the last one of the previous accepted step),
+// each a binned product as above, then the embedded error estimate and the
+// accept/reject decision.  Tableau, error norm, controller, starting step and
+// stopping rules are those of the work-list schedule's adaptive stepper (scaled
+// RMS over the 2N + 6 real state components; factor min(5, max(0.2,
+// 0.9 err^-1/5)), no growth right after a rejection; starting step of Hairer,
+// Norsett and Wanner, Solving ODEs I, Sec. II.4; exit after the first accepted
+// step with R >= R0 and P_R > 0).  Finished trajectories leave the bins.
+
+__constant__ double D5C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+__constant__ double D5A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+__constant__ double D5E[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920,
+                              -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
+
+enum { D5_INIT0 = 0, D5_INIT1 = 1, D5_STAGE = 2, D5_DIAG = 3 };
+enum { D5_DONE = 1, D5_LASTREJ = 2 };
+
+struct D5WS {
+  double2* ks;            // [B][8][Npad]: stage derivatives k_1..k_7 in slots 0..6, y5 in 7
+  double* kc;             // [B][8][4]: the classical ones, y5 of R, Phi, P_R, P_Phi in 7
+  double* h;              // [B] step of the next attempt (the starting step while starting)
+  double* t;              // [B] time of the current state
+  double* rexit;          // [B] exit radius (the starting R)
+  long long* steps;       // [B] accepted steps
+  long long* rejects;     // [B]
+  long long* attempts;    // [B]
+  int* flags;             // [B]
+  int* active;            // [1] unfinished trajectories after the last counted round
+};
+
+// Stage input of every unfinished trajectory (all of them for the final
+// evaluation): amplitudes and classical state, the stage time, interval,
+// weights, knot counts and c columns.
+template <typename S, bool CPLX>
+__global__ void __launch_bounds__(NT)
+d5_prep(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, int mode, int sg) {
+  const int b = blockIdx.x;
+  if (mode != D5_DIAG && (d.flags[b] & D5_DONE)) {
+    if (threadIdx.x == 0) ws.kb[b] = -1;
+    return;
+  }
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const double h = d.h[b], t0 = d.t[b];
+  const double2* ks = d.ks + (int64_t)b * 8 * Npad;
+  const double* kc = d.kc + (int64_t)b * 32;
+  const double* yc = ws.ycl + (int64_t)b * 4;
+  double ys[4];
+  double ts = t0;
+  if (mode == D5_INIT1) {
+    for (int k = 0; k < 4; ++k) ys[k] = fma(h, kc[k], yc[k]);
+    ts = t0 + h;
+  } else if (mode == D5_STAGE) {
+    for (int k = 0; k < 4; ++k) {
+      double acc = fma(h * D5A[sg][0], kc[k], yc[k]);
+      for (int p = 1; p < sg; ++p) acc = fma(h * D5A[sg][p], kc[p * 4 + k], acc);
+      ys[k] = acc;
+    }
+    ts = t0 + D5C[sg] * h;
+  } else {
+    for (int k = 0; k < 4; ++k) ys[k] = yc[k];
+  }
+  if (threadIdx.x == 0) {
+    stage_setup(ws, sy, b, ys, ts, mode != D5_DIAG);
+    if (mode == D5_STAGE && sg == 6)
+      for (int k = 0; k < 4; ++k) d.kc[(int64_t)b * 32 + 28 + k] = ys[k];
+  }
+  for (int n = threadIdx.x; n < Npad; n += NT) {
+    const int64_t o = (int64_t)b * Npad + n;
+    double2 c = make_double2(0.0, 0.0);
+    if (n < N) {
+      double2 cur = ws.a0[o];
+      if (mode == D5_INIT1) {
+        const double2 k = ks[n];
+        cur = make_double2(fma(h, k.x, cur.x), fma(h, k.y, cur.y));
+      } else if (mode == D5_STAGE) {
+        for (int p = 0; p < sg; ++p) {
+          const double2 kp = ks[(int64_t)p * Npad + n];
+          const double cc = h * D5A[sg][p];
+          cur.x = fma(cc, kp.x, cur.x);
+          cur.y = fma(cc, kp.y, cur.y);
+        }
+        if (sg == 6) d.ks[((int64_t)b * 8 + 7) * Npad + n] = cur;
+      }
+      ws.cur[o] = cur;
+      double sn, cs;
+      sincos(sy.E[n] * ts, &sn, &cs);
+      c = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+    }
+    put_cols<S, CPLX>(ws, b, Npad, n, c);
+  }
+}
+
+// Right-hand side of the stage from the two knots' products: the amplitude
+// derivative into slot `slot`, the classical one into kc; at the first
+// evaluation also the conserved quantities' starting values; at the final
+// evaluation the results.
+template <typename S, bool CPLX, bool LDSC>
+__global__ void __launch_bounds__(NT)
+d5_combine(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, int mode, int slot,
+           TrajOut out) {
+  extern __shared__ double2 c_lds[];
+  __shared__ double red[NWT * 8];
+  const int b = blockIdx.x;
+  if (ws.kb[b] < 0) return;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const double mu = sy.mu;
+  double ys[4];
+  for (int i = 0; i < 4; ++i) ys[i] = ws.ysb[b * 4 + i];
+  const double t = ws.tst[b];
+  const double R = ys[0];
+  const double phidot = ys[3] / (mu * R * R);
+  double2* cb = LDSC ? c_lds : ws.c64 + (int64_t)b * Npad;
+  double sums[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int n = threadIdx.x; n < N; n += NT) {
+    const double2 cur = ws.cur[(int64_t)b * Npad + n];
+    double sn, cs;
+    sincos(sy.E[n] * t, &sn, &cs);
+    cb[n] = make_double2(cs * cur.x + sn * cur.y, cs * cur.y - sn * cur.x);
+    const double pn = cur.x * cur.x + cur.y * cur.y;
+    sums[3] += sy.E[n] * pn;
+    sums[4] += pn;
+  }
+  __syncthreads();
+  const double* wt = ws.wts + (int64_t)b * 8;
+  const double w0 = wt[0], w1 = wt[1], w2 = wt[2], w3 = wt[3];
+  const double d0 = wt[4], d1 = wt[5], d2 = wt[6], d3 = wt[7];
+  using S4 = typename std::conditional<sizeof(S) == 4, float4, double4>::type;
+  const S4* uvl = (const S4*)ws.uv;
+  double2* kout = d.ks + ((int64_t)b * 8 + slot) * Npad;
+  for (int n = threadIdx.x; n < N; n += NT) {
+    const int64_t o = (int64_t)b * Npad + n;
+    const S4 L = uvl[o], Rr = uvl[(int64_t)ws.B * Npad + o];
+    const double2 u = make_double2((w0 * (double)L.x + w2 * (double)L.y) +
+                                       (w1 * (double)Rr.x + w3 * (double)Rr.y),
+                                   (w0 * (double)L.z + w2 * (double)L.w) +
+                                       (w1 * (double)Rr.z + w3 * (double)Rr.w));
+    const double2 v = make_double2((d0 * (double)L.x + d2 * (double)L.y) +
+                                       (d1 * (double)Rr.x + d3 * (double)Rr.y),
+                                   (d0 * (double)L.z + d2 * (double)L.w) +
+                                       (d1 * (double)Rr.z + d3 * (double)Rr.w));
+    const double2 c = cb[n];
+    double2 xc = make_double2(0.0, 0.0);
+    for (int qq = 0; qq < sy.jx_w; ++qq) {
+      const int col = sy.jx_col[(int64_t)n * sy.jx_w + qq];
+      const double jv = sy.jx_val[(int64_t)n * sy.jx_w + qq];
+      const double2 cm = cb[col];
+      xc.x = fma(jv, cm.x, xc.x);
+      xc.y = fma(jv, cm.y, xc.y);
+    }
+    sums[0] += c.x * v.x + c.y * v.y;
+    sums[1] += xc.x * u.y - xc.y * u.x;
+    sums[2] += c.x * u.x + c.y * u.y;
+    sums[5] += c.x * xc.x + c.y * xc.y;
+    if (mode != D5_DIAG) {
+      double sn, cs;
+      sincos(sy.E[n] * t, &sn, &cs);
+      const double gx = u.x + phidot * xc.x, gy = u.y + phidot * xc.y;
+      const double yx = cs * gx - sn * gy, yy = cs * gy + sn * gx;
+      kout[n] = make_double2(yy, -yx);
+    }
+  }
+  block_sum<6, NWT>(sums, red);
+  if (tj.flags & TRAJ_AT) {
+    const int k = ws.kb[b];
+    sums[2] = w0 * sy.drv[k] + w1 * sy.drv[k + 1] + w2 * sy.drv2[k] + w3 * sy.drv2[k + 1];
+    sums[0] = d0 * sy.drv[k] + d1 * sy.drv[k + 1] + d2 * sy.drv2[k] + d3 * sy.drv2[k + 1];
+    sums[1] = sums[3] = sums[5] = 0.0;
+  }
+  const double force = sums[0], torque = sums[1], vexp = sums[2], erot = sums[3];
+  const double norm = sums[4], jx = sums[5];
+  const double E = ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * R * R) + erot + vexp;
+  if (mode == D5_DIAG) {
+    for (int n = threadIdx.x; n < N; n += NT) {
+      const double2 a = ws.a0[(int64_t)b * Npad + n];
+      out.P[tj.amp_off + n] = a.x * a.x + a.y * a.y;
+      if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a;
+    }
+    if (threadIdx.x == 0) {
+      const int64_t id = tj.id;
+      if (out.classical) {
+        double* o = out.classical + id * 6;
+        o[0] = ys[0]; o[1] = ws.diag[b * 4 + 2]; o[2] = ys[1]; o[3] = ys[2];
+        o[4] = ws.diag[b * 4 + 3]; o[5] = ys[3];
+      }
+      if (out.t_final) out.t_final[id] = t;
+      if (out.steps) out.steps[id] = d.steps[b];
+      if (out.rejects) out.rejects[id] = d.rejects[b];
+      if (out.status) out.status[id] = ws.status[b];
+      if (out.norm_err) out.norm_err[id] = norm - 1.0;
+      if (out.energy_err) out.energy_err[id] = (E - ws.diag[b * 4]) / fabs(ws.diag[b * 4]);
+      if (out.angmom_err) out.angmom_err[id] = (ys[3] - jx) - ws.diag[b * 4 + 1];
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    if (mode == D5_INIT0) {
+      ws.diag[b * 4] = E;
+      ws.diag[b * 4 + 1] = ys[3] - jx;
+    }
+    double* kc = d.kc + (int64_t)b * 32 + slot * 4;
+    kc[0] = ys[2] / mu;
+    kc[1] = phidot;
+    kc[2] = -force + ys[3] * ys[3] / (mu * R * R * R);
+    kc[3] = 2.0 * torque;
+  }
+}
+
+// Starting step, first half (d0 = ||y0||, d1 = ||f(t0, y0)||, h0) and second half
+// (d2 = ||f(t0 + h0, y0 + h0 f0) - f0|| / h0, then the step).
+__global__ void __launch_bounds__(NT)
+d5_start(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, double rtol, double atol,
+         int second) {
+  __shared__ double red[NWT * 8];
+  const int b = blockIdx.x;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const double ncomp = 2.0 * N + 6.0;
+  const double2* ks = d.ks + (int64_t)b * 8 * Npad;
+  double s2[2] = {0.0, 0.0};
+  for (int n = threadIdx.x; n < N; n += NT) {
+    const double2 a = ws.a0[(int64_t)b * Npad + n], f0 = ks[n];
+    const double sx = atol + rtol * fabs(a.x), sy_ = atol + rtol * fabs(a.y);
+    if (!second) {
+      s2[0] += (a.x / sx) * (a.x / sx) + (a.y / sy_) * (a.y / sy_);
+      s2[1] += (f0.x / sx) * (f0.x / sx) + (f0.y / sy_) * (f0.y / sy_);
+    } else {
+      const double2 f1 = ks[Npad + n];
+      const double ex = (f1.x - f0.x) / sx, ey = (f1.y - f0.y) / sy_;
+      s2[0] += ex * ex + ey * ey;
+    }
+  }
+  block_sum<2, NWT>(s2, red);
+  if (threadIdx.x != 0) return;
+  const double* y = ws.ycl + (int64_t)b * 4;
+  const double* kc = d.kc + (int64_t)b * 32;
+  const double yfull[6] = {y[0], ws.diag[b * 4 + 2], y[1], y[2], ws.diag[b * 4 + 3], y[3]};
+  if (!second) {
+    const double kf[6] = {kc[0], 0.0, kc[1], kc[2], 0.0, kc[3]};
+    for (int k = 0; k < 6; ++k) {
+      const double sc = atol + rtol * fabs(yfull[k]);
+      s2[0] += (yfull[k] / sc) * (yfull[k] / sc);
+      s2[1] += (kf[k] / sc) * (kf[k] / sc);
+    }
+    const double d0 = sqrt(s2[0] / ncomp), d1 = sqrt(s2[1] / ncomp);
+    d.h[b] = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    d.rexit[b] = d1;   // kept for the second half
+  } else {
+    const double dk[6] = {kc[4] - kc[0], 0.0, kc[5] - kc[1], kc[6] - kc[2], 0.0, kc[7] - kc[3]};
+    for (int k = 0; k < 6; ++k) {
+      const double sc = atol + rtol * fabs(yfull[k]);
+      s2[0] += (dk[k] / sc) * (dk[k] / sc);
+    }
+    const double h0 = d.h[b], d1 = d.rexit[b];
+    const double d2 = sqrt(s2[0] / ncomp) / h0;
+    const double dm = fmax(d1, d2);
+    const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / 5.0);
+    d.h[b] = fmin(100.0 * h0, h1);
+    d.rexit[b] = y[0];
+  }
+}
+
+// Error estimate and decision of one attempt; on acceptance the state moves to
+// y5 and k_7 becomes the next attempt's first stage.  Counts the trajectories
+// still running.
+__global__ void __launch_bounds__(NT)
+d5_accept(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, DpCtl ctl,
+          long long max_attempts) {
+  __shared__ double red[NWT * 8];
+  __shared__ int decision;
+  const int b = blockIdx.x;
+  if (d.flags[b] & D5_DONE) return;
+  const TrajIn tj = ws.traj[b];
+  const DevSystem sy = systems[tj.sys];
+  const int N = sy.N, Npad = sy.Npad;
+  const double ncomp = 2.0 * N + 6.0;
+  const double h = d.h[b];
+  double2* ks = d.ks + (int64_t)b * 8 * Npad;
+  double* kc = d.kc + (int64_t)b * 32;
+  double* yc = ws.ycl + (int64_t)b * 4;
+  double e2[1] = {0.0};
+  for (int n = threadIdx.x; n < N; n += NT) {
+    double ex = 0.0, ey = 0.0;
+    for (int p = 0; p < 7; ++p) {
+      const double2 kp = ks[(int64_t)p * Npad + n];
+      ex = fma(D5E[p], kp.x, ex);
+      ey = fma(D5E[p], kp.y, ey);
+    }
+    ex *= h; ey *= h;
+    const double2 y0 = ws.a0[(int64_t)b * Npad + n], y5 = ks[(int64_t)7 * Npad + n];
+    const double sx = ctl.atol + ctl.rtol * fmax(fabs(y0.x), fabs(y5.x));
+    const double sy_ = ctl.atol + ctl.rtol * fmax(fabs(y0.y), fabs(y5.y));
+    e2[0] += (ex / sx) * (ex / sx) + (ey / sy_) * (ey / sy_);
+  }
+  block_sum<1, NWT>(e2, red);
+  if (threadIdx.x == 0) {
+    double ecl = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      double e = D5E[0] * kc[k];
+      for (int p = 1; p < 7; ++p) e = fma(D5E[p], kc[p * 4 + k], e);
+      e *= h;
+      const double sc = ctl.atol + ctl.rtol * fmax(fabs(yc[k]), fabs(kc[28 + k]));
+      ecl += (e / sc) * (e / sc);
+    }
+    const double en = sqrt((e2[0] + ecl) / ncomp);
+    int flags = d.flags[b];
+    d.attempts[b] += 1;
+    bool done = false, accept = false;
+    double hn = h;
+    if (!isfinite(en)) {
+      ws.status[b] |= ST_NONFINITE;
+      done = true;
+    } else if (en <= 1.0) {
+      accept = true;
+      d.t[b] += h;
+      for (int k = 0; k < 4; ++k) {
+        yc[k] = kc[28 + k];
+        kc[k] = kc[24 + k];
+      }
+      d.steps[b] += 1;
+      double fac = en == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(en, -0.2)));
+      if (flags & D5_LASTREJ) fac = fmin(1.0, fac);
+      flags &= ~D5_LASTREJ;
+      if (yc[0] >= d.rexit[b] && yc[2] > 0.0) {
+        ws.status[b] |= ST_EXITED;
+        done = true;
+      } else {
+        hn = h * fac;
+      }
+    } else {
+      d.rejects[b] += 1;
+      hn = h * fmax(0.2, 0.9 * pow(en, -0.2));
+      flags |= D5_LASTREJ;
+    }
+    if (!done && hn < ctl.h_min) { ws.status[b] |= ST_STEP_UNDERFLOW; done = true; }
+    if (!done && d.steps[b] >= ctl.max_steps) { ws.status[b] |= ST_MAX_STEPS; done = true; }
+    if (!done && d.attempts[b] >= max_attempts) { ws.status[b] |= ST_MAX_STEPS; done = true; }
+    d.h[b] = hn;
+    if (done) flags |= D5_DONE;
+    else atomicAdd(d.active, 1);
+    d.flags[b] = flags;
+    decision = accept;
+  }
+  __syncthreads();
+  if (decision) {
+    // the accepted state y5 and the first-same-as-last stage
+    for (int n = threadIdx.x; n < N; n += NT) {
+      ws.a0[(int64_t)b * Npad + n] = ks[(int64_t)7 * Npad + n];
+      ks[n] = ks[(int64_t)6 * Npad + n];
+    }
+  }
+}
+
+__global__ void d5_init(BinWS ws, D5WS d) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ws.B) return;
+  d.t[b] = ws.traj[b].t0;
+  d.h[b] = 0.0;
+  d.rexit[b] = 0.0;
+  d.steps[b] = 0;
+  d.rejects[b] = 0;
+  d.attempts[b] = 0;
+  d.flags[b] = 0;
+}
+
 }  // namespace
 
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
@@ -682,11 +1062,11 @@ size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32) {
   return s;
 }
 
-hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
-                      int B, int64_t max_steps, const double* d_a0, TrajOut out, void* wsp,
-                      hipStream_t s, Prof* prof) {
+namespace {
+
+// Carves the schedule's buffers out of the workspace; returns the first byte past them.
+char* carve(BinWS& ws, const DevSystem& hs, const TrajIn* d_traj, int B, void* wsp) {
   const bool fp32 = dtype_fp32(hs.dtype);
-  BinWS ws;
   ws.B = B; ws.N = hs.N; ws.Npad = hs.Npad; ws.K = hs.K;
   ws.traj = d_traj;
   char* p = (char*)wsp;
@@ -716,11 +1096,36 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   ws.items = (int4*)take((size_t)max_items * 16);
   ws.n_items = (int*)take(16);
   ws.occ = (unsigned long long*)take(16);
+  return p;
+}
 
+// The product of one stage: bin offsets and work list, bin lists, products
+// (timed when profiling).
+hipError_t stage_product(BinWS& ws, const DevSystem* d_systems, const DevSystem& hs, int B,
+                         hipStream_t s, Prof* prof) {
+  const int max_items = 2 * B / TB + hs.K + 1;
   const int rows_per_block = 2 * 4 * 16;
   const int nrb = (hs.N + rows_per_block - 1) / rows_per_block;
-  const int64_t gblocks = (int64_t)(max_items + NXCD - 1) / NXCD * nrb * NXCD;
-  const dim3 ggrid((unsigned)gblocks);
+  const dim3 ggrid((unsigned)((int64_t)(max_items + NXCD - 1) / NXCD * nrb * NXCD));
+  bin_scan<<<1, 1024, 0, s>>>(ws);
+  bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
+  hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
+  prof_mark(prof, e0, s);
+  if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+  else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+  else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+  else bin_gemm<R64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
+  prof_mark(prof, e1, s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                      int B, int64_t max_steps, const double* d_a0, TrajOut out, void* wsp,
+                      hipStream_t s, Prof* prof) {
+  BinWS ws;
+  carve(ws, hs, d_traj, B, wsp);
   hipError_t e;
   bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
   bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cnt, hs.K);
@@ -743,15 +1148,8 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
     else bin_combine<S, CX, false><<<B, NT, 0, s>>>(ws, d_systems, j, st, diag, next, out);
   };
   auto stage = [&](int64_t j, int st, int diag, int next) -> hipError_t {
-    bin_scan<<<1, 1024, 0, s>>>(ws);
-    bin_scatter<<<(B + 255) / 256, 256, 0, s>>>(ws);
-    hipEvent_t e0 = prof ? prof->next() : nullptr, e1 = prof ? prof->next() : nullptr;
-    prof_mark(prof, e0, s);
-    if (hs.dtype == C64) bin_gemm<C64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
-    else if (hs.dtype == C128) bin_gemm<C128><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
-    else if (hs.dtype == R32) bin_gemm<R32><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
-    else bin_gemm<R64><<<ggrid, 256, GEMM_LDS_CAP, s>>>(ws, d_systems, nrb);
-    prof_mark(prof, e1, s);
+    hipError_t pe = stage_product(ws, d_systems, hs, B, s, prof);
+    if (pe != hipSuccess) return pe;
     if (hs.dtype == C64) combine(0.0f, std::true_type{}, j, st, diag, next);
     else if (hs.dtype == C128) combine(0.0, std::true_type{}, j, st, diag, next);
     else if (hs.dtype == R32) combine(0.0f, std::false_type{}, j, st, diag, next);
@@ -768,6 +1166,89 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
   if ((e = stage(max_steps, 0, 1, 0)) != hipSuccess) return e;
   // algorithmic table bytes of the timed products: each occupied knot's value
   // and second-derivative slices, read once per stage
+  unsigned long long* slot =
+      prof ? prof->knot_slot(2.0 * hs.N * (double)hs.Npad * dtype_bytes(hs.dtype)) : nullptr;
+  if (slot) e = hipMemcpyAsync(slot, ws.occ, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  return e;
+}
+
+size_t binned_dp5_workspace_bytes(int B, int Npad, int K, bool fp32) {
+  size_t s = binned_workspace_bytes(B, Npad, K, fp32);
+  s += al((size_t)B * 8 * Npad * 16);     // ks
+  s += al((size_t)B * 32 * 8);            // kc
+  s += 3 * al((size_t)B * 8);             // h t rexit
+  s += 3 * al((size_t)B * 8);             // steps rejects attempts
+  s += al((size_t)B * 4) + al(16);        // flags active
+  return s;
+}
+
+hipError_t run_binned_dp5(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                          int B, const double* d_a0, TrajOut out, DpCtl ctl,
+                          int64_t max_attempts, void* wsp, hipStream_t s, Prof* prof) {
+  BinWS ws;
+  char* p = carve(ws, hs, d_traj, B, wsp);
+  auto take = [&](size_t bytes) { void* q = p; p += al(bytes); return q; };
+  D5WS d;
+  d.ks = (double2*)take((size_t)B * 8 * hs.Npad * 16);
+  d.kc = (double*)take((size_t)B * 32 * 8);
+  d.h = (double*)take((size_t)B * 8);
+  d.t = (double*)take((size_t)B * 8);
+  d.rexit = (double*)take((size_t)B * 8);
+  d.steps = (long long*)take((size_t)B * 8);
+  d.rejects = (long long*)take((size_t)B * 8);
+  d.attempts = (long long*)take((size_t)B * 8);
+  d.flags = (int*)take((size_t)B * 4);
+  d.active = (int*)take(16);
+  hipError_t e;
+  bin_init<<<B, NT, 0, s>>>(ws, d_systems, d_a0);
+  d5_init<<<(B + 255) / 256, 256, 0, s>>>(ws, d);
+  bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cnt, hs.K);
+  bin_zero<<<(hs.K + 255) / 256, 256, 0, s>>>(ws.cursor, hs.K);
+  bin_zero<<<1, 256, 0, s>>>((int*)ws.occ, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const bool ldsc = (size_t)hs.Npad * 16 <= 65536;
+  const size_t clds = ldsc ? (size_t)hs.Npad * 16 : 0;
+  auto run = [&](auto sc, auto cx) -> hipError_t {
+    using S = decltype(sc);
+    constexpr bool CX = decltype(cx)::value;
+    auto stage = [&](int mode, int sg, int slot) -> hipError_t {
+      d5_prep<S, CX><<<B, NT, 0, s>>>(ws, d, d_systems, mode, sg);
+      hipError_t pe = stage_product(ws, d_systems, hs, B, s, prof);
+      if (pe != hipSuccess) return pe;
+      if (ldsc) d5_combine<S, CX, true><<<B, NT, clds, s>>>(ws, d, d_systems, mode, slot, out);
+      else d5_combine<S, CX, false><<<B, NT, 0, s>>>(ws, d, d_systems, mode, slot, out);
+      return hipGetLastError();
+    };
+    hipError_t r;
+    if ((r = stage(D5_INIT0, 0, 0)) != hipSuccess) return r;
+    d5_start<<<B, NT, 0, s>>>(ws, d, d_systems, ctl.rtol, ctl.atol, 0);
+    if ((r = stage(D5_INIT1, 0, 1)) != hipSuccess) return r;
+    d5_start<<<B, NT, 0, s>>>(ws, d, d_systems, ctl.rtol, ctl.atol, 1);
+    // attempt rounds; the count of running trajectories is read every few rounds
+    constexpr int CHECK = 8;
+    for (int64_t a = 0; a < max_attempts; ++a) {
+      for (int sg = 1; sg < 7; ++sg)
+        if ((r = stage(D5_STAGE, sg, sg)) != hipSuccess) return r;
+      const bool check = (a % CHECK) == CHECK - 1 || a == max_attempts - 1;
+      if (check) bin_zero<<<1, 64, 0, s>>>(d.active, 1);
+      d5_accept<<<B, NT, 0, s>>>(ws, d, d_systems, ctl, (long long)max_attempts);
+      if ((r = hipGetLastError()) != hipSuccess) return r;
+      if (check) {
+        int running = 0;
+        if ((r = hipMemcpyAsync(&running, d.active, sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+          return r;
+        if ((r = hipStreamSynchronize(s)) != hipSuccess) return r;
+        if (running == 0) break;
+      }
+    }
+    return stage(D5_DIAG, 0, 0);
+  };
+  if (hs.dtype == C64) e = run(0.0f, std::true_type{});
+  else if (hs.dtype == C128) e = run(0.0, std::true_type{});
+  else if (hs.dtype == R32) e = run(0.0f, std::false_type{});
+  else e = run(0.0, std::false_type{});
+  if (e != hipSuccess) return e;
   unsigned long long* slot =
       prof ? prof->knot_slot(2.0 * hs.N * (double)hs.Npad * dtype_bytes(hs.dtype)) : nullptr;
   if (slot) e = hipMemcpyAsync(slot, ws.occ, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);

@@ -273,6 +273,15 @@ hipError_t run_binned(const DevSystem* d_systems, const DevSystem& hs, const Tra
                       int B, int64_t max_steps, const double* d_a0, TrajOut out, void* ws,
                       hipStream_t s, Prof* prof = nullptr);
 
+// Adaptive Dormand-Prince 5(4) on the binned product: one attempt per round for
+// every unfinished trajectory (same tableau, error norm, controller and stopping
+// rules as the work-list schedule's), single-system batches.
+size_t binned_dp5_workspace_bytes(int B, int Npad, int K, bool fp32);
+hipError_t run_binned_dp5(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                          int B, const double* d_a0, TrajOut out, DpCtl ctl,
+                          int64_t max_attempts, void* wsp, hipStream_t s, Prof* prof);
+
+
 // Adjoint (discrete RK4 adjoint with checkpointed recomputation).  The G_t of
 // the parametric form enter as nonzero lists: entries goff[t] .. goff[t+1]-1,
 // gent = row | col << 16, gval the values.

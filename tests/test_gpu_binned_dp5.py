@@ -1,0 +1,101 @@
+"""GPU parity of adaptive Dormand-Prince 5(4) on the binned schedule.
+
+Every unfinished trajectory makes one attempt per round, each of its six stage
+evaluations a knot-binned product on the matrix cores.  Tableau, error norm,
+controller and stopping rules are the work-list schedule's; the right-hand sides
+differ from the oracle's and the work-list schedule's only in summation order,
+so the accept/reject decisions agree except when an error estimate lands within
+rounding of 1: step counts may differ by a few steps and final probabilities
+are compared at 10 x rtol (FP64 tables) and 1e-4 (FP32 tables), as for the
+work-list schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import systems as S
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-8
+DP5 = dict(integrator="dp5", rtol=RTOL, atol=RTOL, max_steps=50000, h_min=1e-6)
+
+
+def say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context()
+    yield c
+    c.synchronize()
+    c.close()
+
+
+def start(b):
+    return dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
+
+
+def test_binned_dp5_fp64_matches_oracle_and_work_list(ctx):
+    s = S.rotor_atom_system(jmax=5)
+    rng = np.random.default_rng(20231203)
+    init = np.where(s.labels["j"] == 2)[0]
+    b = S.mc_batch(s, 12, 500.0, 10.0, init, rng, n_steps=1)
+    say("binned dp5 rotor N=%d R64 B=%d" % (s.N, b.B))
+    sid = ctx.load_system(s)
+    g = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="binned", **start(b), **DP5)
+    q = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="queue", **start(b), **DP5)
+    ctx.free_system(sid)
+    o = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=RTOL, atol=RTOL, max_steps=50000,
+                                         h_min=1e-6)
+    say("  steps binned %s work-list %s oracle %s" % (g["steps"].tolist(), q["steps"].tolist(),
+                                                      o["steps"].tolist()))
+    assert np.all(g["status"] & 1) and np.all(o["status"] & 1)            # exited
+    assert np.max(np.abs(g["steps"] - o["steps"])) <= 2
+    assert np.max(np.abs(g["steps"] - q["steps"])) <= 2
+    P = g["P"].reshape(b.B, s.N)
+    assert np.max(np.abs(P - o["P"])) < 10 * RTOL
+    assert np.max(np.abs(P - q["P"].reshape(b.B, s.N))) < 10 * RTOL
+    assert np.max(np.abs(g["t_final"] - o["t_final"]) / o["t_final"]) < 1e-3
+    assert np.max(np.abs(g["energy_err"] - o["energy_err"])) < 1e-8
+    assert np.max(np.abs(g["norm_err"] - o["norm_err"])) < 1e-8
+
+
+@pytest.mark.parametrize("storage", ["C128", "C64"])
+def test_binned_dp5_complex_tables(ctx, storage):
+    (s,), b = S.config2(n_traj=6, jmax=3)
+    say("binned dp5 config2 reduced N=%d %s B=%d" % (s.N, storage, b.B))
+    sid = ctx.load_system(s, storage=storage)
+    g = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="binned", **start(b), **DP5)
+    ctx.free_system(sid)
+    o = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=RTOL, atol=RTOL, max_steps=50000,
+                                         h_min=1e-6)
+    d = np.max(np.abs(g["P"].reshape(b.B, s.N) - o["P"]))
+    say("  steps binned %s oracle %s, max|dP| %.2e" % (g["steps"].tolist(), o["steps"].tolist(), d))
+    assert np.array_equal(g["status"] & 1, o["status"] & 1)
+    assert d < (10 * RTOL if storage == "C128" else 1e-4)
+    if storage == "C128":
+        assert np.max(np.abs(g["steps"] - o["steps"])) <= 2
+
+
+def test_binned_dp5_stopping_rules(ctx):
+    """A step limit and a step floor stop trajectories with the work-list
+    schedule's status bits and counts."""
+    s = S.rotor_atom_system(jmax=3)
+    rng = np.random.default_rng(7)
+    b = S.mc_batch(s, 5, 500.0, 8.0, np.arange(4), rng, n_steps=1)
+    sid = ctx.load_system(s)
+    for kw in (dict(DP5, max_steps=10), dict(DP5, rtol=1e-30, atol=1e-30, h_min=1e-3)):
+        g = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="binned", **start(b), **kw)
+        q = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="queue", **start(b), **kw)
+        say("  limits %s: status binned %s work-list %s, steps %s %s" % (
+            {k: kw[k] for k in ("max_steps", "h_min", "rtol")}, g["status"].tolist(),
+            q["status"].tolist(), g["steps"].tolist(), q["steps"].tolist()))
+        assert np.array_equal(g["status"], q["status"])
+        assert np.array_equal(g["steps"], q["steps"])
+        assert np.max(np.abs(g["rejects"] - q["rejects"])) <= 1
+    ctx.free_system(sid)
