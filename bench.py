@@ -84,6 +84,10 @@ def main():
                     help="run only the first windows of the collision (0: all)")
     ap.add_argument("--uneven-traj", type=int, default=20000)
     ap.add_argument("--uneven-max-steps", type=int, default=100000)
+    ap.add_argument("--uneven-schedule", choices=["mixed", "queue"], default="mixed",
+                    help="uneven workload: the N=969 class on the binned schedule (adaptive "
+                         "steps on the matrix cores) and the rest on the work list (mixed), or "
+                         "everything in one work-list call (queue)")
     ap.add_argument("--uneven-layout", choices=["dense", "sparse"], default="sparse",
                     help="sparse: systems whose tables are mostly structural zeros keep only the "
                          "nonzeros (drop_below = 0, the same results)")
@@ -697,8 +701,25 @@ def uneven_workload(args):
                  R0=b.R0[w], max_steps=50, **DP)
     log("uneven: autotuner %s" % ctx.tuning_report())
     torch.cuda.synchronize()
+    big_sys = int(np.argmax([x.N for x in systems]))
+    parts = {}
     t1 = time.time()
-    g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, **start, **DP)
+    if args.uneven_schedule == "queue":
+        g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, **start, **DP)
+    else:
+        # the largest system alone on the binned schedule, the others on the work list
+        g = {}
+        for name, m, sched in (("work_list", b.system_index != big_sys, "queue"),
+                               ("binned", b.system_index == big_sys, "binned")):
+            ta = time.time()
+            part = ctx.run_host(sids[m], Ns[m], max_steps=args.uneven_max_steps, schedule=sched,
+                                **{k: v[m] for k, v in start.items()}, **DP)
+            parts[name] = {"seconds": time.time() - ta, "trajectories": int(m.sum()),
+                           "steps": int(part["steps"].sum())}
+            for k in ("steps", "rejects", "status"):
+                if k not in g:
+                    g[k] = np.zeros(b.B, part[k].dtype)
+                g[k][m] = part[k]
     sec = time.time() - t1
     steps, rej = g["steps"], g["rejects"]
     evals = 6 * (steps + rej) + 3          # attempts x 6, the two starting evaluations, the end
@@ -721,8 +742,11 @@ def uneven_workload(args):
             "data": "synthetic",
             "config": {"workload": "uneven batch of %d trajectories: N=49/256/969 systems "
                                    "60/30/10 %%, E_coll log-uniform 10-5000 cm^-1, DP5 rtol 1e-8, "
-                                   "FP32 tables (%s layout where mostly zero), "
-                                   "work-list schedule" % (b.B, args.uneven_layout),
+                                   "FP32 tables (%s layout where mostly zero), %s" % (
+                                       b.B, args.uneven_layout,
+                                       "work-list schedule" if args.uneven_schedule == "queue"
+                                       else "N=969 on the binned schedule, the rest on the "
+                                            "work list"),
                        "trajectories": b.B},
             "N2_traj_steps_per_s": float(np.sum(steps * Ns.astype(float) ** 2)) / sec,
             "coupling_GBps": gbps,
@@ -730,8 +754,20 @@ def uneven_workload(args):
                          "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                          "frac": gbps / HBM_PEAK_GBPS, "traffic": None},
             "per_system": per, "autotuner": ctx.tuning_report()}
-    log("uneven: %.1f s, %d steps, %.3g traj-steps/s, %.0f GB/s coupling" % (
-        sec, int(steps.sum()), line["value"], gbps))
+    if parts:
+        # per-trajectory algorithmic bytes over the work-list call only: the binned
+        # call reads each occupied knot once per stage for all its trajectories
+        m = b.system_index != big_sys
+        wl_bytes = float(np.sum(evals[m] * np.array([rhs_bytes[i] for i in b.system_index[m]])))
+        wl_gbps = wl_bytes / parts["work_list"]["seconds"] / 1e9
+        line["roofline"] = {"kernel": "q_step (work-list classes, incl. tail)", "bound": "hbm",
+                            "achieved": wl_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "frac": wl_gbps / HBM_PEAK_GBPS, "traffic": None}
+        line["calls"] = parts
+        del line["coupling_GBps"]
+    log("uneven: %.1f s, %d steps, %.3g traj-steps/s, %s" % (
+        sec, int(steps.sum()), line["value"], json.dumps(parts) if parts else
+        "%.0f GB/s coupling" % gbps))
     ctx.close()
     if not args.no_cpu:
         line["cpu_baseline"] = uneven_cpu_baseline(systems, b)

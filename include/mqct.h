@@ -74,11 +74,13 @@ enum {
   MQCT_SCHED_AUTO = 0,        /* library chooses                                        */
   MQCT_SCHED_GEMV = 1,        /* one workgroup per trajectory, step loop inside a kernel */
   MQCT_SCHED_BINNED = 2,      /* lockstep stages, trajectories binned by spline knot,
-                                 table x amplitude-columns products on matrix cores    */
+                                 table x amplitude-columns products on matrix cores;
+                                 one system per batch; RK4 steps or DP5 attempts    */
   MQCT_SCHED_QUEUE = 3        /* work list: one step attempt per launch for every
                                  unfinished trajectory, finished ones retired between
                                  chunks of launches (replayed as HIP graphs); mixes
-                                 systems of any size; the schedule DP5 always uses    */
+                                 systems of any size; DP5 uses it unless BINNED is
+                                 asked for                                          */
 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -235,9 +237,13 @@ typedef struct {
  * step with R >= R0 and P_R > 0 (EXITED), at max_steps accepted steps or
  * 4 max_steps + 256 attempts (MAX_STEPS), when h < h_min (STEP_UNDERFLOW), or on
  * a non-finite error (NONFINITE).  The work-list schedule (MQCT_SCHED_QUEUE, and
- * every DP5 batch) runs until every trajectory has finished and returns after
- * the results are enqueued; it synchronises with the context stream between
- * chunks of launches. */
+ * DP5 batches on any schedule but MQCT_SCHED_BINNED) runs until every trajectory
+ * has finished and returns after the results are enqueued; it synchronises with
+ * the context stream between chunks of launches.  DP5 on MQCT_SCHED_BINNED makes
+ * one attempt per round for every unfinished trajectory of its single system
+ * (six knot-binned products per round) with the same tableau, controller and
+ * stopping rules, and synchronises with the stream every eight rounds to count
+ * the trajectories still running. */
 mqct_status mqct_run(mqct_context* ctx, const mqct_batch_desc* batch,
                      mqct_batch_result* result);
 

@@ -284,14 +284,21 @@ def test_cross_sections_on_device(ctx):
 
 
 def test_unsupported_combinations_report_cleanly(ctx, gpu_lib):
-    """Adaptive steps on the lockstep binned schedule and an unknown schedule fail
-    before any launch."""
+    """Two systems in one batch on the binned schedule (its products multiply one
+    system's tables), sparse tables there, and an unknown schedule fail before any
+    launch."""
     (s,), b = S.config1(n_traj=2, n_steps=10, jmax=1)
     sid = ctx.load_system(s)
+    sid2 = ctx.load_system(s)
+    sps = ctx.load_system(s, layout="sparse")
     common = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0)
-    with pytest.raises(gpu_lib.MQCTError) as e:
-        ctx.run_host([sid] * 2, [s.N] * 2, integrator="dp5", schedule="binned", **common)
-    assert e.value.code == gpu_lib.ERR_UNSUPPORTED
+    for ids, integ in (([sid, sid2], "dp5"), ([sid, sid2], "rk4"), ([sps, sps], "dp5")):
+        with pytest.raises(gpu_lib.MQCTError) as e:
+            ctx.run_host(ids, [s.N] * 2, integrator=integ, schedule="binned", dt=b.dt,
+                         n_steps=b.n_steps, **common)
+        assert e.value.code == gpu_lib.ERR_UNSUPPORTED
+    ctx.free_system(sid2)
+    ctx.free_system(sps)
     gpu_lib.SCHEDULES["bogus"] = 7
     try:
         with pytest.raises(gpu_lib.MQCTError) as e:
