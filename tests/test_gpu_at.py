@@ -2,7 +2,7 @@
 equations propagated along a classical trajectory that does not feel the
 quantum state, driven here by a tabulated potential U(R)).
 
-* every schedule (per trajectory, binned, work list with RK4 and DP5) against
+* every schedule (per trajectory, binned and work list, RK4 and DP5) against
   the oracle's AT dynamics: 1e-9 with FP64 tables (DP5: 10 x rtol);
 * many initial states on one trajectory: records that share (E_coll, b, R0)
   have bitwise identical classical results on the GPU, and the final
@@ -66,14 +66,15 @@ def test_at_rk4_matches_oracle(ctx, schedule):
     ctx.free_system(sid)
 
 
-def test_at_dp5_matches_oracle(ctx):
+@pytest.mark.parametrize("schedule", ["queue", "binned"])
+def test_at_dp5_matches_oracle(ctx, schedule):
     (s,), b = S.config1(n_traj=6, n_steps=1, jmax=3)
     U = driver_of(s)
-    say("AT dp5 N=%d B=%d" % (s.N, b.B))
+    say("AT dp5 %s N=%d B=%d" % (schedule, s.N, b.B))
     sid = ctx.load_system(s)
     ctx.set_driver(sid, U)
     g = ctx.run_host([sid] * b.B, [s.N] * b.B, integrator="dp5", dynamics="at", rtol=RTOL,
-                     atol=RTOL, max_steps=50000, h_min=1e-6, **start(b))
+                     atol=RTOL, max_steps=50000, h_min=1e-6, schedule=schedule, **start(b))
     o = oracle.OracleSystem(s, driver=U).propagate(b, method="dp5", rtol=RTOL, atol=RTOL,
                                                    max_steps=50000, h_min=1e-6)
     assert np.all(g["status"] & 1) and np.max(np.abs(g["steps"] - o["steps"])) <= 2
