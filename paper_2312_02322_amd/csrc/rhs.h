@@ -69,25 +69,33 @@ struct Sums {
 
 // Complex accumulation of u += conj(val) c and v += conj(der) c for one element
 // (complex tables) or u += val c, v += der c (real tables).
+// The operations are written as explicit fused multiply-adds, so that every
+// code path that calls this (dense rows, sparse slots in any batching) rounds
+// alike and a sparse layout that keeps every nonzero gives the dense results
+// bit for bit.
+template <typename F>
+__device__ __forceinline__ F fmaf_(F a, F b, F c) {
+  if constexpr (sizeof(F) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
 template <bool CPLX, typename F, typename F2>
 __device__ __forceinline__ void elem(F2& u, F2& v, F s0r, F s0i, F s1r, F s1i, F s2r, F s2i,
                                      F s3r, F s3i, const F (&w)[4], const F (&d)[4], F2 c) {
+  const F vr = fmaf_(w[3], s3r, fmaf_(w[2], s2r, fmaf_(w[1], s1r, w[0] * s0r)));
+  const F dr = fmaf_(d[3], s3r, fmaf_(d[2], s2r, fmaf_(d[1], s1r, d[0] * s0r)));
   if constexpr (CPLX) {
-    F vr = w[0] * s0r + w[1] * s1r + w[2] * s2r + w[3] * s3r;
-    F vi = w[0] * s0i + w[1] * s1i + w[2] * s2i + w[3] * s3i;
-    F dr = d[0] * s0r + d[1] * s1r + d[2] * s2r + d[3] * s3r;
-    F di = d[0] * s0i + d[1] * s1i + d[2] * s2i + d[3] * s3i;
-    u.x += vr * c.x + vi * c.y;
-    u.y += vr * c.y - vi * c.x;
-    v.x += dr * c.x + di * c.y;
-    v.y += dr * c.y - di * c.x;
+    const F vi = fmaf_(w[3], s3i, fmaf_(w[2], s2i, fmaf_(w[1], s1i, w[0] * s0i)));
+    const F di = fmaf_(d[3], s3i, fmaf_(d[2], s2i, fmaf_(d[1], s1i, d[0] * s0i)));
+    u.x = fmaf_(vi, c.y, fmaf_(vr, c.x, u.x));
+    u.y = fmaf_(-vi, c.x, fmaf_(vr, c.y, u.y));
+    v.x = fmaf_(di, c.y, fmaf_(dr, c.x, v.x));
+    v.y = fmaf_(-di, c.x, fmaf_(dr, c.y, v.y));
   } else {
-    F vr = w[0] * s0r + w[1] * s1r + w[2] * s2r + w[3] * s3r;
-    F dr = d[0] * s0r + d[1] * s1r + d[2] * s2r + d[3] * s3r;
-    u.x += vr * c.x;
-    u.y += vr * c.y;
-    v.x += dr * c.x;
-    v.y += dr * c.y;
+    u.x = fmaf_(vr, c.x, u.x);
+    u.y = fmaf_(vr, c.y, u.y);
+    v.x = fmaf_(dr, c.x, v.x);
+    v.y = fmaf_(dr, c.y, v.y);
   }
 }
 
@@ -146,6 +154,10 @@ struct Rhs {
   // stored rows in flight per lane (the split-row form streams fewer rows per
   // wave and is latency-bound, so it keeps more in flight)
   static constexpr int UNR = SPLIT ? (RPT >= 8 ? 1 : 8 / RPT) : (RPT >= 4 ? 1 : 4 / RPT);
+  // sparse real tables: slots per batch whose row indices and table elements are
+  // all requested before the first gather of c (their elements are small enough
+  // to hold a batch in registers)
+  static constexpr int ELLB = RPT >= 8 ? 1 : 8 / RPT;
   // keep each row's phase factor from the c computation for the epilogue
   static constexpr bool CPH = NR <= 4;
   using F = typename std::conditional<FP32, float, double>::type;
@@ -245,41 +257,98 @@ struct Rhs {
         for (int r = 0; r < NR; ++r) {
           pu[r].x = pu[r].y = pv[r].x = pv[r].y = (F)0;
         }
-#pragma unroll UNR
-        for (int m = m0; m < m1; ++m) {
-          CS cm;
-          if constexpr (!ELL) cm = lds.c[m];
-          const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
-          // No lane guard: a lane whose column group lies past the last one reads
-          // into the next stored row (or past the slice, which returns zero) and
-          // its sums are never used, so the loads of consecutive m stay in flight
-          // together.
+        if constexpr (ELL && !CPLX) {
+          // a batch of slots: every row index, then every table element, then
+          // the gathers of c and the products (loads retire in order, so an
+          // index load issued after a table load would wait for it)
+          for (int mb0 = m0; mb0 < m1; mb0 += ELLB) {
+            int ci[ELLB][RPT][VEC];
+            L tv[ELLB][RPT][4];
 #pragma unroll
-          for (int j = 0; j < RPT; ++j) {
-            const uint32_t grp = (uint32_t)(rlane() + j * ROWW);
-            const uint32_t off = rowoff + grp * (uint32_t)sizeof(L);
-            const L v0 = load16<L>(rs0, off);
-            const L v1 = load16<L>(rs1, off);
-            const L v2 = load16<L>(rs2, off);
-            const L v3 = load16<L>(rs3, off);
-            F r0[VEC], i0[VEC], r1[VEC], i1[VEC], r2[VEC], i2[VEC], r3[VEC], i3[VEC];
-            split(v0, r0, i0); split(v1, r1, i1); split(v2, r2, i2); split(v3, r3, i3);
-            int cidx[VEC];
-            if constexpr (ELL) {
-              const uint32_t coff = ((uint32_t)m * (uint32_t)Npad + grp * VEC) * 4u;
-              if constexpr (VEC == 2) {
-                const int2 cc = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(rcol, coff, 0, 0));
-                cidx[0] = cc.x;
-                cidx[1] = cc.y;
-              } else {
-                cidx[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, coff, 0, 0);
+            for (int u = 0; u < ELLB; ++u) {
+              const int m = min(mb0 + u, m1 - 1);
+#pragma unroll
+              for (int j = 0; j < RPT; ++j) {
+                const uint32_t grp = (uint32_t)(rlane() + j * ROWW);
+                const uint32_t coff = ((uint32_t)m * (uint32_t)Npad + grp * VEC) * 4u;
+                if constexpr (VEC == 2) {
+                  const int2 cc = __builtin_bit_cast(
+                      int2, __builtin_amdgcn_raw_buffer_load_b64(rcol, coff, 0, 0));
+                  ci[u][j][0] = cc.x;
+                  ci[u][j][1] = cc.y;
+                } else {
+                  ci[u][j][0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, coff, 0, 0);
+                }
               }
             }
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-              if constexpr (ELL) cm = lds.c[cidx[q]];
-              elem<CPLX, F, F2>(pu[j * VEC + q], pv[j * VEC + q], r0[q], i0[q], r1[q], i1[q],
-                                r2[q], i2[q], r3[q], i3[q], w, d, cm);
+            for (int u = 0; u < ELLB; ++u) {
+              const int m = min(mb0 + u, m1 - 1);
+              const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
+#pragma unroll
+              for (int j = 0; j < RPT; ++j) {
+                const uint32_t off =
+                    rowoff + (uint32_t)(rlane() + j * ROWW) * (uint32_t)sizeof(L);
+                tv[u][j][0] = load16<L>(rs0, off);
+                tv[u][j][1] = load16<L>(rs1, off);
+                tv[u][j][2] = load16<L>(rs2, off);
+                tv[u][j][3] = load16<L>(rs3, off);
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < ELLB; ++u) {
+              if (mb0 + u >= m1) break;
+#pragma unroll
+              for (int j = 0; j < RPT; ++j) {
+                F r0[VEC], i0[VEC], r1[VEC], i1[VEC], r2[VEC], i2[VEC], r3[VEC], i3[VEC];
+                split(tv[u][j][0], r0, i0); split(tv[u][j][1], r1, i1);
+                split(tv[u][j][2], r2, i2); split(tv[u][j][3], r3, i3);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                  const CS cm = lds.c[ci[u][j][q]];
+                  elem<CPLX, F, F2>(pu[j * VEC + q], pv[j * VEC + q], r0[q], i0[q], r1[q],
+                                    i1[q], r2[q], i2[q], r3[q], i3[q], w, d, cm);
+                }
+              }
+            }
+          }
+        } else {
+#pragma unroll UNR
+          for (int m = m0; m < m1; ++m) {
+            CS cm;
+            if constexpr (!ELL) cm = lds.c[m];
+            const uint32_t rowoff = (uint32_t)m * (uint32_t)ngroups * (uint32_t)sizeof(L);
+            // No lane guard: a lane whose column group lies past the last one reads
+            // into the next stored row (or past the slice, which returns zero) and
+            // its sums are never used, so the loads of consecutive m stay in flight
+            // together.
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+              const uint32_t grp = (uint32_t)(rlane() + j * ROWW);
+              const uint32_t off = rowoff + grp * (uint32_t)sizeof(L);
+              const L v0 = load16<L>(rs0, off);
+              const L v1 = load16<L>(rs1, off);
+              const L v2 = load16<L>(rs2, off);
+              const L v3 = load16<L>(rs3, off);
+              F r0[VEC], i0[VEC], r1[VEC], i1[VEC], r2[VEC], i2[VEC], r3[VEC], i3[VEC];
+              split(v0, r0, i0); split(v1, r1, i1); split(v2, r2, i2); split(v3, r3, i3);
+              int cidx[VEC];
+              if constexpr (ELL) {
+                const uint32_t coff = ((uint32_t)m * (uint32_t)Npad + grp * VEC) * 4u;
+                if constexpr (VEC == 2) {
+                  const int2 cc = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(rcol, coff, 0, 0));
+                  cidx[0] = cc.x;
+                  cidx[1] = cc.y;
+                } else {
+                  cidx[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, coff, 0, 0);
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < VEC; ++q) {
+                if constexpr (ELL) cm = lds.c[cidx[q]];
+                elem<CPLX, F, F2>(pu[j * VEC + q], pv[j * VEC + q], r0[q], i0[q], r1[q], i1[q],
+                                  r2[q], i2[q], r3[q], i3[q], w, d, cm);
+              }
             }
           }
         }
