@@ -80,9 +80,10 @@ def main():
     ap.add_argument("--large-traj", type=int, default=512)
     ap.add_argument("--large-steps", type=int, default=10000)
     ap.add_argument("--large-window", type=int, default=1000)
-    ap.add_argument("--large-integrator", choices=["rk4", "dp5"], default="rk4",
-                    help="large workload: fixed RK4 windows, or one adaptive DP5 call "
-                         "(rtol = atol = 1e-8) on the binned schedule for the whole collision")
+    ap.add_argument("--large-integrator", choices=["rk4", "dp5", "both"], default="rk4",
+                    help="large workload: fixed RK4 windows, one adaptive DP5 call "
+                         "(rtol = atol = 1e-8) on the binned schedule for the whole collision, "
+                         "or both (with the largest difference of their final probabilities)")
     ap.add_argument("--large-windows", type=int, default=0,
                     help="run only the first windows of the collision (0: all)")
     ap.add_argument("--uneven-traj", type=int, default=20000)
@@ -302,6 +303,8 @@ def large_workload(args):
             finals[storage] = res[storage].pop("P")
             ctx.free_system(sid)
             continue
+        dp5 = large_dp5(ctx, sid, sids, Ns, b, storage) if args.large_integrator == "both" \
+            else None
         stream = torch.cuda.current_stream(dev)
         state = None
         ms_tot = 0.0
@@ -351,12 +354,19 @@ def large_workload(args):
         roof = dict(hb if hb["frac"] > mf["frac"] else mf)
         roof["other_roof"] = {k: (mf if roof["bound"] == "hbm" else hb)[k]
                               for k in ("bound", "achieved", "peak", "unit", "frac")}
+        if dp5 is not None:
+            Pd = dp5.pop("P")
+            dp5["max_abs_dP_vs_rk4"] = float(np.max(np.abs(Pd - P)))
+            log("large %s: DP5 vs RK4 (%d steps) max|dP| = %.3e" % (
+                storage, T, dp5["max_abs_dP_vs_rk4"]))
         res[storage] = {
             "value": B * W * n_win / (ms_tot * 1e-3), "ms_per_window": ms_tot / n_win,
             "total_s": ms_tot * 1e-3, "windows": n_win,
             "N2_traj_steps_per_s": B * W * n_win * float(N) * N / (ms_tot * 1e-3),
             "roofline": roof,
             "max_norm_err": float(np.max(np.abs(P.sum(1) - 1.0)))}
+        if dp5 is not None:
+            res[storage]["dp5"] = dp5
         log("large %s: %.3g traj-steps/s, bin_gemm %.3f ms (%.1f TFLOP/s = %.1f%%; %.0f GB/s "
             "of tables = %.1f%%)" % (storage, res[storage]["value"], kms, tf, 100 * tf / peak,
                                      gbps, 100 * gbps / HBM_PEAK_GBPS))
