@@ -36,7 +36,7 @@ MFMA_PEAK_TFLOPS = {"C64": 157.3, "C128": 78.6}   # dense FP32 / FP64 matrix pea
 MEASURED_TRAFFIC = {
     # FETCH_SIZE (x 1.99992, the copy calibration) + WRITE_SIZE of bin_gemm<C64>,
     # mean of the 41 launches of one bench step, taken on this source revision
-    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "1cea80daf3d8d891",
+    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "51379955866012cd",
                         "bytes": 2.928e9, "window": 10, "trajectories": 4096},
 }
 

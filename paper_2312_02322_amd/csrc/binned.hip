@@ -698,6 +698,7 @@ struct D5WS {
   double* h;              // [B] step of the next attempt (the starting step while starting)
   double* t;              // [B] time of the current state
   double* rexit;          // [B] exit radius (the starting R)
+  double* d1;             // [B] ||f(t0, y0)|| of the starting-step estimate
   long long* steps;       // [B] accepted steps
   long long* rejects;     // [B]
   long long* attempts;    // [B]
@@ -925,19 +926,18 @@ d5_start(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, double rtol, d
     }
     const double d0 = sqrt(s2[0] / ncomp), d1 = sqrt(s2[1] / ncomp);
     d.h[b] = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-    d.rexit[b] = d1;   // kept for the second half
+    d.d1[b] = d1;
   } else {
     const double dk[6] = {kc[4] - kc[0], 0.0, kc[5] - kc[1], kc[6] - kc[2], 0.0, kc[7] - kc[3]};
     for (int k = 0; k < 6; ++k) {
       const double sc = atol + rtol * fabs(yfull[k]);
       s2[0] += (dk[k] / sc) * (dk[k] / sc);
     }
-    const double h0 = d.h[b], d1 = d.rexit[b];
+    const double h0 = d.h[b], d1 = d.d1[b];
     const double d2 = sqrt(s2[0] / ncomp) / h0;
     const double dm = fmax(d1, d2);
     const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / 5.0);
     d.h[b] = fmin(100.0 * h0, h1);
-    d.rexit[b] = y[0];
   }
 }
 
@@ -1037,7 +1037,8 @@ __global__ void d5_init(BinWS ws, D5WS d) {
   if (b >= ws.B) return;
   d.t[b] = ws.traj[b].t0;
   d.h[b] = 0.0;
-  d.rexit[b] = 0.0;
+  d.rexit[b] = ws.ycl[(int64_t)b * 4];   // set by bin_init, launched before
+  d.d1[b] = 0.0;
   d.steps[b] = 0;
   d.rejects[b] = 0;
   d.attempts[b] = 0;
@@ -1176,7 +1177,7 @@ size_t binned_dp5_workspace_bytes(int B, int Npad, int K, bool fp32) {
   size_t s = binned_workspace_bytes(B, Npad, K, fp32);
   s += al((size_t)B * 8 * Npad * 16);     // ks
   s += al((size_t)B * 32 * 8);            // kc
-  s += 3 * al((size_t)B * 8);             // h t rexit
+  s += 4 * al((size_t)B * 8);             // h t rexit d1
   s += 3 * al((size_t)B * 8);             // steps rejects attempts
   s += al((size_t)B * 4) + al(16);        // flags active
   return s;
@@ -1194,6 +1195,7 @@ hipError_t run_binned_dp5(const DevSystem* d_systems, const DevSystem& hs, const
   d.h = (double*)take((size_t)B * 8);
   d.t = (double*)take((size_t)B * 8);
   d.rexit = (double*)take((size_t)B * 8);
+  d.d1 = (double*)take((size_t)B * 8);
   d.steps = (long long*)take((size_t)B * 8);
   d.rejects = (long long*)take((size_t)B * 8);
   d.attempts = (long long*)take((size_t)B * 8);
