@@ -99,3 +99,28 @@ def test_binned_dp5_stopping_rules(ctx):
         assert np.array_equal(g["steps"], q["steps"])
         assert np.max(np.abs(g["rejects"] - q["rejects"])) <= 1
     ctx.free_system(sid)
+
+
+def test_binned_dp5_restart_from_a_given_state(ctx):
+    """A run stopped at 15 accepted steps and continued from its amplitudes,
+    classical state and time (a0, classical0, t0) ends where the work-list
+    schedule's chain of the same two calls ends."""
+    s = S.rotor_atom_system(jmax=4)
+    rng = np.random.default_rng(99)
+    init = np.where(s.labels["j"] == 2)[0]
+    b = S.mc_batch(s, 6, 400.0, 9.0, init, rng, n_steps=1)
+    sid = ctx.load_system(s)
+    ends = {}
+    for sched in ("binned", "queue"):
+        g1 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule=sched, **start(b),
+                          **dict(DP5, max_steps=15))
+        assert np.all(g1["status"] & 2)                       # stopped at the step limit
+        g2 = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule=sched, a0=g1["a_final"],
+                          classical0=g1["classical"], t0=g1["t_final"], **DP5)
+        ends[sched] = g2
+    ctx.free_system(sid)
+    say("  restart: steps binned %s work-list %s" % (ends["binned"]["steps"].tolist(),
+                                                     ends["queue"]["steps"].tolist()))
+    assert np.array_equal(ends["binned"]["status"], ends["queue"]["status"])
+    assert np.max(np.abs(ends["binned"]["steps"] - ends["queue"]["steps"])) <= 2
+    assert np.max(np.abs(ends["binned"]["P"] - ends["queue"]["P"])) < 10 * RTOL
