@@ -50,6 +50,8 @@ def lib():
         _lib.oracle_rhs.argtypes = [vp, d, vp, vp]
         _lib.oracle_rhs.restype = d
         _lib.oracle_total_energy.argtypes = [vp, d, vp]
+        _lib.oracle_dp5_error.argtypes = [vp, d, vp, d, d, d, vp]
+        _lib.oracle_dp5_error.restype = d
         _lib.oracle_total_energy.restype = d
         _lib.oracle_propagate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp,
                                           d, d, i64, d] + [vp] * 10
@@ -136,6 +138,15 @@ class OracleSystem:
         f = np.empty_like(y)
         eq = lib().oracle_rhs(C.byref(self.s), float(t), _p(y), _p(f))
         return f, eq
+
+    def dp5_error(self, t, y, h, rtol, atol):
+        """(error norm, fifth-order solution) of one Dormand-Prince 5(4) attempt of
+        size h from (t, y)."""
+        y = _f64(y)
+        ynew = np.empty_like(y)
+        en = lib().oracle_dp5_error(C.byref(self.s), float(t), _p(y), float(h), float(rtol),
+                                    float(atol), _p(ynew))
+        return en, ynew
 
     def total_energy(self, t, y):
         y = _f64(y)

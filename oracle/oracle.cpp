@@ -31,7 +31,8 @@
 // closed form, the frozen-trajectory matrix exponential, free straight-line
 // motion with Wigner-d Coriolis populations, norm / energy / angular-momentum
 // invariants, RK4 convergence order, an independent DOP853 integration,
-// m-reflection symmetry, the literal-phase form, and the dual-number derivative
+// scipy's RK45 (the same Dormand-Prince pair and controller) step for step, the
+// h^5 scaling of the embedded error estimate, m-reflection symmetry, the literal-phase form, and the dual-number derivative
 // against finite differences.
 
 #include <cmath>
@@ -420,6 +421,34 @@ double rms_scaled(const std::vector<double>& e, const std::vector<double>& sc) {
 
 struct Dp5Result { int32_t status; int64_t steps, rejects; double t; };
 
+// One Dormand-Prince 5(4) attempt of size h from (t, y), with k[0] = f(t, y)
+// given: the stages k[1..6] (k[6] = f(t + h, ynew), first same as last), the
+// fifth-order solution ynew, and the returned scaled RMS norm of the embedded
+// error estimate h sum_q DP_E[q] k[q] with sc_i = atol + rtol max(|y_i|, |ynew_i|).
+double dp5_attempt(const oracle_system* s, double t, const double* y, double h, double rtol,
+                   double atol, std::vector<std::vector<double>>& k, std::vector<double>& ynew,
+                   int32_t& status) {
+  const int n = 2 * s->N + 6;
+  std::vector<double> tmp(n), err(n), sc(n);
+  for (int st = 1; st < 7; ++st) {
+    for (int i = 0; i < n; ++i) {
+      double acc = y[i];
+      for (int q = 0; q < st; ++q) acc += h * DP_A[st][q] * k[q][i];
+      tmp[i] = acc;
+    }
+    Diag<double> d = rhs<double>(s, t + DP_C[st] * h, tmp.data(), k[st].data());
+    if (d.below) status |= OR_BELOW_GRID;
+    if (st == 6) ynew = tmp;
+  }
+  for (int i = 0; i < n; ++i) {
+    double e = 0.0;
+    for (int q = 0; q < 7; ++q) e += DP_E[q] * k[q][i];
+    err[i] = h * e;
+    sc[i] = atol + rtol * std::max(std::fabs(y[i]), std::fabs(ynew[i]));
+  }
+  return rms_scaled(err, sc);
+}
+
 // Adaptive Dormand-Prince 5(4) with first-same-as-last, scaled RMS error norm
 // sc_i = atol + rtol max(|y_i|, |y_new,i|), step factor min(5, max(0.2, 0.9 err^-1/5))
 // (no growth right after a rejection), starting step from the Hairer-Norsett-Wanner
@@ -449,23 +478,7 @@ Dp5Result dp5(const oracle_system* s, double* y, double t0, double rtol, double 
   bool last_rejected = false;
   for (;;) {
     if (res.steps >= max_steps) { status |= OR_MAX_STEPS; break; }
-    for (int st = 1; st < 7; ++st) {
-      for (int i = 0; i < n; ++i) {
-        double acc = y[i];
-        for (int q = 0; q < st; ++q) acc += h * DP_A[st][q] * k[q][i];
-        tmp[i] = acc;
-      }
-      Diag<double> d = rhs<double>(s, t + DP_C[st] * h, tmp.data(), k[st].data());
-      if (d.below) status |= OR_BELOW_GRID;
-      if (st == 6) ynew = tmp;
-    }
-    for (int i = 0; i < n; ++i) {
-      double e = 0.0;
-      for (int q = 0; q < 7; ++q) e += DP_E[q] * k[q][i];
-      err[i] = h * e;
-      sc[i] = atol + rtol * std::max(std::fabs(y[i]), std::fabs(ynew[i]));
-    }
-    double en = rms_scaled(err, sc);
+    double en = dp5_attempt(s, t, y, h, rtol, atol, k, ynew, status);
     if (!std::isfinite(en)) { status |= OR_NONFINITE; break; }
     if (en <= 1.0) {
       t += h;
@@ -536,6 +549,21 @@ int32_t oracle_spline_eval(int32_t K, const double* x, int64_t ncol, const doubl
 // Right-hand side at (t, y); also returns the quantum energy <H_rot + V>.
 double oracle_rhs(const oracle_system* s, double t, const double* y, double* f) {
   return rhs<double>(s, t, y, f).Eq;
+}
+
+// Scaled RMS norm of the embedded error estimate of one Dormand-Prince 5(4)
+// attempt of size h from (t, y); ynew (may be NULL) receives the fifth-order
+// solution.
+double oracle_dp5_error(const oracle_system* s, double t, const double* y, double h, double rtol,
+                        double atol, double* ynew) {
+  const int n = 2 * s->N + 6;
+  std::vector<std::vector<double>> k(7, std::vector<double>(n));
+  std::vector<double> yn(n);
+  int32_t status = 0;
+  rhs<double>(s, t, y, k[0].data());
+  double en = dp5_attempt(s, t, y, h, rtol, atol, k, yn, status);
+  if (ynew) for (int i = 0; i < n; ++i) ynew[i] = yn[i];
+  return en;
 }
 
 double oracle_total_energy(const oracle_system* s, double t, const double* y) {

@@ -79,7 +79,7 @@ def rate_coefficient(U, s_e, dE, g_i, mu, beta):
     total = 0.0
     for a, b in zip(pts[:-1], pts[1:]):
         if b > a:
-            total += integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-11, limit=400)[0]
+            total += integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-12, limit=400)[0]
     # constant tail beyond the last energy: s_n int_{U_n}^inf U e^{-(U-U_th)/beta} dU
     Un = max(U[-1], U_th)
     total += s_e[-1] * beta * (Un + beta) * math.exp(-(Un - U_th) / beta)

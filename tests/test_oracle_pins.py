@@ -13,7 +13,11 @@ one of them:
   P_Phi - <J_x> conservation                                             -> torque (Eq. 10)
   norm conservation                                                      -> Hermitian generator
   m-reflection symmetry                                                  -> J_x indices
-  RK4 order and DOP853 / DP5 comparison                                  -> the time steppers
+  RK4 order and DOP853 comparison                                        -> the RK4 stepper
+  scipy RK45 on the oracle's right-hand side (same tableau and controller) -> DP5 weights, error
+                                                                           norm, step-factor rule,
+                                                                           starting step
+  h^5 scaling of one attempt's embedded error estimate on a' = -iVa      -> DP5 error weights
   dual-number derivative vs central differences                          -> forward mode
   Monte-Carlo estimator closed form and the l_max = k b_max relation     -> cross sections, initial state
 """
@@ -242,8 +246,9 @@ def _state0(o, ch, E_coll, bpar, R0):
     return y
 
 
-def test_rk4_and_dp5_against_dop853():
-    """An independent integrator (scipy DOP853) on the oracle's right-hand side."""
+def test_rk4_against_dop853():
+    """An independent integrator (scipy DOP853) on the oracle's right-hand side
+    pins the fixed-step RK4 stepper."""
     (s,), b = S.config1(n_traj=1, n_steps=1, jmax=2)
     o = oracle.OracleSystem(s)
     E_coll, bpar, R0 = b.E_coll[0], 3.0, s.R_grid[-1]
@@ -261,6 +266,95 @@ def test_rk4_and_dp5_against_dop853():
     # RK4 at this step is converged to ~1e-12.  A wrong RK4 weight would show ~1e-3.
     assert np.max(np.abs(out["a_final"][0] - aT)) < 2e-8
     assert np.max(np.abs(out["classical"][0] - yT[2 * N:]) / (1 + np.abs(yT[2 * N:]))) < 2e-8
+
+
+def _scipy_rk45(o, y0, rtol, atol, until_exit=None, n_accepted=None):
+    """scipy's RK45 (the Dormand-Prince 5(4) pair with first-same-as-last, the RMS
+    norm scaled by atol + rtol max(|y|, |y_new|), the factor 0.9 err^-1/5 bounded by
+    0.2 below, no growth right after a rejection, the Hairer-Norsett-Wanner starting
+    step) with its growth bound set to 5, stepping the oracle's right-hand side.
+    Returns (accepted, rejected, t, y)."""
+    import scipy.integrate._ivp.rk as rk
+    from scipy.integrate import RK45
+    nfev = [0]
+
+    def f(t, y):
+        nfev[0] += 1
+        return o.rhs(t, y)[0]
+
+    old = rk.MAX_FACTOR
+    rk.MAX_FACTOR = 5.0
+    try:
+        sol = RK45(f, 0.0, y0.copy(), t_bound=1e15, rtol=rtol, atol=atol)
+        n = 0
+        while True:
+            sol.step()
+            n += 1
+            if n_accepted is not None and n == n_accepted:
+                break
+            if until_exit is not None and sol.y[2 * o.N] >= until_exit and sol.y[2 * o.N + 3] > 0:
+                break
+    finally:
+        rk.MAX_FACTOR = old
+    # two evaluations before the first attempt (f(t0, y0) and the starting-step
+    # probe), then six per attempt
+    attempts = (nfev[0] - 2) // 6
+    assert nfev[0] == 2 + 6 * attempts
+    return n, attempts - n, sol.t, sol.y
+
+
+@pytest.mark.parametrize("bpar", [3.0, 8.0])
+def test_dp5_controller_matches_scipy_rk45(bpar):
+    """The oracle's adaptive stepper against scipy's RK45 on the same right-hand
+    side: the same accepted and rejected step counts over a whole collision (and
+    over the first 40 accepted steps, stopped by the accepted-step limit), the same
+    end time and state.  The decisions agree one by one only if the error weights,
+    the norm, the factor rule and the starting step all agree; the times then differ
+    only by rounding of the error estimates (amplified along the step sequence)."""
+    (s,), b = S.config1(n_traj=1, n_steps=1, jmax=2)
+    o = oracle.OracleSystem(s)
+    N = o.N
+    E_coll, R0 = b.E_coll[0], s.R_grid[-1]
+    ch = int(b.init_channel[0])
+    y0 = _state0(o, ch, E_coll, bpar, R0)
+    kw = dict(init_channel=[ch], E_coll=[E_coll], b=[bpar], R0=[R0], method="dp5", rtol=1e-8,
+              atol=1e-8)
+    full = o.propagate(**kw)
+    assert full["status"][0] & oracle.STATUS["EXITED"]
+    n, rej, t, y = _scipy_rk45(o, y0, 1e-8, 1e-8, until_exit=R0)
+    assert rej > 5, rej             # the rejection branch is exercised
+    assert (int(full["steps"][0]), int(full["rejects"][0])) == (n, rej)
+    assert abs(full["t_final"][0] - t) <= 1e-7 * t
+    a = y[:2 * N:2] + 1j * y[1:2 * N:2]
+    assert np.max(np.abs(full["a_final"][0] - a)) < 1e-7
+    assert np.max(np.abs(full["classical"][0] - y[2 * N:]) / (1 + np.abs(y[2 * N:]))) < 1e-7
+    part = o.propagate(max_steps=40, **kw)
+    n, rej, t, y = _scipy_rk45(o, y0, 1e-8, 1e-8, n_accepted=40)
+    assert part["status"][0] & oracle.STATUS["MAX_STEPS"]
+    assert (int(part["steps"][0]), int(part["rejects"][0])) == (n, rej)
+    assert abs(part["t_final"][0] - t) <= 1e-9 * t
+    a = y[:2 * N:2] + 1j * y[1:2 * N:2]
+    assert np.max(np.abs(part["a_final"][0] - a)) < 1e-8
+
+
+def test_dp5_embedded_error_is_fifth_order():
+    """One attempt on a' = -i V a (one channel, constant coupling, head-on free
+    flight: the classical part is linear in t and integrated exactly): the embedded
+    estimate is the difference of a fifth- and a fourth-order solution, so it scales
+    as h^5 -- a wrong error weight breaks an order condition and changes the power."""
+    V = 0.01
+    R = np.linspace(3.0, 40.0, 12)
+    o = oracle.OracleSystem(make_system(R, [0.0], np.full((12, 1, 1), V), mu=2000.0))
+    y0 = np.zeros(8)
+    y0[0] = 1.0
+    y0[2:] = [20.0, math.pi / 2, 0.0, -5.0, 0.0, 0.0]
+    errs = [o.dp5_error(0.0, y0, h, 1e-8, 1e-8)[0] for h in (4.0, 2.0, 1.0)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 30.0 < r1 < 34.0 and 31.0 < r2 < 33.0, errs
+    # the fifth-order solution itself is the exponential to O(h^6)
+    en, yn = o.dp5_error(0.0, y0, 1.0, 1e-8, 1e-8)
+    assert abs(complex(yn[0], yn[1]) - np.exp(-1j * V * 1.0)) < 1e-13
+    assert abs(yn[2] - (20.0 - 5.0 / 2000.0)) < 1e-13
 
 
 def test_dp5_exit_and_accuracy():
