@@ -498,6 +498,26 @@ class Context:
         return sig
 
 
+# batch keys whose forward computation the adjoint differentiates: fixed-step RK4
+# from init_channel / E_coll / b / R0 (mean-field dynamics, any schedule)
+ADJOINT_KEYS = ("init_channel", "E_coll", "b", "R0", "dt", "n_steps", "schedule")
+
+
+def _check_adjoint_batch(batch):
+    """Raise unless the backward pass differentiates exactly the forward's batch."""
+    extra = sorted(k for k in batch if k not in ADJOINT_KEYS and batch[k] is not None)
+    for k, ok in (("integrator", "rk4"), ("dynamics", "ehrenfest")):
+        if k in extra and batch[k] == ok:
+            extra.remove(k)
+    if extra:
+        raise ValueError("the adjoint differentiates fixed-step RK4 mean-field batches started "
+                         "from init_channel / E_coll / b / R0; unsupported batch keys: %s"
+                         % ", ".join(extra))
+    for k in ("init_channel", "E_coll", "b", "dt", "n_steps"):
+        if batch.get(k) is None:
+            raise ValueError("the adjoint needs batch[%r]" % k)
+
+
 def _autograd_function():
     import torch
 
@@ -507,6 +527,7 @@ def _autograd_function():
 
         @staticmethod
         def forward(fctx, theta, mq, sid, N, batch, checkpoint_every):
+            _check_adjoint_batch(batch)
             th = theta.detach().cpu().double().numpy()
             mq.set_theta(sid, th)
             B = len(batch["E_coll"])

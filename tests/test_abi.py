@@ -48,3 +48,22 @@ def test_struct_layouts_match_header():
     assert C.sizeof(mq.BatchDesc) == 136   # the trailing int32 dynamics fits the padding
     assert C.sizeof(mq.BatchResult) == 88
     assert C.sizeof(mq.CouplingDesc) == 120
+
+
+def test_autograd_forward_rejects_batches_the_adjoint_does_not_differentiate():
+    """The backward pass differentiates RK4 mean-field batches started from
+    init_channel / E_coll / b / R0 only; any other batch is refused before the
+    forward runs (a gradient of a different computation would otherwise come back)."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    base = dict(init_channel=[0], E_coll=[1e-3], b=[1.0], dt=[10.0], n_steps=[5])
+    mq._check_adjoint_batch(dict(base, R0=[30.0], schedule="binned", integrator="rk4",
+                                 dynamics="ehrenfest"))
+    theta = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+    for bad in (dict(t0=[5.0]), dict(a0=np.ones(4)), dict(classical0=np.zeros(6)),
+                dict(integrator="dp5"), dict(dynamics="at"), dict(rtol=1e-6)):
+        with pytest.raises(ValueError, match="unsupported batch keys"):
+            mq.propagate(theta, None, 0, 4, dict(base, **bad))
+    with pytest.raises(ValueError, match="needs"):
+        mq.propagate(theta, None, 0, 4, {k: v for k, v in base.items() if k != "dt"})
