@@ -48,8 +48,8 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--window", type=int, default=10, help="RK4 steps per bench step")
     ap.add_argument("--traj", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -64,10 +64,14 @@ def main():
                          "nonzero: the same gradient)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--workload", choices=["window", "large", "uneven", "at", "coupling",
-                                           "coupling_paper", "rates"],
-                    default="window",
-                    help="window: N=969 mid-collision windows (default, the headline); "
+    ap.add_argument("--workload", choices=["headline", "window", "large", "uneven", "at",
+                                           "coupling", "coupling_paper", "rates"],
+                    default="headline",
+                    help="headline (default): the N=4096 collision (512 trajectories x 10,000 RK4 "
+                         "steps, binned, FP32 tables), one bench step = 1/--steps of it, with "
+                         "the FP32-vs-FP64 adaptive runs, the N=969 windows, the uneven batch and "
+                         "the adjoint as variants; "
+                         "window: N=969 mid-collision windows; "
                          "large: N=4096, 512 full collisions of 10,000 RK4 steps on the binned "
                          "schedule; uneven: 20,000 trajectories of three systems with adaptive DP5; "
                          "at: decoupled (AT) dynamics, 64 trajectories x 100 initial states; "
@@ -86,12 +90,19 @@ def main():
                          "or both (with the largest difference of their final probabilities)")
     ap.add_argument("--large-windows", type=int, default=0,
                     help="run only the first windows of the collision (0: all)")
+    ap.add_argument("--large-scatter", type=int, default=0,
+                    help="large workload: instead of the collision, time --steps windows of this "
+                         "many RK4 steps of a scattered mid-collision population (R0 uniform in "
+                         "4-19.5 A), the regime where few trajectories share a knot")
     ap.add_argument("--uneven-traj", type=int, default=20000)
-    ap.add_argument("--uneven-max-steps", type=int, default=100000)
-    ap.add_argument("--uneven-schedule", choices=["mixed", "queue"], default="mixed",
-                    help="uneven workload: the N=969 class on the binned schedule (adaptive "
-                         "steps on the matrix cores) and the rest on the work list (mixed), or "
-                         "everything in one work-list call (queue)")
+    ap.add_argument("--uneven-max-steps", type=int, default=50000,
+                    help="accepted-step limit (the workload's step counts range up to 50,000)")
+    ap.add_argument("--uneven-schedule", choices=["auto", "queue"], default="auto",
+                    help="uneven workload, one call: the library's default split (the N=969 "
+                         "class on the binned schedule beside the work list) or everything on "
+                         "the work list (queue)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="headline workload without the variants (for profiler runs)")
     ap.add_argument("--uneven-layout", choices=["dense", "sparse"], default="sparse",
                     help="sparse: systems whose tables are mostly structural zeros keep only the "
                          "nonzeros (drop_below = 0, the same results)")
@@ -119,6 +130,12 @@ def main():
         print(json.dumps(adjoint_timing(args.adjoint_traj, args.adjoint_steps,
                                         layout=args.adjoint_layout)), flush=True)
         return
+    if args.workload == "headline":
+        print(json.dumps(headline(args)), flush=True)
+        return
+    if args.workload == "large" and args.large_scatter > 0:
+        print(json.dumps(large_scatter(args)), flush=True)
+        return
     if args.workload == "large":
         print(json.dumps(large_workload(args)), flush=True)
         return
@@ -137,6 +154,18 @@ def main():
     if args.workload == "at":
         print(json.dumps(at_workload(args)), flush=True)
         return
+    line = window_workload(args)
+    print(json.dumps(line), flush=True)
+
+
+def window_variants(args, storages=None, gemv_steps=None):
+    """The N = 969 mid-collision windows: --traj trajectories, --window RK4 steps of
+    12 a.u. per bench step, per-trajectory and binned schedules, FP32 and FP64
+    tables.  gemv_steps: fewer timed steps for the per-trajectory schedule."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
     t0 = time.time()
     (s,), b = S.config2(n_traj=args.traj, full_collision=False, window_steps=args.window)
     log("generated N=%d K=%d B=%d in %.1fs" % (s.N, s.K, b.B, time.time() - t0))
@@ -145,7 +174,8 @@ def main():
     dev = ctx.device
     results = {}
     P_of = {}
-    storages = [args.only] if args.only else ["C64", "C128"]
+    if storages is None:
+        storages = [args.only] if args.only else ["C64", "C128"]
     schedules = [args.schedule] if args.schedule != "both" else ["gemv", "binned"]
     for storage in storages:
         t0 = time.time()
@@ -166,6 +196,8 @@ def main():
         Ns = np.full(B, N, np.int64)
         es = 8 if storage == "C64" else 16
         for sched in schedules:
+            n_timed = gemv_steps if (sched == "gemv" and gemv_steps) else args.steps
+
             def step():
                 ctx.run(sids, Ns, init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0,
                         dt=b.dt, n_steps=b.n_steps, out=out, schedule=sched)
@@ -179,19 +211,21 @@ def main():
             ctx.set_profiling(True)
             wall0 = time.time()
             e0.record(stream)
-            for _ in range(args.steps):
+            for _ in range(n_timed):
                 step()
             e1.record(stream)
             torch.cuda.synchronize()
-            wall = (time.time() - wall0) / args.steps
+            wall = (time.time() - wall0) / n_timed
             kern_ms, kern_n, kern_bytes = ctx.profile_read(with_bytes=True)
             ctx.set_profiling(False)
-            ms = e0.elapsed_time(e1) / args.steps
+            ms = e0.elapsed_time(e1) / n_timed
             evals = B * (4 * W + 1)              # RK4 stages + the final diagnostic evaluation
             alg_bytes = evals * 4.0 * N * N * es  # four spline slices of N x N per evaluation
             st = out["status"].cpu().numpy()
             r = {"value": B * W / (ms * 1e-3), "ms_per_step": ms, "wall_ms_per_step": wall * 1e3,
-                 "coupling_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+                 # the four spline slices every trajectory's evaluation needs, per second: a
+                 # work rate (the binned schedule reads each occupied knot once per stage)
+                 "coupling_work_GBps": alg_bytes / (ms * 1e-3) / 1e9,
                  "N2_traj_steps_per_s": B * W * N * N / (ms * 1e-3),
                  "status_nonzero": int(np.count_nonzero(st)),
                  "max_norm_err": float(out["norm_err"].abs().max().item())}
@@ -228,6 +262,23 @@ def main():
                                     r["roofline"]["unit"], 100 * r["roofline"]["frac"]))
         ctx.free_system(sid)
 
+    out = {"variants": {"%s/%s" % k: v for k, v in results.items()}, "results": results,
+           "P_of": P_of, "s": s, "b": b, "W": W}
+    if ("C64", "binned") in P_of and ("C128", "binned") in P_of:
+        out["fp32_vs_fp64_max_abs_dP"] = float(
+            np.max(np.abs(P_of[("C64", "binned")] - P_of[("C128", "binned")])))
+    ctx.close()
+    return out
+
+
+def window_workload(args):
+    """The N = 969 window workload as its own line."""
+    import numpy as np
+    wv = window_variants(args)
+    results, P_of, s, b, W = wv["results"], wv["P_of"], wv["s"], wv["b"], wv["W"]
+    N, B = s.N, b.B
+    storages = sorted({k[0] for k in results})
+
     def best(storage):
         cands = [(k, v) for k, v in results.items() if k[0] == storage]
         return max(cands, key=lambda kv: kv[1]["value"]) if cands else (None, None)
@@ -244,7 +295,7 @@ def main():
                    "N": N, "K": s.K, "trajectories": B, "rk4_steps_per_bench_step": W,
                    "schedule": hk[1], "tables": hk[0]},
         "roofline": head["roofline"],
-        "coupling_GBps": head["coupling_GBps"],
+        "coupling_work_GBps": head["coupling_work_GBps"],
         "N2_traj_steps_per_s": head["N2_traj_steps_per_s"],
         "status_nonzero": head["status_nonzero"],
         "variants": {"%s/%s" % k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
@@ -263,11 +314,12 @@ def main():
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s, b, W)
-    ctx.close()
     if args.adjoint == "on":
         line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps,
                                          layout=args.adjoint_layout)
-    print(json.dumps(line), flush=True)
+    return line
+
+
 
 
 def large_workload(args):
@@ -332,9 +384,12 @@ def large_workload(args):
             state = (out["a_final"].cpu().numpy().reshape(B, N), out["classical"].cpu().numpy(),
                      out["t_final"].cpu().numpy())
             R = state[1][:, 0]
-            log("large %s: window %d/%d %.0f ms, R %.1f..%.1f bohr, max|norm-1| %.2e" % (
-                storage, w + 1, n_win, ms, R.min(), R.max(),
-                float(out["norm_err"].abs().max().item())))
+            log("large %s: window %d/%d %.0f ms, R %.1f..%.1f bohr, max|norm-1| %.2e, "
+                "bin_gemm %.3f ms x %d, %.1f knots, %.0f GB/s" % (
+                    storage, w + 1, n_win, ms, R.min(), R.max(),
+                    float(out["norm_err"].abs().max().item()), km / max(kn, 1), kn,
+                    kb / max(kn, 1) / (2.0 * N * N * (8 if storage == "C64" else 16)),
+                    kb / max(km * 1e-3, 1e-30) / 1e9))
         P = np.abs(state[0]) ** 2
         finals[storage] = P
         flops = 32.0 * N * N * B
@@ -413,6 +468,308 @@ def large_workload(args):
                                    "p99": float(np.percentile(d, 99))}
         line["fp32_speedup_over_fp64"] = res["C64"]["value"] / res["C128"]["value"]
     return line
+
+
+def system_info():
+    """GPU, ROCm and host CPU of the run."""
+    import torch
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
+    return {"gpu": torch.cuda.get_device_name(0), "rocm_hip": torch.version.hip,
+            "torch": torch.__version__, "host_cpu": cpu, "host_threads_visible": os.cpu_count(),
+            "host_threads_affinity": affinity}
+
+
+def collision_windows(ctx, sids, Ns, b, n_windows, warmup, total_steps, storage):
+    """The N = 4096 collision as n_windows consecutive calls of total_steps / n_windows
+    RK4 steps (each continues the stored state of the one before, resume = 1), after
+    `warmup` windows of the same collision from its start.  Returns the timed run's
+    per-window kernel records and its final probabilities."""
+    import numpy as np
+    import torch
+    B, N = len(sids), int(Ns[0])
+    spw = -(-total_steps // n_windows)
+    start = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, R0=b.R0, dt=b.dt)
+    sizes = [min(spw, total_steps - w * spw) for w in range(n_windows)]
+    for w in range(warmup):
+        ctx.run(sids, Ns, n_steps=np.full(B, spw), schedule="binned",
+                **(start if w == 0 else {}), resume=w > 0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(ctx.device)
+    rec = []
+    ctx.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.time()
+    e0.record(stream)
+    for w, n in enumerate(sizes):
+        out = ctx.run(sids, Ns, n_steps=np.full(B, n), schedule="binned",
+                      **(start if w == 0 else {}), resume=w > 0)
+        km, kn, kb = ctx.profile_read(with_bytes=True)   # waits for the window
+        rec.append({"steps": n, "kernel_ms": km, "launches": kn, "table_bytes": kb})
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    ctx.set_profiling(False)
+    ms = e0.elapsed_time(e1)
+    st = out["status"].cpu().numpy()
+    P = out["P"].reshape(B, N).cpu().numpy()
+    R = out["classical"][:, 0].cpu().numpy()
+    for w, r in enumerate(rec):
+        flops = 32.0 * N * N * B * r["launches"]
+        peak = MFMA_PEAK_TFLOPS[storage] * 1e12
+        ideal = max(r["table_bytes"] / (HBM_PEAK_GBPS * 1e9), flops / peak)
+        r["knots_per_launch"] = r["table_bytes"] / max(r["launches"], 1) / (
+            2.0 * N * N * (8 if storage == "C64" else 16))
+        r["GBps"] = r["table_bytes"] / (r["kernel_ms"] * 1e-3) / 1e9
+        r["TFLOPs"] = flops / (r["kernel_ms"] * 1e-3) / 1e12
+        r["roofline_ms"] = ideal * 1e3
+        log("  %s window %2d: %4d steps, bin_gemm %.3f ms x %d, %.1f knots, %5.0f GB/s, "
+            "%5.1f TFLOP/s, %.0f%% of its roofline" % (
+                storage, w + 1, r["steps"], r["kernel_ms"] / max(r["launches"], 1), r["launches"],
+                r["knots_per_launch"], r["GBps"], r["TFLOPs"],
+                100 * r["roofline_ms"] / r["kernel_ms"]))
+    return {"ms": ms, "wall_s": wall, "windows": rec, "P": P, "status": st,
+            "norm_err_max": float(out["norm_err"].abs().max().item()), "R_final": R}
+
+
+def headline(args):
+    """The N = 4096 collision (the largest configuration) as the headline, with
+    the other workloads as variants of the same line."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S
+    t_all = time.time()
+    info = system_info()
+    log("system %s" % json.dumps(info))
+    N, B, T = args.large_n, args.large_traj, args.large_steps
+    K_win, W = args.steps, args.warmup
+    t0 = time.time()
+    (s, ), b = S.config5(n_traj=B, n_steps=T, N=N, build_tables=False)
+    ctx = mq.Context(0)
+    Md = S.gp_tables_device(s, ctx.device)
+    torch.cuda.synchronize()
+    log("large: N=%d tables built on the device in %.1fs" % (N, time.time() - t0))
+    sids, Ns = np.full(B, 0, np.int32), np.full(B, N, np.int64)
+    variants = {}
+    finals = {}
+    # the headline: FP32 tables, the whole collision of T RK4 steps in K_win windows
+    sid = ctx.load_system(R_grid=s.R_grid, E=s.E, M=Md, jx=None, mu=s.mu, storage="C64")
+    sids[:] = sid
+    cw = collision_windows(ctx, sids, Ns, b, K_win, W, T, "C64")
+    rec = cw["windows"]
+    kms = sum(r["kernel_ms"] for r in rec)
+    kn = sum(r["launches"] for r in rec)
+    kb = sum(r["table_bytes"] for r in rec)
+    flops = 32.0 * N * N * B * kn
+    roof_ms = sum(r["roofline_ms"] for r in rec)
+    gbps = kb / (kms * 1e-3) / 1e9
+    tf = flops / (kms * 1e-3) / 1e12
+    hbm_time, mfma_time = kb / (HBM_PEAK_GBPS * 1e9), flops / (MFMA_PEAK_TFLOPS["C64"] * 1e12)
+    head = {"value": B * T / (cw["ms"] * 1e-3), "ms_per_step": cw["ms"] / K_win,
+            "total_s": cw["ms"] * 1e-3, "wall_s": cw["wall_s"],
+            "N2_traj_steps_per_s": B * T * float(N) * N / (cw["ms"] * 1e-3),
+            "status_nonzero": int(np.count_nonzero(cw["status"])),
+            "max_norm_err": cw["norm_err_max"]}
+    # the product moves between the two roofs during the collision: the bound is the
+    # one its ideal time spends longer under, and the mixed fraction compares the
+    # ideal time of every window (the larger of its bytes at 8 TB/s and its flops at
+    # the matrix peak) with the measured time
+    if hbm_time >= mfma_time:
+        roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": gbps / HBM_PEAK_GBPS}
+        other = {"bound": "mfma", "achieved": tf, "peak": MFMA_PEAK_TFLOPS["C64"],
+                 "unit": "TFLOP/s", "frac": tf / MFMA_PEAK_TFLOPS["C64"]}
+    else:
+        roof = {"bound": "mfma", "achieved": tf, "peak": MFMA_PEAK_TFLOPS["C64"],
+                "unit": "TFLOP/s", "frac": tf / MFMA_PEAK_TFLOPS["C64"]}
+        other = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                 "frac": gbps / HBM_PEAK_GBPS}
+    roof.update({"kernel": "bin_gemm (wide + narrow launches of a stage)", "traffic": None,
+                 "alg_bytes_per_launch": kb / kn, "alg_flops_per_launch": flops / kn,
+                 "launch_ms": kms / kn, "launches_timed": kn,
+                 "mixed_frac": roof_ms / kms, "other_roof": other})
+    tr = MEASURED_TRAFFIC.get(("C64", "large"))
+    if tr and tr["source_sha256_16"] == _source_hash(tr["source"]) and tr["trajectories"] == B:
+        roof["traffic"] = tr["bytes"]
+    head["roofline"] = roof
+    head["windows"] = [{k: v for k, v in r.items()} for r in rec]
+    finals["C64/rk4"] = cw["P"]
+    log("large C64: %.1f s for the collision, %.3g traj-steps/s, bin_gemm %.3f ms x %d: "
+        "%.0f GB/s (%.1f%% of HBM), %.1f TFLOP/s (%.1f%%), %.1f%% of the mixed roofline" % (
+            head["total_s"], head["value"], kms / kn, kn, gbps, 100 * gbps / HBM_PEAK_GBPS, tf,
+            100 * tf / MFMA_PEAK_TFLOPS["C64"], 100 * roof_ms / kms))
+    variants["large/C64/binned/rk4"] = {k: v for k, v in head.items() if k != "windows"}
+    if not args.headline_only:
+        # the same collisions with adaptive steps, FP32 and FP64 tables
+        d = large_dp5(ctx, sid, sids, Ns, b, "C64")
+        finals["C64/dp5"] = d.pop("P")
+        variants["large/C64/binned/dp5"] = d
+        ctx.free_system(sid)
+        sid = ctx.load_system(R_grid=s.R_grid, E=s.E, M=Md, jx=None, mu=s.mu, storage="C128")
+        sids[:] = sid
+        d = large_dp5(ctx, sid, sids, Ns, b, "C128")
+        finals["C128/dp5"] = d.pop("P")
+        variants["large/C128/binned/dp5"] = d
+    ctx.free_system(sid)
+    del Md
+    ctx.close()
+    torch.cuda.empty_cache()
+    line = {"metric": METRIC, "value": head["value"], "unit": "traj-steps/s", "n_gpus": 1,
+            "steps": K_win, "warmup": W, "ms_per_step": head["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "N=%d random Hermitian channels on 200 R points (53.7 GB of "
+                                   "FP32 tables), %d trajectories from 20 A, the whole collision "
+                                   "of %d RK4 steps of T/%d on the binned schedule; one bench "
+                                   "step = %d steps (the %d timed steps cover the collision)"
+                                   % (N, B, T, T, -(-T // K_win), K_win),
+                       "N": N, "K": s.K, "trajectories": B, "rk4_steps": T,
+                       "schedule": "binned", "tables": "C64"},
+            "roofline": head["roofline"],
+            "N2_traj_steps_per_s": head["N2_traj_steps_per_s"],
+            "status_nonzero": head["status_nonzero"], "system": info,
+            "windows": head["windows"]}
+    if "C128/dp5" in finals:
+        dd = np.abs(finals["C64/dp5"] - finals["C128/dp5"])
+        line["fp32_vs_fp64_dP"] = {"max": float(dd.max()), "mean": float(dd.mean()),
+                                   "p99": float(np.percentile(dd, 99)),
+                                   "runs": "whole collision, adaptive DP5 rtol=atol=1e-8, "
+                                           "FP32 vs FP64 tables"}
+        line["dp5_vs_rk4_fp32_max_dP"] = float(np.max(np.abs(finals["C64/dp5"] -
+                                                           finals["C64/rk4"])))
+        line["fp32_speedup_over_fp64_dp5"] = (variants["large/C64/binned/dp5"]["value"] /
+                                              variants["large/C128/binned/dp5"]["value"])
+        log("large: FP32 vs FP64 (DP5) max|dP| %.2e, DP5 vs RK4 (FP32) max|dP| %.2e" % (
+            line["fp32_vs_fp64_dP"]["max"], line["dp5_vs_rk4_fp32_max_dP"]))
+    if not args.headline_only:
+        # the N = 969 mid-collision windows (FP32 and FP64 tables, binned and per trajectory)
+        wa = argparse.Namespace(**vars(args))
+        wa.steps, wa.warmup, wa.only, wa.schedule = 10, 2, None, "both"
+        win = window_variants(wa, storages=["C64", "C128"], gemv_steps=2)
+        for k, v in win["variants"].items():
+            variants["window/" + k] = v
+        line["window_fp32_vs_fp64_max_abs_dP"] = win.get("fp32_vs_fp64_max_abs_dP")
+        # the uneven batch, one call
+        un = uneven_workload(argparse.Namespace(**dict(vars(args), no_cpu=True)))
+        variants["uneven"] = {k: un[k] for k in ("value", "ms_per_step", "config", "per_system",
+                                                 "N2_traj_steps_per_s")}
+        # the adjoint
+        line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps,
+                                         layout=args.adjoint_layout)
+    line["variants"] = variants
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_large(s, b)
+    log("headline run %.0f s in all" % (time.time() - t_all))
+    return line
+
+
+def cpu_baseline_large(s, b, target_s=15.0):
+    """The FP64 oracle on the headline workload: the first trajectories of the batch
+    (one per host thread the oracle uses, OpenMP over trajectories) over the first
+    steps of their collision (about target_s of propagation), on the knots those
+    steps touch; then one trajectory on one thread."""
+    import numpy as np
+    import oracle
+    from synth import systems as S
+    t0 = time.time()
+    phi, v, H, scale = S.gp_rank_factors(s)
+    ks = np.arange(s.K - 6, s.K)
+    o = oracle.OracleSystem(s, knots=oracle.rank_q_knot_tables(s.R_grid, phi, v, H, ks, scale))
+    log("oracle: %d knots of the N=%d tables in %.1fs" % (len(ks), s.N, time.time() - t0))
+    th = oracle.threads()
+
+    def timed(n_traj):
+        sub = b.subset(range(n_traj))
+        sub.n_steps[:] = 1
+        t0 = time.time()
+        o.propagate(sub)
+        t1 = time.time() - t0
+        n = int(max(1, min(40, round(target_s / max(t1, 1e-3)))))
+        sub.n_steps[:] = n
+        t0 = time.time()
+        r = o.propagate(sub)
+        dt = time.time() - t0
+        assert np.all(r["classical"][:, 0] > s.R_grid[ks[0]])
+        log("oracle: %d trajectories x %d steps in %.1fs" % (n_traj, n, dt))
+        return n_traj * n / dt, n
+
+    n_all = min(th, b.B)
+    v_all, n1 = timed(n_all)
+    v_one, n2 = timed(1)
+    return {"value": v_all, "unit": "traj-steps/s", "cores": n_all, "kind": "oracle",
+            "single_thread_value": v_one,
+            "sample": "the first %d of the %d trajectories x the first %d of the %d RK4 steps "
+                      "on %d threads (OpenMP over trajectories), and the first trajectory x %d "
+                      "steps on one thread (FP64 oracle, N=%d complex tables held at the %d knots "
+                      "those steps touch); wall time of the propagation only" % (
+                          n_all, b.B, n1, int(b.n_steps[0]), n_all, n2, s.N, len(ks))}
+
+
+def large_scatter(args):
+    """bin_gemm on the N = 4096 tables where it streams: 512 trajectories spread over
+    the interaction region (R0 uniform in 4-19.5 A, b uniform below min(12 A, 0.9 R0),
+    E_coll 1000 cm^-1), windows of --large-scatter RK4 steps of 10.1 a.u."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import systems as S, units as U
+    N, B, W = args.large_n, args.large_traj, args.large_scatter
+    t0 = time.time()
+    (s,), b = S.config5(n_traj=B, n_steps=10000, N=N, build_tables=False)
+    rng = np.random.default_rng(231202322 + 55)
+    R0 = U.ang_to_bohr(rng.uniform(4.0, 19.5, B))
+    bb = np.minimum(b.b, 0.9 * R0)
+    ctx = mq.Context(0)
+    dev = ctx.device
+    Md = S.gp_tables_device(s, dev)
+    torch.cuda.synchronize()
+    log("large scatter: N=%d tables built in %.1fs" % (N, time.time() - t0))
+    res = {}
+    for storage in ([args.only] if args.only else ["C64", "C128"]):
+        sid = ctx.load_system(R_grid=s.R_grid, E=s.E, M=Md, jx=None, mu=s.mu, storage=storage)
+        sids, Ns = np.full(B, sid, np.int32), np.full(B, N, np.int64)
+        kw = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=bb, R0=R0, dt=b.dt,
+                  n_steps=np.full(B, W), schedule="binned")
+        for _ in range(args.warmup):
+            ctx.run(sids, Ns, **kw)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.set_profiling(True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.run(sids, Ns, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        km, kn, kb = ctx.profile_read(with_bytes=True)
+        ctx.set_profiling(False)
+        ms = e0.elapsed_time(e1) / args.steps
+        kms = km / kn
+        gbps = kb / (km * 1e-3) / 1e9
+        tf = 32.0 * N * N * B / (kms * 1e-3) / 1e12
+        res[storage] = {"value": B * W / (ms * 1e-3), "ms_per_step": ms, "launch_ms": kms,
+                        "launches": kn, "table_bytes_per_launch": kb / kn,
+                        "occupied_knots_per_launch": kb / kn / (2.0 * N * N * (8 if storage == "C64" else 16)),
+                        "table_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS, "TFLOPs": tf}
+        log("large scatter %s: %.2f ms per window of %d steps, bin_gemm %.3f ms x %d, %.1f knots, "
+            "%.0f GB/s (%.1f%% of HBM), %.1f TFLOP/s" % (
+                storage, ms, W, kms, kn, res[storage]["occupied_knots_per_launch"], gbps,
+                100 * gbps / HBM_PEAK_GBPS, tf))
+        ctx.free_system(sid)
+    del Md
+    ctx.close()
+    return {"workload": "N=%d scattered window" % N, "variants": res}
 
 
 def large_dp5(ctx, sid, sids, Ns, b, storage, rtol=1e-8):
@@ -772,25 +1129,9 @@ def uneven_workload(args):
                  R0=b.R0[w], max_steps=50, **DP)
     log("uneven: autotuner %s" % ctx.tuning_report())
     torch.cuda.synchronize()
-    big_sys = int(np.argmax([x.N for x in systems]))
-    parts = {}
     t1 = time.time()
-    if args.uneven_schedule == "queue":
-        g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, **start, **DP)
-    else:
-        # the largest system alone on the binned schedule, the others on the work list
-        g = {}
-        for name, m, sched in (("work_list", b.system_index != big_sys, "queue"),
-                               ("binned", b.system_index == big_sys, "binned")):
-            ta = time.time()
-            part = ctx.run_host(sids[m], Ns[m], max_steps=args.uneven_max_steps, schedule=sched,
-                                **{k: v[m] for k, v in start.items()}, **DP)
-            parts[name] = {"seconds": time.time() - ta, "trajectories": int(m.sum()),
-                           "steps": int(part["steps"].sum())}
-            for k in ("steps", "rejects", "status"):
-                if k not in g:
-                    g[k] = np.zeros(b.B, part[k].dtype)
-                g[k][m] = part[k]
+    g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, schedule=args.uneven_schedule,
+                     **start, **DP)
     sec = time.time() - t1
     steps, rej = g["steps"], g["rejects"]
     evals = 6 * (steps + rej) + 3          # attempts x 6, the two starting evaluations, the end
@@ -806,39 +1147,25 @@ def uneven_workload(args):
                              "rejects": int(rej[m].sum()),
                              "exited": int(np.count_nonzero(g["status"][m] & 1)),
                              "max_steps_reached": int(np.count_nonzero(g["status"][m] & 2))}
-    gbps = alg_bytes / sec / 1e9
+    gbps = alg_bytes / sec / 1e9   # per-trajectory streaming equivalent (the binned share reads less)
     line = {"metric": METRIC, "value": float(steps.sum()) / sec, "unit": "traj-steps/s",
             "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sec * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "uneven batch of %d trajectories: N=49/256/969 systems "
                                    "60/30/10 %%, E_coll log-uniform 10-5000 cm^-1, DP5 rtol 1e-8, "
-                                   "FP32 tables (%s layout where mostly zero), %s" % (
-                                       b.B, args.uneven_layout,
+                                   "at most %d steps, FP32 tables (%s layout where mostly zero), "
+                                   "one call, %s" % (
+                                       b.B, args.uneven_max_steps, args.uneven_layout,
                                        "work-list schedule" if args.uneven_schedule == "queue"
-                                       else "N=969 on the binned schedule, the rest on the "
-                                            "work list"),
+                                       else "default schedule: the N=969 class binned on a "
+                                            "second stream beside the work list"),
                        "trajectories": b.B},
             "N2_traj_steps_per_s": float(np.sum(steps * Ns.astype(float) ** 2)) / sec,
-            "coupling_GBps": gbps,
-            "roofline": {"kernel": "q_step (all classes, whole job incl. tail)", "bound": "hbm",
-                         "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": gbps / HBM_PEAK_GBPS, "traffic": None},
+            "coupling_work_GBps": gbps,
             "per_system": per, "autotuner": ctx.tuning_report()}
-    if parts:
-        # per-trajectory algorithmic bytes over the work-list call only: the binned
-        # call reads each occupied knot once per stage for all its trajectories
-        m = b.system_index != big_sys
-        wl_bytes = float(np.sum(evals[m] * np.array([rhs_bytes[i] for i in b.system_index[m]])))
-        wl_gbps = wl_bytes / parts["work_list"]["seconds"] / 1e9
-        line["roofline"] = {"kernel": "q_step (work-list classes, incl. tail)", "bound": "hbm",
-                            "achieved": wl_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                            "frac": wl_gbps / HBM_PEAK_GBPS, "traffic": None}
-        line["calls"] = parts
-        del line["coupling_GBps"]
-    log("uneven: %.1f s, %d steps, %.3g traj-steps/s, %s" % (
-        sec, int(steps.sum()), line["value"], json.dumps(parts) if parts else
-        "%.0f GB/s coupling" % gbps))
+    log("uneven: %.1f s, %d steps, %.3g traj-steps/s (%s)" % (
+        sec, int(steps.sum()), line["value"], json.dumps(per)))
     ctx.close()
     if not args.no_cpu:
         line["cpu_baseline"] = uneven_cpu_baseline(systems, b)
@@ -888,17 +1215,30 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256, layout="sparse"):
     w = np.array([(2 * np.pi * b.b_max / b.B) * b.b[i] * (lev != b.init_level[i])
                   for i in range(b.B)])
     kw = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, dt=b.dt, n_steps=b.n_steps,
-              R0=b.R0, checkpoint_every=checkpoint_every)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    grad, P = ctx.adjoint(sid, s.N, w, **kw)
-    sec = time.time() - t0
+              R0=b.R0)
+    # the forward propagation of the same batch alone (per-trajectory schedule)
+    fwd = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        ctx.run([sid] * b.B, [s.N] * b.B, schedule="gemv", **kw)
+        torch.cuda.synchronize()
+        fwd.append(time.time() - t0)
+    sec_all = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        grad, P = ctx.adjoint(sid, s.N, w, checkpoint_every=checkpoint_every, **kw)
+        sec_all.append(time.time() - t0)
+    sec, fsec = sec_all[-1], fwd[-1]
     table_bytes = ctx.system_bytes(sid)
     ctx.close()
-    log("adjoint (%s tables): %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad, "
-        "|grad| = %.3e" % (layout, b.B, n_steps, s.N, grad.shape[0], sec,
-                           float(np.linalg.norm(grad))))
-    return {"s_per_grad": sec, "unit": "s", "layout": layout, "table_bytes": table_bytes,
+    log("adjoint (%s tables): %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad "
+        "(first call %.2f s), forward alone %.2f s (ratio %.1f), |grad| = %.3e" % (
+            layout, b.B, n_steps, s.N, grad.shape[0], sec, sec_all[0], fsec, sec / fsec,
+            float(np.linalg.norm(grad))))
+    return {"s_per_grad": sec, "unit": "s", "first_call_s": sec_all[0], "forward_s": fsec,
+            "adjoint_over_forward": sec / fsec, "layout": layout, "table_bytes": table_bytes,
             "trajectories": b.B,
             "rk4_steps": n_steps, "N": s.N,
             "n_coefficients": int(grad.shape[0]), "checkpoint_every": checkpoint_every,

@@ -180,6 +180,20 @@ mqct_status mqct_system_free(mqct_context* ctx, int32_t system_id);
  *                    their initial amplitudes: many initial states per trajectory.
  *                    energy_err then follows P^2/2mu + P_Phi^2/(2 mu R^2) + U(R)
  *                    and angmom_err follows P_Phi.
+ *   resume           0: start as above.  1: continue every trajectory from the
+ *                    context's state store (mqct_get_state / mqct_set_state: the
+ *                    final state of the previous mqct_run on this context, or
+ *                    what mqct_set_state put there).  B and system_id must match
+ *                    the store; init_channel, a0, classical0, E_coll, b, R0, t0
+ *                    and dt are then ignored.  RK4 takes n_steps[b] further
+ *                    steps of the stored h at t = t_origin + (n_origin + j) h, so
+ *                    that a run split in two equals the whole run bit for bit;
+ *                    DP5 continues with the stored step size, rejection flag
+ *                    and counts (max_steps bounds the total), re-evaluating the
+ *                    first stage at the stored state (first same as last), and
+ *                    returns trajectories whose status holds EXITED,
+ *                    STEP_UNDERFLOW or NONFINITE unchanged (MAX_STEPS is
+ *                    cleared: the limit may have been raised).
  */
 typedef struct {
   int64_t B;
@@ -199,6 +213,7 @@ typedef struct {
   double h_min;
   int32_t schedule;
   int32_t dynamics;
+  int32_t resume;
 } mqct_batch_desc;
 
 /*
@@ -246,6 +261,55 @@ typedef struct {
  * the trajectories still running. */
 mqct_status mqct_run(mqct_context* ctx, const mqct_batch_desc* batch,
                      mqct_batch_result* result);
+
+/*
+ * Full state of one trajectory (Section II: the amplitudes a_n of Eq. 4 and the
+ * classical R, Theta, Phi, P_R, P_Theta, P_Phi of Eqs. 7-10), with what the time
+ * steppers carry from step to step.  Every mqct_run leaves the final state of
+ * each of its trajectories in the context's state store (device memory owned
+ * by the context; the amplitudes are kept beside the records, concatenated in
+ * batch order), where mqct_run with resume = 1 picks it up.
+ *   t              time of the state.
+ *   t_origin, n_origin   t = t_origin + n_origin h as fixed-step RK4 computes its
+ *                  step times (a DP5 run writes t_origin = t, n_origin = 0).
+ *   h              RK4: the step; DP5: the size of the next attempt.
+ *   classical      R, Theta, Phi, P_R, P_Theta, P_Phi.
+ *   E0, J0         total energy and P_Phi - <J_x> at the trajectory's start (the
+ *                  references of energy_err and angmom_err).
+ *   R_exit         DP5 exit radius.
+ *   steps, rejects, attempts   accepted steps, rejected and all DP5 attempts.
+ *   status         MQCT_T_* bits so far.
+ *   flags          MQCT_S_LAST_REJECTED: the last DP5 attempt was rejected (the
+ *                  next accepted step may not grow h).
+ *   system_id, N   the trajectory's system and channel count.
+ */
+enum { MQCT_S_LAST_REJECTED = 1 };
+typedef struct {
+  double t, t_origin, h;
+  double classical[6];
+  double E0, J0, R_exit;
+  int64_t n_origin, steps, rejects, attempts;
+  int32_t status, flags;
+  int32_t system_id, N;
+} mqct_traj_state;
+
+/* Number of trajectories the state store holds (0 before the first run). */
+mqct_status mqct_state_count(mqct_context* ctx, int64_t* count);
+/* Copy the stored state of trajectories [first, first + count) to the host:
+ * state [count] records, amps [sum of their N][2] (complex interleaved, may be
+ * NULL).  Waits for the context stream.  Errors: MQCT_ERR_ARG (range beyond the
+ * store, null state), MQCT_ERR_DEVICE. */
+mqct_status mqct_get_state(mqct_context* ctx, int64_t first, int64_t count,
+                           mqct_traj_state* state, double* amps);
+/* Write host states into the store.  With first = 0 and count different from the
+ * stored count the store is redefined to hold `count` trajectories (their
+ * systems and N from the records); otherwise [first, first + count) must lie in
+ * the store and each record must keep the system and N stored there.  amps
+ * [sum of N][2] is required.  Values must be finite, R > 0, h >= 0, counts >= 0.
+ * Synchronous.  Errors: MQCT_ERR_ARG, MQCT_ERR_STATE (unknown system),
+ * MQCT_ERR_NONFINITE, MQCT_ERR_OOM, MQCT_ERR_DEVICE. */
+mqct_status mqct_set_state(mqct_context* ctx, int64_t first, int64_t count,
+                           const mqct_traj_state* state, const double* amps);
 
 /*
  * Monte-Carlo cross sections (end of Section II; b sampled uniformly on

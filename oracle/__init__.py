@@ -102,17 +102,31 @@ class OracleSystem:
     """A system prepared for the oracle: complex tables and their spline curvature."""
 
     def __init__(self, system, literal_phase=False, tables=None, tangent_tables=None,
-                 plant_coriolis_flip=False, driver=None):
+                 plant_coriolis_flip=False, driver=None, knots=None):
         """driver: U(R_k) [K] hartree -- switches to decoupled (AT) dynamics, in
         which the trajectory is driven by the natural spline of U and feels no
-        force or torque from the quantum state."""
-        M = system.M if tables is None else tables
-        self.N, self.K = int(system.E.shape[0]), int(system.R_grid.shape[0])
-        self.R = _f64(system.R_grid)
+        force or torque from the quantum state.
+
+        knots: (R_sub, M_sub, M2_sub) -- only a run of consecutive knots of the
+        grid with the tables there and their natural-spline second derivatives of
+        the whole grid (see rank_q_knot_tables), for systems too large to hold at
+        every knot; trajectories must stay inside that run of knots."""
+        self.N = int(system.E.shape[0])
         self.E = _f64(system.E)
-        self.M = np.ascontiguousarray(M, dtype=np.complex128)
-        self.M2 = spline_prepare(self.R, self.M.view(np.float64).reshape(self.K, -1)) \
-            .reshape(self.K, self.N, self.N, 2)
+        if knots is not None:
+            R_sub, M_sub, M2_sub = knots
+            self.R = _f64(R_sub)
+            self.K = int(self.R.shape[0])
+            self.M = np.ascontiguousarray(M_sub, dtype=np.complex128)
+            self.M2 = np.ascontiguousarray(M2_sub, dtype=np.complex128).view(np.float64) \
+                .reshape(self.K, self.N, self.N, 2)
+        else:
+            M = system.M if tables is None else tables
+            self.K = int(system.R_grid.shape[0])
+            self.R = _f64(system.R_grid)
+            self.M = np.ascontiguousarray(M, dtype=np.complex128)
+            self.M2 = spline_prepare(self.R, self.M.view(np.float64).reshape(self.K, -1)) \
+                .reshape(self.K, self.N, self.N, 2)
         self.dM = self.dM2 = None
         if tangent_tables is not None:
             self.dM = np.ascontiguousarray(tangent_tables, dtype=np.complex128)
@@ -202,6 +216,35 @@ class OracleSystem:
         lib().oracle_tangent_rk4(C.byref(self.s), B, _p(ic), _p(Ec), _p(bb), _p(r0), _p(dtc),
                                  _p(ns), _p(P), _p(dP))
         return P, dP
+
+
+def rank_q_knot_tables(R, phi, v_diag, H, ks, scale=1.0):
+    """Tables of the form M(R_k) = scale (sum_q phi[k, q] H_q + v_diag[k] 1) at the
+    consecutive knots ks only, with the natural-spline second derivatives of M on
+    the whole grid R at those knots.  The spline's second derivatives are linear
+    in the tabulated values, so those of M are the factors' (each column phi[:, q]
+    and v_diag splined on the whole grid) combined in the same way -- the same
+    numbers, up to rounding, as splining every element of M.  Returns (R[ks],
+    M [len(ks), N, N], M2 [len(ks), N, N])."""
+    ks = np.asarray(ks)
+    assert np.all(np.diff(ks) == 1), "a run of consecutive knots"
+    R = _f64(R)
+    phi = _f64(phi)
+    v_diag = _f64(v_diag)
+    phi2 = spline_prepare(R, phi)
+    v2 = spline_prepare(R, v_diag.reshape(-1, 1)).reshape(-1)
+    Q, N, _ = H.shape
+    Hf = np.ascontiguousarray(H).view(np.float64).reshape(Q, 2 * N * N)
+    eye = np.arange(N)
+
+    def at(coef, diag):
+        out = (coef @ Hf).view(np.complex128).reshape(-1, N, N)
+        for i in range(out.shape[0]):
+            out[i] = 0.5 * (out[i] + out[i].conj().T)
+            out[i][eye, eye] += diag[i]
+        return out * scale
+
+    return R[ks], at(phi[ks], v_diag[ks]), at(phi2[ks], v2[ks])
 
 
 def cross_sections(init_level, b, P, level_of_channel, n_levels, b_max):

@@ -36,7 +36,8 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_system_set_params", "mqct_system_set_theta", "mqct_adjoint",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
            "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients",
-           "mqct_coupling_build_sparse"]
+           "mqct_coupling_build_sparse", "mqct_get_state", "mqct_set_state",
+           "mqct_state_count"]
 
 
 class CouplingDesc(C.Structure):
@@ -67,7 +68,24 @@ class BatchDesc(C.Structure):
                 ("b", C.c_void_p), ("R0", C.c_void_p), ("t0", C.c_void_p),
                 ("integrator", C.c_int32), ("dt", C.c_void_p), ("n_steps", C.c_void_p),
                 ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int64),
-                ("h_min", C.c_double), ("schedule", C.c_int32), ("dynamics", C.c_int32)]
+                ("h_min", C.c_double), ("schedule", C.c_int32), ("dynamics", C.c_int32),
+                ("resume", C.c_int32)]
+
+
+class TrajState(C.Structure):
+    """mqct_traj_state: the stored state of one trajectory."""
+    _fields_ = [("t", C.c_double), ("t_origin", C.c_double), ("h", C.c_double),
+                ("classical", C.c_double * 6), ("E0", C.c_double), ("J0", C.c_double),
+                ("R_exit", C.c_double), ("n_origin", C.c_int64), ("steps", C.c_int64),
+                ("rejects", C.c_int64), ("attempts", C.c_int64), ("status", C.c_int32),
+                ("flags", C.c_int32), ("system_id", C.c_int32), ("N", C.c_int32)]
+
+
+# the same record as a numpy structured type (host copies of the store)
+STATE_DTYPE = np.dtype([("t", "<f8"), ("t_origin", "<f8"), ("h", "<f8"), ("classical", "<f8", (6,)),
+                        ("E0", "<f8"), ("J0", "<f8"), ("R_exit", "<f8"), ("n_origin", "<i8"),
+                        ("steps", "<i8"), ("rejects", "<i8"), ("attempts", "<i8"),
+                        ("status", "<i4"), ("flags", "<i4"), ("system_id", "<i4"), ("N", "<i4")])
 
 
 class BatchResult(C.Structure):
@@ -131,6 +149,12 @@ def lib():
         L.mqct_xs_symmetrize.restype = i32
         L.mqct_rate_coefficients.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, d, i32, vp, vp]
         L.mqct_rate_coefficients.restype = i32
+        L.mqct_get_state.argtypes = [vp, i64, i64, vp, vp]
+        L.mqct_get_state.restype = i32
+        L.mqct_set_state.argtypes = [vp, i64, i64, vp, vp]
+        L.mqct_set_state.restype = i32
+        L.mqct_state_count.argtypes = [vp, C.POINTER(i64)]
+        L.mqct_state_count.restype = i32
         _lib = L
     return _lib
 
@@ -248,10 +272,12 @@ class Context:
     def run(self, system_id, N_of, *, init_channel=None, a0=None, classical0=None, E_coll=None,
             b=None, R0=None, t0=None, dt=None, n_steps=None, integrator="rk4", rtol=1e-8,
             atol=1e-8, max_steps=100000, h_min=1e-6, schedule="auto", out=None,
-            with_amplitudes=True, dynamics="ehrenfest"):
+            with_amplitudes=True, dynamics="ehrenfest", resume=False):
         """Propagate a batch; results are CUDA tensors filled asynchronously on the stream.
 
         system_id: [B] system ids; N_of: [B] channel count of each trajectory's system.
+        resume=True continues every trajectory from the context's state store (the
+        previous run's final states, or set_state's); RK4 then needs only n_steps.
         """
         torch = self.torch
         sid = _host(system_id, np.int32)
@@ -278,7 +304,7 @@ class Context:
         bd = BatchDesc(
             B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None, INTEGRATORS[integrator], None, None,
             float(rtol), float(atol), int(max_steps), float(h_min), SCHEDULES[schedule],
-            DYNAMICS[dynamics])
+            DYNAMICS[dynamics], 1 if resume else 0)
         hold = []
         for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
                                ("b", b, np.float64), ("R0", R0, np.float64), ("t0", t0, np.float64),
@@ -310,6 +336,7 @@ class Context:
         schedule = kw.pop("schedule", "auto")
         integrator = kw.pop("integrator", "rk4")
         dynamics = kw.pop("dynamics", "ehrenfest")
+        resume = kw.pop("resume", False)
         a0 = kw.pop("a0", None)
         classical0 = kw.pop("classical0", None)
         a0h = None
@@ -319,7 +346,8 @@ class Context:
         bd = BatchDesc(B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None,
                        INTEGRATORS[integrator], None, None, float(kw.pop("rtol", 1e-8)),
                        float(kw.pop("atol", 1e-8)), int(kw.pop("max_steps", 100000)),
-                       float(kw.pop("h_min", 1e-6)), SCHEDULES[schedule], DYNAMICS[dynamics])
+                       float(kw.pop("h_min", 1e-6)), SCHEDULES[schedule], DYNAMICS[dynamics],
+                       1 if resume else 0)
         hold = []
         for name, dtp in (("init_channel", np.int32), ("E_coll", np.float64), ("b", np.float64),
                           ("R0", np.float64), ("t0", np.float64), ("dt", np.float64),
@@ -337,6 +365,37 @@ class Context:
                                        "status", "norm_err", "energy_err", "angmom_err")])
         self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
         return out
+
+    # ------------------------------------------------------------------ state store
+    def get_state(self, first=0, count=None):
+        """Host copies of the stored states of trajectories [first, first + count)
+        (default: all of the last run): (records as a STATE_DTYPE array, amplitudes
+        as one complex array concatenated in batch order)."""
+        if count is None:
+            count = self.stored_count() - first
+        rec = np.zeros(count, STATE_DTYPE)
+        self._check(lib().mqct_get_state(self.h, int(first), int(count), rec.ctypes.data, None))
+        amps = np.empty(int(rec["N"].sum()), np.complex128)
+        self._check(lib().mqct_get_state(self.h, int(first), int(count), rec.ctypes.data,
+                                         amps.ctypes.data))
+        return rec, amps
+
+    def set_state(self, rec, amps, first=0):
+        """Write states (STATE_DTYPE records and their concatenated amplitudes) into
+        the store; with first = 0 and a different count the store is redefined."""
+        rec = np.ascontiguousarray(rec, STATE_DTYPE)
+        a = np.ascontiguousarray(np.asarray(amps, np.complex128).reshape(-1))
+        if a.shape[0] != int(rec["N"].sum()):
+            raise ValueError("set_state: %d amplitudes for records holding %d channels"
+                             % (a.shape[0], int(rec["N"].sum())))
+        self._check(lib().mqct_set_state(self.h, int(first), rec.shape[0], rec.ctypes.data,
+                                         a.ctypes.data))
+
+    def stored_count(self):
+        """Number of trajectories in the state store."""
+        n = C.c_int64()
+        self._check(lib().mqct_state_count(self.h, C.byref(n)))
+        return n.value
 
     # ------------------------------------------------------------------ gradients
     def set_params(self, sid, radial, gidx, G):

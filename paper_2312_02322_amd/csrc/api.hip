@@ -11,12 +11,18 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
 using namespace mqct;
 
 namespace {
+
+// An adaptive batch on the default schedule sends the trajectories of a dense
+// system with at least this padded size and count to the binned schedule.
+constexpr int SPLIT_MIN_NPAD = 512;
+constexpr int64_t SPLIT_MIN_TRAJ = 256;
 
 struct SysHost {
   bool live = false;
@@ -29,6 +35,7 @@ struct SysHost {
   void* pbufs[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   void* dbuf = nullptr;   // driving potential of AT dynamics and its curvature: [2][K]
   void* ebuf[2] = {nullptr, nullptr};   // sparse tables: slot lists [W][Npad], kept per column [N]
+  double R_last = 0.0;    // last knot (the default start radius), kept on the host
 };
 
 // Grow-only device buffer.
@@ -49,6 +56,8 @@ struct mqct_context {
   size_t d_systems_cap = 0;
   DevBuf traj, a0, outs[10], xs[4], qws, binws;
   hipStream_t cap = nullptr;       // non-default stream on which graphs are captured
+  hipStream_t side = nullptr;      // second stream: the binned share of a split adaptive batch
+  hipEvent_t side_done = nullptr;  // recorded on `side` when that share has been enqueued
   int* h_counts = nullptr;         // pinned host copy of the work-list counts
   size_t h_counts_cap = 0;
   QueueOpts qopt;                  // work-list schedule options
@@ -58,6 +67,12 @@ struct mqct_context {
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
   Prof prof;                       // optional timing of the dominant step kernel
+  // state store: the final state of every trajectory of the last run (or what
+  // mqct_set_state wrote), records by batch index, amplitudes concatenated
+  DevBuf st_rec, st_amp;
+  int64_t st_B = 0;
+  std::vector<int32_t> st_sys;     // system of each stored trajectory
+  std::vector<int64_t> st_off;     // amplitude offsets, [st_B + 1]
 };
 
 namespace {
@@ -171,7 +186,11 @@ mqct_status mqct_create(int32_t device, void* hip_stream, mqct_context** out) {
     delete c;
     return MQCT_ERR_DEVICE;
   }
-  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) != hipSuccess) {
+    if (c->cap) hipStreamDestroy(c->cap);
+    if (c->side) hipStreamDestroy(c->side);
     hipEventDestroy(c->staged);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -188,12 +207,15 @@ void mqct_destroy(mqct_context* c) {
   for (auto& s : c->systems) free_system(s);
   if (c->d_systems) hipFree(c->d_systems);
   DevBuf* all[] = {&c->traj, &c->a0, &c->xs[0], &c->xs[1], &c->xs[2], &c->xs[3],
-                   &c->qws, &c->binws};
+                   &c->qws, &c->binws, &c->st_rec, &c->st_amp};
   for (DevBuf* b : all) if (b->p) hipFree(b->p);
   for (auto& b : c->outs) if (b.p) hipFree(b.p);
   if (c->h_traj) hipHostFree(c->h_traj);
   if (c->h_counts) hipHostFree(c->h_counts);
+  if (c->side) hipStreamSynchronize(c->side);
   if (c->cap) hipStreamDestroy(c->cap);
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->side_done) hipEventDestroy(c->side_done);
   if (c->staged) hipEventDestroy(c->staged);
   for (hipEvent_t e : c->prof.ev) hipEventDestroy(e);
   if (c->prof.slots) hipHostFree(c->prof.slots);
@@ -420,6 +442,7 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   sh.dev.E = (const double*)sh.bufs[3];
   sh.dev.jx_col = (const int32_t*)sh.bufs[4];
   sh.dev.jx_val = (const double*)sh.bufs[5];
+  sh.R_last = d->R_grid[K - 1];
   sh.live = true;
   int id = -1;
   for (size_t i = 0; i < c->systems.size(); ++i)
@@ -505,15 +528,34 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   if (dp5) {
     if (!(bd->rtol > 0.0) || !(bd->atol > 0.0) || bd->max_steps < 1 || !(bd->h_min >= 0.0))
       return fail(c, MQCT_ERR_ARG, "run: DP5 needs rtol > 0, atol > 0, max_steps >= 1, h_min >= 0");
-  } else if (!bd->dt || !bd->n_steps) {
-    return fail(c, MQCT_ERR_ARG, "run: RK4 needs dt and n_steps");
+  } else if ((!bd->dt && bd->resume != 1) || !bd->n_steps) {
+    return fail(c, MQCT_ERR_ARG, "run: RK4 needs dt and n_steps (n_steps when resuming)");
   }
-  if (!bd->classical0 && (!bd->E_coll || !bd->b))
+  if (bd->resume != 0 && bd->resume != 1)
+    return fail(c, MQCT_ERR_ARG, "run: resume must be 0 or 1");
+  const bool resume = bd->resume == 1;
+  if (!resume && !bd->classical0 && (!bd->E_coll || !bd->b))
     return fail(c, MQCT_ERR_ARG, "run: E_coll and b are required without classical0");
   if (bd->dynamics != MQCT_EHRENFEST && bd->dynamics != MQCT_AT)
     return fail(c, MQCT_ERR_ARG, "run: unknown dynamics %d", bd->dynamics);
-  if (!bd->a0 && !bd->init_channel)
+  if (!resume && !bd->a0 && !bd->init_channel)
     return fail(c, MQCT_ERR_ARG, "run: init_channel is required without a0");
+  // a continued batch: the stored records (read back once) replace the start data
+  std::vector<mqct_traj_state> rec;
+  if (resume) {
+    if (B != c->st_B)
+      return fail(c, MQCT_ERR_STATE, "run: resume needs the %lld stored trajectories, got B = %lld",
+                  (long long)c->st_B, (long long)B);
+    for (int64_t b = 0; b < B; ++b)
+      if (bd->system_id[b] != c->st_sys[b])
+        return fail(c, MQCT_ERR_STATE, "run: trajectory %lld is stored with system %d, not %d",
+                    (long long)b, c->st_sys[b], bd->system_id[b]);
+    rec.resize(B);
+    HIP_TRY(c, hipSetDevice(c->device), "run");
+    HIP_TRY(c, hipMemcpyAsync(rec.data(), c->st_rec.p, B * sizeof(mqct_traj_state),
+                              hipMemcpyDeviceToHost, c->stream), "run: stored state");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "run: stored state");
+  }
 
   // trajectory records
   HIP_TRY(c, hipSetDevice(c->device), "run");
@@ -545,6 +587,46 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     t.t0 = bd->t0 ? bd->t0[b] : 0.0;
     if (t.n_steps < 0) return fail(c, MQCT_ERR_ARG, "run: n_steps[%lld] < 0", (long long)b);
     if (!isfinite(t.dt) || !isfinite(t.t0)) return fail(c, MQCT_ERR_ARG, "run: non-finite dt/t0");
+    if (resume) {
+      const mqct_traj_state& r = rec[b];
+      if (r.N != sy.N || r.system_id != sid)
+        return fail(c, MQCT_ERR_STATE, "run: stored trajectory %lld does not match its system",
+                    (long long)b);
+      t.flags |= TRAJ_HAS_A0 | TRAJ_HAS_C0 | TRAJ_RESUME;
+      for (int i = 0; i < 6; ++i) t.c0[i] = r.classical[i];
+      t.steps0 = r.steps;
+      t.rejects0 = r.rejects;
+      t.attempts0 = r.attempts;
+      t.E0 = r.E0;
+      t.J0 = r.J0;
+      t.R_exit = r.R_exit;
+      t.dflags = r.flags & MQCT_S_LAST_REJECTED;
+      t.status0 = r.status & ~MQCT_T_MAX_STEPS;
+      if (dp5) {
+        // adaptive: continue from t with the stored step size
+        t.t0 = r.t;
+        t.h0 = r.h;
+        if (r.status & (MQCT_T_EXITED | MQCT_T_STEP_UNDERFLOW | MQCT_T_NONFINITE))
+          t.flags |= TRAJ_FINISHED;
+      } else {
+        // fixed steps: t_j = t_origin + j h with j counted on from n_origin
+        t.t0 = r.t_origin;
+        t.step0 = r.n_origin;
+        t.dt = r.h;
+      }
+      if (!(t.c0[0] > 0.0) || !isfinite(t.t0) || !isfinite(t.dt) || !(dp5 ? t.h0 > 0.0 : t.dt > 0.0))
+        return fail(c, MQCT_ERR_STATE, "run: stored trajectory %lld cannot be continued",
+                    (long long)b);
+      if (bd->dynamics == MQCT_AT && !sy.drv)
+        return fail(c, MQCT_ERR_STATE, "run: AT dynamics needs a driving potential for system %d "
+                    "(mqct_system_set_driver)", sid);
+      if (bd->dynamics == MQCT_AT) t.flags |= TRAJ_AT;
+      amp_total += sy.N;
+      order[sy.dtype].push_back(b);
+      max_npad[sy.dtype] = std::max(max_npad[sy.dtype], sy.Npad);
+      c->h_traj[b] = t;
+      continue;
+    }
     if (bd->a0) {
       t.flags |= TRAJ_HAS_A0;
     } else {
@@ -577,7 +659,7 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     c->h_traj[b] = t;
   }
   // default R0 = last knot (needs the grid on the host: read it back once per system)
-  if (!bd->classical0) {
+  if (!bd->classical0 && !resume) {
     std::map<int, double> last;
     for (int64_t b = 0; b < B; ++b) {
       TrajIn& t = c->h_traj[b];
@@ -604,6 +686,8 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   sorted.reserve(B);
   std::vector<std::pair<int64_t, int64_t>> ranges(4, {0, 0});
   std::vector<QueueClass> classes;
+  struct SideGroup { int sys; int64_t first, n; };
+  std::vector<SideGroup> side_groups;   // binned shares of an adaptive batch (records first..)
   auto cost_of = [&](int64_t b) {
     const TrajIn& t = c->h_traj[b];
     const double n = c->systems[t.sys].dev.N;
@@ -621,8 +705,28 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
       ranges[d].second = (int64_t)sorted.size();
     }
   } else {
+    // An adaptive batch left to the library: the trajectories of a large dense
+    // system that holds many of them go to the binned schedule (their stages
+    // become table x columns products on the matrix cores), on a second stream
+    // beside the work list that takes the rest.
+    std::map<int, std::vector<int64_t>> of_system;
+    if (dp5 && bd->schedule == MQCT_SCHED_AUTO)
+      for (int64_t b = 0; b < B; ++b) of_system[c->h_traj[b].sys].push_back(b);
+    std::vector<char> on_side(B, 0);
+    for (auto& kv : of_system) {
+      const DevSystem& sy = c->systems[kv.first].dev;
+      if (sy.ell_w > 0 || sy.Npad < SPLIT_MIN_NPAD || (int64_t)kv.second.size() < SPLIT_MIN_TRAJ ||
+          kv.second.size() > (size_t)INT32_MAX)
+        continue;
+      side_groups.push_back({kv.first, (int64_t)sorted.size(), (int64_t)kv.second.size()});
+      for (int64_t b : kv.second) {
+        sorted.push_back(c->h_traj[b]);
+        on_side[b] = 1;
+      }
+    }
     std::map<std::pair<int, int>, std::vector<int64_t>> by_class;
     for (int64_t b = 0; b < B; ++b) {
+      if (on_side[b]) continue;
       const DevSystem& sy = c->systems[c->h_traj[b].sys].dev;
       by_class[{sy.dtype, sy.Npad}].push_back(b);
     }
@@ -643,13 +747,24 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
                             c->stream), "run: upload");
   HIP_TRY(c, hipEventRecord(c->staged, c->stream), "run: upload");
   const double* d_a0 = nullptr;
-  if (bd->a0) {
+  if (resume) {
+    // the stored amplitudes, copied aside: this run overwrites the store
+    if ((st = ensure(c, c->a0, amp_total * 16, "run: a0")) != MQCT_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->a0.p, c->st_amp.p, amp_total * 16, hipMemcpyDeviceToDevice,
+                              c->stream), "run: stored amplitudes");
+    d_a0 = (const double*)c->a0.p;
+  } else if (bd->a0) {
     if ((st = ensure(c, c->a0, amp_total * 16, "run: a0")) != MQCT_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(c->a0.p, bd->a0, amp_total * 16, hipMemcpyHostToDevice, c->stream),
             "run: a0");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "run: a0");
     d_a0 = (const double*)c->a0.p;
   }
+  // the state store receives every trajectory's final state
+  if ((st = ensure(c, c->st_rec, B * sizeof(mqct_traj_state), "run: state store")) != MQCT_OK)
+    return st;
+  if ((st = ensure(c, c->st_amp, amp_total * 16, "run: state store")) != MQCT_OK) return st;
+  c->st_B = 0;   // valid again once this run is enqueued
 
   // result arrays: caller's device pointers, or device staging for host results
   TrajOut out{};
@@ -673,6 +788,8 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   out.t_final = (double*)dp[3]; out.steps = (int64_t*)dp[4]; out.rejects = (int64_t*)dp[5];
   out.status = (int32_t*)dp[6]; out.norm_err = (double*)dp[7]; out.energy_err = (double*)dp[8];
   out.angmom_err = (double*)dp[9];
+  out.state = (mqct_traj_state*)c->st_rec.p;
+  out.st_amp = (double2*)c->st_amp.p;
 
   if (binned && dp5) {
     const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
@@ -724,26 +841,148 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     } else {
       for (int64_t b = 0; b < B; ++b) max_attempts = std::max(max_attempts, c->h_traj[b].n_steps);
     }
-    if ((st = ensure(c, c->qws, queue_workspace_bytes(classes, method), "run: work-list workspace")) != MQCT_OK)
-      return st;
-    if (classes.size() > c->h_counts_cap) {
-      if (c->h_counts) hipHostFree(c->h_counts);
-      c->h_counts = nullptr;
-      c->h_counts_cap = 0;
-      HIP_TRY(c, hipHostMalloc((void**)&c->h_counts, classes.size() * 4 + 64, 0), "run: counts");
-      c->h_counts_cap = classes.size() + 16;
+    if (!classes.empty()) {
+      if ((st = ensure(c, c->qws, queue_workspace_bytes(classes, method), "run: work-list workspace")) != MQCT_OK)
+        return st;
+      if (classes.size() > c->h_counts_cap) {
+        if (c->h_counts) hipHostFree(c->h_counts);
+        c->h_counts = nullptr;
+        c->h_counts_cap = 0;
+        HIP_TRY(c, hipHostMalloc((void**)&c->h_counts, classes.size() * 4 + 64, 0), "run: counts");
+        c->h_counts_cap = classes.size() + 16;
+      }
     }
-    hipError_t e = run_queue(c->d_systems, (const TrajIn*)c->traj.p, classes, d_a0, out, method,
-                             ctl, max_attempts, c->qopt, c->qcache, c->qws.p, c->stream, c->cap,
-                             c->h_counts, &c->prof);
+    // the binned shares run on the side stream, driven by a host thread of their
+    // own, while this thread drives the work list
+    if (!side_groups.empty()) {
+      size_t wsb = 0;
+      for (const SideGroup& g : side_groups) {
+        const DevSystem& hs = c->systems[g.sys].dev;
+        wsb = std::max(wsb, binned_dp5_workspace_bytes((int)g.n, hs.Npad, hs.K, dtype_fp32(hs.dtype)));
+      }
+      if ((st = ensure(c, c->binws, wsb, "run: binned workspace")) != MQCT_OK) return st;
+      // records and start amplitudes are on the device before the side starts
+      HIP_TRY(c, hipStreamSynchronize(c->stream), "run: upload");
+    }
+    hipError_t side_err = hipSuccess;
+    std::thread side_thread;
+    if (!side_groups.empty())
+      side_thread = std::thread([c, ctl, max_attempts, d_a0, out, &side_groups, &side_err]() {
+        hipError_t e = hipSetDevice(c->device);
+        for (size_t k = 0; k < side_groups.size() && e == hipSuccess; ++k) {
+          const SideGroup& g = side_groups[k];
+          e = run_binned_dp5(c->d_systems, c->systems[g.sys].dev, (const TrajIn*)c->traj.p + g.first,
+                             (int)g.n, d_a0, out, ctl, max_attempts, c->binws.p, c->side, nullptr);
+        }
+        if (e == hipSuccess) e = hipEventRecord(c->side_done, c->side);
+        side_err = e;
+      });
+    hipError_t e = hipSuccess;
+    if (!classes.empty())
+      e = run_queue(c->d_systems, (const TrajIn*)c->traj.p, classes, d_a0, out, method, ctl,
+                    max_attempts, c->qopt, c->qcache, c->qws.p, c->stream, c->cap, c->h_counts,
+                    &c->prof);
+    if (side_thread.joinable()) {
+      side_thread.join();
+      if (side_err != hipSuccess) return hip_fail(c, side_err, "run: binned share");
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, c->side_done, 0), "run: binned share");
+    }
     if (e == hipErrorInvalidValue)
       return fail(c, MQCT_ERR_UNSUPPORTED, "run: no workgroup shape for this N and storage type");
     if (e != hipSuccess) return hip_fail(c, e, "run: work-list schedule");
   }
+  // the store now describes this batch (records by batch index)
+  c->st_B = B;
+  c->st_sys.assign(bd->system_id, bd->system_id + B);
+  c->st_off.assign(B + 1, 0);
+  for (int64_t b = 0; b < B; ++b)
+    c->st_off[b + 1] = c->st_off[b] + c->systems[bd->system_id[b]].dev.N;
   for (auto& p : back)
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
             "run: results");
   if (res->mem == MQCT_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream), "run: results");
+  return MQCT_OK;
+}
+
+mqct_status mqct_state_count(mqct_context* c, int64_t* count) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!count) return fail(c, MQCT_ERR_ARG, "state_count: null argument");
+  *count = c->st_B;
+  return MQCT_OK;
+}
+
+mqct_status mqct_get_state(mqct_context* c, int64_t first, int64_t count, mqct_traj_state* state,
+                           double* amps) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!state || first < 0 || count < 0 || first + count > c->st_B)
+    return fail(c, MQCT_ERR_ARG, "get_state: range [%lld, %lld) beyond the %lld stored "
+                "trajectories (or null state)", (long long)first, (long long)(first + count),
+                (long long)c->st_B);
+  if (count == 0) return MQCT_OK;
+  HIP_TRY(c, hipSetDevice(c->device), "get_state");
+  HIP_TRY(c, hipMemcpyAsync(state, (const mqct_traj_state*)c->st_rec.p + first,
+                            count * sizeof(mqct_traj_state), hipMemcpyDeviceToHost, c->stream),
+          "get_state");
+  if (amps) {
+    const int64_t a0 = c->st_off[first], a1 = c->st_off[first + count];
+    HIP_TRY(c, hipMemcpyAsync(amps, (const double2*)c->st_amp.p + a0, (a1 - a0) * 16,
+                              hipMemcpyDeviceToHost, c->stream), "get_state");
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "get_state");
+  return MQCT_OK;
+}
+
+mqct_status mqct_set_state(mqct_context* c, int64_t first, int64_t count,
+                           const mqct_traj_state* state, const double* amps) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!state || !amps || first < 0 || count < 1)
+    return fail(c, MQCT_ERR_ARG, "set_state: need count >= 1, first >= 0, state and amps");
+  const bool redefine = first == 0 && count != c->st_B;
+  if (!redefine && first + count > c->st_B)
+    return fail(c, MQCT_ERR_ARG, "set_state: range [%lld, %lld) beyond the %lld stored "
+                "trajectories", (long long)first, (long long)(first + count), (long long)c->st_B);
+  int64_t amp_n = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const mqct_traj_state& r = state[i];
+    const int sid = r.system_id;
+    if (sid < 0 || sid >= (int)c->systems.size() || !c->systems[sid].live)
+      return fail(c, MQCT_ERR_STATE, "set_state: record %lld names unknown system %d",
+                  (long long)i, sid);
+    if (r.N != c->systems[sid].dev.N)
+      return fail(c, MQCT_ERR_ARG, "set_state: record %lld has N = %d, its system %d", (long long)i,
+                  r.N, c->systems[sid].dev.N);
+    if (!redefine && (sid != c->st_sys[first + i]))
+      return fail(c, MQCT_ERR_ARG, "set_state: record %lld changes the stored system", (long long)i);
+    const double v[12] = {r.t, r.t_origin, r.h, r.classical[0], r.classical[1], r.classical[2],
+                          r.classical[3], r.classical[4], r.classical[5], r.E0, r.J0, r.R_exit};
+    if (!finite_arr(v, 12)) return fail(c, MQCT_ERR_NONFINITE, "set_state: record %lld", (long long)i);
+    if (!(r.classical[0] > 0.0) || !(r.h >= 0.0) || r.n_origin < 0 || r.steps < 0 ||
+        r.rejects < 0 || r.attempts < 0)
+      return fail(c, MQCT_ERR_ARG, "set_state: record %lld: need R > 0, h >= 0, counts >= 0",
+                  (long long)i);
+    amp_n += r.N;
+  }
+  if (!finite_arr(amps, 2 * amp_n)) return fail(c, MQCT_ERR_NONFINITE, "set_state: amplitudes");
+  HIP_TRY(c, hipSetDevice(c->device), "set_state");
+  mqct_status st;
+  if (redefine) {
+    if ((st = ensure(c, c->st_rec, count * sizeof(mqct_traj_state), "set_state")) != MQCT_OK)
+      return st;
+    if ((st = ensure(c, c->st_amp, amp_n * 16, "set_state")) != MQCT_OK) return st;
+    c->st_B = count;
+    c->st_sys.resize(count);
+    c->st_off.assign(count + 1, 0);
+    for (int64_t i = 0; i < count; ++i) {
+      c->st_sys[i] = state[i].system_id;
+      c->st_off[i + 1] = c->st_off[i] + state[i].N;
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync((mqct_traj_state*)c->st_rec.p + first, state,
+                            count * sizeof(mqct_traj_state), hipMemcpyHostToDevice, c->stream),
+          "set_state");
+  HIP_TRY(c, hipMemcpyAsync((double2*)c->st_amp.p + c->st_off[first], amps, amp_n * 16,
+                            hipMemcpyHostToDevice, c->stream), "set_state");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "set_state");
   return MQCT_OK;
 }
 
@@ -899,7 +1138,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
   if (bd->integrator != MQCT_RK4) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: RK4 only");
   if (bd->dynamics != MQCT_EHRENFEST)
     return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: Ehrenfest dynamics only");
-  if (bd->a0 || bd->classical0 || bd->t0)
+  if (bd->a0 || bd->classical0 || bd->t0 || bd->resume)
     return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: start states come from init_channel/E_coll/b/R0");
   if (checkpoint_every < 1) return fail(c, MQCT_ERR_ARG, "adjoint: checkpoint_every must be >= 1");
   const int sid = bd->system_id[0];

@@ -27,6 +27,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace mqct {
@@ -48,7 +49,9 @@ struct BinWS {
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
   double2* c64;           // [B][Npad] c = e^{-iEt} a of the stage in the combine, FP64,
                           // when Npad is too large for LDS
-  void* cst;              // [B][2][KR] the two real columns of c in the table precision
+  void* cst;              // c of every trajectory in the table precision: complex tables
+                          // [B][KR] the real column (Re c, -Im c) (the product forms the
+                          // second one, (Im c, Re c), from it); real tables [B][2][KR]
   void* uv;               // [2][B][Npad][4] in the table precision, left / right knot:
                           // (zA_re, zB_re, zA_im, zB_im), the value (A) and second-
                           // derivative (B) slices times c, before the spline weights
@@ -67,7 +70,7 @@ struct BinWS {
   int* offset;            // [K]
   int* list;              // [2B] bin entries 2 b + side (0: left knot, 1: right knot)
   int4* items;            // [max_items] (knot, first entry, count, 0)
-  int* n_items;           // [1]
+  int* n_items;           // [1] work items
   unsigned long long* occ;   // [1] occupied knots summed over the stages of the run
 };
 
@@ -111,9 +114,20 @@ bin_init(BinWS ws, const DevSystem* __restrict__ systems, const double* __restri
     }
     ws.diag[b * 4 + 2] = theta;
     ws.diag[b * 4 + 3] = ptheta;
-    ws.status[b] = 0;
+    if (tj.flags & TRAJ_RESUME) {
+      // a stored state: the references of the diagnostics continue
+      ws.diag[b * 4] = tj.E0;
+      ws.diag[b * 4 + 1] = tj.J0;
+    }
+    ws.status[b] = tj.status0;
     ws.done[b] = -1;
   }
+}
+
+// The starting separation of a trajectory (its exit radius unless it continues
+// a stored state).
+__device__ __forceinline__ double start_R(const TrajIn& tj) {
+  return (tj.flags & TRAJ_HAS_C0) ? tj.c0[0] : tj.R0;
 }
 
 __global__ void bin_zero(int* p, int n) {
@@ -137,22 +151,19 @@ __device__ __forceinline__ void stage_setup(const BinWS& ws, const DevSystem& sy
   if (sp.below && count_below) ws.status[b] |= ST_BELOW_GRID;
 }
 
-// Element n of the two real columns of c in the table precision (KR = 2 Npad
-// reals for complex tables, Npad for real ones): complex tables take
-// (Re c_n, -Im c_n) and (Im c_n, Re c_n) at reals 2n, 2n+1; real tables take
-// Re c_n and Im c_n.
+// Element n of c in the table precision: complex tables store the real column
+// (Re c_n, -Im c_n) at reals 2n, 2n+1 (KR = 2 Npad reals per trajectory); real
+// tables store the two columns Re c and Im c (KR = Npad each).
 template <typename S, bool CPLX>
 __device__ __forceinline__ void put_cols(const BinWS& ws, int b, int Npad, int n, double2 c) {
-  const int64_t KR = (CPLX ? 2 : 1) * (int64_t)Npad;
-  S* col0 = (S*)ws.cst + (int64_t)b * 2 * KR;
-  S* col1 = col0 + KR;
   const S re = (S)c.x, im = (S)c.y;
   if constexpr (CPLX) {
+    S* col0 = (S*)ws.cst + (int64_t)b * 2 * Npad;
     col0[2 * n] = re; col0[2 * n + 1] = -im;
-    col1[2 * n] = im; col1[2 * n + 1] = re;
   } else {
+    S* col0 = (S*)ws.cst + (int64_t)b * 2 * Npad;
     col0[n] = re;
-    col1[n] = im;
+    col0[Npad + n] = im;
   }
 }
 
@@ -177,7 +188,7 @@ bin_prep(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, int
   const double h = tj.dt;
   const double cf = diag ? 0.0 : stage_frac(st) * h;
   const int64_t jsteps = diag ? (dn >= 0 ? (int64_t)dn : tj.n_steps) : j;
-  const double t = tj.t0 + (double)jsteps * h + cf;
+  const double t = tj.t0 + (double)(tj.step0 + jsteps) * h + cf;
   double ys[4];
   for (int i = 0; i < 4; ++i) ys[i] = fma(cf, ws.kcl[b * 4 + i], ws.ycl[b * 4 + i]);
   if (threadIdx.x == 0) stage_setup(ws, sy, b, ys, t, !diag);
@@ -265,7 +276,15 @@ __global__ void bin_scatter(BinWS ws) {
   ws.list[ws.offset[k + 1] + p1] = 2 * b + 1;
 }
 
-constexpr int GEMM_PF32 = 2;   // K steps of operands in flight, FP32 tables (deeper rings measured slower)
+// K steps of operands in flight in the product of an item of NX column blocks.
+// Wide items are bound by the matrix cores (a deeper ring measured slower
+// there); items of one to three column blocks are bound by streaming the knot's
+// slices and need more bytes in flight than one step ahead gives, which the
+// registers their few accumulators leave free provide.
+template <bool FP32, int NX> constexpr int gemm_pf() {
+  if constexpr (FP32) return NX <= 2 ? 6 : (NX == 3 ? 4 : 2);
+  else return NX <= 2 ? 4 : 2;
+}
 // ring periods per loop iteration: the compiler's waits for the loads are exact
 // inside an iteration and conservative only across the loop's back edge
 constexpr int GEMM_UF = 1;
@@ -316,8 +335,7 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   using S = typename std::conditional<FP32, float, double>::type;
   using V = typename MF<S>::V;
   constexpr int RB = 2;
-  // K steps of operands in flight: the FP32 form has the registers for a deeper ring
-  constexpr int PF = FP32 ? GEMM_PF32 : 2;
+  constexpr int PF = gemm_pf<FP32, NX>();
   constexpr int NCOMP = CPLX ? 2 : 1;
   const int N = sy.N, Npad = sy.Npad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -333,13 +351,16 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   // the steps beyond would add exact zeros
   const int KE = (N * NCOMP + 15) & ~15;
 
-  // this lane's real column in each column block
+  // this lane's real column in each column block: complex tables keep one real
+  // column per trajectory, (Re c, -Im c); the second, (Im c, Re c), is that
+  // column with each pair swapped and one sign changed, formed in registers by
+  // the odd lanes from the same 16 bytes (one load address per trajectory)
   const S* col[NX];
 #pragma unroll
   for (int cb = 0; cb < NX; ++cb) {
     const int jt = (cb * 16 + c16) >> 1;
     const int e = ws.list[start + (jt < count ? jt : 0)];
-    col[cb] = (const S*)ws.cst + ((int64_t)(e >> 1) * 2 + part) * KR + 4 * q;
+    col[cb] = (const S*)ws.cst + (int64_t)(e >> 1) * 2 * Npad + (CPLX ? 0 : part * Npad) + 4 * q;
   }
   V acc[RB][2][NX];
 #pragma unroll
@@ -362,30 +383,47 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
     }
 #pragma unroll
     for (int cb = 0; cb < NX; ++cb) {
+      S v[4];
       if constexpr (FP32) {
-        const float4 v = *(const float4*)(col[cb] + k0);
-        bo[cb][0] = v.x; bo[cb][1] = v.y; bo[cb][2] = v.z; bo[cb][3] = v.w;
+        const float4 w = *(const float4*)(col[cb] + k0);
+        v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
       } else {
         const double2 v0 = *(const double2*)(col[cb] + k0);
         const double2 v1 = *(const double2*)(col[cb] + k0 + 2);
-        bo[cb][0] = v0.x; bo[cb][1] = v0.y; bo[cb][2] = v1.x; bo[cb][3] = v1.y;
+        v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
       }
+      bo[cb][0] = v[0]; bo[cb][1] = v[1]; bo[cb][2] = v[2]; bo[cb][3] = v[3];
     }
   };
+  // the odd lanes of complex tables turn the loaded (Re c, -Im c) pairs into (Im c,
+  // Re c) pairs here, where the step's operands are used (at load time the
+  // select would wait for the loads in flight)
   auto mma = [&](const S (&ai)[RB][2][4], const S (&bi)[NX][4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int cb = 0; cb < NX; ++cb)
+      for (int cb = 0; cb < NX; ++cb) {
+        S bval = bi[cb][i];
+        if constexpr (CPLX) {
+          const S sw = bi[cb][i ^ 1];
+          bval = part ? ((i & 1) ? sw : -sw) : bval;
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
           for (int s = 0; s < 2; ++s)
-            acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bi[cb][i], acc[r][s][cb]);
+            acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bval, acc[r][s][cb]);
+      }
   };
-  // K steps past the last one reload that step's operands (unused) rather than branch
+  // K steps past the last one reload that step's operands (unused) rather than branch.
+  // The prologue issues the ring's steps in ring order, as the loop does: the
+  // compiler's wait counts at the loop head hold for both the entry and the back
+  // edge, and a reordered prologue would make them wait for the whole ring.
 #pragma unroll
-  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KE - 16), a[j], bv[j]);
+  for (int j = 0; j < PF - 1; ++j) {
+    load(min(16 * j, KE - 16), a[j], bv[j]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   for (int k0 = 0; k0 < KE; k0 += 16 * PF * GEMM_UF) {
 #pragma unroll
     for (int j = 0; j < PF * GEMM_UF; ++j) {
@@ -424,12 +462,12 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   }
 }
 
-template <int DT, int NX>
+template <int DT, int NX, int NXMIN>
 __device__ __forceinline__ void gemm_dispatch(const BinWS& ws, const DevSystem& sy, int rb, int g,
                                               int start, int count, int ncb) {
-  if constexpr (NX > 1) {
+  if constexpr (NX > NXMIN) {
     if (ncb < NX) {
-      gemm_dispatch<DT, NX - 1>(ws, sy, rb, g, start, count, ncb);
+      gemm_dispatch<DT, NX - 1, NXMIN>(ws, sy, rb, g, start, count, ncb);
       return;
     }
   }
@@ -451,6 +489,7 @@ constexpr size_t GEMM_LDS_CAP = 96 * 1024;
 // j-th workgroup takes row block j mod nrb of item x + 8 (j / nrb).  The items
 // arrive largest first, so every die starts on its long items and ends on its
 // short ones.
+//
 template <int DT>
 __global__ void __launch_bounds__(256)
 bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
@@ -463,10 +502,10 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
     // real FP64 tables: at most four column blocks per pass (eight would spill)
     for (int c0 = 0; c0 < it.z; c0 += 32) {
       const int cnt = min(32, it.z - c0);
-      gemm_dispatch<DT, 4>(ws, sy, rb, it.x, it.y + c0, cnt, (cnt + 7) >> 3);
+      gemm_dispatch<DT, 4, 1>(ws, sy, rb, it.x, it.y + c0, cnt, (cnt + 7) >> 3);
     }
   } else {
-    gemm_dispatch<DT, TB / 8>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
+    gemm_dispatch<DT, TB / 8, 1>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
   }
 }
 
@@ -515,7 +554,7 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   const int stn = st == 3 ? 0 : st + 1;
   const int64_t jn = st == 3 ? j + 1 : j;
   const double cfn = stage_frac(stn) * h;
-  const double tn = tj.t0 + (double)jn * h + cfn;
+  const double tn = tj.t0 + (double)(tj.step0 + jn) * h + cfn;
   const bool same_t = tn == t;
   const double* wt = ws.wts + (int64_t)b * 8;
   const double w0 = wt[0], w1 = wt[1], w2 = wt[2], w3 = wt[3];
@@ -596,14 +635,20 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
   const double norm = sums[4], jx = sums[5];
   const double E = ys[2] * ys[2] / (2.0 * mu) + ys[3] * ys[3] / (2.0 * mu * R * R) + erot + vexp;
   if (diag) {
-    const int64_t steps = ws.done[b] >= 0 ? (int64_t)ws.done[b] : tj.n_steps;
+    const int64_t taken = ws.done[b] >= 0 ? (int64_t)ws.done[b] : tj.n_steps;
+    const int64_t steps = tj.steps0 + taken;
     for (int n = threadIdx.x; n < N; n += NT) {
       const double2 a = ws.a0[(int64_t)b * Npad + n];
       out.P[tj.amp_off + n] = a.x * a.x + a.y * a.y;
       if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a;
+      if (out.st_amp) out.st_amp[tj.amp_off + n] = a;
     }
     if (threadIdx.x == 0) {
       const int64_t id = tj.id;
+      // the references were taken at the first evaluation, or come with a stored state
+      const bool ref = taken > 0 || (tj.flags & TRAJ_RESUME);
+      const double E0 = ref ? ws.diag[b * 4] : E;
+      const double J0 = ref ? ws.diag[b * 4 + 1] : ys[3] - jx;
       if (out.classical) {
         double* o = out.classical + id * 6;
         o[0] = ys[0]; o[1] = ws.diag[b * 4 + 2]; o[2] = ys[1]; o[3] = ys[2];
@@ -611,22 +656,19 @@ bin_combine(BinWS ws, const DevSystem* __restrict__ systems, int64_t j, int st, 
       }
       if (out.t_final) out.t_final[id] = t;
       if (out.steps) out.steps[id] = steps;
-      if (out.rejects) out.rejects[id] = 0;
+      if (out.rejects) out.rejects[id] = tj.rejects0;
       if (out.status) out.status[id] = ws.status[b];
       if (out.norm_err) out.norm_err[id] = norm - 1.0;
-      if (out.energy_err) {
-        const double E0 = steps > 0 ? ws.diag[b * 4] : E;
-        out.energy_err[id] = (E - E0) / fabs(E0);
-      }
-      if (out.angmom_err) {
-        const double J0 = steps > 0 ? ws.diag[b * 4 + 1] : ys[3] - jx;
-        out.angmom_err[id] = (ys[3] - jx) - J0;
-      }
+      if (out.energy_err) out.energy_err[id] = (E - E0) / fabs(E0);
+      if (out.angmom_err) out.angmom_err[id] = (ys[3] - jx) - J0;
+      put_traj_state(out, tj, N, t, tj.t0, tj.step0 + taken, h, ys, ws.diag[b * 4 + 2],
+                     ws.diag[b * 4 + 3], E0, J0, start_exit_radius(tj, start_R(tj)), steps,
+                     tj.rejects0, tj.attempts0 + taken, ws.status[b], tj.dflags);
     }
     return;
   }
   if (threadIdx.x == 0) {
-    if (j == 0 && st == 0) {
+    if (j == 0 && st == 0 && !(tj.flags & TRAJ_RESUME)) {
       ws.diag[b * 4] = E;
       ws.diag[b * 4 + 1] = ys[3] - jx;
     }
@@ -856,6 +898,7 @@ d5_combine(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, int mode, in
       const double2 a = ws.a0[(int64_t)b * Npad + n];
       out.P[tj.amp_off + n] = a.x * a.x + a.y * a.y;
       if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a;
+      if (out.st_amp) out.st_amp[tj.amp_off + n] = a;
     }
     if (threadIdx.x == 0) {
       const int64_t id = tj.id;
@@ -871,11 +914,15 @@ d5_combine(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, int mode, in
       if (out.norm_err) out.norm_err[id] = norm - 1.0;
       if (out.energy_err) out.energy_err[id] = (E - ws.diag[b * 4]) / fabs(ws.diag[b * 4]);
       if (out.angmom_err) out.angmom_err[id] = (ys[3] - jx) - ws.diag[b * 4 + 1];
+      put_traj_state(out, tj, N, t, t, 0, d.h[b], ys, ws.diag[b * 4 + 2], ws.diag[b * 4 + 3],
+                     ws.diag[b * 4], ws.diag[b * 4 + 1], d.rexit[b], d.steps[b], d.rejects[b],
+                     d.attempts[b], ws.status[b],
+                     (d.flags[b] & D5_LASTREJ) ? MQCT_S_LAST_REJECTED : 0);
     }
     return;
   }
   if (threadIdx.x == 0) {
-    if (mode == D5_INIT0) {
+    if (mode == D5_INIT0 && !(tj.flags & TRAJ_RESUME)) {
       ws.diag[b * 4] = E;
       ws.diag[b * 4 + 1] = ys[3] - jx;
     }
@@ -895,6 +942,7 @@ d5_start(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, double rtol, d
   __shared__ double red[NWT * 8];
   const int b = blockIdx.x;
   const TrajIn tj = ws.traj[b];
+  if (tj.flags & TRAJ_RESUME) return;   // a stored state keeps its step size
   const DevSystem sy = systems[tj.sys];
   const int N = sy.N, Npad = sy.Npad;
   const double ncomp = 2.0 * N + 6.0;
@@ -1035,10 +1083,23 @@ d5_accept(BinWS ws, D5WS d, const DevSystem* __restrict__ systems, DpCtl ctl,
 __global__ void d5_init(BinWS ws, D5WS d) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= ws.B) return;
-  d.t[b] = ws.traj[b].t0;
+  const TrajIn& tj = ws.traj[b];
+  d.t[b] = tj.t0;
+  d.d1[b] = 0.0;
+  if (tj.flags & TRAJ_RESUME) {
+    // a stored state: step size, rejection flag and counts continue; a
+    // trajectory that has stopped for good stays as it is
+    d.h[b] = tj.h0;
+    d.rexit[b] = tj.R_exit;
+    d.steps[b] = tj.steps0;
+    d.rejects[b] = tj.rejects0;
+    d.attempts[b] = tj.attempts0;
+    d.flags[b] = ((tj.dflags & MQCT_S_LAST_REJECTED) ? D5_LASTREJ : 0) |
+                 ((tj.flags & TRAJ_FINISHED) ? D5_DONE : 0);
+    return;
+  }
   d.h[b] = 0.0;
   d.rexit[b] = ws.ycl[(int64_t)b * 4];   // set by bin_init, launched before
-  d.d1[b] = 0.0;
   d.steps[b] = 0;
   d.rejects[b] = 0;
   d.attempts[b] = 0;

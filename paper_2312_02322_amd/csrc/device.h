@@ -125,4 +125,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   }
 }
 
+// The stored state of a trajectory at the end of a call (one thread): the
+// record of mqct_traj_state; y = (R, Phi, P_R, P_Phi).
+__device__ __forceinline__ void put_traj_state(const TrajOut& out, const TrajIn& tj, int N,
+                                               double t, double t_origin, int64_t n_origin,
+                                               double h, const double (&y)[4], double theta,
+                                               double ptheta, double E0, double J0,
+                                               double R_exit, int64_t steps, int64_t rejects,
+                                               int64_t attempts, int32_t status, int32_t flags) {
+  if (!out.state) return;
+  mqct_traj_state r;
+  r.t = t; r.t_origin = t_origin; r.h = h;
+  r.classical[0] = y[0]; r.classical[1] = theta; r.classical[2] = y[1];
+  r.classical[3] = y[2]; r.classical[4] = ptheta; r.classical[5] = y[3];
+  r.E0 = E0; r.J0 = J0; r.R_exit = R_exit;
+  r.n_origin = n_origin; r.steps = steps; r.rejects = rejects; r.attempts = attempts;
+  r.status = status; r.flags = flags;
+  r.system_id = tj.sys; r.N = N;
+  out.state[tj.id] = r;
+}
+
+// The exit radius a trajectory starts with: the stored one when it continues a
+// stored state, else its starting R.
+__device__ __forceinline__ double start_exit_radius(const TrajIn& tj, double R_start) {
+  return (tj.flags & TRAJ_RESUME) ? tj.R_exit : R_start;
+}
+
 }  // namespace mqct

@@ -20,7 +20,8 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
   using Base::init_state;
   using Base::write_out;
 
-  // Fixed-step classical RK4: exactly n_steps steps, t_j = t0 + j h.
+  // Fixed-step classical RK4: exactly n_steps steps, t_j = t0 + (j0 + j) h, where
+  // j0 > 0 continues a stored state.
   __device__ static void run_rk4(const DevSystem& sy, const TrajIn& tj,
                                  const double* __restrict__ a0_all, TrajOut& out,
                                  const Lds<DT>& lds) {
@@ -28,18 +29,21 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
     double2 a0[NR], kk[NR], acc[NR];   // kk: stage input, then its derivative
     double y[4], ky[4] = {0.0, 0.0, 0.0, 0.0}, ay[4], theta, ptheta;
     init_state(sy, tj, a0_all, a0, y, theta, ptheta);
+    const double R_exit = start_exit_radius(tj, y[0]);
 #pragma unroll
     for (int r = 0; r < NR; ++r) kk[r] = make_double2(0.0, 0.0);
     const double h = tj.dt, t0 = tj.t0;
+    const bool resume = (tj.flags & TRAJ_RESUME) != 0;
+    const int64_t j0 = tj.step0;
     bool below = false;
-    int32_t status = 0;
-    double E0 = 0.0, J0 = 0.0;
-    bool first = true;
+    int32_t status = tj.status0;
+    double E0 = tj.E0, J0 = tj.J0;
+    bool first = !resume;
     const bool at = (tj.flags & TRAJ_AT) != 0;
     Sums tot;
     int64_t j = 0;
     for (; j < tj.n_steps; ++j) {
-      const double t = t0 + (double)j * h;
+      const double t = t0 + (double)(j0 + j) * h;
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
 #pragma unroll
@@ -84,7 +88,7 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
       }
     }
     // diagnostics at the final state (one more evaluation; its derivative is unused)
-    const double tend = t0 + (double)j * h;
+    const double tend = t0 + (double)(j0 + j) * h;
     bool b2 = false;
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = a0[r];
@@ -94,7 +98,11 @@ struct Kern : Rhs<DT, BLOCK, RPT> {
       J0 = y[3] - tot.jx;
     }
     if (below) status |= ST_BELOW_GRID;
-    write_out(sy, tj, out, a0, y, theta, ptheta, tend, j, 0, status, tot, E0, J0);
+    const int64_t steps = tj.steps0 + j;
+    write_out(sy, tj, out, a0, y, theta, ptheta, tend, steps, tj.rejects0, status, tot, E0, J0);
+    if (threadIdx.x == 0)
+      put_traj_state(out, tj, sy.N, tend, t0, j0 + j, h, y, theta, ptheta, E0, J0, R_exit, steps,
+                     tj.rejects0, tj.attempts0 + j, status, tj.dflags);
   }
 };
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mqct.h"
+
 #include <utility>
 #include <vector>
 
@@ -43,16 +45,27 @@ struct DevSystem {
 struct TrajIn {
   int64_t id;                // index in the caller's batch
   int64_t amp_off;           // offset of this trajectory's amplitudes (sum of N before it)
-  int64_t n_steps;           // RK4 steps
+  int64_t n_steps;           // RK4 steps of this call
   int32_t sys;               // index into the device system table
   int32_t init_channel;
-  int32_t flags;             // bit 0: a0 given; bit 1: classical0 given
-  int32_t pad0;
+  int32_t flags;             // TRAJ_* bits
+  int32_t status0;           // status bits carried from a stored state (TRAJ_RESUME)
   double E_coll, b, R0, t0, dt;
-  double c0[6];              // classical0 when flags & 2
+  double c0[6];              // classical0 when flags & TRAJ_HAS_C0
+  // continuation of a stored state (TRAJ_RESUME; zero otherwise)
+  int64_t step0;             // RK4: time index of the first step, t_j = t0 + (step0 + j) dt
+  int64_t steps0, rejects0, attempts0;   // counts carried
+  double h0;                 // DP5: size of the next attempt
+  double E0, J0, R_exit;     // references of the diagnostics, DP5 exit radius
+  int32_t dflags;            // MQCT_S_LAST_REJECTED
+  int32_t pad1;
 };
 
-enum { TRAJ_HAS_A0 = 1, TRAJ_HAS_C0 = 2, TRAJ_AT = 4 };
+// TRAJ_RESUME: the trajectory continues a stored state (amplitudes and classical
+// state come as a0 / classical0; the fields after c0 hold the stepper's state);
+// TRAJ_FINISHED: a stored adaptive trajectory that has stopped for good (exited,
+// step underflow, non-finite): it is returned unchanged.
+enum { TRAJ_HAS_A0 = 1, TRAJ_HAS_C0 = 2, TRAJ_AT = 4, TRAJ_RESUME = 8, TRAJ_FINISHED = 16 };
 
 // Where a kernel writes its per-trajectory results (device pointers; any may be
 // null except P).
@@ -67,6 +80,8 @@ struct TrajOut {
   double* norm_err;
   double* energy_err;
   double* angmom_err;
+  mqct_traj_state* state;    // [B] the context's state store (by id), or null
+  double2* st_amp;           // its amplitudes (by amp_off), or null
 };
 
 enum { ST_EXITED = 1, ST_MAX_STEPS = 2, ST_STEP_UNDERFLOW = 4, ST_BELOW_GRID = 8,
@@ -197,6 +212,7 @@ struct QState {
   double kc1[4];       // classical derivative at (t, y): first stage of the next attempt
   double E0, J0, R_exit, theta, ptheta;
   int64_t steps, rejects, attempts;
+  int64_t n_idx;       // RK4: time index, t = t0 + n_idx h
   int32_t status, flags;
 };
 enum { Q_DONE = 1, Q_LASTREJ = 2 };

@@ -59,10 +59,25 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     if (threadIdx.x == 0) *p = s;
   }
 
+  // The stored state of a trajectory at the end of the call; rk4: the time is
+  // t0 + n_idx h of fixed steps, else an adaptive time (origin = t).
+  __device__ static void store_state(const DevSystem& sy, const TrajIn& tj, const TrajOut& out,
+                                     const QState& s, bool rk4) {
+    if (threadIdx.x == 0)
+      put_traj_state(out, tj, sy.N, s.t, rk4 ? tj.t0 : s.t, rk4 ? s.n_idx : 0, s.h, s.yc,
+                     s.theta, s.ptheta, s.E0, s.J0, s.R_exit, s.steps, s.rejects, s.attempts,
+                     s.status, (s.flags & Q_LASTREJ) ? MQCT_S_LAST_REJECTED : 0);
+  }
+
   // Results of a finished trajectory: one more right-hand side at its end
-  // state gives the norm, energy and J_x diagnostics.
-  __device__ static void finish(const DevSystem& sy, const TrajIn& tj, const TrajOut& out,
-                                const double2 (&a)[NR], const QState& s, const Lds<DT>& lds) {
+  // state gives the norm, energy and J_x diagnostics.  Compiled once (not
+  // inlined), so that every caller -- a finishing step, or the init of a stored
+  // trajectory that has stopped for good -- forms the results with the same
+  // instructions (the compiler may contract multiply-adds differently in each
+  // inlined copy).
+  __device__ __noinline__ static void finish(const DevSystem& sy, const TrajIn& tj, const TrajOut& out,
+                                const double2 (&a)[NR], const QState& s, const Lds<DT>& lds,
+                                bool rk4) {
     double2 cur[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[r] = a[r];
@@ -71,6 +86,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, b2, lds, (tj.flags & TRAJ_AT) != 0);
     write_out(sy, tj, out, a, s.yc, s.theta, s.ptheta, s.t, s.steps, s.rejects, s.status, tot,
               s.E0, s.J0);
+    if (out.P) store_state(sy, tj, out, s, rk4);
   }
 
   __device__ static void load_rows(const double2* __restrict__ v, int N, double2 (&a)[NR]) {
@@ -97,24 +113,35 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     double2 a[NR], cur[NR];
     QState s{};
     init_state(sy, tj, q.a0_all, a, s.yc, s.theta, s.ptheta);
-    s.t = tj.t0;
+    const bool resume = (tj.flags & TRAJ_RESUME) != 0;
+    s.n_idx = tj.step0;
+    s.t = tj.t0 + (double)s.n_idx * tj.dt;
     s.h = tj.dt;
+    s.R_exit = start_exit_radius(tj, s.yc[0]);
+    s.steps = tj.steps0;
+    s.rejects = tj.rejects0;
+    s.attempts = tj.attempts0;
+    s.status = tj.status0;
+    s.flags = (tj.dflags & MQCT_S_LAST_REJECTED) ? Q_LASTREJ : 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[r] = a[r];
     Sums tot;
     bool below = false;
     eval(sy, s.t, s.yc[0], s.yc[3], cur, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
-    s.E0 = energy(sy.mu, s.yc, tot);
-    s.J0 = s.yc[3] - tot.jx;
+    s.E0 = resume ? tj.E0 : energy(sy.mu, s.yc, tot);
+    s.J0 = resume ? tj.J0 : s.yc[3] - tot.jx;
     store_rows(q.ws.amp + (int64_t)i * q.ws.npad, sy.N, a);
     if (tj.n_steps <= 0) {
-      s.flags = Q_DONE;
-      write_out(sy, tj, q.out, a, s.yc, s.theta, s.ptheta, s.t, 0, 0, 0, tot, s.E0, s.J0);
+      s.flags |= Q_DONE;
+      write_out(sy, tj, q.out, a, s.yc, s.theta, s.ptheta, s.t, s.steps, s.rejects, s.status,
+                tot, s.E0, s.J0);
+      if (q.out.P) store_state(sy, tj, q.out, s, true);
     }
     put_state(q.ws.st + i, s);
   }
 
-  // One classical RK4 step, t_j = t0 + j h; exactly n_steps steps in total.
+  // One classical RK4 step, t_j = t0 + j h (j counted from the start of the
+  // trajectory, also across a stored state); exactly n_steps steps per call.
   __device__ static void step_rk4(const QArgs& q, int i, QState& s, const Lds<DT>& lds) {
     const TrajIn tj = q.ws.traj[i];
     const DevSystem sy = q.systems[tj.sys];
@@ -130,7 +157,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
       kk[r] = make_double2(0.0, 0.0);
       acc[r] = make_double2(0.0, 0.0);
     }
-    const double t = tj.t0 + (double)s.steps * h;
+    const double t = tj.t0 + (double)s.n_idx * h;
     bool below = false;
     Sums tot;
     for (int st = 0; st < 4; ++st) {
@@ -162,16 +189,17 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     for (int k = 0; k < 4; ++k) s.yc[k] = uni(y[k] + h6 * ay[k]);
     s.steps += 1;
     s.attempts += 1;
-    s.t = tj.t0 + (double)s.steps * h;
+    s.n_idx += 1;
+    s.t = tj.t0 + (double)s.n_idx * h;
     if (below) s.status |= ST_BELOW_GRID;
     if (!isfinite(tot.force) || !isfinite(tot.torque) || !isfinite(tot.norm) ||
         !isfinite(s.yc[0]) || !isfinite(s.yc[2]) || !isfinite(s.yc[3])) {
       s.status |= ST_NONFINITE;
       s.flags |= Q_DONE;
     }
-    if (s.steps >= tj.n_steps) s.flags |= Q_DONE;
+    if (s.n_idx - tj.step0 >= tj.n_steps) s.flags |= Q_DONE;
     store_rows(amp, sy.N, a0);
-    if (s.flags & Q_DONE) finish(sy, tj, q.out, a0, s, lds);
+    if (s.flags & Q_DONE) finish(sy, tj, q.out, a0, s, lds, true);
   }
 
   // ---- adaptive Dormand-Prince 5(4) -----------------------------------------
@@ -198,18 +226,37 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     double2 a[NR], f0[NR], st[NR];
     QState s{};
     init_state(sy, tj, q.a0_all, a, s.yc, s.theta, s.ptheta);
+    const bool resume = (tj.flags & TRAJ_RESUME) != 0;
     s.t = tj.t0;
-    s.R_exit = s.yc[0];
+    s.R_exit = start_exit_radius(tj, s.yc[0]);
 #pragma unroll
     for (int r = 0; r < NR; ++r) f0[r] = a[r];
     Sums tot;
     bool below = false;
     eval(sy, s.t, s.yc[0], s.yc[3], f0, tot, below, lds, (tj.flags & TRAJ_AT) != 0);
-    s.E0 = energy(mu, s.yc, tot);
-    s.J0 = s.yc[3] - tot.jx;
+    s.E0 = resume ? tj.E0 : energy(mu, s.yc, tot);
+    s.J0 = resume ? tj.J0 : s.yc[3] - tot.jx;
     classical_rhs(mu, s.yc, tot, s.kc1);
     store_rows(ks, N, f0);
     store_rows(q.ws.amp + (int64_t)i * q.ws.npad, N, a);
+    if (resume) {
+      // a stored state: its step size, rejection flag and counts continue (the
+      // first stage above is f at the stored state, first same as last)
+      s.h = tj.h0;
+      s.steps = tj.steps0;
+      s.rejects = tj.rejects0;
+      s.attempts = tj.attempts0;
+      s.status = tj.status0;
+      s.flags = (tj.dflags & MQCT_S_LAST_REJECTED) ? Q_LASTREJ : 0;
+      if (below) s.status |= ST_BELOW_GRID;
+      if (tj.flags & TRAJ_FINISHED) {
+        // stopped for good: the results as the finishing step gave them
+        s.flags |= Q_DONE;
+        finish(sy, tj, q.out, a, s, lds, false);
+      }
+      put_state(q.ws.st + i, s);
+      return;
+    }
     const double yfull[6] = {s.yc[0], s.theta, s.yc[1], s.yc[2], s.ptheta, s.yc[3]};
     // d0 = ||y||, d1 = ||f(t0, y0)||
     double s2[2] = {0.0, 0.0};
@@ -381,7 +428,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
       s.flags |= Q_DONE;
       double2 a[NR];
       load_rows(amp, N, a);
-      finish(sy, tj, q.out, a, s, lds);
+      finish(sy, tj, q.out, a, s, lds, false);
     }
   }
 };

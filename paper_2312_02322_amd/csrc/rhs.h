@@ -496,6 +496,7 @@ struct Rhs {
       if (n < sy.N) {
         out.P[tj.amp_off + n] = a[r].x * a[r].x + a[r].y * a[r].y;
         if (out.a_final) ((double2*)out.a_final)[tj.amp_off + n] = a[r];
+        if (out.st_amp) out.st_amp[tj.amp_off + n] = a[r];
       }
     }
     if (threadIdx.x == 0) {

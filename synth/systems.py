@@ -136,10 +136,12 @@ def _check_turning_point(v_cm, R_ang, U_cm, r_min_ang=2.5):
 # system 1: rigid-rotor diatom + atom
 
 
-def rotor_atom_system(jmax=6, K=200, B_cm=2.0, mu_amu=4.0, cfg_index=1, with_coriolis=True):
+def rotor_atom_system(jmax=6, K=200, B_cm=2.0, mu_amu=4.0, cfg_index=1, with_coriolis=True,
+                      R_ang=None):
+    """R_ang: the radial grid in angstrom (default K points uniform on 2-20 A)."""
     rng_pot, _, _ = _streams(cfg_index)
     params = _legendre_potential_params(rng_pot, lam_max=4)
-    R_ang = np.linspace(2.0, 20.0, K)
+    R_ang = np.linspace(2.0, 20.0, K) if R_ang is None else np.asarray(R_ang, np.float64)
     V = _v_lambda_cm(params, R_ang)                     # [5, K]
     chans = [(j, m) for j in range(jmax + 1) for m in range(-j, j + 1)]
     N = len(chans)
@@ -177,12 +179,32 @@ def rotor_atom_system(jmax=6, K=200, B_cm=2.0, mu_amu=4.0, cfg_index=1, with_cor
 # Gaussian-process random Hermitian tables (systems 2 and 5)
 
 
-def gp_factors(rng, N, Q=32, length_ang=1.0):
-    """Random-Fourier-feature factors of a squared-exponential GP: (omega, phase, H)."""
+def gp_factors(rng, N, Q=32, length_ang=1.0, workers=0):
+    """Random-Fourier-feature factors of a squared-exponential GP: (omega, phase, H).
+
+    workers > 0: each H_q is drawn from a generator of its own (seeded from rng)
+    on a pool of that many threads -- other values than the serial draw, for
+    sizes where one stream would take a minute."""
     omega = rng.standard_normal(Q) / length_ang
     phase = rng.uniform(0.0, 2.0 * math.pi, Q)
-    X = (rng.standard_normal((Q, N, N)) + 1j * rng.standard_normal((Q, N, N))) / math.sqrt(2.0)
-    H = (X + np.conj(np.swapaxes(X, 1, 2))) / math.sqrt(2.0)   # entry std 1, Hermitian
+    if workers <= 0:
+        X = (rng.standard_normal((Q, N, N)) + 1j * rng.standard_normal((Q, N, N))) / math.sqrt(2.0)
+        H = (X + np.conj(np.swapaxes(X, 1, 2))) / math.sqrt(2.0)   # entry std 1, Hermitian
+        return omega, phase, H
+    from concurrent.futures import ThreadPoolExecutor
+    seeds = rng.integers(0, 2 ** 63 - 1, Q)
+    H = np.empty((Q, N, N), np.complex128)
+
+    def one(q):
+        g = np.random.default_rng(int(seeds[q]))
+        X = np.empty((N, N), np.complex128)
+        X.real = g.standard_normal((N, N))
+        X.imag = g.standard_normal((N, N))
+        X /= math.sqrt(2.0)
+        H[q] = (X + X.conj().T) / math.sqrt(2.0)
+
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(one, range(Q)))
     return omega, phase, H
 
 
@@ -196,13 +218,9 @@ def gp_tables_cm(omega, phase, H, R_ang, s_cm, v_iso_cm):
     K = R_ang.shape[0]
     Q, N, _ = H.shape
     phi = gp_basis(omega, phase, R_ang) * (s_cm * np.exp(-(R_ang - 3.0)))[:, None]
-    Hf = H.reshape(Q, N * N)
-    re = (phi @ Hf.real).reshape(K, N, N)
-    im = (phi @ Hf.imag).reshape(K, N, N)
-    M = np.empty((K, N, N), np.complex128)
-    M.real = re
-    M.imag = im
-    del re, im
+    # real and imaginary parts in one product over the interleaved storage
+    Hv = np.ascontiguousarray(H).view(np.float64).reshape(Q, 2 * N * N)
+    M = (phi @ Hv).view(np.complex128).reshape(K, N, N)
     for k in range(K):
         Mk = M[k]
         M[k] = 0.5 * (Mk + Mk.conj().T)
@@ -340,13 +358,17 @@ def parametric_tables(system, theta):
 
 
 def large_random_system(N=4096, K=200, s_cm=2.0, mu_amu=9.0, cfg_index=5, Q=32,
-                        E_span_cm=2000.0, build_tables=True, dtype=np.complex128):
+                        E_span_cm=2000.0, build_tables=True, dtype=np.complex128, workers=16,
+                        R_ang=None):
+    """N random Hermitian channels (the N = 4096 workload); the GP factors are
+    drawn on `workers` threads (0: one serial stream).  R_ang: the radial grid in
+    angstrom (default K points uniform on 2-20 A)."""
     rng_pot, rng_tab, _ = _streams(cfg_index)
     params = _legendre_potential_params(rng_pot, lam_max=0)
-    R_ang = np.linspace(2.0, 20.0, K)
+    R_ang = np.linspace(2.0, 20.0, K) if R_ang is None else np.asarray(R_ang, np.float64)
     v_iso = _v_lambda_cm(params, R_ang)[0]
     E = np.sort(rng_pot.uniform(0.0, 1.0, N)) * E_span_cm
-    omega, phase, H = gp_factors(rng_tab, N, Q=Q)
+    omega, phase, H = gp_factors(rng_tab, N, Q=Q, workers=workers)
     sysm = System(
         name="random_N%d" % N, R_grid=U.ang_to_bohr(R_ang), E=U.cm_to_hartree(E),
         M=None, jx_row=np.zeros(0, np.int32), jx_col=np.zeros(0, np.int32),
@@ -383,6 +405,16 @@ def gp_tables_device(system, device):
         Mk.copy_(0.5 * (Mk + Mk.conj().transpose(0, 1).contiguous()))
         Mk.diagonal().real.add_(diag[k])
     return M
+
+
+def gp_rank_factors(system):
+    """The generator's factors of a random-table system: phi [K, Q] and v_iso [K]
+    in cm^-1 on its grid, the H_q [Q, N, N] and the cm^-1 -> hartree scale, so that
+    M(R_k) = scale (sum_q phi[k, q] H_q + v_iso[k] 1)."""
+    omega, phase, H = system.labels["gp"]
+    R_ang = system.labels["R_ang"]
+    phi = gp_basis(omega, phase, R_ang) * (system.labels["s_cm"] * np.exp(-(R_ang - 3.0)))[:, None]
+    return phi, np.asarray(system.labels["V_iso_cm"], np.float64), H, U.cm_to_hartree(1.0)
 
 
 def gp_knot_tables(system, ks):

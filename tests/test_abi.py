@@ -45,7 +45,8 @@ def test_struct_layouts_match_header():
     """The ctypes mirrors have the sizes the C compiler gives the header's structs."""
     import paper_2312_02322_amd as mq
     assert C.sizeof(mq.SystemDesc) == 96
-    assert C.sizeof(mq.BatchDesc) == 136   # the trailing int32 dynamics fits the padding
+    assert C.sizeof(mq.BatchDesc) == 144
+    assert C.sizeof(mq.TrajState) == 144 == mq.STATE_DTYPE.itemsize
     assert C.sizeof(mq.BatchResult) == 88
     assert C.sizeof(mq.CouplingDesc) == 120
 

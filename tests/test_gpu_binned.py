@@ -132,12 +132,13 @@ def test_profiled_table_bytes(ctx):
     ctx.free_system(sid)
 
 
-def test_binned_wide_system_c_outside_lds(ctx):
+@pytest.mark.parametrize("storage", ["C128", "C64"])
+def test_binned_wide_system_c_outside_lds(ctx, storage):
     """N = 2100 (padded past 2048 columns): the combine keeps c in device memory
     instead of LDS.  Channels come in degenerate pairs (2i, 2i+1) coupled by a
     real-symmetric J_x, so every row's Coriolis term reads c of another row.
-    Binned against the per-trajectory schedule (both FP64 tables) and against
-    the oracle."""
+    Binned against the per-trajectory schedule and against the oracle (FP64
+    tables 1e-12 / 1e-9, FP32 tables 1e-4)."""
     s = S.large_random_system(N=2100, K=12, cfg_index=7)
     s.E = np.repeat(s.E[0::2], 2)
     s.level_of_channel = (np.arange(s.N) // 2).astype(np.int32)
@@ -149,17 +150,72 @@ def test_binned_wide_system_c_outside_lds(ctx):
     rng = np.random.default_rng(21)
     b = S.mc_batch(s, 3, 600.0, 6.0, [0, 1000, 2099], rng, n_steps=12, dt=20.0,
                    R0_bohr=0.5 * (s.R_grid[6] + s.R_grid[7]))
-    say("binned N=%d (c outside LDS), %d trajectories x %d steps" % (s.N, b.B, 12))
-    sid = ctx.load_system(s, storage="C128")
+    say("binned N=%d %s (c outside LDS), %d trajectories x %d steps" % (s.N, storage, b.B, 12))
+    sid = ctx.load_system(s, storage=storage)
     gb = run(ctx, sid, s, b, "binned")
     gg = run(ctx, sid, s, b, "gemv")
     ctx.free_system(sid)
+    fp64 = storage == "C128"
     d = np.max(np.abs(gb["P"] - gg["P"]))
     say("  max|P_binned - P_gemv| = %.3e" % d)
-    assert d < 1e-12
-    assert np.max(np.abs(gb["classical"] - gg["classical"]) / (1 + np.abs(gg["classical"]))) < 1e-12
+    assert d < (1e-12 if fp64 else 1e-5)
+    assert np.max(np.abs(gb["classical"] - gg["classical"]) / (1 + np.abs(gg["classical"]))) < \
+        (1e-12 if fp64 else 1e-6)
     o = oracle.OracleSystem(s).propagate(b.subset([1]))
-    assert np.max(np.abs(gb["P"][1] - o["P"][0])) < 1e-9
+    d = np.max(np.abs(gb["P"][1] - o["P"][0]))
+    say("  max|P_binned - P_oracle| = %.3e" % d)
+    assert d < (1e-9 if fp64 else 1e-4)
+
+
+@pytest.fixture(scope="module")
+def n4096():
+    """N = 4096 random Hermitian tables on 12 knots (the large workload's size; the
+    grid is short so the oracle can hold it), two trajectories in the middle."""
+    s = S.large_random_system(N=4096, K=12, cfg_index=8)
+    rng = np.random.default_rng(22)
+    b = S.mc_batch(s, 2, 1000.0, 4.0, [0, 7], rng, n_steps=10, dt=20.0,
+                   R0_bohr=0.5 * (s.R_grid[6] + s.R_grid[7]))
+    return s, b
+
+
+@pytest.mark.parametrize("storage", ["C128", "C64"])
+def test_binned_n4096_rk4_against_oracle(ctx, n4096, storage):
+    """The shape of every stage of the large workload: 4096 channels, the c columns
+    and phases outside LDS, the FP32 product summing all 8192 reals of a row in the
+    matrix-core accumulators."""
+    s, b = n4096
+    say("binned N=4096 %s RK4: %d trajectories x %d steps" % (storage, b.B, b.n_steps[0]))
+    sid = ctx.load_system(s, storage=storage)
+    g = run(ctx, sid, s, b, "binned")
+    ctx.free_system(sid)
+    o = oracle.OracleSystem(s).propagate(b)
+    d = np.max(np.abs(g["P"] - o["P"]))
+    say("  max|dP| = %.3e (norm err %.2e)" % (d, np.max(np.abs(g["norm_err"]))))
+    assert d < (1e-9 if storage == "C128" else 1e-4)
+    assert np.max(np.abs(g["classical"] - o["classical"]) / (1 + np.abs(o["classical"]))) < \
+        (1e-9 if storage == "C128" else 1e-6)
+
+
+@pytest.mark.parametrize("storage", ["C128", "C64"])
+def test_binned_n4096_dp5_against_oracle(ctx, n4096, storage):
+    """Adaptive steps at N = 4096 (the binned DP5 stage kernels with c outside
+    LDS): the starting step and four accepted steps against the oracle's."""
+    s, b = n4096
+    say("binned N=4096 %s DP5, 4 accepted steps" % storage)
+    sid = ctx.load_system(s, storage=storage)
+    g = ctx.run_host([sid] * b.B, [s.N] * b.B, init_channel=b.init_channel, E_coll=b.E_coll,
+                     b=b.b, R0=b.R0, integrator="dp5", rtol=1e-8, atol=1e-8, max_steps=4,
+                     h_min=1e-6, schedule="binned")
+    ctx.free_system(sid)
+    o = oracle.OracleSystem(s).propagate(b, method="dp5", rtol=1e-8, atol=1e-8, max_steps=4,
+                                         h_min=1e-6)
+    assert np.all(g["steps"] == 4) and np.all(o["steps"] == 4)
+    if storage == "C128":
+        assert np.array_equal(g["rejects"], o["rejects"])
+        assert np.max(np.abs(g["t_final"] - o["t_final"]) / o["t_final"]) < 1e-9
+    d = np.max(np.abs(g["P"].reshape(b.B, s.N) - o["P"]))
+    say("  max|dP| = %.3e, t %s vs %s" % (d, g["t_final"], o["t_final"]))
+    assert d < (1e-7 if storage == "C128" else 1e-4)
 
 
 @pytest.mark.parametrize("schedule", ["binned", "gemv", "queue"])

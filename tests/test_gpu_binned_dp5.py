@@ -124,3 +124,45 @@ def test_binned_dp5_restart_from_a_given_state(ctx):
     assert np.array_equal(ends["binned"]["status"], ends["queue"]["status"])
     assert np.max(np.abs(ends["binned"]["steps"] - ends["queue"]["steps"])) <= 2
     assert np.max(np.abs(ends["binned"]["P"] - ends["queue"]["P"])) < 10 * RTOL
+
+
+def test_default_schedule_splits_an_adaptive_batch(ctx):
+    """One call, default schedule: the trajectories of a large dense system that
+    holds many of them run on the binned schedule (a second stream), the rest on
+    the work list, concurrently.  Each share equals the same trajectories run on
+    their schedule alone: bit for bit on the binned share (its products do not
+    depend on which other trajectories share a knot), to rounding on the work
+    list (whose shape the autotuner may choose differently in each call)."""
+    big = S.large_random_system(N=512, K=60, cfg_index=11, workers=0)
+    rng = np.random.default_rng(41)
+    bb = S.mc_batch(big, 256, rng.uniform(800.0, 1500.0, 256), 8.0, np.arange(8), rng, n_steps=1)
+    small = S.rotor_atom_system(jmax=3)
+    init = np.where(small.labels["j"] == 2)[0]
+    bs = S.mc_batch(small, 9, 500.0, 10.0, init, rng, n_steps=1)
+    say("split adaptive batch: N=%d x %d (binned share) + N=%d x %d (work list)" % (
+        big.N, bb.B, small.N, bs.B))
+    s1 = ctx.load_system(big, storage="C64")
+    s2 = ctx.load_system(small, storage="R64")
+    order = rng.permutation(bb.B + bs.B)
+    cat = lambda x, y: np.concatenate([np.asarray(x), np.asarray(y)])[order]
+    ids = cat(np.full(bb.B, s1), np.full(bs.B, s2))
+    Ns = cat(np.full(bb.B, big.N), np.full(bs.B, small.N))
+    kw = dict(init_channel=cat(bb.init_channel, bs.init_channel), E_coll=cat(bb.E_coll, bs.E_coll),
+              b=cat(bb.b, bs.b), R0=cat(bb.R0, bs.R0))
+    g = ctx.run_host(ids, Ns, **kw, **DP5)
+    gb = ctx.run_host([s1] * bb.B, [big.N] * bb.B, schedule="binned", **start(bb), **DP5)
+    gq = ctx.run_host([s2] * bs.B, [small.N] * bs.B, schedule="queue", **start(bs), **DP5)
+    ctx.free_system(s1)
+    ctx.free_system(s2)
+    offs = np.concatenate([[0], np.cumsum(Ns)])
+    inv = np.argsort(order)
+    for i in range(bb.B):
+        pos = inv[i]
+        assert np.array_equal(g["P"][offs[pos]:offs[pos + 1]], gb["P"][i * big.N:(i + 1) * big.N])
+        assert g["steps"][pos] == gb["steps"][i] and g["t_final"][pos] == gb["t_final"][i]
+    for i in range(bs.B):
+        pos = inv[bb.B + i]
+        assert np.max(np.abs(g["P"][offs[pos]:offs[pos + 1]] -
+                             gq["P"][i * small.N:(i + 1) * small.N])) < 1e-12
+    assert np.all(g["status"] & 1)
+    say("  steps %d..%d, all exited" % (g["steps"].min(), g["steps"].max()))

@@ -131,21 +131,24 @@ def test_dp5_uneven_mixed_batch(ctx, fam):
     g = ctx.run_host(sids, Ns, **start(b), **DP5)
     offs = np.concatenate([[0], np.cumsum(Ns)])
     # FP64: the same accepted steps as the oracle, so every channel agrees to the
-    # tolerance.  FP32: the step sequence may differ by a step or two, and the exit
-    # step with it (t_final moves by up to one large step at R0, where the Coriolis
-    # term still turns the m populations within a level); the level populations,
-    # which the cross sections use, are unaffected and carry the FP32 bar.
+    # tolerance.  FP32: the step sequence may differ from the oracle's by a step or
+    # two, and the exit time with it; every channel is compared with the exact
+    # solution at the GPU trajectory's own end time (the oracle's RK4 from the
+    # start to that time in steps a hundred times finer than the adaptive ones).
     tol = 10 * RTOL if fam == "fp64" else 1e-4
     worst = 0.0
     for si, x in enumerate(systems):
         idx = np.where(b.system_index == si)[0]
-        o = oracle.OracleSystem(x).propagate(b.subset(idx), method="dp5", rtol=RTOL, atol=RTOL,
-                                             max_steps=50000, h_min=1e-6)
-        lev = np.zeros((x.n_levels, x.N))
-        lev[x.level_of_channel, np.arange(x.N)] = 1.0
+        ox = oracle.OracleSystem(x)
+        o = ox.propagate(b.subset(idx), method="dp5", rtol=RTOL, atol=RTOL, max_steps=50000,
+                         h_min=1e-6)
+        if fam == "fp32":
+            sub = b.subset(idx)
+            n_fine = np.maximum(2000, 100 * g["steps"][idx]).astype(np.int64)
+            ref = ox.propagate(sub, dt=g["t_final"][idx] / n_fine, n_steps=n_fine)["P"]
         for k, i in enumerate(idx):
-            dP = g["P"][offs[i]:offs[i + 1]] - o["P"][k]
-            worst = max(worst, np.max(np.abs(dP if fam == "fp64" else lev @ dP)))
+            dP = g["P"][offs[i]:offs[i + 1]] - (o["P"][k] if fam == "fp64" else ref[k])
+            worst = max(worst, np.max(np.abs(dP)))
             assert g["status"][i] & 1
             assert abs(int(g["steps"][i]) - int(o["steps"][k])) <= 3 + 0.01 * o["steps"][k]
     say("  max|dP| = %.3e, steps %d..%d" % (worst, g["steps"].min(), g["steps"].max()))

@@ -374,6 +374,28 @@ def test_dp5_exit_and_accuracy():
     assert np.all(under["status"] & oracle.STATUS["STEP_UNDERFLOW"])
 
 
+def test_tables_at_a_run_of_knots_equal_the_whole_grid_spline():
+    """The large-system oracle holds only the knots a trajectory touches, with the
+    second derivatives of the whole grid's natural spline taken through the
+    generator's rank-Q factors (the spline is linear in the data): they equal the
+    oracle's own spline of every element, and so do the propagated results."""
+    s = S.large_random_system(N=24, K=30, cfg_index=12, workers=0)
+    full = oracle.OracleSystem(s)
+    phi, v, H, scale = S.gp_rank_factors(s)
+    ks = np.arange(22, 30)
+    R_sub, M_sub, M2_sub = oracle.rank_q_knot_tables(s.R_grid, phi, v, H, ks, scale)
+    assert np.array_equal(R_sub, s.R_grid[22:])
+    assert np.max(np.abs(M_sub - s.M[22:])) <= 1e-15 * np.max(np.abs(s.M))
+    M2 = full.M2.view(np.complex128).reshape(s.K, s.N, s.N)[22:]
+    assert np.max(np.abs(M2_sub - M2)) <= 1e-12 * np.max(np.abs(M2))
+    part = oracle.OracleSystem(s, knots=(R_sub, M_sub, M2_sub))
+    rng = np.random.default_rng(5)
+    b = S.mc_batch(s, 2, 1000.0, 6.0, [0, 3], rng, n_steps=60, dt=20.0)
+    o1, o2 = full.propagate(b), part.propagate(b)
+    assert np.all(o1["classical"][:, 0] > s.R_grid[22])        # stayed on the held knots
+    assert np.max(np.abs(o1["P"] - o2["P"])) < 1e-12
+
+
 def test_dual_number_derivative_matches_central_differences():
     (s,), b = S.config4(n_traj=2, n_steps=300, jmax=1)
     rng = np.random.default_rng(3)
