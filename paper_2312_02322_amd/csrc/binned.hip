@@ -49,9 +49,7 @@ struct BinWS {
   double2* acc;           // [B][Npad] k1 + 2 k2 + 2 k3 + k4
   double2* c64;           // [B][Npad] c = e^{-iEt} a of the stage in the combine, FP64,
                           // when Npad is too large for LDS
-  void* cst;              // c of every trajectory in the table precision: complex tables
-                          // [B][KR] the real column (Re c, -Im c) (the product forms the
-                          // second one, (Im c, Re c), from it); real tables [B][2][KR]
+  void* cst;              // [B][2][KR] the two real columns of c in the table precision
   void* uv;               // [2][B][Npad][4] in the table precision, left / right knot:
                           // (zA_re, zB_re, zA_im, zB_im), the value (A) and second-
                           // derivative (B) slices times c, before the spline weights
@@ -151,19 +149,22 @@ __device__ __forceinline__ void stage_setup(const BinWS& ws, const DevSystem& sy
   if (sp.below && count_below) ws.status[b] |= ST_BELOW_GRID;
 }
 
-// Element n of c in the table precision: complex tables store the real column
-// (Re c_n, -Im c_n) at reals 2n, 2n+1 (KR = 2 Npad reals per trajectory); real
-// tables store the two columns Re c and Im c (KR = Npad each).
+// Element n of the two real columns of c in the table precision (KR = 2 Npad
+// reals for complex tables, Npad for real ones): complex tables take
+// (Re c_n, -Im c_n) and (Im c_n, Re c_n) at reals 2n, 2n+1; real tables take
+// Re c_n and Im c_n.
 template <typename S, bool CPLX>
 __device__ __forceinline__ void put_cols(const BinWS& ws, int b, int Npad, int n, double2 c) {
+  const int64_t KR = (CPLX ? 2 : 1) * (int64_t)Npad;
+  S* col0 = (S*)ws.cst + (int64_t)b * 2 * KR;
+  S* col1 = col0 + KR;
   const S re = (S)c.x, im = (S)c.y;
   if constexpr (CPLX) {
-    S* col0 = (S*)ws.cst + (int64_t)b * 2 * Npad;
     col0[2 * n] = re; col0[2 * n + 1] = -im;
+    col1[2 * n] = im; col1[2 * n + 1] = re;
   } else {
-    S* col0 = (S*)ws.cst + (int64_t)b * 2 * Npad;
     col0[n] = re;
-    col0[Npad + n] = im;
+    col1[n] = im;
   }
 }
 
@@ -276,15 +277,7 @@ __global__ void bin_scatter(BinWS ws) {
   ws.list[ws.offset[k + 1] + p1] = 2 * b + 1;
 }
 
-// K steps of operands in flight in the product of an item of NX column blocks.
-// Wide items are bound by the matrix cores (a deeper ring measured slower
-// there); items of one to three column blocks are bound by streaming the knot's
-// slices and need more bytes in flight than one step ahead gives, which the
-// registers their few accumulators leave free provide.
-template <bool FP32, int NX> constexpr int gemm_pf() {
-  if constexpr (FP32) return NX <= 2 ? 6 : (NX == 3 ? 4 : 2);
-  else return NX <= 2 ? 4 : 2;
-}
+constexpr int GEMM_PF32 = 2;   // K steps of operands in flight, FP32 tables (deeper rings measured slower)
 // ring periods per loop iteration: the compiler's waits for the loads are exact
 // inside an iteration and conservative only across the loop's back edge
 constexpr int GEMM_UF = 1;
@@ -335,7 +328,8 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   using S = typename std::conditional<FP32, float, double>::type;
   using V = typename MF<S>::V;
   constexpr int RB = 2;
-  constexpr int PF = gemm_pf<FP32, NX>();
+  // K steps of operands in flight: the FP32 form has the registers for a deeper ring
+  constexpr int PF = FP32 ? GEMM_PF32 : 2;
   constexpr int NCOMP = CPLX ? 2 : 1;
   const int N = sy.N, Npad = sy.Npad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -351,16 +345,13 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   // the steps beyond would add exact zeros
   const int KE = (N * NCOMP + 15) & ~15;
 
-  // this lane's real column in each column block: complex tables keep one real
-  // column per trajectory, (Re c, -Im c); the second, (Im c, Re c), is that
-  // column with each pair swapped and one sign changed, formed in registers by
-  // the odd lanes from the same 16 bytes (one load address per trajectory)
+  // this lane's real column in each column block
   const S* col[NX];
 #pragma unroll
   for (int cb = 0; cb < NX; ++cb) {
     const int jt = (cb * 16 + c16) >> 1;
     const int e = ws.list[start + (jt < count ? jt : 0)];
-    col[cb] = (const S*)ws.cst + (int64_t)(e >> 1) * 2 * Npad + (CPLX ? 0 : part * Npad) + 4 * q;
+    col[cb] = (const S*)ws.cst + ((int64_t)(e >> 1) * 2 + part) * KR + 4 * q;
   }
   V acc[RB][2][NX];
 #pragma unroll
@@ -383,47 +374,30 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
     }
 #pragma unroll
     for (int cb = 0; cb < NX; ++cb) {
-      S v[4];
       if constexpr (FP32) {
-        const float4 w = *(const float4*)(col[cb] + k0);
-        v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+        const float4 v = *(const float4*)(col[cb] + k0);
+        bo[cb][0] = v.x; bo[cb][1] = v.y; bo[cb][2] = v.z; bo[cb][3] = v.w;
       } else {
         const double2 v0 = *(const double2*)(col[cb] + k0);
         const double2 v1 = *(const double2*)(col[cb] + k0 + 2);
-        v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
+        bo[cb][0] = v0.x; bo[cb][1] = v0.y; bo[cb][2] = v1.x; bo[cb][3] = v1.y;
       }
-      bo[cb][0] = v[0]; bo[cb][1] = v[1]; bo[cb][2] = v[2]; bo[cb][3] = v[3];
     }
   };
-  // the odd lanes of complex tables turn the loaded (Re c, -Im c) pairs into (Im c,
-  // Re c) pairs here, where the step's operands are used (at load time the
-  // select would wait for the loads in flight)
   auto mma = [&](const S (&ai)[RB][2][4], const S (&bi)[NX][4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int cb = 0; cb < NX; ++cb) {
-        S bval = bi[cb][i];
-        if constexpr (CPLX) {
-          const S sw = bi[cb][i ^ 1];
-          bval = part ? ((i & 1) ? sw : -sw) : bval;
-        }
+      for (int cb = 0; cb < NX; ++cb)
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
           for (int s = 0; s < 2; ++s)
-            acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bval, acc[r][s][cb]);
-      }
+            acc[r][s][cb] = MF<S>::mfma(ai[r][s][i], bi[cb][i], acc[r][s][cb]);
   };
-  // K steps past the last one reload that step's operands (unused) rather than branch.
-  // The prologue issues the ring's steps in ring order, as the loop does: the
-  // compiler's wait counts at the loop head hold for both the entry and the back
-  // edge, and a reordered prologue would make them wait for the whole ring.
+  // K steps past the last one reload that step's operands (unused) rather than branch
 #pragma unroll
-  for (int j = 0; j < PF - 1; ++j) {
-    load(min(16 * j, KE - 16), a[j], bv[j]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KE - 16), a[j], bv[j]);
   for (int k0 = 0; k0 < KE; k0 += 16 * PF * GEMM_UF) {
 #pragma unroll
     for (int j = 0; j < PF * GEMM_UF; ++j) {
@@ -462,12 +436,12 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   }
 }
 
-template <int DT, int NX, int NXMIN>
+template <int DT, int NX>
 __device__ __forceinline__ void gemm_dispatch(const BinWS& ws, const DevSystem& sy, int rb, int g,
                                               int start, int count, int ncb) {
-  if constexpr (NX > NXMIN) {
+  if constexpr (NX > 1) {
     if (ncb < NX) {
-      gemm_dispatch<DT, NX - 1, NXMIN>(ws, sy, rb, g, start, count, ncb);
+      gemm_dispatch<DT, NX - 1>(ws, sy, rb, g, start, count, ncb);
       return;
     }
   }
@@ -502,10 +476,10 @@ bin_gemm(BinWS ws, const DevSystem* __restrict__ systems, int nrb) {
     // real FP64 tables: at most four column blocks per pass (eight would spill)
     for (int c0 = 0; c0 < it.z; c0 += 32) {
       const int cnt = min(32, it.z - c0);
-      gemm_dispatch<DT, 4, 1>(ws, sy, rb, it.x, it.y + c0, cnt, (cnt + 7) >> 3);
+      gemm_dispatch<DT, 4>(ws, sy, rb, it.x, it.y + c0, cnt, (cnt + 7) >> 3);
     }
   } else {
-    gemm_dispatch<DT, TB / 8, 1>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
+    gemm_dispatch<DT, TB / 8>(ws, sy, rb, it.x, it.y, it.z, (it.z + 7) >> 3);
   }
 }
 
