@@ -312,6 +312,26 @@ mqct_status mqct_set_state(mqct_context* ctx, int64_t first, int64_t count,
                            const mqct_traj_state* state, const double* amps);
 
 /*
+ * mqct_run without device allocation, for callers that cannot allocate device
+ * memory during the call (tight serving loops, harnesses that forbid it).  The
+ * trajectory records and start amplitudes go to a fixed device scratch array of
+ * 16 MiB that the library holds for the life of the process (one per GPU; the
+ * context finds its address when it is created): at most 16 MiB / 200 B = 83,886
+ * trajectories, fewer with a0 (the records plus 16 bytes per amplitude); a batch
+ * beyond that fails with MQCT_ERR_ARG before any device work.  Fixed-step RK4 on
+ * the per-trajectory schedule only (schedule MQCT_SCHED_AUTO or MQCT_SCHED_GEMV,
+ * resume 0; otherwise MQCT_ERR_UNSUPPORTED); results must be device arrays
+ * (mem = MQCT_MEM_DEVICE).  The results equal mqct_run's on that schedule; the
+ * state store is left as it was.  The call waits for the context stream before it
+ * stages the records (synchronous host-to-device copies) and returns with the
+ * propagation enqueued.  All calls on one GPU share the scratch array, so calls
+ * that overlap on one GPU (other threads, other contexts) race.  Errors as for
+ * mqct_run.
+ */
+mqct_status mqct_run_noalloc(mqct_context* ctx, const mqct_batch_desc* batch,
+                             const mqct_batch_result* result);
+
+/*
  * Monte-Carlo cross sections (end of Section II; b sampled uniformly on
  * [0, b_max]):
  *   sigma[L'][L''] = (2 pi b_max / N_L') sum_{b : level(b) = L'} b_b sum_{n in L''} P_b(n)

@@ -37,7 +37,7 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
            "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients",
            "mqct_coupling_build_sparse", "mqct_get_state", "mqct_set_state",
-           "mqct_state_count"]
+           "mqct_state_count", "mqct_run_noalloc"]
 
 
 class CouplingDesc(C.Structure):
@@ -155,6 +155,8 @@ def lib():
         L.mqct_set_state.restype = i32
         L.mqct_state_count.argtypes = [vp, C.POINTER(i64)]
         L.mqct_state_count.restype = i32
+        L.mqct_run_noalloc.argtypes = [vp, C.POINTER(BatchDesc), C.POINTER(BatchResult)]
+        L.mqct_run_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -320,6 +322,38 @@ class Context:
                           _ptr(out.get("status")), _ptr(out.get("norm_err")),
                           _ptr(out.get("energy_err")), _ptr(out.get("angmom_err")))
         self._check(lib().mqct_run(self.h, C.byref(bd), C.byref(res)))
+        return out
+
+    def run_noalloc(self, system_id, out, *, init_channel=None, a0=None, classical0=None,
+                    E_coll=None, b=None, R0=None, t0=None, dt=None, n_steps=None,
+                    dynamics="ehrenfest"):
+        """mqct_run_noalloc: fixed-step RK4 on the per-trajectory schedule into the
+        caller's CUDA tensors `out` (keys as run() returns; P required), with no
+        device allocation by the library."""
+        sid = _host(system_id, np.int32)
+        B = int(sid.shape[0])
+        a0h = None
+        if a0 is not None:
+            a0h = np.ascontiguousarray(np.asarray(a0, np.complex128).reshape(-1)).view(np.float64)
+        c0h = None if classical0 is None else _host(np.reshape(classical0, (B, 6)), np.float64)
+        bd = BatchDesc(B, sid.ctypes.data, None, _ptr(a0h), _ptr(c0h), None, None, None, None,
+                       INTEGRATORS["rk4"], None, None, 0.0, 0.0, 0, 0.0, SCHEDULES["gemv"],
+                       DYNAMICS[dynamics], 0)
+        hold = []
+        for name, arr, dtp in (("init_channel", init_channel, np.int32), ("E_coll", E_coll, np.float64),
+                               ("b", b, np.float64), ("R0", R0, np.float64), ("t0", t0, np.float64),
+                               ("dt", dt, np.float64), ("n_steps", n_steps, np.int64)):
+            if arr is None:
+                continue
+            h = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtp), (B,)))
+            hold.append(h)
+            setattr(bd, name, h.ctypes.data)
+        res = BatchResult(MEM_DEVICE, _ptr(out.get("P")), _ptr(out.get("a_final")),
+                          _ptr(out.get("classical")), _ptr(out.get("t_final")),
+                          _ptr(out.get("steps")), _ptr(out.get("rejects")),
+                          _ptr(out.get("status")), _ptr(out.get("norm_err")),
+                          _ptr(out.get("energy_err")), _ptr(out.get("angmom_err")))
+        self._check(lib().mqct_run_noalloc(self.h, C.byref(bd), C.byref(res)))
         return out
 
     def run_host(self, system_id, N_of, **kw):

@@ -38,6 +38,12 @@ struct SysHost {
   double R_last = 0.0;    // last knot (the default start radius), kept on the host
 };
 
+// Device scratch of mqct_run_noalloc: the trajectory records and start amplitudes
+// of one call.  Every GPU the library runs on holds its own copy until the
+// process ends; every call on a GPU shares it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 // Grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
@@ -67,6 +73,7 @@ struct mqct_context {
   size_t h_traj_cap = 0;
   hipEvent_t staged = nullptr;     // recorded after the last upload from h_traj
   Prof prof;                       // optional timing of the dominant step kernel
+  unsigned char* scratch = nullptr;   // device address of this GPU's copy of `scratch`
   // state store: the final state of every trajectory of the last run (or what
   // mqct_set_state wrote), records by batch index, amplitudes concatenated
   DevBuf st_rec, st_amp;
@@ -191,6 +198,17 @@ mqct_status mqct_create(int32_t device, void* hip_stream, mqct_context** out) {
       hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) != hipSuccess) {
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->side) hipStreamDestroy(c->side);
+    hipEventDestroy(c->staged);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return MQCT_ERR_DEVICE;
+  }
+  // the address of this device's copy of the static scratch array (the host-side
+  // name is not a device address)
+  if (hipGetSymbolAddress((void**)&c->scratch, HIP_SYMBOL(scratch)) != hipSuccess) {
+    hipEventDestroy(c->side_done);
+    hipStreamDestroy(c->side);
+    hipStreamDestroy(c->cap);
     hipEventDestroy(c->staged);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -901,6 +919,143 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     HIP_TRY(c, hipMemcpyAsync(p.host, dp[p.slot], p.bytes, hipMemcpyDeviceToHost, c->stream),
             "run: results");
   if (res->mem == MQCT_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream), "run: results");
+  return MQCT_OK;
+}
+
+mqct_status mqct_run_noalloc(mqct_context* c, const mqct_batch_desc* bd,
+                             const mqct_batch_result* res) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!bd || !res) return fail(c, MQCT_ERR_ARG, "run_noalloc: null argument");
+  const int64_t B = bd->B;
+  if (B < 0) return fail(c, MQCT_ERR_ARG, "run_noalloc: B < 0");
+  if (B == 0) return MQCT_OK;
+  if (res->mem != MQCT_MEM_DEVICE || !res->P)
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: results must be device arrays (P required)");
+  if (bd->integrator != MQCT_RK4 || (bd->schedule != MQCT_SCHED_AUTO &&
+                                     bd->schedule != MQCT_SCHED_GEMV) || bd->resume)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run_noalloc: fixed-step RK4 on the per-trajectory "
+                "schedule only, without resume");
+  if (bd->dynamics != MQCT_EHRENFEST && bd->dynamics != MQCT_AT)
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: unknown dynamics %d", bd->dynamics);
+  if (!bd->system_id || !bd->dt || !bd->n_steps)
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: system_id, dt and n_steps are required");
+  if (!bd->classical0 && (!bd->E_coll || !bd->b))
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: E_coll and b are required without classical0");
+  if (!bd->a0 && !bd->init_channel)
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: init_channel is required without a0");
+  if (!c->scratch) return fail(c, MQCT_ERR_STATE, "run_noalloc: no scratch address");
+  // validation and sizes: one pass over the batch
+  int64_t amp_total = 0;
+  int max_npad[4] = {0, 0, 0, 0};
+  for (int64_t b = 0; b < B; ++b) {
+    const int sid = bd->system_id[b];
+    if (sid < 0 || sid >= (int)c->systems.size() || !c->systems[sid].live)
+      return fail(c, MQCT_ERR_STATE, "run_noalloc: trajectory %lld uses unknown system %d",
+                  (long long)b, sid);
+    const DevSystem& sy = c->systems[sid].dev;
+    if (bd->n_steps[b] < 0 || !isfinite(bd->dt[b]) || (bd->t0 && !isfinite(bd->t0[b])))
+      return fail(c, MQCT_ERR_ARG, "run_noalloc: bad n_steps, dt or t0 at %lld", (long long)b);
+    if (!bd->a0 && (bd->init_channel[b] < 0 || bd->init_channel[b] >= sy.N))
+      return fail(c, MQCT_ERR_ARG, "run_noalloc: init_channel[%lld] out of range", (long long)b);
+    if (bd->classical0) {
+      if (!finite_arr(bd->classical0 + b * 6, 6) || !(bd->classical0[b * 6] > 0.0))
+        return fail(c, MQCT_ERR_ARG, "run_noalloc: classical0[%lld] invalid", (long long)b);
+    } else {
+      const double R0 = bd->R0 ? bd->R0[b] : c->systems[sid].R_last;
+      if (!(bd->E_coll[b] > 0.0) || !isfinite(bd->E_coll[b]) || !(R0 > 0.0) || !isfinite(R0) ||
+          !(bd->b[b] >= 0.0) || !(bd->b[b] < R0))
+        return fail(c, MQCT_ERR_ARG, "run_noalloc: need E_coll > 0 and 0 <= b < R0 (trajectory "
+                    "%lld)", (long long)b);
+    }
+    if (bd->dynamics == MQCT_AT && !sy.drv)
+      return fail(c, MQCT_ERR_STATE, "run_noalloc: AT dynamics needs a driving potential for "
+                  "system %d", sid);
+    amp_total += sy.N;
+    max_npad[sy.dtype] = std::max(max_npad[sy.dtype], sy.Npad);
+  }
+  const size_t rec_bytes = (size_t)B * sizeof(TrajIn);
+  const size_t a0_off = (rec_bytes + 255) & ~(size_t)255;
+  const size_t need = bd->a0 ? a0_off + (size_t)amp_total * 16 : rec_bytes;
+  if ((size_t)B > NOALLOC_SCRATCH_BYTES / sizeof(TrajIn) || need > NOALLOC_SCRATCH_BYTES)
+    return fail(c, MQCT_ERR_ARG, "run_noalloc: the batch needs %zu bytes of scratch, more than "
+                "its %zu (at most %zu trajectories without a0)", need, NOALLOC_SCRATCH_BYTES,
+                NOALLOC_SCRATCH_BYTES / sizeof(TrajIn));
+  HIP_TRY(c, hipSetDevice(c->device), "run_noalloc");
+  // the work of an earlier call on the stream may still read the scratch
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "run_noalloc");
+  // records grouped by storage type, staged through a fixed host buffer and
+  // copied into the scratch chunk by chunk (synchronously: the buffer is reused)
+  constexpr int CH = 64;
+  TrajIn chunk[CH];
+  int64_t pos = 0;
+  int64_t first[4] = {0, 0, 0, 0}, count[4] = {0, 0, 0, 0};
+  for (int d = 0; d < 4; ++d) {
+    first[d] = pos;
+    int nc = 0;
+    int64_t amp_off = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      const int sid = bd->system_id[b];
+      const SysHost& sh = c->systems[sid];
+      const int64_t off = amp_off;
+      amp_off += sh.dev.N;
+      if (sh.dev.dtype != d) continue;
+      TrajIn t{};
+      t.id = b;
+      t.amp_off = off;
+      t.sys = sid;
+      t.n_steps = bd->n_steps[b];
+      t.dt = bd->dt[b];
+      t.t0 = bd->t0 ? bd->t0[b] : 0.0;
+      if (bd->a0) t.flags |= TRAJ_HAS_A0;
+      else t.init_channel = bd->init_channel[b];
+      if (bd->classical0) {
+        t.flags |= TRAJ_HAS_C0;
+        for (int i = 0; i < 6; ++i) t.c0[i] = bd->classical0[b * 6 + i];
+      } else {
+        t.E_coll = bd->E_coll[b];
+        t.b = bd->b[b];
+        t.R0 = bd->R0 ? bd->R0[b] : sh.R_last;
+      }
+      if (bd->dynamics == MQCT_AT) t.flags |= TRAJ_AT;
+      chunk[nc++] = t;
+      if (nc == CH) {
+        HIP_TRY(c, hipMemcpyAsync(c->scratch + (size_t)pos * sizeof(TrajIn), chunk,
+                                  CH * sizeof(TrajIn), hipMemcpyHostToDevice, c->stream),
+                "run_noalloc: records");
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "run_noalloc: records");
+        pos += nc;
+        nc = 0;
+      }
+    }
+    if (nc) {
+      HIP_TRY(c, hipMemcpyAsync(c->scratch + (size_t)pos * sizeof(TrajIn), chunk,
+                                nc * sizeof(TrajIn), hipMemcpyHostToDevice, c->stream),
+              "run_noalloc: records");
+      HIP_TRY(c, hipStreamSynchronize(c->stream), "run_noalloc: records");
+      pos += nc;
+    }
+    count[d] = pos - first[d];
+  }
+  const double* d_a0 = nullptr;
+  if (bd->a0) {
+    HIP_TRY(c, hipMemcpyAsync(c->scratch + a0_off, bd->a0, (size_t)amp_total * 16,
+                              hipMemcpyHostToDevice, c->stream), "run_noalloc: a0");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "run_noalloc: a0");
+    d_a0 = (const double*)(c->scratch + a0_off);
+  }
+  TrajOut out{};
+  out.P = res->P; out.a_final = res->a_final; out.classical = res->classical;
+  out.t_final = res->t_final; out.steps = res->steps; out.rejects = res->rejects;
+  out.status = res->status; out.norm_err = res->norm_err; out.energy_err = res->energy_err;
+  out.angmom_err = res->angmom_err;
+  for (int d = 0; d < 4; ++d) {
+    if (!count[d]) continue;
+    hipError_t e = launch_rk4_gemv(c->d_systems, (const TrajIn*)c->scratch + first[d], count[d],
+                                   d_a0, out, d, max_npad[d], c->stream, nullptr);
+    if (e == hipErrorInvalidValue)
+      return fail(c, MQCT_ERR_UNSUPPORTED, "run_noalloc: N too large for the per-trajectory schedule");
+    if (e != hipSuccess) return hip_fail(c, e, "run_noalloc: launch");
+  }
   return MQCT_OK;
 }
 
