@@ -242,7 +242,8 @@ def rank_q_knot_tables(R, phi, v_diag, H, ks, scale=1.0):
         for i in range(out.shape[0]):
             out[i] = 0.5 * (out[i] + out[i].conj().T)
             out[i][eye, eye] += diag[i]
-        return out * scale
+            out[i] *= scale
+        return out
 
     return R[ks], at(phi[ks], v_diag[ks]), at(phi2[ks], v2[ks])
 
