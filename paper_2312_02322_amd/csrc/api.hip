@@ -6,6 +6,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -43,6 +44,29 @@ struct SysHost {
 // process ends; every call on a GPU shares it.
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Every device allocation of the library goes through here.  Fault injection
+// for the error paths, from the environment (read at every call):
+// MQCT_FAULT=alloc fails each allocation as out of device memory;
+// MQCT_FAULT=alloc@n fails only the n-th allocation counted from the call that
+// first saw that value.
+template <typename T>
+hipError_t dev_malloc(T** p, size_t bytes) {
+  static std::string seen;
+  static long count = 0;
+  const char* f = getenv("MQCT_FAULT");
+  if (f && strncmp(f, "alloc", 5) == 0) {
+    if (f[5] == '\0') return hipErrorOutOfMemory;
+    if (f[5] == '@') {
+      if (seen != f) {
+        seen = f;
+        count = 0;
+      }
+      if (++count == atol(f + 6)) return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc((void**)p, bytes);
+}
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -118,7 +142,7 @@ mqct_status ensure(mqct_context* c, DevBuf& b, size_t bytes, const char* what) {
     b.cap = 0;
   }
   size_t want = std::max(bytes, (size_t)4096);
-  HIP_TRY(c, hipMalloc(&b.p, want), what);
+  HIP_TRY(c, dev_malloc(&b.p, want), what);
   b.cap = want;
   return MQCT_OK;
 }
@@ -132,7 +156,7 @@ mqct_status upload_systems(mqct_context* c) {
     if (c->d_systems) hipFree(c->d_systems);
     c->d_systems = nullptr;
     size_t want = bytes * 2;
-    HIP_TRY(c, hipMalloc((void**)&c->d_systems, want), "system table");
+    HIP_TRY(c, dev_malloc((void**)&c->d_systems, want), "system table");
     c->d_systems_cap = want;
   }
   HIP_TRY(c, hipMemcpyAsync(c->d_systems, h.data(), h.size() * sizeof(DevSystem),
@@ -347,14 +371,14 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   };
   hipError_t e;
   if (d->M_mem == MQCT_MEM_HOST) {
-    if ((e = hipMalloc((void**)&din, in_elems * 8)) != hipSuccess) return dfail(e, "system_load: input");
+    if ((e = dev_malloc((void**)&din, in_elems * 8)) != hipSuccess) return dfail(e, "system_load: input");
     own_in = true;
     if ((e = hipMemcpy(din, d->M, in_elems * 8, hipMemcpyHostToDevice)) != hipSuccess)
       return dfail(e, "system_load: upload");
   } else {
     din = (double*)d->M;
   }
-  if ((e = hipMalloc((void**)&stats, 3 * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = dev_malloc((void**)&stats, 3 * sizeof(unsigned long long))) != hipSuccess)
     return dfail(e, "system_load: stats");
   if ((e = hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), c->stream)) != hipSuccess)
     return dfail(e, "system_load: stats");
@@ -377,14 +401,14 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
                 herm, 1e-12 * amax);
   }
   // storage, spline curvature, small arrays
-  if ((e = hipMalloc(&sh.bufs[0], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
-  if ((e = hipMalloc(&sh.bufs[1], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
-  if ((e = hipMalloc(&sh.bufs[2], K * 8)) != hipSuccess) return dfail(e, "system_load: grid");
-  if ((e = hipMalloc(&sh.bufs[3], N * 8)) != hipSuccess) return dfail(e, "system_load: energies");
+  if ((e = dev_malloc(&sh.bufs[0], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
+  if ((e = dev_malloc(&sh.bufs[1], store_elems * es)) != hipSuccess) return dfail(e, "system_load: tables");
+  if ((e = dev_malloc(&sh.bufs[2], K * 8)) != hipSuccess) return dfail(e, "system_load: grid");
+  if ((e = dev_malloc(&sh.bufs[3], N * 8)) != hipSuccess) return dfail(e, "system_load: energies");
   int64_t per_col = (int64_t)N * Npad * ncomp;
   int64_t tmp_doubles = std::min<int64_t>((int64_t)K * per_col, (int64_t)64 << 20);
   tmp_doubles = std::max<int64_t>(tmp_doubles, K);
-  if ((e = hipMalloc((void**)&tmp, tmp_doubles * 8)) != hipSuccess) return dfail(e, "system_load: scratch");
+  if ((e = dev_malloc((void**)&tmp, tmp_doubles * 8)) != hipSuccess) return dfail(e, "system_load: scratch");
   if ((e = hipMemcpy(sh.bufs[2], d->R_grid, K * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return dfail(e, "system_load: grid");
   if ((e = hipMemcpy(sh.bufs[3], d->E, N * 8, hipMemcpyHostToDevice)) != hipSuccess)
@@ -400,8 +424,8 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
       if (amax) hipFree(amax);
       return dfail(err, what);
     };
-    if ((e = hipMalloc((void**)&amax, (size_t)N * N * 8)) != hipSuccess) return efail(e, "system_load: pattern");
-    if ((e = hipMalloc(&sh.ebuf[1], (size_t)N * 4)) != hipSuccess) return efail(e, "system_load: pattern");
+    if ((e = dev_malloc((void**)&amax, (size_t)N * N * 8)) != hipSuccess) return efail(e, "system_load: pattern");
+    if ((e = dev_malloc(&sh.ebuf[1], (size_t)N * 4)) != hipSuccess) return efail(e, "system_load: pattern");
     if ((e = launch_ell_pattern(din, N, K, ncomp, d->drop_below, amax, (int*)sh.ebuf[1], c->stream)) != hipSuccess)
       return efail(e, "system_load: pattern");
     std::vector<int> cnt(N);
@@ -413,11 +437,11 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
     void* E = nullptr;
     void* E2 = nullptr;
     const size_t ebytes = (size_t)K * Wm * Npad * ncomp * es;
-    if ((e = hipMalloc(&sh.ebuf[0], (size_t)Wm * Npad * 4)) != hipSuccess) return efail(e, "system_load: slots");
+    if ((e = dev_malloc(&sh.ebuf[0], (size_t)Wm * Npad * 4)) != hipSuccess) return efail(e, "system_load: slots");
     if ((e = launch_ell_fill(amax, N, Npad, Wm, d->drop_below, (int32_t*)sh.ebuf[0], c->stream)) != hipSuccess)
       return efail(e, "system_load: slots");
-    if ((e = hipMalloc(&E, ebytes)) != hipSuccess) return efail(e, "system_load: sparse tables");
-    if ((e = hipMalloc(&E2, ebytes)) != hipSuccess) { hipFree(E); return efail(e, "system_load: sparse tables"); }
+    if ((e = dev_malloc(&E, ebytes)) != hipSuccess) return efail(e, "system_load: sparse tables");
+    if ((e = dev_malloc(&E2, ebytes)) != hipSuccess) { hipFree(E); return efail(e, "system_load: sparse tables"); }
     if ((e = launch_ell_gather(sh.bufs[0], sh.bufs[1], (const int32_t*)sh.ebuf[0], (const int*)sh.ebuf[1],
                                N, Npad, K, Wm, ncomp, d->storage, E, E2, c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
@@ -447,8 +471,8 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
           col[(size_t)r * W + w] = r;
         }
       }
-    if ((e = hipMalloc(&sh.bufs[4], col.size() * 4)) != hipSuccess) return dfail(e, "system_load: J_x");
-    if ((e = hipMalloc(&sh.bufs[5], val.size() * 8)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = dev_malloc(&sh.bufs[4], col.size() * 4)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = dev_malloc(&sh.bufs[5], val.size() * 8)) != hipSuccess) return dfail(e, "system_load: J_x");
     if ((e = hipMemcpy(sh.bufs[4], col.data(), col.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(sh.bufs[5], val.data(), val.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
       return dfail(e, "system_load: J_x");
@@ -483,7 +507,7 @@ mqct_status mqct_system_set_driver(mqct_context* c, int32_t id, const double* U)
   if (!finite_arr(U, K)) return fail(c, MQCT_ERR_NONFINITE, "set_driver: non-finite U");
   HIP_TRY(c, hipSetDevice(c->device), "set_driver");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "set_driver");
-  if (!sh.dbuf) HIP_TRY(c, hipMalloc(&sh.dbuf, (size_t)4 * K * sizeof(double)), "set_driver");
+  if (!sh.dbuf) HIP_TRY(c, dev_malloc(&sh.dbuf, (size_t)4 * K * sizeof(double)), "set_driver");
   double* d = (double*)sh.dbuf;   // U [K], U'' [K], then 2K of elimination scratch
   HIP_TRY(c, hipMemcpyAsync(d, U, (size_t)K * sizeof(double), hipMemcpyHostToDevice, c->stream),
           "set_driver");
@@ -1203,14 +1227,14 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
     free_params(sh);
     return hip_fail(c, err, "set_params");
   };
-  if ((e = hipMalloc(&sh.pbufs[0], Gp.size() * 8)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[1], (size_t)P * K * 8)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[2], (size_t)P * K * 8)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[3], (size_t)P * 4)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[4], (size_t)(nG + 1) * 4)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[5], nnz * 4)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc(&sh.pbufs[6], nnz * 8)) != hipSuccess) return bail(e);
-  if ((e = hipMalloc((void**)&tmp, (size_t)2 * P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[0], Gp.size() * 8)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[1], (size_t)P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[2], (size_t)P * K * 8)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[3], (size_t)P * 4)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[4], (size_t)(nG + 1) * 4)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[5], nnz * 4)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc(&sh.pbufs[6], nnz * 8)) != hipSuccess) return bail(e);
+  if ((e = dev_malloc((void**)&tmp, (size_t)2 * P * K * 8)) != hipSuccess) return bail(e);
   if ((e = hipMemcpy(sh.pbufs[4], goff.data(), (size_t)(nG + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (!gent.empty() &&
        ((e = hipMemcpy(sh.pbufs[5], gent.data(), gent.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -1249,9 +1273,9 @@ mqct_status mqct_system_set_theta(mqct_context* c, int32_t id, const double* the
     if (tmp) hipFree(tmp);
     return err == hipSuccess ? MQCT_OK : hip_fail(c, err, "set_theta");
   };
-  if ((e = hipMalloc((void**)&Min, (size_t)K * N * N * 8)) != hipSuccess) return done(e);
-  if ((e = hipMalloc((void**)&th, (size_t)sh.P * 8)) != hipSuccess) return done(e);
-  if ((e = hipMalloc((void**)&tmp, (size_t)tmp_doubles * 8)) != hipSuccess) return done(e);
+  if ((e = dev_malloc((void**)&Min, (size_t)K * N * N * 8)) != hipSuccess) return done(e);
+  if ((e = dev_malloc((void**)&th, (size_t)sh.P * 8)) != hipSuccess) return done(e);
+  if ((e = dev_malloc((void**)&tmp, (size_t)tmp_doubles * 8)) != hipSuccess) return done(e);
   if ((e = hipMemcpyAsync(th, theta, (size_t)sh.P * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return done(e);
   if ((e = launch_build_param_tables((const double*)sh.pbufs[0], (const double*)sh.pbufs[1],
@@ -1269,8 +1293,8 @@ mqct_status mqct_system_set_theta(mqct_context* c, int32_t id, const double* the
   void* D = nullptr;
   void* D2 = nullptr;
   const size_t dbytes = (size_t)K * N * Npad * dtype_bytes(sh.dev.dtype);
-  if ((e = hipMalloc(&D, dbytes)) != hipSuccess) return done(e);
-  if ((e = hipMalloc(&D2, dbytes)) != hipSuccess) { hipFree(D); return done(e); }
+  if ((e = dev_malloc(&D, dbytes)) != hipSuccess) return done(e);
+  if ((e = dev_malloc(&D2, dbytes)) != hipSuccess) { hipFree(D); return done(e); }
   e = launch_spline_prepare(Min, sh.dev.R, N, K, Npad, 1, sh.dev.dtype, D, D2, tmp, tmp_doubles,
                             c->stream);
   if (e == hipSuccess)
@@ -1623,7 +1647,7 @@ mqct_status coupling_setup(mqct_context* c, const mqct_coupling_desc* d, const c
   const size_t total = ibytes + (n_b + n_v + n_lf + n_K + n_F + n_cg) * 8;
   HIP_TRY(c, hipSetDevice(c->device), what);
   char* w = nullptr;
-  hipError_t e = hipMalloc((void**)&w, total);
+  hipError_t e = dev_malloc((void**)&w, total);
   if (e != hipSuccess) return hip_fail(c, e, what);
   int32_t* di = (int32_t*)w;
   double* dd = (double*)(w + ibytes);
@@ -1694,7 +1718,7 @@ mqct_status mqct_coupling_build_sparse(mqct_context* c, const mqct_coupling_desc
   for (int t = 0; t < dev.T; ++t)
     for (int q = 0; q < n_screen; ++q) vs[(size_t)t * n_screen + q] = v_screen[(size_t)perm[t] * n_screen + q];
   char* sbuf = nullptr;
-  hipError_t e = hipMalloc((void**)&sbuf, 256 + vs.size() * 8);
+  hipError_t e = dev_malloc((void**)&sbuf, 256 + vs.size() * 8);
   if (e == hipSuccess) {
     unsigned long long* cnt = (unsigned long long*)sbuf;
     double* dvs = (double*)(sbuf + 256);
