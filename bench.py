@@ -97,10 +97,11 @@ def main():
     ap.add_argument("--uneven-traj", type=int, default=20000)
     ap.add_argument("--uneven-max-steps", type=int, default=50000,
                     help="accepted-step limit (the workload's step counts range up to 50,000)")
-    ap.add_argument("--uneven-schedule", choices=["auto", "queue"], default="auto",
-                    help="uneven workload, one call: the library's default split (the N=969 "
-                         "class on the binned schedule beside the work list) or everything on "
-                         "the work list (queue)")
+    ap.add_argument("--uneven-schedule", choices=["auto", "queue", "split"], default="auto",
+                    help="uneven workload: one call with the library's default split (the N=969 "
+                         "class on the binned schedule beside the work list), everything on "
+                         "the work list in one call (queue), or two calls one after the other "
+                         "(split: the N=969 class binned, then the rest on the work list)")
     ap.add_argument("--headline-only", action="store_true",
                     help="headline workload without the variants (for profiler runs)")
     ap.add_argument("--uneven-layout", choices=["dense", "sparse"], default="sparse",
@@ -564,6 +565,7 @@ def headline(args):
     t0 = time.time()
     (s, ), b = S.config5(n_traj=B, n_steps=T, N=N, build_tables=False)
     ctx = mq.Context(0)
+    probe = read_bandwidth_probe(ctx=ctx)["read_bandwidth_probe"]
     Md = S.gp_tables_device(s, ctx.device)
     torch.cuda.synchronize()
     log("large: N=%d tables built on the device in %.1fs" % (N, time.time() - t0))
@@ -609,6 +611,9 @@ def headline(args):
     tr = MEASURED_TRAFFIC.get(("C64", "large"))
     if tr and tr["source_sha256_16"] == _source_hash(tr["source"]) and tr["trajectories"] == B:
         roof["traffic"] = tr["bytes"]
+    # against the streaming-read rate this GPU reaches with 1 KiB wave loads (2 GB buffer)
+    roof["measured_read_peak_GBps"] = probe["2GB"]["GBps"]
+    roof["frac_of_measured_read_peak"] = gbps / probe["2GB"]["GBps"]
     head["roofline"] = roof
     head["windows"] = [{k: v for k, v in r.items()} for r in rec]
     finals["C64/rk4"] = cw["P"]
@@ -646,7 +651,7 @@ def headline(args):
             "roofline": head["roofline"],
             "N2_traj_steps_per_s": head["N2_traj_steps_per_s"],
             "status_nonzero": head["status_nonzero"], "system": info,
-            "windows": head["windows"]}
+            "read_bandwidth_probe": probe, "windows": head["windows"]}
     if "C128/dp5" in finals:
         dd = np.abs(finals["C64/dp5"] - finals["C128/dp5"])
         line["fp32_vs_fp64_dP"] = {"max": float(dd.max()), "mean": float(dd.mean()),
@@ -1136,9 +1141,25 @@ def uneven_workload(args):
                  R0=b.R0[w], max_steps=50, **DP)
     log("uneven: autotuner %s" % ctx.tuning_report())
     torch.cuda.synchronize()
+    parts = {}
     t1 = time.time()
-    g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, schedule=args.uneven_schedule,
-                     **start, **DP)
+    if args.uneven_schedule == "split":
+        big = b.system_index == int(np.argmax([x.N for x in systems]))
+        g = {}
+        for name, m, sched in (("binned", big, "binned"), ("work_list", ~big, "queue")):
+            tp = time.time()
+            gp = ctx.run_host(sids[m], Ns[m], max_steps=args.uneven_max_steps, schedule=sched,
+                              **{k: v[m] for k, v in start.items()}, **DP)
+            parts[name] = time.time() - tp
+            log("uneven split: %s part (%d trajectories) %.2f s" % (name, int(m.sum()),
+                                                                    parts[name]))
+            for k in ("steps", "rejects", "status"):
+                if k not in g:
+                    g[k] = np.zeros(b.B, gp[k].dtype)
+                g[k][m] = gp[k]
+    else:
+        g = ctx.run_host(sids, Ns, max_steps=args.uneven_max_steps, schedule=args.uneven_schedule,
+                         **start, **DP)
     sec = time.time() - t1
     steps, rej = g["steps"], g["rejects"]
     evals = 6 * (steps + rej) + 3          # attempts x 6, the two starting evaluations, the end
@@ -1162,15 +1183,20 @@ def uneven_workload(args):
             "config": {"workload": "uneven batch of %d trajectories: N=49/256/969 systems "
                                    "60/30/10 %%, E_coll log-uniform 10-5000 cm^-1, DP5 rtol 1e-8, "
                                    "at most %d steps, FP32 tables (%s layout where mostly zero), "
-                                   "one call, %s" % (
+                                   "%s" % (
                                        b.B, args.uneven_max_steps, args.uneven_layout,
-                                       "work-list schedule" if args.uneven_schedule == "queue"
-                                       else "default schedule: the N=969 class binned on a "
-                                            "second stream beside the work list"),
+                                       {"queue": "one call, work-list schedule",
+                                        "split": "two calls: the N=969 class binned, then the "
+                                                 "rest on the work list",
+                                        "auto": "one call, default schedule: the N=969 class binned on a "
+                                                "second stream beside the work list"}[
+                                           args.uneven_schedule]),
                        "trajectories": b.B},
             "N2_traj_steps_per_s": float(np.sum(steps * Ns.astype(float) ** 2)) / sec,
             "coupling_work_GBps": gbps,
             "per_system": per, "autotuner": ctx.tuning_report()}
+    if parts:
+        line["parts_s"] = parts
     log("uneven: %.1f s, %d steps, %.3g traj-steps/s (%s)" % (
         sec, int(steps.sum()), line["value"], json.dumps(per)))
     ctx.close()
@@ -1284,27 +1310,26 @@ def cpu_baseline(s, b, W):
                       "complex N=969 tables); wall time of the propagation only" % (n, b.B, W)}
 
 
-def read_bandwidth_probe(reps=20):
-    """Achievable streaming-read bandwidth: a float32 sum over buffers of 2 GB
-    (HBM), 200 MB (fits the 256 MB Infinity Cache) and 8 MB, timed with events
-    over `reps` back-to-back reductions (the result is 4 bytes)."""
+def read_bandwidth_probe(reps=20, ctx=None):
+    """Achievable streaming-read bandwidth with the library's read kernel (1 KiB
+    contiguous wave loads, four workgroups per compute unit) over buffers of 2 GB
+    (HBM), 200 MB (fits the 256 MB Infinity Cache) and 8 MB (fits the L2 of the
+    dies), `reps` passes each timed with events."""
     import torch
+    import paper_2312_02322_amd as mq
+    own = ctx is None
+    if own:
+        ctx = mq.Context(0)
     out = {}
     for name, nbytes in (("2GB", 2 << 30), ("200MB", 200 << 20), ("8MB", 8 << 20)):
-        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        for _ in range(3):
-            x.sum()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            x.sum()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device=ctx.device)
+        ms = ctx.read_bandwidth(x, reps)
         out[name] = {"bytes": nbytes, "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}
-        log("read probe %s: %.3f ms, %.0f GB/s" % (name, ms, out[name]["GBps"]))
+        log("read probe %s: %.4f ms, %.0f GB/s" % (name, ms, out[name]["GBps"]))
         del x
+    if own:
+        ctx.close()
+    torch.cuda.empty_cache()
     return {"read_bandwidth_probe": out}
 
 

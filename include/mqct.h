@@ -546,6 +546,19 @@ mqct_status mqct_set_profiling(mqct_context* ctx, int32_t enable);
 mqct_status mqct_profile_read(mqct_context* ctx, double* total_ms, int64_t* launches,
                               double* table_bytes);
 
+/*
+ * Achievable streaming-read bandwidth, the measured reference for the
+ * bandwidth-bound kernels beside the datasheet peak (not part of the method).
+ * Reads `bytes` at the device buffer `buf` (caller-owned, 16-byte aligned,
+ * bytes a positive multiple of 16; its contents are only read) once untimed,
+ * then `reps` (>= 1) times between two events on the context stream, with
+ * 1 KiB-contiguous wave loads and four workgroups per compute unit.
+ * *ms_per_pass (host) receives the mean milliseconds of one pass.  Synchronous.
+ * Errors: MQCT_ERR_ARG (null pointers, size, alignment, reps), MQCT_ERR_DEVICE.
+ */
+mqct_status mqct_read_bandwidth(mqct_context* ctx, const void* buf, int64_t bytes, int32_t reps,
+                                double* ms_per_pass);
+
 #ifdef __cplusplus
 }
 #endif

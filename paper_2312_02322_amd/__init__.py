@@ -37,7 +37,7 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
            "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients",
            "mqct_coupling_build_sparse", "mqct_get_state", "mqct_set_state",
-           "mqct_state_count", "mqct_run_noalloc"]
+           "mqct_state_count", "mqct_run_noalloc", "mqct_read_bandwidth"]
 
 
 class CouplingDesc(C.Structure):
@@ -128,6 +128,8 @@ def lib():
         L.mqct_set_profiling.restype = i32
         L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)]
         L.mqct_profile_read.restype = i32
+        L.mqct_read_bandwidth.argtypes = [vp, vp, i64, i32, C.POINTER(d)]
+        L.mqct_read_bandwidth.restype = i32
         L.mqct_system_set_params.argtypes = [vp, i32, i32, vp, vp, i32, vp]
         L.mqct_system_set_params.restype = i32
         L.mqct_system_set_theta.argtypes = [vp, i32, vp]
@@ -575,6 +577,15 @@ class Context:
         if with_bytes:
             return ms.value, n.value, by.value
         return ms.value, n.value
+
+    def read_bandwidth(self, buf, reps=20):
+        """Mean milliseconds of one streaming read of the device tensor `buf` (the
+        measured read reference for bandwidth-bound kernels)."""
+        ms = C.c_double()
+        self._check(lib().mqct_read_bandwidth(self.h, C.c_void_p(buf.data_ptr()),
+                                              buf.numel() * buf.element_size(), int(reps),
+                                              C.byref(ms)))
+        return ms.value
 
     def cross_sections(self, P, b, init_level, level_of_channel, n_levels, b_max):
         """Monte-Carlo cross sections (bohr^2) from P [B, N] on the device."""

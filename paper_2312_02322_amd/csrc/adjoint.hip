@@ -58,7 +58,12 @@ struct AdjArgs {
   const double* rad2;      // [P][K] their natural-spline second derivatives
   int P, nG;
   const int* gidx;         // [P]
+  const int* order;        // [B] trajectories in the order they are dealt to the dies
+  int64_t B;
+  int per_die;             // workgroups per die (blocks x, x + 8, ... of die x)
 };
+
+constexpr int ADIES = 8;   // accelerator dies of the device, each with its own L2
 
 template <bool CPLX, int NR, bool ELL>
 struct Adj {
@@ -370,7 +375,11 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   using K = Adj<CPLX, NR, ELL>;
   using St = typename K::St;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+  // workgroups are handed to the dies round-robin: die x runs blocks x, x + 8, ...,
+  // which take a contiguous share of the ordered trajectories
+  const int64_t pos = (int64_t)(blockIdx.x % ADIES) * A.per_die + blockIdx.x / ADIES;
+  if (pos >= A.B) return;
+  const int b = A.order[pos];
   const TrajIn tj = A.traj[b];
   const DevSystem sy = systems[tj.sys];
   const int N = sy.N, Npad = sy.Npad;
@@ -528,24 +537,26 @@ int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S) {
 }
 
 hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
-                          const TrajIn* d_traj,
+                          const TrajIn* d_traj, const int* order,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const uint32_t* gent, const double* gval,
                           const double* rad, const double* rad2, const int* gidx, int P, int nG,
                           hipStream_t s) {
   if (nG > NGMAX || P > AB) return hipErrorInvalidValue;
+  const int per = (int)((B + ADIES - 1) / ADIES);
   AdjArgs A{d_traj, dLdP, grad_part, P_out, scratch, scratch_stride, S, goff, gent, gval,
-            rad, rad2, P, nG, gidx};
+            rad, rad2, P, nG, gidx, order, B, per};
+  const unsigned grid = (unsigned)per * ADIES;
   // four double2 vectors, then red [ANW][NSC] and tq [3 NGMAX]
   const size_t lds = (size_t)Npad * 64 + (size_t)ANW * NSC * 8 + (size_t)3 * NGMAX * 8;
   const int nr = (Npad + AB - 1) / AB;
   hipError_t e;
   auto go = [&](auto cp, auto el) {
     constexpr bool C = decltype(cp)::value, E = decltype(el)::value;
-    if (nr <= 1) adjoint_kernel<C, 1, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 2) adjoint_kernel<C, 2, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
-    else adjoint_kernel<C, 4, E><<<(unsigned)B, AB, lds, s>>>(d_systems, A);
+    if (nr <= 1) adjoint_kernel<C, 1, E><<<grid, AB, lds, s>>>(d_systems, A);
+    else if (nr <= 2) adjoint_kernel<C, 2, E><<<grid, AB, lds, s>>>(d_systems, A);
+    else adjoint_kernel<C, 4, E><<<grid, AB, lds, s>>>(d_systems, A);
   };
   if (nr > 4) return hipErrorInvalidValue;
   if (cplx) {

@@ -908,7 +908,10 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     }
     hipError_t side_err = hipSuccess;
     std::thread side_thread;
-    if (!side_groups.empty())
+    // started once the work list's autotuner has timed its candidates, so that
+    // the timing runs have the device to themselves
+    auto start_side = [&]() {
+      if (side_groups.empty() || side_thread.joinable()) return;
       side_thread = std::thread([c, ctl, max_attempts, d_a0, out, &side_groups, &side_err]() {
         hipError_t e = hipSetDevice(c->device);
         for (size_t k = 0; k < side_groups.size() && e == hipSuccess; ++k) {
@@ -919,11 +922,14 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
         if (e == hipSuccess) e = hipEventRecord(c->side_done, c->side);
         side_err = e;
       });
+    };
     hipError_t e = hipSuccess;
     if (!classes.empty())
       e = run_queue(c->d_systems, (const TrajIn*)c->traj.p, classes, d_a0, out, method, ctl,
                     max_attempts, c->qopt, c->qcache, c->qws.p, c->stream, c->cap, c->h_counts,
-                    &c->prof);
+                    &c->prof, start_side);
+    else
+      start_side();
     if (side_thread.joinable()) {
       side_thread.join();
       if (side_err != hipSuccess) return hip_fail(c, side_err, "run: binned share");
@@ -1320,6 +1326,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
   if (bd->a0 || bd->classical0 || bd->t0 || bd->resume)
     return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: start states come from init_channel/E_coll/b/R0");
   if (checkpoint_every < 1) return fail(c, MQCT_ERR_ARG, "adjoint: checkpoint_every must be >= 1");
+  if (B > INT32_MAX) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: B too large");
   const int sid = bd->system_id[0];
   for (int64_t b = 0; b < B; ++b)
     if (bd->system_id[b] != sid) return fail(c, MQCT_ERR_UNSUPPORTED, "adjoint: one system per batch");
@@ -1352,6 +1359,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
   size_t off = 0;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_traj = off; off += al(B * sizeof(TrajIn));
+  const size_t o_ord = off; off += al((size_t)B * 4);
   const size_t o_w = off; off += al((size_t)amp * 8);
   const size_t o_part = off; off += al((size_t)B * sh.P * 8);
   const size_t o_g = off; off += al((size_t)sh.P * 8);
@@ -1362,12 +1370,26 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
   char* base = (char*)c->binws.p;
   HIP_TRY(c, hipMemcpyAsync(base + o_traj, tr.data(), B * sizeof(TrajIn), hipMemcpyHostToDevice,
                             c->stream), "adjoint");
+  // trajectories of similar paths (same energy and start, neighbouring impact
+  // parameters) go to the same die, so the spline slices they read at a time are
+  // fewer and stay in that die's L2; every trajectory writes its own results
+  std::vector<int> ord(B);
+  for (int64_t b = 0; b < B; ++b) ord[b] = (int)b;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const TrajIn &p = tr[x], &q = tr[y];
+    if (p.E_coll != q.E_coll) return p.E_coll < q.E_coll;
+    if (p.R0 != q.R0) return p.R0 < q.R0;
+    return p.b < q.b;
+  });
+  HIP_TRY(c, hipMemcpyAsync(base + o_ord, ord.data(), (size_t)B * 4, hipMemcpyHostToDevice,
+                            c->stream), "adjoint");
   HIP_TRY(c, hipMemcpyAsync(base + o_w, dL_dP, (size_t)amp * 8, hipMemcpyHostToDevice, c->stream),
           "adjoint");
   hipEvent_t e0 = c->prof.next(), e1 = c->prof.next();
   prof_mark(&c->prof, e0, c->stream);
   HIP_TRY(c, launch_adjoint(c->d_systems, dtype_complex(sy.dtype), sy.ell_w > 0, sy.Npad,
-                            (const TrajIn*)(base + o_traj), B, (const double*)(base + o_w),
+                            (const TrajIn*)(base + o_traj), (const int*)(base + o_ord), B,
+                            (const double*)(base + o_w),
                             (double*)(base + o_part), (double*)(base + o_g),
                             (double*)(base + o_P), (double*)(base + o_s), stride, S,
                             (const int*)sh.pbufs[4], (const uint32_t*)sh.pbufs[5],
@@ -1746,6 +1768,38 @@ mqct_status mqct_coupling_build_sparse(mqct_context* c, const mqct_coupling_desc
   if (*n_kept > capacity)
     return fail(c, MQCT_ERR_ARG, "coupling_build_sparse: %lld elements kept, capacity %lld",
                 (long long)*n_kept, (long long)capacity);
+  return MQCT_OK;
+}
+
+mqct_status mqct_read_bandwidth(mqct_context* c, const void* buf, int64_t bytes, int32_t reps,
+                                double* ms_per_pass) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!buf || !ms_per_pass) return fail(c, MQCT_ERR_ARG, "read_bandwidth: null argument");
+  if (bytes < 16 || bytes % 16 != 0 || ((uintptr_t)buf & 15) != 0)
+    return fail(c, MQCT_ERR_ARG, "read_bandwidth: bytes must be a positive multiple of 16 "
+                                 "and buf 16-byte aligned");
+  if (reps < 1) return fail(c, MQCT_ERR_ARG, "read_bandwidth: reps must be >= 1");
+  HIP_TRY(c, hipSetDevice(c->device), "read_bandwidth");
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  // one untimed pass, then reps passes between two events
+  HIP_TRY(c, launch_read_probe(buf, bytes, cus, c->stream), "read_bandwidth");
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0), "read_bandwidth");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(c, MQCT_ERR_DEVICE, "read_bandwidth: event");
+  }
+  hipError_t e = hipEventRecord(e0, c->stream);
+  for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_read_probe(buf, bytes, cus, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "read_bandwidth");
+  *ms_per_pass = (double)ms / reps;
   return MQCT_OK;
 }
 

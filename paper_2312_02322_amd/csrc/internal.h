@@ -6,6 +6,7 @@
 
 #include "../../include/mqct.h"
 
+#include <functional>
 #include <utility>
 #include <vector>
 
@@ -215,7 +216,9 @@ struct QState {
   int64_t n_idx;       // RK4: time index, t = t0 + n_idx h
   int32_t status, flags;
 };
-enum { Q_DONE = 1, Q_LASTREJ = 2 };
+// Q_FINISH: a stored trajectory that had stopped for good; the next step launch
+// forms its results (through the same code as a step that finishes) and retires it.
+enum { Q_DONE = 1, Q_LASTREJ = 2, Q_FINISH = 4 };
 
 // Device workspace of one class (trajectories sharing storage type and Npad).
 struct QWS {
@@ -277,11 +280,14 @@ struct QueueCache {
 size_t queue_workspace_bytes(const std::vector<QueueClass>& cls, int method);
 // Runs a batch on the work-list schedule.  `cap` is a non-default stream used
 // only to capture graphs; `h_counts` is pinned host memory for cls.size() ints.
+// `on_tuned` (may be empty) is called once the autotuner has timed its
+// candidates, before the first step launch: work on other streams that would
+// share the device with the timing runs starts there.
 hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
                      const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
                      int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
                      QueueCache& cache, void* ws, hipStream_t s, hipStream_t cap, int* h_counts,
-                     Prof* prof);
+                     Prof* prof, const std::function<void()>& on_tuned = {});
 
 // R-binned lockstep RK4 (all trajectories on one system, d_traj in any order).
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32);
@@ -303,7 +309,7 @@ hipError_t run_binned_dp5(const DevSystem* d_systems, const DevSystem& hs, const
 // gent = row | col << 16, gval the values.
 int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S);
 hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
-                          const TrajIn* d_traj,
+                          const TrajIn* d_traj, const int* order,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const uint32_t* gent, const double* gval,
@@ -314,6 +320,9 @@ hipError_t launch_build_param_tables(const double* G, const double* rad, const i
                                      double* Mout, hipStream_t s);
 hipError_t launch_spline_rows(const double* y, const double* x, int K, int ncol, double* y2,
                               double* tmp, hipStream_t s);
+
+// Streaming read of `bytes` (a multiple of 16) at buf (measure.hip).
+hipError_t launch_read_probe(const void* buf, int64_t bytes, int n_cu, hipStream_t s);
 
 // Cross sections on the device.
 hipError_t launch_xsec(int64_t B, int N, const double* P, const double* b, const int32_t* init_level,

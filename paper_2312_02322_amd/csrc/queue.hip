@@ -203,7 +203,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
                      const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
                      int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
                      QueueCache& cache, void* wsp, hipStream_t s, hipStream_t cap, int* h_counts,
-                     Prof* prof) {
+                     Prof* prof, const std::function<void()>& on_tuned) {
   hipError_t e;
   char* p = (char*)wsp;
   int32_t* d_counts = (int32_t*)p;
@@ -355,6 +355,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
   for (size_t k = 0; k < runs.size(); ++k)
     if (init_shape[k] != runs[k].shape)
       if ((e = init_class(runs[k])) != hipSuccess) return e;
+  if (on_tuned) on_tuned();
 
   // step chunks until every work list is empty
   const int chunk = std::max(1, opt.chunk);

@@ -70,12 +70,12 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
   }
 
   // Results of a finished trajectory: one more right-hand side at its end
-  // state gives the norm, energy and J_x diagnostics.  Compiled once (not
-  // inlined), so that every caller -- a finishing step, or the init of a stored
-  // trajectory that has stopped for good -- forms the results with the same
-  // instructions (the compiler may contract multiply-adds differently in each
-  // inlined copy).
-  __device__ __noinline__ static void finish(const DevSystem& sy, const TrajIn& tj, const TrajOut& out,
+  // state gives the norm, energy and J_x diagnostics.  Each step kernel calls it
+  // from one place only (a stored trajectory that had stopped for good comes
+  // back through the same place, see Q_FINISH), so the results of a trajectory
+  // are formed by the same instructions whichever call it finished in (inlined
+  // copies may contract multiply-adds differently).
+  __device__ static void finish(const DevSystem& sy, const TrajIn& tj, const TrajOut& out,
                                 const double2 (&a)[NR], const QState& s, const Lds<DT>& lds,
                                 bool rk4) {
     double2 cur[NR];
@@ -249,11 +249,9 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
       s.status = tj.status0;
       s.flags = (tj.dflags & MQCT_S_LAST_REJECTED) ? Q_LASTREJ : 0;
       if (below) s.status |= ST_BELOW_GRID;
-      if (tj.flags & TRAJ_FINISHED) {
-        // stopped for good: the results as the finishing step gave them
-        s.flags |= Q_DONE;
-        finish(sy, tj, q.out, a, s, lds, false);
-      }
+      // stopped for good: the first step launch forms the results as the
+      // finishing step gave them, without an attempt
+      if (tj.flags & TRAJ_FINISHED) s.flags |= Q_FINISH;
       put_state(q.ws.st + i, s);
       return;
     }
@@ -316,6 +314,11 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     double2* amp = q.ws.amp + (int64_t)i * np;
     double2* ks = q.ws.kst + (int64_t)i * 8 * np;
     double* kcl = lds.kcl;   // [7][4]: slot q = classical derivative of stage q (q >= 1)
+    bool done = false;
+    if (s.flags & Q_FINISH) {
+      s.flags &= ~Q_FINISH;
+      done = true;
+    } else {
     const double h = s.h;
     double2 st[NR];
     double y5c[4] = {0.0, 0.0, 0.0, 0.0};
@@ -388,7 +391,6 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     const double en = uni(sqrt((e2[0] + ecl) / ncomp));
     if (below) s.status |= ST_BELOW_GRID;
     s.attempts += 1;
-    bool done = false;
     if (!isfinite(en)) {
       s.status |= ST_NONFINITE;
       done = true;
@@ -424,6 +426,7 @@ struct QK : Rhs<DT, BLOCK, RPT, SPLIT> {
     if (!done && s.h < q.ctl.h_min) { s.status |= ST_STEP_UNDERFLOW; done = true; }
     if (!done && s.steps >= q.ctl.max_steps) { s.status |= ST_MAX_STEPS; done = true; }
     if (!done && s.attempts >= q.max_attempts) { s.status |= ST_MAX_STEPS; done = true; }
+    }
     if (done) {
       s.flags |= Q_DONE;
       double2 a[NR];

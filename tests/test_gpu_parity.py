@@ -308,3 +308,22 @@ def test_unsupported_combinations_report_cleanly(ctx, gpu_lib):
     finally:
         del gpu_lib.SCHEDULES["bogus"]
     ctx.free_system(sid)
+
+
+def test_read_bandwidth_probe(ctx, gpu_lib):
+    """The streaming-read reference: a 1 GiB read is bounded above by the datasheet
+    8 TB/s and well above a tenth of it; odd sizes, misaligned buffers and reps < 1
+    are refused."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device=ctx.device)       # 1 GiB
+    ms = ctx.read_bandwidth(x, 5)
+    gbps = x.numel() * 4 / (ms * 1e-3) / 1e9
+    print("[gpu] read probe 1 GiB: %.3f ms, %.0f GB/s" % (ms, gbps), flush=True)
+    assert 800.0 < gbps < 8000.0
+    lib = gpu_lib.lib()
+    import ctypes as C
+    out = C.c_double()
+    p = x.data_ptr()
+    for ptr, nbytes, reps in ((p, 24, 1), (p + 4, 1024, 1), (p, 1024, 0), (0, 1024, 1)):
+        rc = lib.mqct_read_bandwidth(ctx.h, C.c_void_p(ptr), nbytes, reps, C.byref(out))
+        assert rc == gpu_lib.ERR_ARG, (ptr - p, nbytes, reps, rc)
