@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--workload", choices=["headline", "window", "large", "uneven", "at",
-                                           "coupling", "coupling_paper", "rates"],
+                                           "coupling", "coupling_paper", "rates", "paper_at"],
                     default="headline",
                     help="headline (default): the N=4096 collision (512 trajectories x 10,000 RK4 "
                          "steps, binned, FP32 tables), one bench step = 1/--steps of it, with "
@@ -79,7 +79,10 @@ def main():
                          "coupling_paper: screened build for the 206,350-state p-H2O + p-H2 "
                          "basis; "
                          "rates: Eq. 20 and rate coefficients for 1032 levels, 10 energies, "
-                         "20 temperatures")
+                         "20 temperatures; "
+                         "paper_at: AT dynamics at the paper's size -- the screened 206,350-state "
+                         "p-H2O + p-H2 matrices as a coordinate list, one path carrying the 100 "
+                         "lowest states, the whole collision in RK4 steps of 10 a.u.")
     ap.add_argument("--large-n", type=int, default=4096)
     ap.add_argument("--large-traj", type=int, default=512)
     ap.add_argument("--large-steps", type=int, default=10000)
@@ -148,6 +151,9 @@ def main():
         return
     if args.workload == "coupling_paper":
         print(json.dumps(coupling_paper_workload(args)), flush=True)
+        return
+    if args.workload == "paper_at":
+        print(json.dumps(paper_at_workload(args)), flush=True)
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_workload(args)), flush=True)
@@ -958,6 +964,107 @@ def coupling_workload(args, cpu_rows=256):
                                           % (cpu_rows, N, csec)}
         log("coupling: oracle %.3g elements/s on %d rows (%.1f s, %d threads)"
             % (cel / csec, cpu_rows, csec, oracle.threads()))
+    return line
+
+
+def paper_at_workload(args, n_init=100, U_cm=300.0, b_bohr=2.0, R0_bohr=20.0, dt=10.0):
+    """AT-MQCT at the paper's size (Section III): the p-H2O (j1 <= 28) + p-H2 (j2 <= 10)
+    basis below 8000 cm^-1 (206,350 states), its screened coupling matrices (elements
+    above the threshold at 6.03 or 7.11 bohr, the kept ones on 63 knots from 3 to 30
+    bohr) as a coordinate list; one classical path driven by the isotropic term,
+    carrying the 100 lowest states as initial states (the paper's 100 initial states
+    of water per trajectory); RK4 steps of 10 a.u. (the paper's smallest step) over
+    the whole collision from 20 bohr.  FP32 and FP64 tables."""
+    import numpy as np
+    import torch
+    import paper_2312_02322_amd as mq
+    from synth import coupling as CP
+    from synth import systems as S
+    t0 = time.time()
+    basis = CP.para_h2o_para_h2_basis()
+    terms = CP.select_terms(CP.expansion_terms(), 83, seed=0)
+    Rg = CP.log_grid(63)
+    ex = CP.synthetic_expansion(terms, Rg, seed=0)
+    vs = CP.synthetic_expansion(terms, np.array(CP.PAPER_SCREEN_R), seed=0).v
+    thr = CP.U.cm_to_hartree(CP.PAPER_SCALE_DROP_CM)
+    ctx = mq.Context(0)
+    out = ctx.build_couplings_sparse(basis, ex, vs, thr)
+    nnz = out["n_kept"]
+    log("paper_at: N=%d, %d kept elements (built in %.1f s with the basis)" % (
+        basis.N, nnz, time.time() - t0))
+    iso = [t for t, tm in enumerate(terms) if tuple(tm) == (0, 0, 0, 0)][0]
+    Udrv = ex.v[iso] / (2.0 * np.pi)       # the isotropic term is v / (2 pi) times the identity
+    mu = CP.U.amu_to_me(1.8)
+    E = CP.U.cm_to_hartree(U_cm)
+    init = np.argsort(basis.E, kind="stable")[:n_init].astype(np.int32)
+    n_steps = int(np.ceil(S.collision_time(R0_bohr, E, mu) / dt))
+    B = n_init
+    kw = dict(init_channel=init, E_coll=np.full(B, E), b=np.full(B, b_bohr),
+              R0=np.full(B, R0_bohr), dt=np.full(B, dt), schedule="columns", dynamics="at")
+    res = {}
+    for storage in ([args.only_paper] if getattr(args, "only_paper", None) else ["R32", "R64"]):
+        t1 = time.time()
+        sid = ctx.load_system_coo(R_grid=Rg, E=basis.E, rows=out["rows"], cols=out["cols"],
+                                  values=out["values"], mu=mu,
+                                  jx=(basis.jx_row, basis.jx_col, basis.jx_val), storage=storage)
+        ctx.set_driver(sid, Udrv)
+        torch.cuda.synchronize()
+        load_s = time.time() - t1
+        sids, Ns = np.full(B, sid, np.int32), np.full(B, basis.N, np.int64)
+        ctx.run(sids, Ns, n_steps=np.full(B, 4), **kw)           # warm-up
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(ctx.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g = ctx.run(sids, Ns, n_steps=np.full(B, n_steps), **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        es = 4 if storage == "R32" else 8
+        stage_ms = ms / (4.0 * n_steps)
+        # per stage: the interval's four slices of every kept element, and the
+        # amplitude passes (a0, accumulator, stage input for J_x read; accumulator,
+        # next stage input written: complex FP64) plus the phased operand written
+        tab = 4.0 * nnz * es
+        amp = float(basis.N) * B * (16 * 5 + 2 * es)
+        gather = float(nnz) * B * 2 * es
+        P = g["P"].reshape(B, basis.N)
+        moved = 1.0 - P[torch.arange(B), torch.as_tensor(init, device=P.device).long()]
+        r = {"seconds": ms * 1e-3, "rk4_steps": n_steps, "columns": B,
+             "column_steps_per_s": B * n_steps / (ms * 1e-3), "stage_ms": stage_ms,
+             "load_s": load_s, "table_bytes": ctx.system_bytes(sid),
+             "hbm_bytes_per_stage": tab + amp, "hbm_GBps": (tab + amp) / (stage_ms * 1e-3) / 1e9,
+             "gather_bytes_per_stage": gather,
+             "gather_GBps": gather / (stage_ms * 1e-3) / 1e9,
+             "max_norm_err": float(g["norm_err"].abs().max().item()),
+             "energy_err": float(g["energy_err"].abs().max().item()),
+             "status": int(g["status"].max().item()),
+             "R_final": float(g["classical"][0, 0].item()),
+             "population_moved_p50_max": [float(moved.median().item()), float(moved.max().item())]}
+        log("paper_at %s: %.2f s for %d columns x %d RK4 steps (%.3g column-steps/s), %.3f ms per "
+            "stage; HBM %.0f GB/s, gathers %.0f GB/s; max|norm-1| %.2e; moved p50/max %.2e/%.2e" % (
+                storage, r["seconds"], B, n_steps, r["column_steps_per_s"], stage_ms, r["hbm_GBps"],
+                r["gather_GBps"], r["max_norm_err"], *r["population_moved_p50_max"]))
+        res[storage] = r
+        if storage == "R32":
+            P32 = P.cpu().numpy()
+        else:
+            res["fp32_vs_fp64_max_abs_dP"] = float(np.max(np.abs(P32 - P.cpu().numpy()))) \
+                if "R32" in res else None
+        del g, P
+        ctx.free_system(sid)
+    ctx.close()
+    line = {"metric": "column-steps/s (AT, paper-size truncated tables)",
+            "value": res[list(res)[0]]["column_steps_per_s"], "unit": "column-steps/s",
+            "n_gpus": 1, "steps": n_steps, "warmup": 1,
+            "ms_per_step": res[list(res)[0]]["stage_ms"] * 4, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "AT-MQCT, p-H2O + p-H2 below 8000 cm^-1 (N=%d), %d screened "
+                                   "couplings on 63 knots, one path (E=%.0f cm^-1, b=%.1f bohr, "
+                                   "from %.0f bohr) x %d initial states, %d RK4 steps of %.0f a.u."
+                                   % (basis.N, nnz, U_cm, b_bohr, R0_bohr, B, n_steps, dt),
+                       "N": basis.N, "kept": nnz, "columns": B},
+            "variants": res}
     return line
 
 

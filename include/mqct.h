@@ -76,11 +76,17 @@ enum {
   MQCT_SCHED_BINNED = 2,      /* lockstep stages, trajectories binned by spline knot,
                                  table x amplitude-columns products on matrix cores;
                                  one system per batch; RK4 steps or DP5 attempts    */
-  MQCT_SCHED_QUEUE = 3        /* work list: one step attempt per launch for every
+  MQCT_SCHED_QUEUE = 3,       /* work list: one step attempt per launch for every
                                  unfinished trajectory, finished ones retired between
                                  chunks of launches (replayed as HIP graphs); mixes
                                  systems of any size; DP5 uses it unless BINNED is
                                  asked for                                          */
+  MQCT_SCHED_COLUMNS = 4      /* decoupled (AT) dynamics on a coordinate-list system
+                                 (mqct_system_load_coo): the trajectories that share a
+                                 path (same start, energy, impact parameter, t0, dt,
+                                 n_steps) are amplitude columns of one matrix, stepped
+                                 by RK4 as a sparse-table x column-matrix product; the
+                                 only schedule for such systems, and AUTO picks it  */
 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -142,6 +148,54 @@ typedef struct {
  * MQCT_ERR_OOM, MQCT_ERR_DEVICE.  Synchronous. */
 mqct_status mqct_system_load(mqct_context* ctx, const mqct_system_desc* desc,
                              int32_t* system_id);
+/*
+ * A collision system from a coordinate list of its coupling elements -- the
+ * truncated coupling matrices of Section III (elements above a threshold kept,
+ * computed on the radial grid only for those), for bases too large for the
+ * dense [K][N][N] input (the paper's 206,350 states).  The list is what
+ * mqct_coupling_build_sparse writes.
+ *   N, K, R_grid, E, mu, jx_*   as in mqct_system_desc.
+ *   in_dtype    MQCT_R64 or MQCT_C128: element type of values.
+ *   mem         MQCT_MEM_HOST or MQCT_MEM_DEVICE: where rows, cols, values live.
+ *   n_el        stored elements, 1 <= n_el < 2^31, both triangles: every
+ *               (n, m) must come with its (m, n) partner, equal (real) or
+ *               conjugate (complex) at every knot to 1e-12 of the largest
+ *               magnitude; no pair twice; any order.
+ *   rows, cols  [n_el] row n and column m of element i (0 <= n, m < N).
+ *   values      [K][ld] (element i at knot k: values[k * ld + i], hartree;
+ *               complex interleaved), ld >= n_el.
+ *   storage     MQCT_R64/MQCT_C128 or MQCT_R32/MQCT_C64 (real with real input).
+ * The elements are sorted into rows (CSR: each row's columns ascending), the
+ * natural-spline second derivative of every element along the grid is computed
+ * on the device in FP64, and values and curvatures are stored per knot in the
+ * storage type: 2 K n_el elements.  Such a system runs only decoupled (AT)
+ * dynamics with RK4 on MQCT_SCHED_COLUMNS and needs mqct_system_set_driver.
+ * Copied; the caller may free its arrays after the call.  Errors: MQCT_ERR_ARG
+ * (sizes, indices, duplicates, a missing partner, null pointers),
+ * MQCT_ERR_NONFINITE, MQCT_ERR_NOT_HERMITIAN (partner values differ),
+ * MQCT_ERR_OOM, MQCT_ERR_DEVICE.  Synchronous.
+ */
+typedef struct {
+  int32_t N, K;
+  const double* R_grid;
+  const double* E;
+  double mu;
+  int32_t in_dtype;
+  int32_t mem;
+  int64_t n_el;
+  const int32_t* rows;
+  const int32_t* cols;
+  const double* values;
+  int64_t ld;
+  int32_t storage;
+  int32_t jx_nnz;
+  const int32_t* jx_row;
+  const int32_t* jx_col;
+  const double* jx_val;
+} mqct_coo_desc;
+mqct_status mqct_system_load_coo(mqct_context* ctx, const mqct_coo_desc* desc,
+                                 int32_t* system_id);
+
 /* The driving potential of decoupled (AT) dynamics (Section III: the classical
  * trajectory is propagated apart from the quantum equations): U [K] host,
  * hartree, on the system's grid, interpolated by its natural cubic spline (the
@@ -509,8 +563,10 @@ mqct_status mqct_coupling_build(mqct_context* ctx, const mqct_coupling_desc* des
  * above 1 cm^-1 were kept and only those were computed on the radial grid).
  * Every element of equal m is evaluated at n_screen radii, given by the
  * expansion coefficients there (v_screen[t * n_screen + s], host, 1 <= n_screen
- * <= 8); it is kept when max_s |M(R_s)| > drop_below (hartree).  The kept
- * elements are written to device memory in an unspecified order:
+ * <= 8); it is kept when max_s |M(R_s)| > drop_below (hartree), the element and
+ * its transpose by the same evaluation, so both triangles are kept or dropped
+ * together (the list loads with mqct_system_load_coo).  The kept elements are
+ * written to device memory in an unspecified order:
  *   rows[i], cols[i]        row n'' and column n' of kept element i;
  *   values[k * capacity + i] its value at knot k (from desc->v), k < K.
  * *n_kept (host) receives the number of kept elements.  When it exceeds

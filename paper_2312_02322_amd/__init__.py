@@ -24,7 +24,7 @@ DTYPES = {"R64": 0, "C128": 1, "R32": 2, "C64": 3}
 INTEGRATORS = {"rk4": 0, "dp5": 1}
 DYNAMICS = {"ehrenfest": 0, "at": 1}
 LAYOUTS = {"dense": 0, "sparse": 1}
-SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3}
+SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3, "columns": 4}
 OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5}
 MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
@@ -37,7 +37,8 @@ EXPORTS = ["mqct_create", "mqct_destroy", "mqct_last_error", "mqct_synchronize",
            "mqct_set_option", "mqct_tuning_report", "mqct_system_set_driver",
            "mqct_coupling_build", "mqct_xs_symmetrize", "mqct_rate_coefficients",
            "mqct_coupling_build_sparse", "mqct_get_state", "mqct_set_state",
-           "mqct_state_count", "mqct_run_noalloc", "mqct_read_bandwidth"]
+           "mqct_state_count", "mqct_run_noalloc", "mqct_read_bandwidth",
+           "mqct_system_load_coo"]
 
 
 class CouplingDesc(C.Structure):
@@ -60,6 +61,15 @@ class SystemDesc(C.Structure):
                 ("storage", C.c_int32), ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p),
                 ("jx_col", C.c_void_p), ("jx_val", C.c_void_p), ("mu", C.c_double),
                 ("layout", C.c_int32), ("drop_below", C.c_double)]
+
+
+class CooDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("R_grid", C.c_void_p), ("E", C.c_void_p),
+                ("mu", C.c_double), ("in_dtype", C.c_int32), ("mem", C.c_int32),
+                ("n_el", C.c_int64), ("rows", C.c_void_p), ("cols", C.c_void_p),
+                ("values", C.c_void_p), ("ld", C.c_int64), ("storage", C.c_int32),
+                ("jx_nnz", C.c_int32), ("jx_row", C.c_void_p), ("jx_col", C.c_void_p),
+                ("jx_val", C.c_void_p)]
 
 
 class BatchDesc(C.Structure):
@@ -128,6 +138,8 @@ def lib():
         L.mqct_set_profiling.restype = i32
         L.mqct_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)]
         L.mqct_profile_read.restype = i32
+        L.mqct_system_load_coo.argtypes = [vp, C.POINTER(CooDesc), C.POINTER(i32)]
+        L.mqct_system_load_coo.restype = i32
         L.mqct_read_bandwidth.argtypes = [vp, vp, i64, i32, C.POINTER(d)]
         L.mqct_read_bandwidth.restype = i32
         L.mqct_system_set_params.argtypes = [vp, i32, i32, vp, vp, i32, vp]
@@ -256,6 +268,53 @@ class Context:
                        LAYOUTS[layout], float(drop_below))
         sid = C.c_int32()
         self._check(lib().mqct_system_load(self.h, C.byref(d), C.byref(sid)))
+        del keep
+        return sid.value
+
+    def load_system_coo(self, *, R_grid, E, rows, cols, values, mu, jx=None, storage=None,
+                        ld=None):
+        """Upload a system given as a coordinate list of its coupling elements (both
+        triangles): rows[i], cols[i] and values[k, i] at every knot k (hartree).
+        rows, cols and values are numpy arrays (host) or CUDA tensors (device, all
+        three); values real or complex, shaped [K, ld] with ld >= len(rows).
+        Such a system runs decoupled (AT) dynamics on the "columns" schedule."""
+        Rg = _host(R_grid, np.float64)
+        Eh = _host(E, np.float64)
+        K, N = Rg.shape[0], Eh.shape[0]
+        is_dev = hasattr(values, "data_ptr")
+        if is_dev:
+            torch = self.torch
+            cplx = values.is_complex()
+            vt = values.contiguous().to(torch.complex128 if cplx else torch.float64)
+            rt = rows.contiguous().to(torch.int32)
+            ct = cols.contiguous().to(torch.int32)
+            keep = (vt, rt, ct)
+            mem = MEM_DEVICE
+            vp_, rp_, cp_ = vt.data_ptr(), rt.data_ptr(), ct.data_ptr()
+        else:
+            cplx = np.iscomplexobj(values)
+            vt = np.ascontiguousarray(values, dtype=np.complex128 if cplx else np.float64)
+            rt, ct = _host(rows, np.int32), _host(cols, np.int32)
+            keep = (vt, rt, ct)
+            mem = MEM_HOST
+            vp_, rp_, cp_ = vt.ctypes.data, rt.ctypes.data, ct.ctypes.data
+        n_el = int(rt.shape[0])
+        if ld is None:
+            ld = int(vt.shape[-1])
+        if vt.shape[0] != K or int(ct.shape[0]) != n_el:
+            raise ValueError("values must be shaped [K, ld] and rows, cols [n_el]")
+        if storage is None:
+            storage = "C128" if cplx else "R64"
+        jr = jc = jv = None
+        nnz = 0
+        if jx is not None and len(jx[0]) > 0:
+            jr, jc, jv = _host(jx[0], np.int32), _host(jx[1], np.int32), _host(jx[2], np.float64)
+            nnz = jr.shape[0]
+        d = CooDesc(N, K, Rg.ctypes.data, Eh.ctypes.data, float(mu),
+                    DTYPES["C128" if cplx else "R64"], mem, n_el, rp_, cp_, vp_, int(ld),
+                    DTYPES[storage], nnz, _ptr(jr), _ptr(jc), _ptr(jv))
+        sid = C.c_int32()
+        self._check(lib().mqct_system_load_coo(self.h, C.byref(d), C.byref(sid)))
         del keep
         return sid.value
 

@@ -10,7 +10,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmqct.so")
 SOURCES = ["api.hip", "prep.hip", "gemv.hip", "binned.hip", "adjoint.hip", "queue.hip",
            "queue_r64.hip", "queue_c128.hip", "queue_r32.hip", "queue_c64.hip",
-           "coupling.hip", "postproc.hip", "measure.hip"]
+           "coupling.hip", "postproc.hip", "measure.hip", "columns.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Wno-unused-value",

@@ -194,6 +194,52 @@ void free_system(SysHost& s) {
   s.live = false;
 }
 
+// J_x (Eq. 5's Coriolis operator) from a coordinate list: range, symmetry and
+// equal-energy checks, then the ELL form [N][W] (padding entries point at the
+// row itself with value 0).  W = 0 when there is no Coriolis term.
+mqct_status build_jx(mqct_context* c, const char* who, int N, const double* E, int nnz,
+                     const int32_t* jrow, const int32_t* jcol, const double* jval,
+                     std::vector<int32_t>& col, std::vector<double>& val, int& W) {
+  if (nnz < 0 || (nnz > 0 && (!jrow || !jcol || !jval)))
+    return fail(c, MQCT_ERR_ARG, "%s: bad J_x arrays", who);
+  std::vector<std::vector<std::pair<int, double>>> rows(N);
+  std::map<std::pair<int, int>, double> jmap;
+  for (int q = 0; q < nnz; ++q) {
+    int r = jrow[q], cc = jcol[q];
+    double v = jval[q];
+    if (r < 0 || r >= N || cc < 0 || cc >= N)
+      return fail(c, MQCT_ERR_ARG, "%s: J_x index out of range at %d", who, q);
+    if (!isfinite(v)) return fail(c, MQCT_ERR_NONFINITE, "%s: non-finite J_x", who);
+    if (jmap.count({r, cc})) return fail(c, MQCT_ERR_ARG, "%s: duplicate J_x entry", who);
+    jmap[{r, cc}] = v;
+    rows[r].push_back({cc, v});
+  }
+  for (auto& kv : jmap) {
+    auto it = jmap.find({kv.first.second, kv.first.first});
+    if (it == jmap.end() || fabs(it->second - kv.second) > 1e-12 * (1.0 + fabs(kv.second)))
+      return fail(c, MQCT_ERR_ARG, "%s: J_x is not symmetric", who);
+  }
+  // Eq. 5: the Coriolis term couples m +- 1 within one channel n, i.e. states of
+  // equal energy; the kernels rely on that (J_x a = e^{iEt} J_x c row by row).
+  double emax = 0.0;
+  for (int n = 0; n < N; ++n) emax = std::max(emax, fabs(E[n]));
+  for (auto& kv : jmap)
+    if (fabs(E[kv.first.first] - E[kv.first.second]) > 1e-12 * emax)
+      return fail(c, MQCT_ERR_ARG, "%s: J_x couples channels of different energy", who);
+  W = 0;
+  for (auto& r : rows) W = std::max<int>(W, (int)r.size());
+  if (W > 8) return fail(c, MQCT_ERR_UNSUPPORTED, "%s: J_x has more than 8 nonzeros per row", who);
+  col.assign((size_t)N * W, 0);
+  val.assign((size_t)N * W, 0.0);
+  for (int r = 0; r < N; ++r)
+    for (int w = 0; w < W; ++w) {
+      const bool have = w < (int)rows[r].size();
+      col[(size_t)r * W + w] = have ? rows[r][w].first : r;
+      val[(size_t)r * W + w] = have ? rows[r][w].second : 0.0;
+    }
+  return MQCT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -304,35 +350,14 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
       return fail(c, MQCT_ERR_ARG, "system_load: R grid not strictly increasing at %d", k);
   if (!finite_arr(d->E, N)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite E");
   // Coriolis operator: coordinate list -> ELL, checked for range and symmetry
-  if (d->jx_nnz < 0 || (d->jx_nnz > 0 && (!d->jx_row || !d->jx_col || !d->jx_val)))
-    return fail(c, MQCT_ERR_ARG, "system_load: bad J_x arrays");
-  std::vector<std::vector<std::pair<int, double>>> rows(N);
-  std::map<std::pair<int, int>, double> jmap;
-  for (int q = 0; q < d->jx_nnz; ++q) {
-    int r = d->jx_row[q], cc = d->jx_col[q];
-    double v = d->jx_val[q];
-    if (r < 0 || r >= N || cc < 0 || cc >= N)
-      return fail(c, MQCT_ERR_ARG, "system_load: J_x index out of range at %d", q);
-    if (!isfinite(v)) return fail(c, MQCT_ERR_NONFINITE, "system_load: non-finite J_x");
-    if (jmap.count({r, cc})) return fail(c, MQCT_ERR_ARG, "system_load: duplicate J_x entry");
-    jmap[{r, cc}] = v;
-    rows[r].push_back({cc, v});
-  }
-  for (auto& kv : jmap) {
-    auto it = jmap.find({kv.first.second, kv.first.first});
-    if (it == jmap.end() || fabs(it->second - kv.second) > 1e-12 * (1.0 + fabs(kv.second)))
-      return fail(c, MQCT_ERR_ARG, "system_load: J_x is not symmetric");
-  }
-  // Eq. 5: the Coriolis term couples m +- 1 within one channel n, i.e. states of
-  // equal energy; the kernels rely on that (J_x a = e^{iEt} J_x c row by row).
-  double emax = 0.0;
-  for (int n = 0; n < N; ++n) emax = std::max(emax, fabs(d->E[n]));
-  for (auto& kv : jmap)
-    if (fabs(d->E[kv.first.first] - d->E[kv.first.second]) > 1e-12 * emax)
-      return fail(c, MQCT_ERR_ARG, "system_load: J_x couples channels of different energy");
+  std::vector<int32_t> jx_col_h;
+  std::vector<double> jx_val_h;
   int W = 0;
-  for (auto& r : rows) W = std::max<int>(W, (int)r.size());
-  if (W > 8) return fail(c, MQCT_ERR_UNSUPPORTED, "system_load: J_x has more than 8 nonzeros per row");
+  {
+    const mqct_status js = build_jx(c, "system_load", N, d->E, d->jx_nnz, d->jx_row, d->jx_col,
+                                    d->jx_val, jx_col_h, jx_val_h, W);
+    if (js != MQCT_OK) return js;
+  }
 
   HIP_TRY(c, hipSetDevice(c->device), "system_load");
   const int ncomp = cplx ? 2 : 1;
@@ -460,21 +485,10 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
     sh.table_bytes = 2 * (int64_t)ebytes;
   }
   if (W > 0) {
-    std::vector<int32_t> col((size_t)N * W);
-    std::vector<double> val((size_t)N * W, 0.0);
-    for (int r = 0; r < N; ++r)
-      for (int w = 0; w < W; ++w) {
-        if (w < (int)rows[r].size()) {
-          col[(size_t)r * W + w] = rows[r][w].first;
-          val[(size_t)r * W + w] = rows[r][w].second;
-        } else {
-          col[(size_t)r * W + w] = r;
-        }
-      }
-    if ((e = dev_malloc(&sh.bufs[4], col.size() * 4)) != hipSuccess) return dfail(e, "system_load: J_x");
-    if ((e = dev_malloc(&sh.bufs[5], val.size() * 8)) != hipSuccess) return dfail(e, "system_load: J_x");
-    if ((e = hipMemcpy(sh.bufs[4], col.data(), col.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(sh.bufs[5], val.data(), val.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = dev_malloc(&sh.bufs[4], jx_col_h.size() * 4)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = dev_malloc(&sh.bufs[5], jx_val_h.size() * 8)) != hipSuccess) return dfail(e, "system_load: J_x");
+    if ((e = hipMemcpy(sh.bufs[4], jx_col_h.data(), jx_col_h.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(sh.bufs[5], jx_val_h.data(), jx_val_h.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
       return dfail(e, "system_load: J_x");
   }
   cleanup();
@@ -492,6 +506,206 @@ mqct_status mqct_system_load(mqct_context* c, const mqct_system_desc* d, int32_t
   if (id < 0) { id = (int)c->systems.size(); c->systems.push_back(sh); }
   else c->systems[id] = sh;
   st = upload_systems(c);
+  if (st != MQCT_OK) return st;
+  *system_id = id;
+  return MQCT_OK;
+}
+
+mqct_status mqct_system_load_coo(mqct_context* c, const mqct_coo_desc* d, int32_t* system_id) {
+  if (!c) return MQCT_ERR_ARG;
+  if (!d || !system_id) return fail(c, MQCT_ERR_ARG, "system_load_coo: null argument");
+  const int N = d->N, K = d->K;
+  if (N < 1 || K < 4 || K > 2048)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: need N >= 1 and 4 <= K <= 2048 (N=%d K=%d)", N, K);
+  if (!d->R_grid || !d->E || !d->rows || !d->cols || !d->values)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: null R_grid/E/rows/cols/values");
+  if (d->in_dtype != MQCT_R64 && d->in_dtype != MQCT_C128)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: in_dtype must be MQCT_R64 or MQCT_C128");
+  if (d->storage < MQCT_R64 || d->storage > MQCT_C64)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: unknown storage type %d", d->storage);
+  const bool cplx = d->in_dtype == MQCT_C128;
+  if (dtype_complex(d->storage) != cplx)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: storage and input must both be real or both complex");
+  if (d->mem != MQCT_MEM_HOST && d->mem != MQCT_MEM_DEVICE)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: mem must be host or device");
+  const int64_t nnz = d->n_el;
+  if (nnz < 1 || nnz >= ((int64_t)1 << 31) || d->ld < nnz)
+    return fail(c, MQCT_ERR_ARG, "system_load_coo: need 1 <= n_el < 2^31 and ld >= n_el");
+  if (!(d->mu > 0.0) || !isfinite(d->mu)) return fail(c, MQCT_ERR_ARG, "system_load_coo: mu must be > 0");
+  if (!finite_arr(d->R_grid, K)) return fail(c, MQCT_ERR_NONFINITE, "system_load_coo: non-finite R grid");
+  for (int k = 1; k < K; ++k)
+    if (!(d->R_grid[k] > d->R_grid[k - 1]))
+      return fail(c, MQCT_ERR_ARG, "system_load_coo: R grid not strictly increasing at %d", k);
+  if (!finite_arr(d->E, N)) return fail(c, MQCT_ERR_NONFINITE, "system_load_coo: non-finite E");
+  std::vector<int32_t> jx_col_h;
+  std::vector<double> jx_val_h;
+  int W = 0;
+  {
+    const mqct_status js = build_jx(c, "system_load_coo", N, d->E, d->jx_nnz, d->jx_row, d->jx_col,
+                                    d->jx_val, jx_col_h, jx_val_h, W);
+    if (js != MQCT_OK) return js;
+  }
+  HIP_TRY(c, hipSetDevice(c->device), "system_load_coo");
+  // rows and columns on the host: sorted into CSR order (rows, then columns),
+  // duplicates and missing (m, n) partners refused
+  std::vector<int32_t> hr(nnz), hc(nnz);
+  if (d->mem == MQCT_MEM_HOST) {
+    memcpy(hr.data(), d->rows, nnz * 4);
+    memcpy(hc.data(), d->cols, nnz * 4);
+  } else {
+    HIP_TRY(c, hipMemcpy(hr.data(), d->rows, nnz * 4, hipMemcpyDeviceToHost), "system_load_coo: indices");
+    HIP_TRY(c, hipMemcpy(hc.data(), d->cols, nnz * 4, hipMemcpyDeviceToHost), "system_load_coo: indices");
+  }
+  std::vector<std::pair<int64_t, int32_t>> key(nnz);
+  for (int64_t i = 0; i < nnz; ++i) {
+    if (hr[i] < 0 || hr[i] >= N || hc[i] < 0 || hc[i] >= N)
+      return fail(c, MQCT_ERR_ARG, "system_load_coo: element %lld index out of range", (long long)i);
+    key[i] = {(int64_t)hr[i] * N + hc[i], (int32_t)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> perm(nnz), ccol(nnz), rowptr(N + 1, 0), partner(nnz);
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (e > 0 && key[e].first == key[e - 1].first)
+      return fail(c, MQCT_ERR_ARG, "system_load_coo: element (%lld, %lld) given twice",
+                  (long long)(key[e].first / N), (long long)(key[e].first % N));
+    perm[e] = key[e].second;
+    ccol[e] = (int32_t)(key[e].first % N);
+    ++rowptr[key[e].first / N + 1];
+  }
+  for (int n = 0; n < N; ++n) rowptr[n + 1] += rowptr[n];
+  for (int n = 0; n < N; ++n)
+    for (int32_t e = rowptr[n]; e < rowptr[n + 1]; ++e) {
+      const int m = ccol[e];
+      const int32_t* lo = ccol.data() + rowptr[m];
+      const int32_t* hi = ccol.data() + rowptr[m + 1];
+      const int32_t* it = std::lower_bound(lo, hi, n);
+      if (it == hi || *it != n)
+        return fail(c, MQCT_ERR_ARG, "system_load_coo: element (%d, %d) has no partner (%d, %d)",
+                    n, m, m, n);
+      partner[e] = (int32_t)(it - ccol.data());
+    }
+  key.clear();
+  key.shrink_to_fit();
+
+  const int NC = cplx ? 2 : 1;
+  const int es = dtype_fp32(d->storage) ? 4 : 8;
+  const int64_t nreal = nnz * NC;
+  SysHost sh;
+  sh.dev.N = N; sh.dev.K = K; sh.dev.Npad = (N + 15) / 16 * 16; sh.dev.dtype = d->storage;
+  sh.dev.jx_w = W; sh.dev.mu = d->mu; sh.dev.knot_stride = nnz;
+  {
+    const double hu = (d->R_grid[K - 1] - d->R_grid[0]) / (K - 1);
+    bool uniform = true;
+    for (int k = 0; k < K && uniform; ++k)
+      uniform = fabs(d->R_grid[k] - (d->R_grid[0] + k * hu)) <= 1e-9 * hu;
+    sh.dev.R_inv_h = uniform ? 1.0 / hu : 0.0;
+  }
+  sh.table_bytes = 2 * (int64_t)K * nreal * es;
+  double* din = nullptr;
+  bool own_in = false;
+  double* v64 = nullptr;
+  double* c64 = nullptr;
+  int32_t* d_perm = nullptr;
+  int32_t* d_partner = nullptr;
+  unsigned long long* stats = nullptr;
+  auto cleanup = [&]() {
+    if (own_in && din) hipFree(din);
+    for (void* q : {(void*)d_perm, (void*)d_partner, (void*)stats}) if (q) hipFree(q);
+    if (v64 && v64 != sh.bufs[0]) hipFree(v64);
+    if (c64 && c64 != sh.bufs[1]) hipFree(c64);
+  };
+  auto dfail = [&](hipError_t e, const char* what) {
+    cleanup();
+    free_system(sh);
+    return hip_fail(c, e, what);
+  };
+  hipError_t e;
+  if (d->mem == MQCT_MEM_HOST) {
+    const size_t in_bytes = (size_t)K * d->ld * NC * 8;
+    if ((e = dev_malloc((void**)&din, in_bytes)) != hipSuccess) return dfail(e, "system_load_coo: input");
+    own_in = true;
+    if ((e = hipMemcpy(din, d->values, in_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return dfail(e, "system_load_coo: upload");
+  } else {
+    din = (double*)d->values;
+  }
+  if ((e = dev_malloc((void**)&d_perm, nnz * 4)) != hipSuccess ||
+      (e = dev_malloc((void**)&d_partner, nnz * 4)) != hipSuccess ||
+      (e = dev_malloc((void**)&stats, 3 * sizeof(unsigned long long))) != hipSuccess ||
+      (e = dev_malloc((void**)&v64, (size_t)K * nreal * 8)) != hipSuccess ||
+      (e = dev_malloc((void**)&c64, (size_t)K * nreal * 8)) != hipSuccess ||
+      (e = dev_malloc(&sh.bufs[2], K * 8)) != hipSuccess ||
+      (e = dev_malloc(&sh.bufs[3], N * 8)) != hipSuccess ||
+      (e = dev_malloc(&sh.ebuf[0], (size_t)(N + 1) * 4)) != hipSuccess ||
+      (e = dev_malloc(&sh.ebuf[1], (size_t)nnz * 4)) != hipSuccess)
+    return dfail(e, "system_load_coo: buffers");
+  if ((e = hipMemcpy(d_perm, perm.data(), nnz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_partner, partner.data(), nnz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.bufs[2], d->R_grid, K * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.bufs[3], d->E, N * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.ebuf[0], rowptr.data(), (size_t)(N + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(sh.ebuf[1], ccol.data(), (size_t)nnz * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return dfail(e, "system_load_coo: upload");
+  if ((e = hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), c->stream)) != hipSuccess ||
+      (e = launch_coo_gather(din, d->ld, d_perm, nnz, K, NC, v64, stats + 2, c->stream)) != hipSuccess ||
+      (e = launch_csr_partner_check(v64, d_partner, nnz, K, NC, stats, stats + 1, c->stream)) != hipSuccess)
+    return dfail(e, "system_load_coo: validate");
+  unsigned long long hs[3];
+  if ((e = hipMemcpyAsync(hs, stats, sizeof hs, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return dfail(e, "system_load_coo: validate");
+  if (hs[2] > 0) {
+    cleanup();
+    free_system(sh);
+    return fail(c, MQCT_ERR_NONFINITE, "system_load_coo: %llu non-finite values", hs[2]);
+  }
+  double dmax, amax;
+  memcpy(&dmax, &hs[0], 8);
+  memcpy(&amax, &hs[1], 8);
+  if (dmax > 1e-12 * amax) {
+    cleanup();
+    free_system(sh);
+    return fail(c, MQCT_ERR_NOT_HERMITIAN, "system_load_coo: |M_nm - conj(M_mn)| = %.3e > 1e-12 "
+                "max|M| = %.3e", dmax, 1e-12 * amax);
+  }
+  // natural-spline second derivatives of every real component, FP64
+  if ((e = launch_csr_spline(v64, (const double*)sh.bufs[2], K, nreal, c64, c->stream)) != hipSuccess)
+    return dfail(e, "system_load_coo: spline");
+  if (es == 8) {
+    sh.bufs[0] = v64;
+    sh.bufs[1] = c64;
+  } else {
+    if ((e = dev_malloc(&sh.bufs[0], (size_t)K * nreal * 4)) != hipSuccess ||
+        (e = dev_malloc(&sh.bufs[1], (size_t)K * nreal * 4)) != hipSuccess ||
+        (e = launch_csr_cast_f32(v64, (int64_t)K * nreal, (float*)sh.bufs[0], c->stream)) != hipSuccess ||
+        (e = launch_csr_cast_f32(c64, (int64_t)K * nreal, (float*)sh.bufs[1], c->stream)) != hipSuccess)
+      return dfail(e, "system_load_coo: storage");
+  }
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return dfail(e, "system_load_coo: spline");
+  if (W > 0) {
+    if ((e = dev_malloc(&sh.bufs[4], jx_col_h.size() * 4)) != hipSuccess ||
+        (e = dev_malloc(&sh.bufs[5], jx_val_h.size() * 8)) != hipSuccess ||
+        (e = hipMemcpy(sh.bufs[4], jx_col_h.data(), jx_col_h.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(sh.bufs[5], jx_val_h.data(), jx_val_h.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      return dfail(e, "system_load_coo: J_x");
+  }
+  cleanup();
+  sh.dev.M = sh.bufs[0];
+  sh.dev.M2 = sh.bufs[1];
+  sh.dev.R = (const double*)sh.bufs[2];
+  sh.dev.E = (const double*)sh.bufs[3];
+  sh.dev.jx_col = (const int32_t*)sh.bufs[4];
+  sh.dev.jx_val = (const double*)sh.bufs[5];
+  sh.dev.csr_row = (const int32_t*)sh.ebuf[0];
+  sh.dev.csr_col = (const int32_t*)sh.ebuf[1];
+  sh.R_last = d->R_grid[K - 1];
+  sh.live = true;
+  int id = -1;
+  for (size_t i = 0; i < c->systems.size(); ++i)
+    if (!c->systems[i].live) { id = (int)i; break; }
+  if (id < 0) { id = (int)c->systems.size(); c->systems.push_back(sh); }
+  else c->systems[id] = sh;
+  const mqct_status st = upload_systems(c);
   if (st != MQCT_OK) return st;
   *system_id = id;
   return MQCT_OK;
@@ -550,8 +764,32 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     return fail(c, MQCT_ERR_ARG, "run: result mem must be host or device");
   if (bd->integrator != MQCT_RK4 && bd->integrator != MQCT_DP5)
     return fail(c, MQCT_ERR_ARG, "run: unknown integrator %d", bd->integrator);
-  if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_QUEUE)
+  if (bd->schedule < MQCT_SCHED_AUTO || bd->schedule > MQCT_SCHED_COLUMNS)
     return fail(c, MQCT_ERR_ARG, "run: unknown schedule %d", bd->schedule);
+  // coordinate-list systems run on the columns schedule, and only there
+  bool any_csr = false, all_csr = true;
+  for (int64_t b = 0; b < B; ++b) {
+    const int sid = bd->system_id[b];
+    const bool csr = sid >= 0 && sid < (int)c->systems.size() && c->systems[sid].live &&
+                     c->systems[sid].dev.csr_row != nullptr;
+    any_csr |= csr;
+    all_csr &= csr;
+  }
+  const bool columns = bd->schedule == MQCT_SCHED_COLUMNS ||
+                       (bd->schedule == MQCT_SCHED_AUTO && any_csr);
+  if (any_csr && !columns)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "run: coordinate-list systems run on the columns schedule only");
+  if (columns) {
+    if (!all_csr)
+      return fail(c, MQCT_ERR_UNSUPPORTED, "run: the columns schedule needs a coordinate-list system");
+    for (int64_t b = 1; b < B; ++b)
+      if (bd->system_id[b] != bd->system_id[0])
+        return fail(c, MQCT_ERR_UNSUPPORTED, "run: a columns batch must use a single system");
+    if (bd->integrator != MQCT_RK4 || bd->dynamics != MQCT_AT || bd->resume)
+      return fail(c, MQCT_ERR_UNSUPPORTED,
+                  "run: the columns schedule runs AT dynamics with RK4 (no resume)");
+    if (B > INT32_MAX) return fail(c, MQCT_ERR_UNSUPPORTED, "run: B too large for the columns schedule");
+  }
   const bool binned = bd->schedule == MQCT_SCHED_BINNED;
   if (binned) {
     for (int64_t b = 1; b < B; ++b)
@@ -740,7 +978,35 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
       T = (double)t.n_steps;
     return n * n * T;
   };
-  if (!queue) {
+  std::vector<ColGroup> col_groups;
+  int col_ct = 2;
+  if (columns) {
+    // columns that share a path (the same start state or E_coll, b, R0, and the
+    // same t0, dt, n_steps), in groups of at most COL_MAX
+    std::map<std::vector<uint64_t>, std::vector<int64_t>> paths;
+    for (int64_t b = 0; b < B; ++b) {
+      const TrajIn& t = c->h_traj[b];
+      std::vector<double> v = {t.t0, t.dt, (double)t.n_steps, (double)(t.flags & TRAJ_HAS_C0)};
+      if (t.flags & TRAJ_HAS_C0) v.insert(v.end(), t.c0, t.c0 + 6);
+      else v.insert(v.end(), {t.E_coll, t.b, t.R0});
+      std::vector<uint64_t> k(v.size());
+      memcpy(k.data(), v.data(), v.size() * 8);
+      paths[k].push_back(b);
+    }
+    int64_t stage_off = 0;
+    for (auto& kv : paths)
+      for (size_t i0 = 0; i0 < kv.second.size(); i0 += COL_MAX) {
+        ColGroup g{};
+        g.first = (int32_t)sorted.size();
+        g.count = (int32_t)std::min<size_t>(COL_MAX, kv.second.size() - i0);
+        g.n_steps = c->h_traj[kv.second[i0]].n_steps;
+        g.stage_off = stage_off;
+        stage_off += 4 * g.n_steps;
+        for (int q = 0; q < g.count; ++q) sorted.push_back(c->h_traj[kv.second[i0 + q]]);
+        col_ct = std::max(col_ct, (g.count + 1) & ~1);
+        col_groups.push_back(g);
+      }
+  } else if (!queue) {
     for (int d = 0; d < 4; ++d) {
       ranges[d].first = (int64_t)sorted.size();
       for (int64_t b : order[d]) sorted.push_back(c->h_traj[b]);
@@ -833,7 +1099,19 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
   out.state = (mqct_traj_state*)c->st_rec.p;
   out.st_amp = (double2*)c->st_amp.p;
 
-  if (binned && dp5) {
+  if (columns) {
+    const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
+    int64_t stages = 0;
+    for (const ColGroup& g : col_groups) stages = std::max(stages, g.stage_off + 4 * g.n_steps);
+    const size_t wsb = columns_workspace_bytes((int)col_groups.size(), hs.N, col_ct, stages,
+                                               dtype_fp32(hs.dtype));
+    if ((st = ensure(c, c->binws, wsb, "run: columns workspace")) != MQCT_OK) return st;
+    out.state = nullptr;    // the columns schedule keeps no stored states
+    out.st_amp = nullptr;
+    hipError_t e = run_columns(c->d_systems, hs, (const TrajIn*)c->traj.p, col_groups, col_ct,
+                               d_a0, out, c->binws.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "run: columns schedule");
+  } else if (binned && dp5) {
     const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
     if (B > INT32_MAX) return fail(c, MQCT_ERR_UNSUPPORTED, "run: B too large for the binned schedule");
     const DpCtl ctl{bd->rtol, bd->atol, bd->h_min, bd->max_steps};
@@ -939,8 +1217,9 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
       return fail(c, MQCT_ERR_UNSUPPORTED, "run: no workgroup shape for this N and storage type");
     if (e != hipSuccess) return hip_fail(c, e, "run: work-list schedule");
   }
-  // the store now describes this batch (records by batch index)
-  c->st_B = B;
+  // the store now describes this batch (records by batch index); a columns batch
+  // leaves it empty
+  c->st_B = columns ? 0 : B;
   c->st_sys.assign(bd->system_id, bd->system_id + B);
   c->st_off.assign(B + 1, 0);
   for (int64_t b = 0; b < B; ++b)
@@ -983,6 +1262,8 @@ mqct_status mqct_run_noalloc(mqct_context* c, const mqct_batch_desc* bd,
       return fail(c, MQCT_ERR_STATE, "run_noalloc: trajectory %lld uses unknown system %d",
                   (long long)b, sid);
     const DevSystem& sy = c->systems[sid].dev;
+    if (sy.csr_row)
+      return fail(c, MQCT_ERR_UNSUPPORTED, "run_noalloc: system %d is a coordinate-list system", sid);
     if (bd->n_steps[b] < 0 || !isfinite(bd->dt[b]) || (bd->t0 && !isfinite(bd->t0[b])))
       return fail(c, MQCT_ERR_ARG, "run_noalloc: bad n_steps, dt or t0 at %lld", (long long)b);
     if (!bd->a0 && (bd->init_channel[b] < 0 || bd->init_channel[b] >= sy.N))
@@ -1178,8 +1459,9 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
     return fail(c, MQCT_ERR_STATE, "set_params: unknown system %d", id);
   SysHost& sh = c->systems[id];
   const int N = sh.dev.N, K = sh.dev.K, Npad = sh.dev.Npad;
-  if (sh.dev.dtype != R64)
-    return fail(c, MQCT_ERR_UNSUPPORTED, "set_params: the parametric form needs R64 storage");
+  if (sh.dev.dtype != R64 || sh.dev.csr_row)
+    return fail(c, MQCT_ERR_UNSUPPORTED, "set_params: the parametric form needs dense or slot "
+                "R64 tables");
   if (P < 1 || P > 256 || nG < 1 || nG > 48 || !radial || !gidx || !G)
     return fail(c, MQCT_ERR_ARG, "set_params: need 1 <= P <= 256, 1 <= nG <= 48 and all arrays");
   for (int p = 0; p < P; ++p)

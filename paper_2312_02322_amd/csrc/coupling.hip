@@ -284,7 +284,9 @@ cpl_screen(CouplingDev d, const int2* __restrict__ work, int S, const double* __
   const int na = act ? d.grp_list[g0 + q] : nb;
   bool keep = false;
   if (act) {
-    const GPtr gp = gptr(d, nb, na);
+    // the element is symmetric, so the decision is taken from one ordering of the
+    // pair: (n, m) and (m, n) are kept or dropped together
+    const GPtr gp = gptr(d, min(nb, na), max(nb, na));
     double acc[CPL_MAX_SCREEN];
 #pragma unroll
     for (int u = 0; u < CPL_MAX_SCREEN; ++u) acc[u] = 0.0;

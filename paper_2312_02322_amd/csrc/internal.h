@@ -38,8 +38,10 @@ struct DevSystem {
   const int32_t* ell_col;    // sparse tables: [ell_w][Npad] stored row of each slot
   const double* drv;         // [K] driving potential U(R_k) of decoupled (AT) dynamics, or null
   const double* drv2;        // [K] its natural-spline second derivatives
-  int64_t knot_stride;       // N * Npad elements
+  int64_t knot_stride;       // N * Npad elements (CSR tables: the stored elements)
   double R_inv_h;            // 1 / spacing when the R grid is uniform, else 0
+  const int32_t* csr_row;    // coordinate-list systems: [N + 1] start of each row's elements
+  const int32_t* csr_col;    // [nnz] their columns, ascending within a row (null: other layouts)
 };
 
 // Per-trajectory launch record.
@@ -320,6 +322,30 @@ hipError_t launch_build_param_tables(const double* G, const double* rad, const i
                                      double* Mout, hipStream_t s);
 hipError_t launch_spline_rows(const double* y, const double* x, int K, int ncol, double* y2,
                               double* tmp, hipStream_t s);
+
+// ---- coordinate-list systems and the columns schedule (columns.hip) ----------
+
+// Columns that share a path: records first .. first + count - 1 (in group order).
+constexpr int COL_MAX = 128;
+struct ColGroup {
+  int32_t first, count;
+  int64_t n_steps;
+  int64_t stage_off;   // its stage records: 4 per RK4 step
+};
+hipError_t launch_coo_gather(const double* values, int64_t ld, const int32_t* perm, int64_t nnz,
+                             int K, int NC, double* v64, unsigned long long* nonfinite,
+                             hipStream_t s);
+hipError_t launch_csr_spline(const double* y, const double* x, int K, int64_t ncol, double* y2,
+                             hipStream_t s);
+hipError_t launch_csr_partner_check(const double* v64, const int32_t* partner, int64_t nnz, int K,
+                                    int NC, unsigned long long* maxdiff,
+                                    unsigned long long* maxabs, hipStream_t s);
+hipError_t launch_csr_cast_f32(const double* in, int64_t n, float* out, hipStream_t s);
+size_t columns_workspace_bytes(int G, int N, int CT, int64_t stages, bool fp32);
+// All groups on one system (hs); d_traj holds the records in group order.
+hipError_t run_columns(const DevSystem* d_systems, const DevSystem& hs, const TrajIn* d_traj,
+                       const std::vector<ColGroup>& groups, int CT, const double* d_a0,
+                       TrajOut out, void* wsp, hipStream_t s);
 
 // Streaming read of `bytes` (a multiple of 16) at buf (measure.hip).
 hipError_t launch_read_probe(const void* buf, int64_t bytes, int n_cu, hipStream_t s);
