@@ -110,6 +110,10 @@ def main():
     ap.add_argument("--uneven-layout", choices=["dense", "sparse"], default="sparse",
                     help="sparse: systems whose tables are mostly structural zeros keep only the "
                          "nonzeros (drop_below = 0, the same results)")
+    ap.add_argument("--paper-steps", type=int, default=0,
+                    help="paper_at workload: RK4 steps to time (0: the whole collision)")
+    ap.add_argument("--only-paper", choices=["R32", "R64"], default=None,
+                    help="paper_at workload: one storage type only")
     ap.add_argument("--probe-bw", action="store_true",
                     help="only measure streaming-read bandwidth at 2 GB, 200 MB and 8 MB footprints")
     args = ap.parse_args()
@@ -998,6 +1002,8 @@ def paper_at_workload(args, n_init=100, U_cm=300.0, b_bohr=2.0, R0_bohr=20.0, dt
     E = CP.U.cm_to_hartree(U_cm)
     init = np.argsort(basis.E, kind="stable")[:n_init].astype(np.int32)
     n_steps = int(np.ceil(S.collision_time(R0_bohr, E, mu) / dt))
+    if args.paper_steps > 0:
+        n_steps = min(n_steps, args.paper_steps)
     B = n_init
     kw = dict(init_channel=init, E_coll=np.full(B, E), b=np.full(B, b_bohr),
               R0=np.full(B, R0_bohr), dt=np.full(B, dt), schedule="columns", dynamics="at")
