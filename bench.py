@@ -689,6 +689,11 @@ def headline(args):
         # the adjoint
         line["adjoint"] = adjoint_timing(args.adjoint_traj, args.adjoint_steps,
                                          layout=args.adjoint_layout)
+        # AT dynamics at the paper's size: one path x 100 initial states on the
+        # screened 206,350-state matrices, FP32 tables, the whole collision
+        pa = paper_at_workload(argparse.Namespace(**dict(vars(args), only_paper="R32",
+                                                          paper_steps=0)))
+        variants["paper_at/R32/columns"] = dict(pa["variants"]["R32"], config=pa["config"])
     line["variants"] = variants
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_large(s, b)

@@ -1186,8 +1186,9 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
     }
     hipError_t side_err = hipSuccess;
     std::thread side_thread;
-    // started once the work list's autotuner has timed its candidates, so that
-    // the timing runs have the device to themselves
+    // started when the work list reaches its latency-bound tail (after its
+    // autotuner's timing runs), so the binned share has most of the device beside
+    // the tail instead of contending with the work list's bulk
     auto start_side = [&]() {
       if (side_groups.empty() || side_thread.joinable()) return;
       side_thread = std::thread([c, ctl, max_attempts, d_a0, out, &side_groups, &side_err]() {

@@ -282,14 +282,16 @@ struct QueueCache {
 size_t queue_workspace_bytes(const std::vector<QueueClass>& cls, int method);
 // Runs a batch on the work-list schedule.  `cap` is a non-default stream used
 // only to capture graphs; `h_counts` is pinned host memory for cls.size() ints.
-// `on_tuned` (may be empty) is called once the autotuner has timed its
-// candidates, before the first step launch: work on other streams that would
-// share the device with the timing runs starts there.
+// `on_tail` (may be empty) is called once, when the work lists hold at most
+// twice as many trajectories as the device has compute units (their
+// latency-bound tail), or when they are done: work on another stream started
+// there has most of the device beside the tail, and never shares it with the
+// autotuner's timing runs.
 hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
                      const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
                      int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
                      QueueCache& cache, void* ws, hipStream_t s, hipStream_t cap, int* h_counts,
-                     Prof* prof, const std::function<void()>& on_tuned = {});
+                     Prof* prof, const std::function<void()>& on_tail = {});
 
 // R-binned lockstep RK4 (all trajectories on one system, d_traj in any order).
 size_t binned_workspace_bytes(int B, int Npad, int K, bool fp32);

@@ -203,7 +203,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
                      const std::vector<QueueClass>& cls, const double* d_a0, TrajOut out,
                      int method, DpCtl ctl, int64_t max_attempts, const QueueOpts& opt,
                      QueueCache& cache, void* wsp, hipStream_t s, hipStream_t cap, int* h_counts,
-                     Prof* prof, const std::function<void()>& on_tuned) {
+                     Prof* prof, const std::function<void()>& on_tail) {
   hipError_t e;
   char* p = (char*)wsp;
   int32_t* d_counts = (int32_t*)p;
@@ -355,7 +355,6 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
   for (size_t k = 0; k < runs.size(); ++k)
     if (init_shape[k] != runs[k].shape)
       if ((e = init_class(runs[k])) != hipSuccess) return e;
-  if (on_tuned) on_tuned();
 
   // step chunks until every work list is empty
   const int chunk = std::max(1, opt.chunk);
@@ -381,6 +380,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
       return e;
   }
   e = hipSuccess;
+  bool tail_called = false;
   int64_t round = 0;
   for (; round < max_rounds; ++round) {
     bool any = false;
@@ -425,9 +425,18 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     if ((e = hipMemcpyAsync(h_counts, d_counts, runs.size() * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
       break;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
-    for (size_t k = 0; k < runs.size(); ++k) runs[k].count = h_counts[k];
+    int64_t active = 0;
+    for (size_t k = 0; k < runs.size(); ++k) {
+      runs[k].count = h_counts[k];
+      active += std::max(runs[k].count, 0);
+    }
+    if (on_tail && !tail_called && active <= 2 * (int64_t)cus) {
+      on_tail();
+      tail_called = true;
+    }
   }
   for (ClassRun& r : runs) drop_graph(r);
+  if (on_tail && !tail_called && e == hipSuccess) on_tail();
   if (e != hipSuccess) return e;
   for (const ClassRun& r : runs)
     if (r.count > 0) return hipErrorLaunchTimeOut;   // attempt bound exceeded (cannot happen)
