@@ -34,10 +34,13 @@ MFMA_PEAK_TFLOPS = {"C64": 157.3, "C128": 78.6}   # dense FP32 / FP64 matrix pea
 # WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (profiles/).
 # Valid only for the kernel source file and workload they were taken on.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE (x 1.99992, the copy calibration) + WRITE_SIZE of bin_gemm<C64>,
-    # mean of the 41 launches of one bench step, taken on this source revision
-    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "51379955866012cd",
+    # FETCH_SIZE (x 1.99992, the copy calibration) + WRITE_SIZE of bin_gemm<C64> per
+    # launch, taken on this source revision: the N=969 window (mean of the 41 launches
+    # of one bench step) and the N=4096 collision (mean of all 40,020 launches)
+    ("C64", "binned"): {"source": "binned.hip", "source_sha256_16": "36178d36d14d6324",
                         "bytes": 2.928e9, "window": 10, "trajectories": 4096},
+    ("C64", "large"): {"source": "binned.hip", "source_sha256_16": "36178d36d14d6324",
+                       "bytes": 1.9866e10, "trajectories": 512},
 }
 
 
@@ -93,6 +96,9 @@ def main():
                          "or both (with the largest difference of their final probabilities)")
     ap.add_argument("--large-windows", type=int, default=0,
                     help="run only the first windows of the collision (0: all)")
+    ap.add_argument("--scatter-rmin", type=float, default=4.0,
+                    help="large scatter population: smallest start radius (A); the start radii "
+                         "are uniform up to 19.5 A")
     ap.add_argument("--large-scatter", type=int, default=0,
                     help="large workload: instead of the collision, time --steps windows of this "
                          "many RK4 steps of a scattered mid-collision population (R0 uniform in "
@@ -614,7 +620,7 @@ def headline(args):
                 "unit": "TFLOP/s", "frac": tf / MFMA_PEAK_TFLOPS["C64"]}
         other = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                  "frac": gbps / HBM_PEAK_GBPS}
-    roof.update({"kernel": "bin_gemm (wide + narrow launches of a stage)", "traffic": None,
+    roof.update({"kernel": "bin_gemm", "traffic": None,
                  "alg_bytes_per_launch": kb / kn, "alg_flops_per_launch": flops / kn,
                  "launch_ms": kms / kn, "launches_timed": kn,
                  "mixed_frac": roof_ms / kms, "other_roof": other})
@@ -755,7 +761,7 @@ def large_scatter(args):
     t0 = time.time()
     (s,), b = S.config5(n_traj=B, n_steps=10000, N=N, build_tables=False)
     rng = np.random.default_rng(231202322 + 55)
-    R0 = U.ang_to_bohr(rng.uniform(4.0, 19.5, B))
+    R0 = U.ang_to_bohr(rng.uniform(args.scatter_rmin, 19.5, B))
     bb = np.minimum(b.b, 0.9 * R0)
     ctx = mq.Context(0)
     dev = ctx.device

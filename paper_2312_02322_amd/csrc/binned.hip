@@ -277,7 +277,11 @@ __global__ void bin_scatter(BinWS ws) {
   ws.list[ws.offset[k + 1] + p1] = 2 * b + 1;
 }
 
-constexpr int GEMM_PF32 = 2;   // K steps of operands in flight, FP32 tables (deeper rings measured slower)
+// K steps of operands in flight, FP32 tables
+#ifndef BIN_GEMM_PF32
+#define BIN_GEMM_PF32 2
+#endif
+constexpr int GEMM_PF32 = BIN_GEMM_PF32;
 // ring periods per loop iteration: the compiler's waits for the loads are exact
 // inside an iteration and conservative only across the loop's back edge
 constexpr int GEMM_UF = 1;

@@ -296,3 +296,43 @@ def test_columns_paper_size_properties(ctx):
     assert lin < 1e-12
     assert np.max(np.abs(g["norm_err"])) < 1e-12
     assert np.all(g["classical"] == g["classical"][0]) and np.all(g["status"] == 0)
+
+
+def test_columns_ragged_steps_start_states_and_t0(ctx):
+    """Groups of different lengths in one call (0, 3 and 10 RK4 steps: a group that
+    stops early keeps its amplitudes while the others go on), and a path given by
+    its start state (classical0) at t0 != 0 (the phases e^{-iE t} start there),
+    against the oracle; every column of a path on the same path bit for bit."""
+    (s,), _ = S.config1(n_traj=1, n_steps=1, jmax=3)               # N = 16, real
+    rows, cols, vals, keep = coo_of(s.M, seed=9)
+    Udrv = driver_of(s.M)
+    sid = ctx.load_system_coo(R_grid=s.R_grid, E=s.E, rows=rows, cols=cols, values=vals, mu=s.mu,
+                              jx=(s.jx_row, s.jx_col, s.jx_val))
+    ctx.set_driver(sid, Udrv)
+    rng = np.random.default_rng(47)
+    b = paths_batch(s, [2, 3, 2], rng, 10, 25.0, [500.0, 500.0, 800.0], 2.0,
+                    [s.R_grid[60], s.R_grid[60], s.R_grid[70]])
+    b.n_steps[:] = [0, 0, 3, 3, 3, 10, 10]
+    g = run_columns(ctx, sid, s.N, b)
+    o = oracle.OracleSystem(s, driver=Udrv).propagate(b)
+    d = np.max(np.abs(g["P"] - o["P"]))
+    say("ragged columns N=%d: steps %s, max|dP| %.3e" % (s.N, g["steps"].tolist(), d))
+    assert d < 1e-12 and np.array_equal(g["steps"], b.n_steps)
+    assert np.all(g["P"][[0, 1], b.init_channel[[0, 1]]] == 1.0)
+    assert np.max(np.abs(g["t_final"] - o["t_final"])) == 0.0
+    # a start state and t0
+    c0 = np.array([[14.0, 0.5 * np.pi, 0.3, -2.0, 0.0, 9.0]] * 3)
+    t0 = np.full(3, 123.5)
+    ic = np.array([1, 4, 7], np.int32)
+    g = ctx.run_host([sid] * 3, [s.N] * 3, schedule="columns", dynamics="at", init_channel=ic,
+                     classical0=c0.reshape(-1), t0=t0, dt=np.full(3, 20.0),
+                     n_steps=np.full(3, 60))
+    o = oracle.OracleSystem(s, driver=Udrv).propagate(init_channel=ic, classical0=c0, t0=t0,
+                                                      dt=np.full(3, 20.0), n_steps=np.full(3, 60))
+    d = np.max(np.abs(g["P"].reshape(3, s.N) - o["P"]))
+    dc = np.max(np.abs(g["classical"] - o["classical"]) / (1 + np.abs(o["classical"])))
+    say("  classical0 at t0 = 123.5: max|dP| %.3e, classical %.3e" % (d, dc))
+    assert d < 1e-12 and dc < 1e-12
+    assert np.all(g["classical"] == g["classical"][0])
+    assert np.max(np.abs(g["t_final"] - o["t_final"])) < 1e-12 * np.max(o["t_final"])
+    ctx.free_system(sid)
