@@ -1101,16 +1101,45 @@ mqct_status mqct_run(mqct_context* c, const mqct_batch_desc* bd, mqct_batch_resu
 
   if (columns) {
     const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
-    int64_t stages = 0;
-    for (const ColGroup& g : col_groups) stages = std::max(stages, g.stage_off + 4 * g.n_steps);
-    const size_t wsb = columns_workspace_bytes((int)col_groups.size(), hs.N, col_ct, stages,
-                                               dtype_fp32(hs.dtype));
+    const bool f32 = dtype_fp32(hs.dtype);
+    // The amplitude columns take 80 or 96 bytes per state and column: a batch
+    // whose groups do not fit the cap runs in passes of whole groups (stage
+    // records rebased per pass), one after the other in the same workspace.
+    size_t cap = (size_t)c->qopt.col_ws;
+    if (cap == 0) {
+      size_t fr = 0, tot = 0;
+      HIP_TRY(c, hipMemGetInfo(&fr, &tot), "run: columns memory query");
+      cap = (size_t)(0.8 * (double)(fr + c->binws.cap));
+    }
+    std::vector<std::vector<ColGroup>> passes;
+    size_t wsb = 0;
+    for (size_t i = 0; i < col_groups.size();) {
+      std::vector<ColGroup> pg;
+      int64_t off = 0;
+      size_t bytes = 0;
+      for (; i < col_groups.size(); ++i) {
+        ColGroup g = col_groups[i];
+        g.stage_off = off;
+        const size_t nb = columns_workspace_bytes((int)pg.size() + 1, hs.N, col_ct, off + 4 * g.n_steps, f32);
+        if (nb > cap && !pg.empty()) break;
+        if (nb > cap)
+          return fail(c, MQCT_ERR_OOM, "run: one path group needs %zu bytes of columns workspace, cap %zu",
+                      nb, cap);
+        pg.push_back(g);
+        off += 4 * g.n_steps;
+        bytes = nb;
+      }
+      wsb = std::max(wsb, bytes);
+      passes.push_back(std::move(pg));
+    }
     if ((st = ensure(c, c->binws, wsb, "run: columns workspace")) != MQCT_OK) return st;
     out.state = nullptr;    // the columns schedule keeps no stored states
     out.st_amp = nullptr;
-    hipError_t e = run_columns(c->d_systems, hs, (const TrajIn*)c->traj.p, col_groups, col_ct,
-                               d_a0, out, c->binws.p, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "run: columns schedule");
+    for (const std::vector<ColGroup>& pg : passes) {
+      hipError_t e = run_columns(c->d_systems, hs, (const TrajIn*)c->traj.p, pg, col_ct, d_a0, out,
+                                 c->binws.p, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "run: columns schedule");
+    }
   } else if (binned && dp5) {
     const DevSystem& hs = c->systems[c->h_traj[0].sys].dev;
     if (B > INT32_MAX) return fail(c, MQCT_ERR_UNSUPPORTED, "run: B too large for the binned schedule");
@@ -1702,6 +1731,10 @@ mqct_status mqct_set_option(mqct_context* c, int32_t option, int64_t value) {
     case MQCT_OPT_TAIL:
       if (value < 0 || value > 2) return fail(c, MQCT_ERR_ARG, "set_option: tail must be 0, 1 or 2");
       c->qopt.tail = (int)value;
+      return MQCT_OK;
+    case MQCT_OPT_COL_WORKSPACE:
+      if (value < 0) return fail(c, MQCT_ERR_ARG, "set_option: columns workspace cap must be >= 0");
+      c->qopt.col_ws = value;
       return MQCT_OK;
   }
   return fail(c, MQCT_ERR_ARG, "set_option: unknown option %d", option);

@@ -265,6 +265,7 @@ struct QueueOpts {
   int tail = 1;        // 1: switch to the tuned split-row shape once few trajectories remain;
                        // 0: never; 2: run every class on a split-row shape (tests)
   int chunk = 16;      // step launches per replay
+  int64_t col_ws = 0;  // columns schedule: workspace cap in bytes (0: 80 % of free memory)
 };
 
 // Autotuner decisions, kept for the life of a context.

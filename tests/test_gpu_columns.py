@@ -336,3 +336,34 @@ def test_columns_ragged_steps_start_states_and_t0(ctx):
     assert np.all(g["classical"] == g["classical"][0])
     assert np.max(np.abs(g["t_final"] - o["t_final"])) < 1e-12 * np.max(o["t_final"])
     ctx.free_system(sid)
+
+
+def test_columns_workspace_cap_runs_in_passes(ctx, gpu_lib, rotor_rotor):
+    """A workspace cap below the whole batch's need: the path groups (5, 1, 128 and
+    2 columns, 4 x 300 RK4 steps, N = 256) run in passes of one or two groups, with
+    the results of the single pass bit for bit; a cap below one group's need is an
+    allocation error, and the library stays usable."""
+    s, b = rotor_rotor
+    rows, cols, vals, keep = coo_of(s.M)
+    sid = ctx.load_system_coo(R_grid=s.R_grid, E=s.E, rows=rows, cols=cols, values=vals, mu=s.mu,
+                              jx=(s.jx_row, s.jx_col, s.jx_val), storage="R32")
+    ctx.set_driver(sid, driver_of(s.M))
+    one_group = s.N * 128 * 80                  # columns of one group, FP32 tables
+    try:
+        ref = run_columns(ctx, sid, s.N, b)
+        for cap in (int(1.2 * one_group), int(2.2 * one_group)):
+            ctx.set_option("col_workspace", cap)
+            g = run_columns(ctx, sid, s.N, b)
+            say("columns workspace cap %.1f MB: max|dP| against one pass %.1e" % (
+                cap / 1e6, np.max(np.abs(g["P"] - ref["P"]))))
+            for k in ("P", "classical", "norm_err", "energy_err", "status", "steps", "t_final"):
+                assert np.array_equal(g[k], ref[k]), k
+        ctx.set_option("col_workspace", one_group // 2)
+        with pytest.raises(gpu_lib.MQCTError) as ei:
+            run_columns(ctx, sid, s.N, b)
+        assert ei.value.code == -4 and "columns workspace" in str(ei.value)
+    finally:
+        ctx.set_option("col_workspace", 0)
+    g = run_columns(ctx, sid, s.N, b)
+    assert np.array_equal(g["P"], ref["P"])
+    ctx.free_system(sid)
