@@ -1350,14 +1350,17 @@ def uneven_cpu_baseline(systems, b, per_system=8, max_steps=2000):
                       "%d steps each); wall time of the propagation only" % (per_system, max_steps)}
 
 
-def adjoint_timing(n_traj, n_steps, checkpoint_every=256, layout="sparse"):
+def adjoint_timing(n_traj, n_steps, checkpoint_every=None, layout="sparse"):
     """Seconds per full 96-coefficient gradient of a b-weighted inelastic cross section.
 
     Two linear rotors, j1, j2 <= 3 (N = 256), potential linear in 96 coefficients,
     n_traj trajectories of n_steps RK4 steps; L = sum_i (2 pi b_max / B) b_i
-    sum_{n outside the initial level} P_i(n); discrete adjoint with checkpoints
-    every 256 steps.  layout="sparse" stores only the structural nonzeros of the
-    tables (drop_below = 0: the gradient of the same model).
+    sum_{n outside the initial level} P_i(n); discrete adjoint.  checkpoint_every
+    None: one segment (every stage state stored by the forward pass, nothing
+    recomputed; 67 MB per trajectory at 4096 steps); the same gradient with
+    checkpoints every 256 steps is timed beside it.  layout="sparse" stores only
+    the structural nonzeros of the tables (drop_below = 0: the gradient of the
+    same model).
     """
     import numpy as np
     import torch
@@ -1381,6 +1384,8 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256, layout="sparse"):
         ctx.run([sid] * b.B, [s.N] * b.B, schedule="gemv", **kw)
         torch.cuda.synchronize()
         fwd.append(time.time() - t0)
+    if checkpoint_every is None:
+        checkpoint_every = int(np.max(b.n_steps))
     sec_all = []
     for _ in range(2):
         torch.cuda.synchronize()
@@ -1388,17 +1393,24 @@ def adjoint_timing(n_traj, n_steps, checkpoint_every=256, layout="sparse"):
         grad, P = ctx.adjoint(sid, s.N, w, checkpoint_every=checkpoint_every, **kw)
         sec_all.append(time.time() - t0)
     sec, fsec = sec_all[-1], fwd[-1]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    g256, _ = ctx.adjoint(sid, s.N, w, checkpoint_every=256, **kw)
+    sec256 = time.time() - t0
+    same = bool(np.array_equal(g256, grad))
     table_bytes = ctx.system_bytes(sid)
     ctx.close()
     log("adjoint (%s tables): %d trajectories x %d steps, N=%d, %d coefficients: %.2f s/grad "
-        "(first call %.2f s), forward alone %.2f s (ratio %.1f), |grad| = %.3e" % (
-            layout, b.B, n_steps, s.N, grad.shape[0], sec, sec_all[0], fsec, sec / fsec,
-            float(np.linalg.norm(grad))))
+        "(first call %.2f s; checkpoints every 256 steps %.2f s, same gradient: %s), forward "
+        "alone %.2f s (ratio %.1f), |grad| = %.3e" % (
+            layout, b.B, n_steps, s.N, grad.shape[0], sec, sec_all[0], sec256, same, fsec,
+            sec / fsec, float(np.linalg.norm(grad))))
     return {"s_per_grad": sec, "unit": "s", "first_call_s": sec_all[0], "forward_s": fsec,
             "adjoint_over_forward": sec / fsec, "layout": layout, "table_bytes": table_bytes,
             "trajectories": b.B,
             "rk4_steps": n_steps, "N": s.N,
             "n_coefficients": int(grad.shape[0]), "checkpoint_every": checkpoint_every,
+            "s_per_grad_checkpoint_256": sec256, "same_gradient_checkpoint_256": same,
             "L": float(np.sum(w * P)), "grad_norm": float(np.linalg.norm(grad))}
 
 

@@ -29,7 +29,8 @@
 // kbar2 = h/3 lambda + h/2 ybar3, kbar1 = h/6 lambda + h/2 ybar2 with
 // ybar_s = VJP at stage state Y_s, and lambda <- lambda + sum_s ybar_s.  Step
 // states come from checkpoints every S steps, recomputed segment by segment by
-// the same forward code, so they are bitwise the forward states.
+// the same forward code, so they are bitwise the forward states; the forward
+// pass stores the last segment's stage states itself.
 #include "device.h"
 
 #include <math.h>
@@ -411,10 +412,14 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
     y.y[2] = -sqrt(2.0 * sy.mu * tj.E_coll - pphi * pphi / (tj.R0 * tj.R0));
     y.y[3] = pphi;
   }
-  // forward pass with checkpoints
+  // forward pass with checkpoints; the last segment's stage states are stored as
+  // they are made, so the backward sweep starts without recomputing it (with one
+  // segment, S >= n_steps, nothing is recomputed)
+  const int64_t jlast = (nseg - 1) * S;
   for (int64_t j = 0; j < n; ++j) {
     if (j % S == 0) K::save(ck + (j / S) * SV, y, N, Npad);
-    K::rk4(sy, t0 + (double)j * h, h, y, lc, red, nullptr, SV);
+    K::rk4(sy, t0 + (double)j * h, h, y, lc, red, j >= jlast ? seg + 4 * (j - jlast) * SV : nullptr,
+           SV);
   }
   // final probabilities and the starting adjoint lambda_a = 2 a dL/dP
   St lam;
@@ -434,9 +439,11 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t j0 = sg * S, j1 = (j0 + S < n) ? j0 + S : n;
     __syncthreads();                     // stage states of the previous segment are consumed
-    K::load(ck + sg * SV, y, N, Npad);
-    for (int64_t j = j0; j < j1; ++j)
-      K::rk4(sy, t0 + (double)j * h, h, y, lc, red, seg + 4 * (j - j0) * SV, SV);
+    if (sg < nseg - 1) {                 // the last segment's states are there already
+      K::load(ck + sg * SV, y, N, Npad);
+      for (int64_t j = j0; j < j1; ++j)
+        K::rk4(sy, t0 + (double)j * h, h, y, lc, red, seg + 4 * (j - j0) * SV, SV);
+    }
     __syncthreads();                     // publishes the stored classical coordinates
     for (int64_t j = j1 - 1; j >= j0; --j) {
       const double t = t0 + (double)j * h;

@@ -1666,7 +1666,8 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
     amp += sy.N;
     tr[b] = t;
   }
-  const int S = checkpoint_every;
+  // an interval beyond the longest trajectory is one segment: no larger workspace
+  const int S = (int)std::min<int64_t>(checkpoint_every, std::max<int64_t>(maxn, 1));
   const int64_t stride = adjoint_scratch_doubles(sy.Npad, maxn, S);
   size_t off = 0;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };

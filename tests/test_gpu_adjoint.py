@@ -94,11 +94,13 @@ def test_adjoint_matches_oracle_forward_mode(setup):
 
 def test_checkpoint_interval_does_not_change_the_gradient(setup):
     ctx, sid, s, b, w = setup
-    say("checkpoint intervals 1, 7, 300")
+    say("checkpoint intervals 1, 7, 300, 2^31-1")
     g1, _ = adjoint(ctx, sid, s, b, w, S_=1)
     g7, _ = adjoint(ctx, sid, s, b, w, S_=7)
     g300, _ = adjoint(ctx, sid, s, b, w, S_=300)
-    assert np.array_equal(g1, g7) and np.array_equal(g1, g300)
+    # one segment: every stage state stored by the forward pass, nothing recomputed
+    gall, _ = adjoint(ctx, sid, s, b, w, S_=2 ** 31 - 1)
+    assert np.array_equal(g1, g7) and np.array_equal(g1, g300) and np.array_equal(g1, gall)
 
 
 def test_autograd_function(setup):
