@@ -401,10 +401,7 @@ __device__ __forceinline__ void gemm_item(const BinWS& ws, const DevSystem& sy, 
   };
   // K steps past the last one reload that step's operands (unused) rather than branch
 #pragma unroll
-  for (int j = 0; j < PF - 1; ++j) {
-    load(min(16 * j, KE - 16), a[j], bv[j]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  for (int j = 0; j < PF - 1; ++j) load(min(16 * j, KE - 16), a[j], bv[j]);
   for (int k0 = 0; k0 < KE; k0 += 16 * PF * GEMM_UF) {
 #pragma unroll
     for (int j = 0; j < PF * GEMM_UF; ++j) {
