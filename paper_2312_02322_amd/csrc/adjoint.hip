@@ -35,6 +35,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 namespace mqct {
 
 namespace {
@@ -62,7 +65,14 @@ struct AdjArgs {
   const int* order;        // [B] trajectories in the order they are dealt to the dies
   int64_t B;
   int per_die;             // workgroups per die (blocks x, x + 8, ... of die x)
+  // angular terms of each wave for the bilinear forms: tord[tbeg[w] .. tbeg[w+1]-1],
+  // balanced by their nonzero counts
+  int tord[NGMAX];
+  int tbeg[ANW + 1];
 };
+
+constexpr int GU = 4;      // nonzeros of G_t per lane whose loads are issued together
+constexpr int JXB = 4;     // J_x widths up to this have their loads issued together
 
 constexpr int ADIES = 8;   // accelerator dies of the device, each with its own L2
 
@@ -122,12 +132,30 @@ struct Adj {
     }
   }
 
-  // J x for this lane's rows from an LDS vector
+  // J x for this lane's rows from an LDS vector (the row's entries are all
+  // requested before the first gather; the sum runs in entry order either way)
   __device__ static double2 jx(const DevSystem& sy, int n, const double2* v) {
     double2 s = make_double2(0.0, 0.0);
-    for (int q = 0; q < sy.jx_w; ++q) {
-      const int col = sy.jx_col[(int64_t)n * sy.jx_w + q];
-      const double jv = sy.jx_val[(int64_t)n * sy.jx_w + q];
+    const int W = sy.jx_w;
+    if (W <= JXB) {
+      int col[JXB];
+      double jv[JXB];
+#pragma unroll
+      for (int q = 0; q < JXB; ++q) {
+        col[q] = q < W ? sy.jx_col[(int64_t)n * W + q] : 0;
+        jv[q] = q < W ? sy.jx_val[(int64_t)n * W + q] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < JXB; ++q) {
+        if (q >= W) break;
+        s.x = fma(jv[q], v[col[q]].x, s.x);
+        s.y = fma(jv[q], v[col[q]].y, s.y);
+      }
+      return s;
+    }
+    for (int q = 0; q < W; ++q) {
+      const int col = sy.jx_col[(int64_t)n * W + q];
+      const double jv = sy.jx_val[(int64_t)n * W + q];
       s.x = fma(jv, v[col].x, s.x);
       s.y = fma(jv, v[col].y, s.y);
     }
@@ -175,9 +203,9 @@ struct Adj {
       const double2 x = jx(sy, n, lc);
       sums[0] += c.x * v.x + c.y * v.y;          // Re(c^H M' c)
       sums[1] += x.x * u.y - x.y * u.x;          // Im((Jc)^H M c)
+      const double2 g = make_double2(u.x + om * x.x, u.y + om * x.y);
       double sn, cs;
       sincos(sy.E[n] * t, &sn, &cs);
-      const double2 g = make_double2(u.x + om * x.x, u.y + om * x.y);
       const double2 y = mc(make_double2(cs, sn), g);
       F.a[r] = make_double2(y.y, -y.x);          // -i e^{iEt} (u + omega J c)
     }
@@ -206,14 +234,16 @@ struct Adj {
     const double gR = Gc.y[0], gPhi = Gc.y[1], gPR = Gc.y[2], gPPhi = Gc.y[3];
     // the previous product still reads lg, lmc and tq after its last barrier
     __syncthreads();
+    double psn[NR], pcs[NR];   // this lane's phase factors, for c, g~ and the result
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int n = row(r);
+      psn[r] = 0.0;
+      pcs[r] = 1.0;
       if (n < N) {
-        double sn, cs;
-        sincos(sy.E[n] * t, &sn, &cs);
-        lc[n] = mc(make_double2(cs, -sn), Y.a[r]);
-        lg[n] = mc(make_double2(cs, -sn), Gc.a[r]);
+        sincos(sy.E[n] * t, &psn[r], &pcs[r]);
+        lc[n] = mc(make_double2(pcs[r], -psn[r]), Y.a[r]);
+        lg[n] = mc(make_double2(pcs[r], -psn[r]), Gc.a[r]);
       }
     }
     __syncthreads();
@@ -223,21 +253,36 @@ struct Adj {
       if (n < N) ljc[n] = jx(sy, n, lc);
     }
     __syncthreads();
-    // bilinear forms of the sparse G_t, one wave per angular term:
+    // bilinear forms of the sparse G_t, one wave per angular term (the terms dealt
+    // to the waves by their nonzero counts); each lane sums its nonzeros e, e + 64,
+    // ... in order, GU of them requested at a time:
     // tq[3t] = Im(g~^H G_t c), tq[3t+1] = Im((Jc)^H G_t c), tq[3t+2] = Re(c^H G_t c)
     {
       const int lane = threadIdx.x & 63;
-      for (int tt = threadIdx.x >> 6; tt < A.nG; tt += ANW) {
+      const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      for (int i = A.tbeg[wv]; i < A.tbeg[wv + 1]; ++i) {
+        const int tt = A.tord[i];
         double f[3] = {0.0, 0.0, 0.0};
         const int e1 = A.goff[tt + 1];
-        for (int e = A.goff[tt] + lane; e < e1; e += 64) {
-          const uint32_t nm = A.gent[e];
-          const int n = nm & 0xffff, m = nm >> 16;
-          const double v = A.gval[e];
-          const double2 cm = lc[m], cn = lc[n], gn = lg[n], jn = ljc[n];
-          f[0] = fma(v, gn.x * cm.y - gn.y * cm.x, f[0]);
-          f[1] = fma(v, jn.x * cm.y - jn.y * cm.x, f[1]);
-          f[2] = fma(v, cn.x * cm.x + cn.y * cm.y, f[2]);
+        for (int e0 = A.goff[tt] + lane; e0 < e1; e0 += 64 * GU) {
+          uint32_t nm[GU];
+          double gv[GU];
+#pragma unroll
+          for (int u = 0; u < GU; ++u) {
+            const int e = e0 + 64 * u;
+            nm[u] = e < e1 ? A.gent[e] : 0u;
+            gv[u] = e < e1 ? A.gval[e] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < GU; ++u) {
+            if (e0 + 64 * u >= e1) break;
+            const int n = nm[u] & 0xffff, m = nm[u] >> 16;
+            const double v = gv[u];
+            const double2 cm = lc[m], cn = lc[n], gn = lg[n], jn = ljc[n];
+            f[0] = fma(v, gn.x * cm.y - gn.y * cm.x, f[0]);
+            f[1] = fma(v, jn.x * cm.y - jn.y * cm.x, f[1]);
+            f[2] = fma(v, cn.x * cm.x + cn.y * cm.y, f[2]);
+          }
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -289,9 +334,7 @@ struct Adj {
       double2 s;
       s.x = -(Mg[r].y + om * jg.y) - 2.0 * gPR * Mpc[r].x + 2.0 * gPPhi * (jmc.y - MJc[r].y);
       s.y = (Mg[r].x + om * jg.x) - 2.0 * gPR * Mpc[r].y - 2.0 * gPPhi * (jmc.x - MJc[r].x);
-      double sn, cs;
-      sincos(sy.E[n] * t, &sn, &cs);
-      Yb.a[r] = mc(make_double2(cs, sn), s);
+      Yb.a[r] = mc(make_double2(pcs[r], psn[r]), s);
     }
     const double R3 = R * R * R;
     const double omR = -2.0 * om / R;
@@ -547,13 +590,35 @@ hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int N
                           const TrajIn* d_traj, const int* order,
                           int64_t B, const double* dLdP, double* grad_part, double* grad_out,
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
-                          const int* goff, const uint32_t* gent, const double* gval,
-                          const double* rad, const double* rad2, const int* gidx, int P, int nG,
-                          hipStream_t s) {
+                          const int* goff, const int* h_goff, const uint32_t* gent,
+                          const double* gval, const double* rad, const double* rad2,
+                          const int* gidx, int P, int nG, hipStream_t s) {
   if (nG > NGMAX || P > AB) return hipErrorInvalidValue;
   const int per = (int)((B + ADIES - 1) / ADIES);
   AdjArgs A{d_traj, dLdP, grad_part, P_out, scratch, scratch_stride, S, goff, gent, gval,
-            rad, rad2, P, nG, gidx, order, B, per};
+            rad, rad2, P, nG, gidx, order, B, per, {}, {}};
+  // angular terms to waves, largest first, each to the wave with the fewest
+  // nonzeros so far (the wave with the most sets the time of the forms)
+  std::vector<int> byn(nG), of(nG);
+  for (int t = 0; t < nG; ++t) byn[t] = t;
+  std::stable_sort(byn.begin(), byn.end(), [&](int x, int y) {
+    return h_goff[x + 1] - h_goff[x] > h_goff[y + 1] - h_goff[y];
+  });
+  int64_t load[ANW] = {};
+  for (int t : byn) {
+    int w = 0;
+    for (int v = 1; v < ANW; ++v)
+      if (load[v] < load[w]) w = v;
+    of[t] = w;
+    load[w] += h_goff[t + 1] - h_goff[t];
+  }
+  int pos = 0;
+  for (int w = 0; w < ANW; ++w) {
+    A.tbeg[w] = pos;
+    for (int t = 0; t < nG; ++t)
+      if (of[t] == w) A.tord[pos++] = t;
+  }
+  A.tbeg[ANW] = pos;
   const unsigned grid = (unsigned)per * ADIES;
   // four double2 vectors, then red [ANW][NSC] and tq [3 NGMAX]
   const size_t lds = (size_t)Npad * 64 + (size_t)ANW * NSC * 8 + (size_t)3 * NGMAX * 8;

@@ -34,6 +34,7 @@ struct SysHost {
   int P = 0, nG = 0;
   // G (dense), rad, rad2, gidx, then the nonzeros of G: offsets, row | col << 16, values
   void* pbufs[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> h_goff;   // the offsets of the G nonzero lists, on the host
   void* dbuf = nullptr;   // driving potential of AT dynamics and its curvature: [2][K]
   void* ebuf[2] = {nullptr, nullptr};   // sparse tables: slot lists [W][Npad], kept per column [N]
   double R_last = 0.0;    // last knot (the default start radius), kept on the host
@@ -1569,6 +1570,7 @@ mqct_status mqct_system_set_params(mqct_context* c, int32_t id, int32_t P, const
   hipFree(tmp);
   sh.P = P;
   sh.nG = nG;
+  sh.h_goff = goff;
   return MQCT_OK;
 }
 
@@ -1705,7 +1707,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
                             (const double*)(base + o_w),
                             (double*)(base + o_part), (double*)(base + o_g),
                             (double*)(base + o_P), (double*)(base + o_s), stride, S,
-                            (const int*)sh.pbufs[4], (const uint32_t*)sh.pbufs[5],
+                            (const int*)sh.pbufs[4], sh.h_goff.data(), (const uint32_t*)sh.pbufs[5],
                             (const double*)sh.pbufs[6], (const double*)sh.pbufs[1],
                             (const double*)sh.pbufs[2], (const int*)sh.pbufs[3], sh.P, sh.nG,
                             c->stream), "adjoint: launch");
