@@ -423,11 +423,12 @@ mqct_status mqct_system_set_theta(mqct_context* ctx, int32_t system_id, const do
  * `checkpoint_every` steps and the four stage states of every step of the last
  * segment, then the segments are swept backward, each earlier one recomputed
  * from its checkpoint first (storing its stage states).  Device workspace:
- * (ceil(n_steps / checkpoint_every) + 4 checkpoint_every) x (2 Npad + 4)
+ * (ceil(n_steps / checkpoint_every) + 4 checkpoint_every + 1) x (2 Npad + 4)
  * doubles per trajectory.  checkpoint_every >= n_steps stores every stage state
  * in the forward pass and recomputes nothing: 8 table passes per step instead of
  * 12, for 4 n_steps (2 Npad + 4) doubles per trajectory (67 MB at N = 256 and
- * 4096 steps).  The gradient is the same bit for bit for every interval.  One
+ * 4096 steps); the forward and the backward pass then run as two launches.  The
+ * gradient is the same bit for bit for every interval.  One
  * system per batch (with a parametric form), trajectories started from
  * init_channel / E_coll / b / R0 (a0, classical0, t0 must be NULL).  dL_dP [sum N_b] and dL_dtheta [P] are host arrays; P_out
  * (host [sum N_b], may be NULL) receives the final probabilities.  Synchronous.

@@ -413,7 +413,13 @@ struct Adj {
   }
 };
 
-template <bool CPLX, int NR, bool ELL>
+// PH = 0: forward pass, then the backward sweep, recomputing the segments before
+// the last from their checkpoints.  With one segment (nothing to recompute) the
+// two passes run as separate launches, each with its own register budget:
+// PH = 1 runs the forward pass and stores the end state; PH = 2 starts from it.
+constexpr int PH_FUSED = 0, PH_FWD = 1, PH_BWD = 2;
+
+template <bool CPLX, int NR, bool ELL, int PH>
 __global__ void __launch_bounds__(AB)
 adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   using K = Adj<CPLX, NR, ELL>;
@@ -440,9 +446,13 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   const int64_t nseg = (n + S - 1) / S;
   double* ck = scr;                                   // [nseg][SV]
   double* seg = scr + (nseg > 0 ? nseg : 1) * SV;     // [S][4][SV] stage states
+  double* fin = seg + 4 * (int64_t)S * SV;            // [SV] end state (split passes)
   const double h = tj.dt, t0 = tj.t0;
 
   St y;
+  if constexpr (PH == PH_BWD) {
+    K::load(fin, y, N, Npad);
+  } else {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int nn = K::row(r);
@@ -464,14 +474,26 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
     K::rk4(sy, t0 + (double)j * h, h, y, lc, red, j >= jlast ? seg + 4 * (j - jlast) * SV : nullptr,
            SV);
   }
-  // final probabilities and the starting adjoint lambda_a = 2 a dL/dP
+  // final probabilities
+  if (A.P_out) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int nn = K::row(r);
+      if (nn < N) A.P_out[tj.amp_off + nn] = y.a[r].x * y.a[r].x + y.a[r].y * y.a[r].y;
+    }
+  }
+  if constexpr (PH == PH_FWD) {
+    K::save(fin, y, N, Npad);
+    return;
+  }
+  }
+  // the starting adjoint lambda_a = 2 a dL/dP
   St lam;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int nn = K::row(r);
     if (nn < N) {
       const double wgt = A.dLdP[tj.amp_off + nn];
-      if (A.P_out) A.P_out[tj.amp_off + nn] = y.a[r].x * y.a[r].x + y.a[r].y * y.a[r].y;
       lam.a[r] = make_double2(2.0 * wgt * y.a[r].x, 2.0 * wgt * y.a[r].y);
     } else {
       lam.a[r] = make_double2(0.0, 0.0);
@@ -482,10 +504,12 @@ adjoint_kernel(const DevSystem* __restrict__ systems, AdjArgs A) {
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
     const int64_t j0 = sg * S, j1 = (j0 + S < n) ? j0 + S : n;
     __syncthreads();                     // stage states of the previous segment are consumed
-    if (sg < nseg - 1) {                 // the last segment's states are there already
-      K::load(ck + sg * SV, y, N, Npad);
-      for (int64_t j = j0; j < j1; ++j)
-        K::rk4(sy, t0 + (double)j * h, h, y, lc, red, seg + 4 * (j - j0) * SV, SV);
+    if constexpr (PH == PH_FUSED) {
+      if (sg < nseg - 1) {               // the last segment's states are there already
+        K::load(ck + sg * SV, y, N, Npad);
+        for (int64_t j = j0; j < j1; ++j)
+          K::rk4(sy, t0 + (double)j * h, h, y, lc, red, seg + 4 * (j - j0) * SV, SV);
+      }
     }
     __syncthreads();                     // publishes the stored classical coordinates
     for (int64_t j = j1 - 1; j >= j0; --j) {
@@ -583,7 +607,7 @@ __global__ void spline_rows(const double* __restrict__ y, const double* __restri
 int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S) {
   const int64_t SV = 2 * (int64_t)Npad + 4;
   const int64_t nseg = (n_steps + S - 1) / S;
-  return ((nseg > 0 ? nseg : 1) + 4 * (int64_t)S) * SV;
+  return ((nseg > 0 ? nseg : 1) + 4 * (int64_t)S + 1) * SV;
 }
 
 hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
@@ -592,7 +616,7 @@ hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int N
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const int* h_goff, const uint32_t* gent,
                           const double* gval, const double* rad, const double* rad2,
-                          const int* gidx, int P, int nG, hipStream_t s) {
+                          const int* gidx, int P, int nG, bool one_segment, hipStream_t s) {
   if (nG > NGMAX || P > AB) return hipErrorInvalidValue;
   const int per = (int)((B + ADIES - 1) / ADIES);
   AdjArgs A{d_traj, dLdP, grad_part, P_out, scratch, scratch_stride, S, goff, gent, gval,
@@ -626,9 +650,18 @@ hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int N
   hipError_t e;
   auto go = [&](auto cp, auto el) {
     constexpr bool C = decltype(cp)::value, E = decltype(el)::value;
-    if (nr <= 1) adjoint_kernel<C, 1, E><<<grid, AB, lds, s>>>(d_systems, A);
-    else if (nr <= 2) adjoint_kernel<C, 2, E><<<grid, AB, lds, s>>>(d_systems, A);
-    else adjoint_kernel<C, 4, E><<<grid, AB, lds, s>>>(d_systems, A);
+    auto run = [&](auto nrt) {
+      constexpr int R = decltype(nrt)::value;
+      if (one_segment) {
+        adjoint_kernel<C, R, E, PH_FWD><<<grid, AB, lds, s>>>(d_systems, A);
+        adjoint_kernel<C, R, E, PH_BWD><<<grid, AB, lds, s>>>(d_systems, A);
+      } else {
+        adjoint_kernel<C, R, E, PH_FUSED><<<grid, AB, lds, s>>>(d_systems, A);
+      }
+    };
+    if (nr <= 1) run(std::integral_constant<int, 1>{});
+    else if (nr <= 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 4>{});
   };
   if (nr > 4) return hipErrorInvalidValue;
   if (cplx) {

@@ -1710,7 +1710,7 @@ mqct_status mqct_adjoint(mqct_context* c, const mqct_batch_desc* bd, int32_t che
                             (const int*)sh.pbufs[4], sh.h_goff.data(), (const uint32_t*)sh.pbufs[5],
                             (const double*)sh.pbufs[6], (const double*)sh.pbufs[1],
                             (const double*)sh.pbufs[2], (const int*)sh.pbufs[3], sh.P, sh.nG,
-                            c->stream), "adjoint: launch");
+                            maxn <= S, c->stream), "adjoint: launch");
   prof_mark(&c->prof, e1, c->stream);
   HIP_TRY(c, hipMemcpyAsync(dL_dtheta, base + o_g, (size_t)sh.P * 8, hipMemcpyDeviceToHost,
                             c->stream), "adjoint");

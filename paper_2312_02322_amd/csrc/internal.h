@@ -312,6 +312,8 @@ hipError_t run_binned_dp5(const DevSystem* d_systems, const DevSystem& hs, const
 // Adjoint (discrete RK4 adjoint with checkpointed recomputation).  The G_t of
 // the parametric form enter as nonzero lists: entries goff[t] .. goff[t+1]-1,
 // gent = row | col << 16, gval the values (h_goff: the offsets on the host).
+// one_segment: every trajectory has at most S steps (the forward and the backward
+// pass then run as two launches, nothing recomputed).
 int64_t adjoint_scratch_doubles(int Npad, int64_t n_steps, int S);
 hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int Npad,
                           const TrajIn* d_traj, const int* order,
@@ -319,7 +321,7 @@ hipError_t launch_adjoint(const DevSystem* d_systems, bool cplx, bool ell, int N
                           double* P_out, double* scratch, int64_t scratch_stride, int S,
                           const int* goff, const int* h_goff, const uint32_t* gent,
                           const double* gval, const double* rad, const double* rad2,
-                          const int* gidx, int P, int nG, hipStream_t s);
+                          const int* gidx, int P, int nG, bool one_segment, hipStream_t s);
 hipError_t launch_build_param_tables(const double* G, const double* rad, const int* gidx,
                                      const double* theta, int P, int nG, int N, int Npad, int K,
                                      double* Mout, hipStream_t s);
