@@ -458,6 +458,12 @@ mqct_status mqct_adjoint(mqct_context* ctx, const mqct_batch_desc* batch, int32_
  *   MQCT_OPT_TAIL          1 (default): use the tuned tail shape; 0: never switch;
  *                          2: run every class on its widest split-row shape from
  *                          the first step (for testing that form).
+ *   MQCT_OPT_PER_LAUNCH    attempts (RK4 steps, DP5 attempts) of a trajectory per
+ *                          step launch once a class is down to twice the number of
+ *                          compute units (1..64; 1, the default: one per launch
+ *                          throughout): a workgroup leaves its loop as soon as its
+ *                          trajectory is done, so the value changes only the
+ *                          number of launches, never a result.
  *   MQCT_OPT_COL_WORKSPACE the columns schedule's workspace cap in bytes (>= 0;
  *                          0, the default: 80 % of the device memory free at the
  *                          call plus the workspace already held).  The workspace
@@ -471,7 +477,7 @@ mqct_status mqct_adjoint(mqct_context* ctx, const mqct_batch_desc* batch, int32_
  * a shape switch happens at a chunk boundary.  Errors: MQCT_ERR_ARG.
  */
 enum { MQCT_OPT_GRAPHS = 1, MQCT_OPT_AUTOTUNE = 2, MQCT_OPT_CHUNK = 3, MQCT_OPT_RESET_TUNING = 4,
-       MQCT_OPT_TAIL = 5, MQCT_OPT_COL_WORKSPACE = 6 };
+       MQCT_OPT_TAIL = 5, MQCT_OPT_COL_WORKSPACE = 6, MQCT_OPT_PER_LAUNCH = 7 };
 mqct_status mqct_set_option(mqct_context* ctx, int32_t option, int64_t value);
 /* The shapes chosen so far, as JSON text: one object per class with dtype,
  * npad, method (0 RK4, 1 DP5), block, rows_per_lane, tuned, the candidates'

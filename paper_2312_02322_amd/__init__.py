@@ -25,7 +25,7 @@ INTEGRATORS = {"rk4": 0, "dp5": 1}
 DYNAMICS = {"ehrenfest": 0, "at": 1}
 LAYOUTS = {"dense": 0, "sparse": 1}
 SCHEDULES = {"auto": 0, "gemv": 1, "binned": 2, "queue": 3, "columns": 4}
-OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5, "col_workspace": 6}
+OPTIONS = {"graphs": 1, "autotune": 2, "chunk": 3, "reset_tuning": 4, "tail": 5, "col_workspace": 6, "per_launch": 7}
 MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {"EXITED": 1, "MAX_STEPS": 2, "STEP_UNDERFLOW": 4, "BELOW_GRID": 8, "NONFINITE": 16}
 
@@ -616,7 +616,7 @@ class Context:
         return k
 
     def set_option(self, name, value=1):
-        """Schedule options: graphs, autotune, chunk, reset_tuning, tail (the work list);
+        """Schedule options: graphs, autotune, chunk, reset_tuning, tail, per_launch (the work list);
         col_workspace (the columns schedule's workspace cap in bytes, 0 = default)."""
         self._check(lib().mqct_set_option(self.h, OPTIONS[name], int(value)))
 

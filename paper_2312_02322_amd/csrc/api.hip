@@ -1735,6 +1735,10 @@ mqct_status mqct_set_option(mqct_context* c, int32_t option, int64_t value) {
       if (value < 0 || value > 2) return fail(c, MQCT_ERR_ARG, "set_option: tail must be 0, 1 or 2");
       c->qopt.tail = (int)value;
       return MQCT_OK;
+    case MQCT_OPT_PER_LAUNCH:
+      if (value < 1 || value > 64) return fail(c, MQCT_ERR_ARG, "set_option: per_launch must be 1..64");
+      c->qopt.per_launch = (int)value;
+      return MQCT_OK;
     case MQCT_OPT_COL_WORKSPACE:
       if (value < 0) return fail(c, MQCT_ERR_ARG, "set_option: columns workspace cap must be >= 0");
       c->qopt.col_ws = value;

@@ -241,6 +241,7 @@ struct QArgs {
   DpCtl ctl;
   int64_t max_attempts;
   TrajOut out;
+  int per_launch;        // attempts (steps) of a trajectory per launch of the tail's kernels
 };
 
 // Kernels of one workgroup shape: init and step for RK4 [0] and DP5 [1]
@@ -250,6 +251,7 @@ struct QKernelSet {
   int split_waves;     // 0: rows shared out over the workgroup; W: split-row form with W waves
   const void* init[2];
   const void* step[2];
+  const void* step_multi[2];   // up to QArgs::per_launch attempts per launch (the tail)
 };
 const QKernelSet* queue_kernels(int dtype);   // [QUEUE_SHAPES]
 constexpr int QUEUE_SHAPES = 17;
@@ -265,6 +267,7 @@ struct QueueOpts {
   int tail = 1;        // 1: switch to the tuned split-row shape once few trajectories remain;
                        // 0: never; 2: run every class on a split-row shape (tests)
   int chunk = 16;      // step launches per replay
+  int per_launch = 1;  // attempts of a trajectory per step launch once few are left
   int64_t col_ws = 0;  // columns schedule: workspace cap in bytes (0: 80 % of free memory)
 };
 

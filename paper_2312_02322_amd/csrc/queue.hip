@@ -184,6 +184,7 @@ struct ClassRun {
   size_t entry = 0;      // its entry in the context's cache
   int count = 0;         // last active count read back
   int grid = 0;          // grid of the current graph / launches
+  bool multi = false;    // several attempts per launch (the tail)
   hipGraphExec_t exec = nullptr;
 };
 
@@ -230,6 +231,7 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     a.ctl = ctl;
     a.max_attempts = max_attempts;
     a.out = out;
+    a.per_launch = std::max(1, opt.per_launch);
     return a;
   };
   auto kset = [&](const ClassRun& r, int shape) -> const QKernelSet& {
@@ -364,8 +366,9 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
     const size_t lds = lds_of(r, r.shape);
     QArgs a = args_for(r.ws);
     hipError_t err;
+    const void* fn = r.multi ? ks.step_multi[method] : ks.step[method];
     for (int j = 0; j < chunk; ++j)
-      if ((err = launch(ks.step[method], r.grid, ks.block, lds, st, a)) != hipSuccess) return err;
+      if ((err = launch(fn, r.grid, ks.block, lds, st, a)) != hipSuccess) return err;
     q_compact<<<1, CT, 0, st>>>(r.ws.list, r.ws.list2, r.ws.count, r.ws.st);
     return hipGetLastError();
   };
@@ -375,8 +378,12 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
   };
   for (ClassRun& r : runs) {
     if ((e = prepare_fn(kset(r, r.shape).step[method], lds_of(r, r.shape))) != hipSuccess) return e;
+    if ((e = prepare_fn(kset(r, r.shape).step_multi[method], lds_of(r, r.shape))) != hipSuccess)
+      return e;
     if (r.tail_shape >= 0 &&
-        (e = prepare_fn(kset(r, r.tail_shape).step[method], lds_of(r, r.tail_shape))) != hipSuccess)
+        ((e = prepare_fn(kset(r, r.tail_shape).step[method], lds_of(r, r.tail_shape))) != hipSuccess ||
+         (e = prepare_fn(kset(r, r.tail_shape).step_multi[method], lds_of(r, r.tail_shape))) !=
+             hipSuccess))
       return e;
   }
   e = hipSuccess;
@@ -391,6 +398,11 @@ hipError_t run_queue(const DevSystem* d_systems, const TrajIn* d_traj,
       if (opt.tail && r.tail_shape >= 0 && r.shape != r.tail_shape &&
           (r.count <= 2 * cus || opt.tail == 2)) {
         r.shape = r.tail_shape;
+        drop_graph(r);
+      }
+      // few trajectories left: several attempts per launch
+      if (opt.per_launch > 1 && !r.multi && r.count <= 2 * cus) {
+        r.multi = true;
         drop_graph(r);
       }
       // shrink the grid once fewer than half of its workgroups have work

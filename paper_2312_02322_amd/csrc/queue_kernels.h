@@ -447,7 +447,15 @@ __global__ void __launch_bounds__(BLOCK) q_init(QArgs q) {
   if (i == 0 && threadIdx.x == 0) *q.ws.count = q.ws.n;
 }
 
-template <int DT, int BLOCK, int RPT, bool SPLIT, int METHOD>
+// One attempt (MULTI = false), or up to q.per_launch attempts of one trajectory
+// (MULTI = true, for the latency-bound tail of a batch; a separate kernel
+// because the loop costs registers that the one-attempt form keeps for
+// occupancy), leaving the loop when the trajectory is done.  Every thread holds
+// the same state (its fields come from workgroup reductions and LDS) and the exit
+// is taken from one workgroup vote, so all waves leave together; each attempt
+// reads back only the rows its own threads wrote, and its LDS areas are separated
+// from the next attempt's writes by the barriers of the stage evaluations.
+template <int DT, int BLOCK, int RPT, bool SPLIT, int METHOD, bool MULTI>
 __global__ void __launch_bounds__(BLOCK) q_step(QArgs q) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cnt = *q.ws.count;
@@ -456,8 +464,12 @@ __global__ void __launch_bounds__(BLOCK) q_step(QArgs q) {
   QState s = q.ws.st[i];
   if (s.flags & Q_DONE) return;
   Lds<DT> lds(smem, q.ws.npad);
-  if (METHOD == 0) QK<DT, BLOCK, RPT, SPLIT>::step_rk4(q, i, s, lds);
-  else QK<DT, BLOCK, RPT, SPLIT>::step_dp5(q, i, s, lds);
+  const int na = MULTI ? q.per_launch : 1;
+  for (int a = 0; a < na; ++a) {
+    if (METHOD == 0) QK<DT, BLOCK, RPT, SPLIT>::step_rk4(q, i, s, lds);
+    else QK<DT, BLOCK, RPT, SPLIT>::step_dp5(q, i, s, lds);
+    if (!MULTI || __syncthreads_or((s.flags & Q_DONE) != 0)) break;
+  }
   if (threadIdx.x == 0) q.ws.st[i] = s;
 }
 
@@ -484,13 +496,16 @@ void fill_one(QKernelSet& ks) {
   // rows per workgroup (per wave for the split-row form) beyond the largest
   // supported column count are not built
   if constexpr ((SP ? 64 : BL) * RP * Tr<DT>::VEC > 4096) {
-    ks.init[0] = ks.init[1] = ks.step[0] = ks.step[1] = nullptr;
+    ks.init[0] = ks.init[1] = ks.step[0] = ks.step[1] = ks.step_multi[0] = ks.step_multi[1] =
+        nullptr;
     return;
   } else {
     ks.init[0] = (const void*)q_init<DT, BL, RP, SP, 0>;
     ks.init[1] = (const void*)q_init<DT, BL, RP, SP, 1>;
-    ks.step[0] = (const void*)q_step<DT, BL, RP, SP, 0>;
-    ks.step[1] = (const void*)q_step<DT, BL, RP, SP, 1>;
+    ks.step[0] = (const void*)q_step<DT, BL, RP, SP, 0, false>;
+    ks.step[1] = (const void*)q_step<DT, BL, RP, SP, 1, false>;
+    ks.step_multi[0] = (const void*)q_step<DT, BL, RP, SP, 0, true>;
+    ks.step_multi[1] = (const void*)q_step<DT, BL, RP, SP, 1, true>;
   }
 }
 

@@ -1,10 +1,11 @@
 """GPU parity of the work-list schedule (one step attempt per launch for every
-unfinished trajectory, finished ones retired between chunks, chunks replayed as
-HIP graphs).
+unfinished trajectory, several once few are left, finished ones retired between
+chunks, chunks replayed as HIP graphs).
 
 * Fixed-step RK4 on a ragged batch computes exactly the arithmetic of the
   per-trajectory kernel when both use the same workgroup shape: the results are
-  compared bit for bit, with graphs on and off and for several chunk sizes.
+  compared bit for bit, with graphs on and off, for several chunk sizes and for
+  one or several attempts per launch.
 * Adaptive Dormand-Prince 5(4) against the FP64 oracle's DP5 (same tableau,
   error norm and controller): the two take the same accept/reject decisions
   except when an error estimate lands within rounding of 1, so step counts may
@@ -68,16 +69,20 @@ def test_queue_rk4_ragged_bitwise_equals_per_trajectory(ctx):
     try:
         common = dict(start(b), dt=b.dt, n_steps=b.n_steps)
         ref = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="gemv", **common)
-        for graphs, chunk in ((1, 16), (0, 16), (1, 1), (1, 7)):
-            say("  graphs=%d chunk=%d" % (graphs, chunk))
+        # per_launch: steps per launch once few trajectories are left (here from the start)
+        for graphs, chunk, per in ((1, 16, 4), (0, 16, 4), (1, 1, 4), (1, 7, 4), (1, 16, 1),
+                                   (0, 5, 1), (1, 3, 64), (0, 16, 7)):
+            say("  graphs=%d chunk=%d per_launch=%d" % (graphs, chunk, per))
             ctx.set_option("graphs", graphs)
             ctx.set_option("chunk", chunk)
+            ctx.set_option("per_launch", per)
             g = ctx.run_host([sid] * b.B, [s.N] * b.B, schedule="queue", **common)
             same(ref, g)
         assert np.array_equal(ref["steps"], b.n_steps)
     finally:
         ctx.set_option("graphs", 1)
         ctx.set_option("chunk", 16)
+        ctx.set_option("per_launch", 1)
         ctx.set_option("autotune", 1)
     ctx.free_system(sid)
 
@@ -153,15 +158,19 @@ def test_dp5_uneven_mixed_batch(ctx, fam):
             assert abs(int(g["steps"][i]) - int(o["steps"][k])) <= 3 + 0.01 * o["steps"][k]
     say("  max|dP| = %.3e, steps %d..%d" % (worst, g["steps"].min(), g["steps"].max()))
     assert worst < tol
-    # the same batch with graphs off and another chunk size: identical results
-    ctx.set_option("graphs", 0)
-    ctx.set_option("chunk", 5)
-    try:
-        g2 = ctx.run_host(sids, Ns, **start(b), **DP5)
-    finally:
-        ctx.set_option("graphs", 1)
-        ctx.set_option("chunk", 16)
-    same(g, g2)
+    # the same batch with graphs off, another chunk size and one or seven attempts
+    # per launch: identical results
+    for per in (4, 7):
+        ctx.set_option("graphs", 0)
+        ctx.set_option("chunk", 5)
+        ctx.set_option("per_launch", per)
+        try:
+            g2 = ctx.run_host(sids, Ns, **start(b), **DP5)
+        finally:
+            ctx.set_option("graphs", 1)
+            ctx.set_option("chunk", 16)
+            ctx.set_option("per_launch", 1)
+        same(g, g2)
     for i in ids:
         ctx.free_system(i)
 
