@@ -103,6 +103,24 @@ def test_checkpoint_interval_does_not_change_the_gradient(setup):
     assert np.array_equal(g1, g7) and np.array_equal(g1, g300) and np.array_equal(g1, gall)
 
 
+def test_ragged_step_counts_one_segment_and_checkpoints(setup):
+    """Trajectories of 300, 150, 0 and 299 steps in one gradient: the one-segment form
+    (a forward and a backward launch, every stage state stored) and the fused form with
+    checkpoints every 7 steps give the same gradient and probabilities bit for bit, and
+    the probabilities are those of the forward propagation."""
+    ctx, sid, s, b, w = setup
+    ctx.set_theta(sid, s.theta)
+    ns = np.array([300, 150, 0, 299], np.int64)
+    kw = dict(init_channel=b.init_channel, E_coll=b.E_coll, b=b.b, dt=b.dt, n_steps=ns, R0=b.R0)
+    say("ragged adjoint: steps %s" % ns.tolist())
+    g1, P1 = ctx.adjoint(sid, s.N, w, checkpoint_every=2 ** 31 - 1, **kw)
+    g7, P7 = ctx.adjoint(sid, s.N, w, checkpoint_every=7, **kw)
+    assert np.array_equal(g1, g7) and np.array_equal(P1, P7)
+    f = ctx.run_host([sid] * b.B, [s.N] * b.B, **kw)
+    assert np.max(np.abs(P1.reshape(b.B, s.N) - f["P"].reshape(b.B, s.N))) < 1e-12
+    assert np.all(P1.reshape(b.B, s.N)[2] == (np.arange(s.N) == b.init_channel[2]))
+
+
 def test_autograd_function(setup):
     import torch
     import paper_2312_02322_amd as mq
