@@ -178,6 +178,7 @@ void free_params(SysHost& s) {
     p = nullptr;
   }
   s.P = s.nG = 0;
+  s.h_goff.clear();
 }
 
 void free_system(SysHost& s) {
