@@ -56,6 +56,7 @@ template <> struct Tr<R32> {
 };
 
 constexpr int CHUNK = 64;   // stored rows per FP32 partial sum
+constexpr int JXB = 4;      // J_x widths up to this have a row's loads issued together
 
 // Sums produced by one right-hand-side evaluation.
 struct Sums {
@@ -403,12 +404,32 @@ struct Rhs {
       const double2 c = make_double2(cs * cur[r].x + sn * cur[r].y,
                                      cs * cur[r].y - sn * cur[r].x);
       double2 xc = make_double2(0.0, 0.0);
-      for (int q = 0; q < sy.jx_w; ++q) {
-        const int col = sy.jx_col[(int64_t)n * sy.jx_w + q];
-        const double jv = sy.jx_val[(int64_t)n * sy.jx_w + q];
-        const double2 cm = lds.c64[col];
-        xc.x = fma(jv, cm.x, xc.x);
-        xc.y = fma(jv, cm.y, xc.y);
+      const int W = sy.jx_w;
+      if (W <= JXB) {
+        // the row's entries are all requested before the first gather (the sum
+        // runs in entry order either way)
+        int jc[JXB];
+        double jv[JXB];
+#pragma unroll
+        for (int q = 0; q < JXB; ++q) {
+          jc[q] = q < W ? sy.jx_col[(int64_t)n * W + q] : 0;
+          jv[q] = q < W ? sy.jx_val[(int64_t)n * W + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < JXB; ++q) {
+          if (q >= W) break;
+          const double2 cm = lds.c64[jc[q]];
+          xc.x = fma(jv[q], cm.x, xc.x);
+          xc.y = fma(jv[q], cm.y, xc.y);
+        }
+      } else {
+        for (int q = 0; q < W; ++q) {
+          const int col = sy.jx_col[(int64_t)n * W + q];
+          const double jv = sy.jx_val[(int64_t)n * W + q];
+          const double2 cm = lds.c64[col];
+          xc.x = fma(jv, cm.x, xc.x);
+          xc.y = fma(jv, cm.y, xc.y);
+        }
       }
       const double2 u = U[r], v = V[r];
       sums[0] += c.x * v.x + c.y * v.y;
