@@ -206,6 +206,11 @@ def test_columns_errors(ctx, gpu_lib):
     (s,), _ = S.config1(n_traj=1, n_steps=1, jmax=2)               # N = 9, real
     rows, cols, vals, keep = coo_of(s.M)
     kw = dict(R_grid=s.R_grid, E=s.E, mu=s.mu)
+    # option values out of range
+    for name, v in (("col_workspace", -1), ("per_launch", 0), ("per_launch", 65)):
+        with pytest.raises(gpu_lib.MQCTError) as e:
+            ctx.set_option(name, v)
+        assert e.value.code == -1, (name, v)
 
     def refused(code, r, c, v):
         with pytest.raises(gpu_lib.MQCTError) as e:
