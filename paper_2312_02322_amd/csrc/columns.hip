@@ -29,9 +29,9 @@ namespace mqct {
 
 namespace {
 
-constexpr int CB = 256;         // threads of the row kernels
+constexpr int CB = 512;         // threads of the row kernels
 constexpr int CW = CB / 64;
-constexpr int ROWS_PER_WAVE = 2;
+constexpr int ROWS_PER_WAVE = 1;
 constexpr int ROWS_PER_WG = CW * ROWS_PER_WAVE;
 constexpr int NXCD = 8;         // dies of the device; workgroups are dealt to them round-robin
 constexpr int GATHER_UNROLL = 8;
