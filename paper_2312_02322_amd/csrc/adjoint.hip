@@ -71,7 +71,7 @@ struct AdjArgs {
   int tbeg[ANW + 1];
 };
 
-constexpr int GU = 4;      // nonzeros of G_t per lane whose loads are issued together
+constexpr int GU = 8;      // nonzeros of G_t per lane whose loads are issued together
 constexpr int JXB = 4;     // J_x widths up to this have their loads issued together
 
 constexpr int ADIES = 8;   // accelerator dies of the device, each with its own L2
@@ -302,7 +302,7 @@ struct Adj {
       Mg[r] = MJc[r] = Mpc[r] = make_double2(0.0, 0.0);
       if (n >= N) continue;
       double2 Mc = make_double2(0.0, 0.0), Mppc = make_double2(0.0, 0.0);
-#pragma unroll 2
+#pragma unroll 1
       for (int j = 0; j < nst; ++j) {
         const int m = ell ? sy.ell_col[(int64_t)j * sy.Npad + n] : j;
         const Raw q = raw(sy, sp.k, j, n);
