@@ -11,7 +11,7 @@
 // (CT: the columns padded to even), so the product's gather of a coupled row m
 // reads CT contiguous values.
 //
-// One launch per RK4 stage: a wave takes rows of one group, two columns per
+// One launch per RK4 stage: a wave takes one row of one group, two columns per
 // lane.  A row's elements are read 64 at a time, one per lane, and turned into
 // the spline value at the stage's R in FP64; then they are broadcast one by one
 // while every lane gathers its columns of the coupled row's phased amplitudes
